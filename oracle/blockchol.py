@@ -1,0 +1,106 @@
+"""Two-block Cholesky of the normal matrix (oracle, medium/large cases).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+The unknowns are split as in the paper's expanded transfer matrix, Sect.
+2.2.3 (``H(1:M, 1:K0)`` background, the rest sky): ``A = [[A_bb, A_sb^T],
+[A_sb, A_ss]]`` with the first ``n_b`` (background) unknowns eliminated
+first.  This is the oracle's *own* ordering (background first, then the
+remaining unknowns in their natural order); it need not match the ordering
+the product chooses.
+
+Factorisation ``A = L L^T`` (Sect. 3.2.2 with D folded into L):
+``L_bb = chol(A_bb)``, ``L_sb = A_sb L_bb^-T``, and the remaining block is the
+Cholesky factor of the Schur complement ``S = A_ss - L_sb L_sb^T``.
+
+Solution (Sect. 3.2.3): forward ``z = L^-1 b`` then backward ``x = L^-T z``.
+
+Variances (Sect. 2.4.1) ``(A^-1)_ii = ||L^-1 e_i||^2`` (the left-looking
+formula of Sect. 4.3 with D = I).  Column i of ``L^-1`` is
+``[u; -L_ss^-1 L_sb u]`` with ``u = L_bb^-1 e_i`` for a background unknown
+and ``[0; L_ss^-1 e_i']`` for a sky unknown.  Requested entries are computed
+in blocks of right-hand sides (128 at a time, as in Sect. 3.3.1 / Table 6).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+
+class BlockCholesky:
+    def __init__(self, A, n_b: int):
+        A = sp.csr_matrix(A)
+        n = A.shape[0]
+        self.n, self.n_b = n, n_b
+        Abb = A[:n_b, :n_b].tocsr()
+        Asb = A[n_b:, :n_b].tocsc()
+        Ass = A[n_b:, n_b:]
+        off = Abb - sp.diags(Abb.diagonal())
+        self.bb_diagonal = off.count_nonzero() == 0
+        if n_b == 0:
+            self.Lbb = np.zeros((0, 0))
+            self.Lsb = sp.csr_matrix((n - n_b, 0))
+        elif self.bb_diagonal:
+            d = Abb.diagonal()
+            if np.any(~(d > 0)):
+                raise ValueError("background block not positive definite")
+            self.Lbb = np.sqrt(d)                       # diagonal factor
+            self.Lsb = (Asb @ sp.diags(1.0 / self.Lbb)).tocsr()
+        else:
+            self.Lbb = np.linalg.cholesky(Abb.toarray())
+            self.Lsb = sp.csr_matrix(
+                sla.solve_triangular(self.Lbb, Asb.toarray().T, lower=True).T)
+        S = Ass.toarray()
+        if n_b:
+            S -= (self.Lsb @ self.Lsb.T).toarray()
+        self.Lss = np.linalg.cholesky(S)
+
+    # -- triangular solves with the block factor ------------------------------
+    def _lbb_solve(self, v, trans=False):
+        if self.n_b == 0:
+            return v
+        if self.bb_diagonal:
+            return v / (self.Lbb[:, None] if v.ndim == 2 else self.Lbb)
+        return sla.solve_triangular(self.Lbb, v, lower=True,
+                                    trans="T" if trans else "N")
+
+    def forward(self, b):
+        """z = L^-1 b."""
+        b = np.asarray(b, dtype=np.float64)
+        zb = self._lbb_solve(b[:self.n_b])
+        zs = sla.solve_triangular(self.Lss, b[self.n_b:] - self.Lsb @ zb,
+                                  lower=True)
+        return np.concatenate([zb, zs])
+
+    def backward(self, z):
+        """x = L^-T z."""
+        zb, zs = z[:self.n_b], z[self.n_b:]
+        xs = sla.solve_triangular(self.Lss, zs, lower=True, trans="T")
+        xb = self._lbb_solve(zb - self.Lsb.T @ xs, trans=True)
+        return np.concatenate([xb, xs])
+
+    def solve(self, b):
+        return self.backward(self.forward(b))
+
+    # -- variances -------------------------------------------------------------
+    def diag_inv(self, idx=None, block: int = 128):
+        """``(A^-1)_ii`` for the requested unknowns (all by default)."""
+        idx = np.arange(self.n) if idx is None else np.asarray(idx)
+        out = np.empty(len(idx))
+        nb, ns = self.n_b, self.n - self.n_b
+        for k0 in range(0, len(idx), block):
+            sel = idx[k0:k0 + block]
+            E = np.zeros((self.n, len(sel)))
+            E[sel, np.arange(len(sel))] = 1.0
+            U = self._lbb_solve(E[:nb])                    # L_bb^-1 part
+            V = sla.solve_triangular(self.Lss, E[nb:] - self.Lsb @ U,
+                                     lower=True)          # L_ss^-1 part
+            out[k0:k0 + block] = (U * U).sum(axis=0) + (V * V).sum(axis=0)
+            del E
+        return out
+
+    def nnz_L(self):
+        ns = self.n - self.n_b
+        lbb = self.n_b if self.bb_diagonal else np.count_nonzero(np.tril(self.Lbb))
+        return int(lbb + self.Lsb.nnz + ns * (ns + 1) // 2)

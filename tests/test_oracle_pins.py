@@ -1,0 +1,369 @@
+"""Pins for the CPU oracle against facts the paper and mathematics fix.
+
+Every test here runs on the CPU.  The oracle is checked against exact
+rational arithmetic, hand-worked fixtures, the paper's worked elimination-tree
+example, closed forms, invariants and a statistical property of the
+variances -- never against itself alone.
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import spi_synth as synth
+from oracle import (normal_equations, normal_equations_bruteforce, cholesky,
+                    forward_subst, backward_subst, solve_dense,
+                    inverse_from_cholesky, diag_inv_colnorms,
+                    selected_entry_pruned, BlockCholesky, oracle_solve)
+from oracle import etree as et
+from oracle.certify import normal_residual_ld, refine_inverse_column
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- exact helpers
+def _frac_matrix(A):
+    return [[Fraction(int(v)) if float(v).is_integer() else Fraction(float(v))
+             for v in row] for row in np.asarray(A)]
+
+
+def _exact_inverse(A):
+    """Gauss-Jordan elimination in exact rational arithmetic."""
+    n = len(A)
+    M = [row[:] + [Fraction(int(i == j)) for j in range(n)]
+         for i, row in enumerate(_frac_matrix(A))]
+    for k in range(n):
+        piv = next(r for r in range(k, n) if M[r][k] != 0)
+        M[k], M[piv] = M[piv], M[k]
+        pk = M[k][k]
+        M[k] = [v / pk for v in M[k]]
+        for r in range(n):
+            if r != k and M[r][k] != 0:
+                f = M[r][k]
+                M[r] = [a - f * b for a, b in zip(M[r], M[k])]
+    return [row[n:] for row in M]
+
+
+def _exact_ldl(A):
+    """A = Lt D Lt^T with unit lower Lt, exact rationals."""
+    n = len(A)
+    F = _frac_matrix(A)
+    Lt = [[Fraction(int(i == j)) for j in range(n)] for i in range(n)]
+    D = [Fraction(0)] * n
+    for j in range(n):
+        D[j] = F[j][j] - sum(Lt[j][k] ** 2 * D[k] for k in range(j))
+        for i in range(j + 1, n):
+            Lt[i][j] = (F[i][j] - sum(Lt[i][k] * Lt[j][k] * D[k]
+                                      for k in range(j))) / D[j]
+    return Lt, D
+
+
+def _integer_spd(n, seed, extra_rows=None):
+    rng = np.random.default_rng(seed)
+    m = extra_rows or 2 * n
+    H = rng.integers(-3, 4, size=(m, n)).astype(float)
+    H[rng.random((m, n)) < 0.5] = 0.0
+    H = np.vstack([H, 2 * np.eye(n)])
+    return H.T @ H, H
+
+
+# ------------------------------------------------------------ normal equations
+def _read_fixture(name):
+    rows = {}
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *vals = line.split()
+            rows.setdefault(key, []).append([float(v) for v in vals])
+    return rows
+
+
+def test_normal_equations_hand_worked_fixture():
+    fx = _read_fixture("normal_eq_3x2.txt")
+    H = np.array(fx["H"])
+    w, y = np.array(fx["w"][0]), np.array(fx["y"][0])
+    Hs = sp.csr_matrix(H)
+    Hs.eliminate_zeros()
+    A, b = normal_equations(Hs.indptr, Hs.indices, Hs.data, w, y, 2)
+    assert np.array_equal(A.toarray(), np.array(fx["A"]))
+    assert np.array_equal(b, np.array(fx["b"][0]))
+    Ab, bb = normal_equations_bruteforce(Hs.indptr, Hs.indices, Hs.data, w, y, 2)
+    assert np.array_equal(Ab, np.array(fx["A"]))
+    assert np.array_equal(bb, np.array(fx["b"][0]))
+
+
+def test_normal_equations_identity_transfer_matrix():
+    n = 7
+    w = np.arange(1, n + 1, dtype=float)
+    y = np.arange(10, 10 + n, dtype=float)
+    I = sp.identity(n, format="csr")
+    A, b = normal_equations(I.indptr, I.indices, I.data, w, y, n)
+    assert np.array_equal(A.toarray(), np.diag(w))
+    assert np.array_equal(b, w * y)
+
+
+def test_normal_equations_bruteforce_matches_sparse_exactly():
+    p = synth.make_random(40, 15, 4, seed=3, integer=True)
+    A, b = normal_equations(p.rowptr, p.col, p.val, p.w, p.y, p.n)
+    Ab, bb = normal_equations_bruteforce(p.rowptr, p.col, p.val, p.w, p.y, p.n)
+    assert np.array_equal(A.toarray(), Ab)       # integers: exact in binary64
+    assert np.array_equal(b, bb)
+    # symmetric, and the diagonal equals the weighted column sums of squares
+    assert np.array_equal(Ab, Ab.T)
+    H = p.scipy_csr().toarray()
+    assert np.array_equal(np.diag(Ab), (H * H * p.w[:, None]).sum(axis=0))
+
+
+# ---------------------------------------------------------- elimination tree
+def _paper_tree():
+    fx = _read_fixture("etree_6node.txt")
+    parent = {int(a): int(b) for a, b in fx["parent"]}
+    return fx, [parent[v] - 1 for v in range(1, 7)]  # 0-based, root -> -1
+
+
+# A pattern whose elimination tree is the paper's tree, with one fill entry
+# (eliminating node 2 connects 3 and 6).  1-based pairs.
+_PAPER_PATTERN = [(1, 4), (1, 5), (2, 3), (2, 6), (3, 5), (4, 5), (5, 6)]
+
+
+def test_etree_paper_example():
+    fx, parent = _paper_tree()
+    edges = [(a - 1, b - 1) for a, b in _PAPER_PATTERN]
+    struct = et.symbolic_cholesky(6, edges)
+    assert et.etree_from_struct(struct) == parent
+    assert struct[1] == [2, 5]                     # fill (6, 3) from node 2
+    assert et.roots(parent) == [5]
+    assert sorted(et.leaves(parent)) == [v - 1 for v in fx["leaves"][0]]
+    assert et.descendants(parent, 4) == [v - 1 for v in fx["descendants"][0][1:]]
+    assert set(et.children(parent)[4]) == {2, 3}
+    assert et.ancestors(parent, 3) == [4, 5]
+    order = [int(v) - 1 for v in fx["postorder"][0]]
+    assert et.is_postorder(order, parent)
+    assert et.is_postorder(et.postorder(parent), parent)
+    assert not et.is_postorder([0, 1, 3, 2, 4, 5], parent)   # 4's subtree split
+
+
+def test_etree_matches_numerical_cholesky_pattern():
+    """Parents from the symbolic code equal those read off a numerical L."""
+    rng = np.random.default_rng(0)
+    for trial in range(20):
+        n = int(rng.integers(5, 25))
+        pairs = [(i, j) for i in range(n) for j in range(i)
+                 if rng.random() < 0.15]
+        A = np.eye(n) * (n + 1.0)
+        for i, j in pairs:
+            A[i, j] = A[j, i] = rng.uniform(0.5, 1.0)
+        Ln = np.linalg.cholesky(A)
+        par_num = []
+        for j in range(n):
+            nz = np.nonzero(np.abs(Ln[j + 1:, j]) > 1e-300)[0]
+            par_num.append(int(nz[0]) + j + 1 if len(nz) else -1)
+        assert et.etree_from_struct(et.symbolic_cholesky(n, pairs)) == par_num
+
+
+def test_pruned_inverse_entry_paper_example():
+    fx, parent = _paper_tree()
+    n = 6
+    A = np.eye(n) * 6.0
+    for a, b in _PAPER_PATTERN:
+        A[a - 1, b - 1] = A[b - 1, a - 1] = 1.0
+    L = cholesky(A)
+    i, j = (int(v) - 1 for v in fx["entry"][0])
+    val, fwd, bwd = selected_entry_pruned(L, parent, i, j)
+    assert fwd == [int(v) - 1 for v in fx["forward"][0]]
+    assert bwd == [int(v) - 1 for v in fx["backward"][0]]
+    skipped = {int(v) - 1 for v in fx["skipped"][0]}
+    assert not skipped & set(fwd + bwd)
+    Zx = _exact_inverse(A)
+    assert abs(val - float(Zx[i][j])) <= 1e-15 * abs(float(Zx[i][j]))
+
+
+# --------------------------------------------------------- dense factorisation
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dense_cholesky_matches_exact_ldl(seed):
+    A, _ = _integer_spd(8, seed)
+    Lt, D = _exact_ldl(A)
+    L_exact = np.array([[float(Lt[i][j]) * np.sqrt(float(D[j])) for j in range(8)]
+                        for i in range(8)])
+    L = cholesky(A)
+    assert np.allclose(L, L_exact, rtol=1e-13, atol=1e-13 * np.abs(L_exact).max())
+    assert np.array_equal(L, np.tril(L))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dense_solve_inverse_and_colnorms_match_exact(seed):
+    A, H = _integer_spd(9, seed)
+    Zx = np.array([[float(v) for v in row] for row in _exact_inverse(A)])
+    b = np.arange(1, 10, dtype=float)
+    x, L = solve_dense(A, b)
+    assert np.allclose(x, Zx @ b, rtol=1e-12, atol=0)
+    assert np.allclose(inverse_from_cholesky(L), Zx, rtol=1e-12, atol=1e-15)
+    assert np.allclose(diag_inv_colnorms(L), np.diag(Zx), rtol=1e-13, atol=0)
+    # forward/backward separately: L z = b and L^T x = z
+    z = forward_subst(L, b)
+    assert np.allclose(L @ z, b, rtol=1e-14, atol=1e-13)
+    assert np.allclose(L.T @ backward_subst(L, z), z, rtol=1e-14, atol=1e-13)
+
+
+def test_pruned_entries_match_exact_inverse_random_pattern():
+    A, _ = _integer_spd(10, 5)
+    n = A.shape[0]
+    pairs = [(i, j) for i in range(n) for j in range(i) if A[i, j] != 0]
+    parent = et.etree_from_struct(et.symbolic_cholesky(n, pairs))
+    L = cholesky(A)
+    Zx = _exact_inverse(A)
+    for i in range(n):
+        for j in range(n):
+            val, _, _ = selected_entry_pruned(L, parent, i, j)
+            ref = float(Zx[i][j])
+            assert abs(val - ref) <= 1e-12 * max(abs(ref), 1e-3)
+
+
+def test_not_spd_is_reported():
+    A = np.array([[4.0, 2.0], [2.0, 1.0 - 1e-3]])
+    with pytest.raises(ValueError):
+        cholesky(A)
+
+
+# ------------------------------------------------------------- closed forms
+def test_two_unknown_closed_form():
+    """1 background unknown (coefficient 1) + 1 sky pixel with responses h."""
+    h = np.array([0.3, 0.9, 0.5, 0.7])
+    w = np.array([0.01, 0.02, 0.015, 0.005])
+    y = np.array([40.0, 61.0, 52.0, 48.0])
+    rowptr = np.arange(0, 9, 2, dtype=np.int64)
+    col = np.tile(np.array([0, 1], dtype=np.int32), 4)
+    val = np.ravel(np.column_stack([np.ones(4), h]))
+    a11, a12, a22 = w.sum(), (w * h).sum(), (w * h * h).sum()
+    b1, b2 = (w * y).sum(), (w * h * y).sum()
+    det = a11 * a22 - a12 * a12
+    x_ref = np.array([(a22 * b1 - a12 * b2) / det, (a11 * b2 - a12 * b1) / det])
+    d_ref = np.array([a22 / det, a11 / det])
+    A, b = normal_equations(rowptr, col, val, w, y, 2)
+    x, L = solve_dense(A.toarray(), b)
+    assert np.allclose(x, x_ref, rtol=1e-13)
+    assert np.allclose(diag_inv_colnorms(L), d_ref, rtol=1e-13)
+    f = BlockCholesky(A, 1)
+    assert np.allclose(f.solve(b), x_ref, rtol=1e-13)
+    assert np.allclose(f.diag_inv(), d_ref, rtol=1e-13)
+
+
+def test_block_diagonal_problem_splits():
+    """Two problems with no shared row: diag(A^-1) is the per-block diagonal."""
+    p1 = synth.make_random(30, 8, 3, seed=11)
+    p2 = synth.make_random(25, 6, 3, seed=12)
+    rowptr = np.concatenate([p1.rowptr, p1.rowptr[-1] + p2.rowptr[1:]])
+    col = np.concatenate([p1.col, p2.col + p1.n]).astype(np.int32)
+    val = np.concatenate([p1.val, p2.val])
+    w = np.concatenate([p1.w, p2.w])
+    y = np.concatenate([p1.y, p2.y])
+    A, b = normal_equations(rowptr, col, val, w, y, p1.n + p2.n)
+    x, L = solve_dense(A.toarray(), b)
+    d = diag_inv_colnorms(L)
+    for p, sl in ((p1, slice(0, p1.n)), (p2, slice(p1.n, None))):
+        Ai, bi = normal_equations(p.rowptr, p.col, p.val, p.w, p.y, p.n)
+        Zi = np.linalg.inv(Ai.toarray())          # textbook inverse (LAPACK)
+        assert np.allclose(d[sl], np.diag(Zi), rtol=1e-12)
+        assert np.allclose(x[sl], Zi @ bi, rtol=1e-11)
+
+
+# ----------------------------------------------- block factorisation (cfg0)
+@pytest.fixture(scope="module")
+def tiny():
+    p = synth.make_config(0)
+    A, b = normal_equations(p.rowptr, p.col, p.val, p.w, p.y, p.n)
+    return p, A, b
+
+
+def test_block_factor_matches_dense_and_invariants(tiny):
+    p, A, b = tiny
+    Ad = A.toarray()
+    x_d, L = solve_dense(Ad, b)
+    d_d = diag_inv_colnorms(L)
+    f = BlockCholesky(A, p.n_bg)
+    assert f.bb_diagonal                      # background unknowns share no row
+    x_b = f.solve(b)
+    d_b = f.diag_inv()
+    assert np.linalg.norm(x_b - x_d) / np.linalg.norm(x_d) < 1e-12
+    assert np.max(np.abs(d_b - d_d) / d_d) < 1e-12
+    # residual and Cauchy-Schwarz lower bound diag(A^-1)_i >= 1/A_ii > 0
+    assert np.linalg.norm(Ad @ x_b - b) / np.linalg.norm(b) < 1e-14
+    assert np.all(d_b * np.diag(Ad) >= 1.0 - 1e-12)
+    # against LAPACK's inverse (a textbook routine, not the oracle's code)
+    Z = np.linalg.inv(Ad)
+    assert np.max(np.abs(d_b - np.diag(Z)) / np.diag(Z)) < 1e-10
+
+
+def test_block_factor_general_pivot_block():
+    """Leading block that is not diagonal goes through the general branch."""
+    p = synth.make_random(60, 12, 4, seed=4)
+    A, b = normal_equations(p.rowptr, p.col, p.val, p.w, p.y, p.n)
+    f = BlockCholesky(A, 5)
+    assert not f.bb_diagonal
+    Z = np.linalg.inv(A.toarray())
+    assert np.allclose(f.solve(b), Z @ b, rtol=1e-10)
+    assert np.allclose(f.diag_inv(), np.diag(Z), rtol=1e-10)
+
+
+def test_certified_solution_and_inverse_column(tiny):
+    p, A, b = tiny
+    out = oracle_solve(p, diag_idx=[0, 5, 400, 779], refine_steps=2)
+    r = normal_residual_ld(p.rowptr, p.col, p.val, p.w, p.y, out["x"])
+    assert float(np.max(np.abs(r))) <= 1e-13 * float(np.max(np.abs(b)))
+    f = out["factor"]
+    for j, dj in zip(out["diag_idx"], out["diag"]):
+        zc = refine_inverse_column(p, f.solve, int(j))
+        assert abs(float(zc[j]) - dj) <= 1e-13 * dj
+
+
+def test_pulls_have_unit_scale():
+    """Unscaled diag(A^-1) is the variance: pulls (x - x_true)/sd ~ N(0, 1).
+
+    Catches a wrong variance scale (a factor 2 moves the std to 0.71 or
+    1.41), a wrong sign or index in the solve (mean drifts away from 0).
+    """
+    pulls = []
+    for seed in range(6):
+        p = synth.make_config(0, seed=seed)
+        A, b = normal_equations(p.rowptr, p.col, p.val, p.w, p.y, p.n)
+        f = BlockCholesky(A, p.n_bg)
+        x = f.solve(b)
+        d = f.diag_inv()
+        pulls.append((x - p.x_true) / np.sqrt(d))
+    pulls = np.concatenate(pulls)
+    assert abs(pulls.mean()) < 0.15
+    assert abs(pulls.std() - 1.0) < 0.06
+
+
+# --------------------------------------------------- planted oracle mistakes
+def test_planted_mistakes_are_caught(tiny):
+    """Variants with a dropped term, a sign flip and a transposed operand
+    must fail the same checks the real oracle passes."""
+    p, A, b = tiny
+    Ad = A.toarray()
+    f = BlockCholesky(A, p.n_bg)
+    # (1) dropped Schur-complement term: factor A_ss instead of S
+    bad = BlockCholesky(A, p.n_bg)
+    bad.Lss = np.linalg.cholesky(A[p.n_bg:, p.n_bg:].toarray())
+    xb = bad.solve(b)
+    assert np.linalg.norm(Ad @ xb - b) / np.linalg.norm(b) > 1e-6
+    # (2) sign flip in the coupling block
+    bad2 = BlockCholesky(A, p.n_bg)
+    bad2.Lsb = -bad2.Lsb
+    assert np.linalg.norm(Ad @ bad2.solve(b) - b) / np.linalg.norm(b) > 1e-6
+    # (3) transposed factor in the backward substitution (L x = z, not L^T)
+    As, bs = Ad[-40:, -40:], b[-40:]          # sky block: L is not diagonal
+    L = cholesky(As)
+    z = forward_subst(L, bs)
+    x_wrong = forward_subst(L, z)
+    assert np.linalg.norm(As @ x_wrong - bs) / np.linalg.norm(bs) > 1e-6
+    x_right = backward_subst(L, z)
+    assert np.linalg.norm(As @ x_right - bs) / np.linalg.norm(bs) < 1e-14
+    # (4) a missing diagonal term in the variances: norm of the sky part only
+    d_ok = f.diag_inv(np.arange(5))
+    U = 1.0 / f.Lbb[:5]
+    assert np.all(np.abs(d_ok - (d_ok - U * U)) / d_ok > 1e-3)
