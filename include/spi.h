@@ -1,0 +1,216 @@
+/*
+ * spi.h -- C ABI of the MI355X (gfx950) sparse weighted least-squares solver.
+ *
+ * The library solves the normal equations of a weighted linear
+ * least-squares problem and returns the variances of the solution, as
+ * stated in Bouchet et al., "Simultaneous analysis of large INTEGRAL/SPI
+ * datasets" (Sect. 2.4.1, the chi-square merit function, the normal
+ * equation and the variance relation):
+ *
+ *     A = H^T W H,   b = H^T W y,   x = A^-1 b,   Var(x_i) ~ (A^-1)_ii
+ *
+ * with H an M x N sparse transfer matrix, W = Sigma^-2 a positive diagonal
+ * weight (one weight per measurement row) and y the data.  The solve is a
+ * sparse direct method in three phases (Sect. 3.2): analysis on the host
+ * (ordering and symbolic structure, Sect. 3.2.1), a multifrontal Cholesky
+ * factorisation A = L L^T on the GPU (Sect. 3.2.2; D of the paper's L D L^T
+ * is folded into L), and forward/backward substitution (Sect. 3.2.3).  The
+ * variances are the diagonal of A^-1 (Sect. 3.3), computed by selected
+ * inversion on the pattern of L.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Status: every call returns an int status (enum spi_status).  Nothing
+ *    aborts or throws across the ABI.  spi_last_error() gives a text.
+ *  - Ownership: the caller owns every buffer it passes.  The library copies
+ *    what it keeps (the pattern during spi_analyze, the values during
+ *    spi_set_values) into memory owned by the handle, freed by spi_destroy.
+ *  - Memory: "host" pointers are ordinary CPU memory; "device" pointers are
+ *    GPU memory of the device that was current at spi_analyze (for instance
+ *    torch.Tensor.data_ptr() of a CUDA/HIP tensor).
+ *  - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
+ *    All device work of a handle is ordered on that stream.  Calls that
+ *    only enqueue work (spi_set_values, spi_rhs, spi_solve, spi_diag_inv)
+ *    return before it completes: device outputs are defined once the
+ *    stream has reached that point, as with hipMemcpyAsync.  spi_factor
+ *    synchronises the stream before returning, because it reports a
+ *    non-positive pivot as a status.
+ *  - Threads: one handle must not be used by two threads at once.
+ *  - Indices are 0-based.  Dense vectors are float64, in the original
+ *    unknown order (column order of H) unless stated otherwise.
+ */
+#ifndef SPI_H
+#define SPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spi_handle spi_handle;
+
+enum spi_status {
+    SPI_OK = 0,
+    SPI_E_ARG = 1,      /* invalid argument / malformed CSR / unobserved unknown */
+    SPI_E_STATE = 2,    /* call out of order (e.g. spi_solve before spi_factor) */
+    SPI_E_NOT_SPD = 3,  /* a non-positive or non-finite pivot (A not SPD) */
+    SPI_E_OOM = 4,      /* device allocation failed */
+    SPI_E_HIP = 5,      /* any other HIP runtime error */
+    SPI_E_NOCONV = 6    /* iterative refinement did not reach its tolerance */
+};
+
+enum spi_precision {
+    SPI_FP64 = 0,       /* every stage in binary64 */
+    SPI_MIXED = 1       /* binary32 root bulk, binary64 pivot tiles + refinement */
+};
+
+typedef struct spi_opts {
+    int32_t precision;      /* enum spi_precision; default SPI_FP64 */
+    int32_t max_group;      /* max leaf columns amalgamated in one front; default 32 */
+    double leaf_max_work;   /* a column is a leaf candidate only if the total
+                               length of the rows it appears in is <= this;
+                               default 65536 */
+    double amalg_density;   /* min fraction of structural non-zeros in an
+                               amalgamated leaf panel; default 0.35 */
+    int32_t refine_steps;   /* refinement steps of spi_solve with a
+                               double-double residual; default 2 */
+    int32_t timing;         /* 1: time the phases with HIP events on the
+                               handle's stream (see spi_info); default 0 */
+    int32_t reserved[6];    /* must be zero */
+} spi_opts;
+
+typedef struct spi_info_t {
+    int64_t m, n, nnz_h;        /* shape of H and its non-zeros */
+    int64_t nnz_a;              /* non-zeros of A = H^T W H (both triangles) */
+    int64_t nnz_l;              /* non-zeros of L (lower, incl. diagonal, as stored) */
+    int64_t n_leaf;             /* unknowns eliminated in leaf fronts */
+    int64_t n_groups;           /* leaf fronts (amalgamated supernodes) */
+    int64_t n_root;             /* order of the dense root front */
+    int64_t n_root_padded;      /* root order padded to the tile size */
+    int64_t failed_col;         /* original column of the first bad pivot, or -1 */
+    double flops_factor;        /* algorithmic flops of spi_factor */
+    double flops_selinv;        /* algorithmic flops of spi_diag_inv */
+    double flops_solve;         /* algorithmic flops of one spi_solve pass, 1 RHS */
+    double flops_assembly;      /* flops of the H^T W H assembly */
+    double t_analyze_ms;        /* host time of spi_analyze */
+    int32_t precision;          /* precision in use */
+    int32_t refine_steps_done;  /* refinement steps of the last spi_solve */
+    double last_refine_norm;    /* max-norm of the last correction / max-norm of x */
+    /* Device time of the phases of the last calls, in ms, measured with HIP
+     * events on the handle's stream when opts.timing = 1 (else 0): */
+    double t_leaf_ms;           /* leaf fronts: assembly, pivots, panels */
+    double t_extend_ms;         /* root assembly + extend-add of the leaves */
+    double t_potrf_ms;          /* root Cholesky */
+    double t_solve_ms;          /* whole spi_solve incl. refinement */
+    double t_trtri_ms;          /* inverse of the root factor */
+    double t_lauum_ms;          /* root block of A^-1 from the inverse factor */
+    double t_selinv_ms;         /* leaf selected inversion + diagonal output */
+} spi_info_t;
+
+/* Fill `o` with the defaults listed above. */
+void spi_default_opts(spi_opts* o);
+
+/*
+ * Analysis (Sect. 3.2.1): validate the pattern of H, choose the
+ * elimination order, build the assembly tree (independent leaf fronts whose
+ * unknowns share no measurement row, amalgamated into supernodes, and one
+ * dense root front), the index maps the kernels use, and upload them.
+ *
+ *  h       [out] new handle (NULL on failure, except SPI_E_ARG detail text
+ *                is not available then; spi_last_error(NULL) returns the
+ *                last analysis error of the calling thread)
+ *  m, n    rows (measurements) and columns (unknowns) of H; m >= 1, n >= 1
+ *  rowptr  host, int64[m + 1], CSR row pointers, rowptr[0] = 0, non-decreasing
+ *  col     host, int32[rowptr[m]], column indices, strictly increasing
+ *          within each row, each in [0, n)
+ *  opts    host, may be NULL for the defaults
+ *  stream  hipStream_t for all device work of this handle
+ *
+ * Errors: SPI_E_ARG for a malformed pattern or an unknown that appears in no
+ * row (A would be singular); SPI_E_OOM / SPI_E_HIP on device failures.
+ */
+int spi_analyze(spi_handle** h, int64_t m, int64_t n, const int64_t* rowptr,
+                const int32_t* col, const spi_opts* opts, void* stream);
+
+/*
+ * Numerical values on the analysed pattern (one energy band): H's values in
+ * CSR order and the row weights W = Sigma^-2 (Sect. 2.4.1).  Stream-ordered
+ * device-to-device copy into handle-owned buffers; invalidates any factor.
+ *
+ *  val  device, float64[nnz(H)]       w  device, float64[m], every w_r > 0
+ */
+int spi_set_values(spi_handle* h, const double* val, const double* w);
+
+/*
+ * Numerical factorisation (Sect. 3.2.2): assembles A = H^T W H directly into
+ * the leaf fronts and the root front (extend-add of the leaf contribution
+ * blocks), then factors the root.  Synchronises the handle's stream.
+ * Returns SPI_E_NOT_SPD if a pivot is not positive; spi_info().failed_col
+ * then names the original column.  SPI_E_STATE before spi_set_values.
+ */
+int spi_factor(spi_handle* h);
+
+/*
+ * Right-hand side of the normal equations b = H^T W y (Sect. 2.4.1).
+ *  y  device, float64[m]       b  device, float64[n] (written)
+ */
+int spi_rhs(spi_handle* h, const double* y, double* b);
+
+/*
+ * Solve A x = b by forward and backward substitution over the assembly tree
+ * (Sect. 3.2.3), followed by opts.refine_steps steps of iterative
+ * refinement whose residual b - H^T W (H x) is accumulated in double-double
+ * arithmetic from H itself.
+ *  b     device, float64, column-major n x nrhs with leading dimension ldb
+ *  x     device, float64, same layout (written); may not alias b
+ *  nrhs  >= 1;  ldb >= n
+ * SPI_E_STATE if no valid factor.
+ */
+int spi_solve(spi_handle* h, const double* b, double* x, int32_t nrhs,
+              int64_t ldb);
+
+/*
+ * Variances: d_i = (A^-1)_ii for every unknown, original order, unscaled
+ * (Sect. 2.4.1 variance relation; Sect. 3.3 partial computation of the
+ * inverse).  Computed by selected inversion on the pattern of L: the full
+ * inverse of the root front, then for every leaf front the entries it needs.
+ *  d  device, float64[n] (written)
+ * SPI_E_STATE if no valid factor.
+ */
+int spi_diag_inv(spi_handle* h, double* d);
+
+/*
+ * The analysis phase alone, on the host, with no device work (Sect. 3.2.1):
+ * useful to size a problem before allocating it, and to inspect the
+ * elimination order and tree.  Same pattern arguments and errors as
+ * spi_analyze.  `info` (may be NULL) receives the analysis counters (the
+ * fields of the last calls stay zero).  If non-NULL:
+ *   elim_order  host int32[n]: original columns in elimination order
+ *               (leaf fronts first, then the root front)
+ *   col_parent  host int32[n]: parent of each original column in the column
+ *               elimination tree of the stored factor (the first later
+ *               column with a non-zero in its column of L), -1 for the root
+ *   front_of    host int32[n]: leaf front of each column, -1 for root columns
+ */
+int spi_symbolic(int64_t m, int64_t n, const int64_t* rowptr,
+                 const int32_t* col, const spi_opts* opts, spi_info_t* info,
+                 int32_t* elim_order, int32_t* col_parent, int32_t* front_of);
+
+/* Counters of the analysis and of the last calls; with opts.timing the
+ * accumulated phase times since spi_analyze (synchronises the stream).
+ * Host struct. */
+int spi_info(const spi_handle* h, spi_info_t* info);
+
+/* Text of the last error of `h` (or of the calling thread's last
+ * spi_analyze if h is NULL).  Valid until the next call on h. */
+const char* spi_last_error(const spi_handle* h);
+
+/* Free the handle and all its device memory (synchronises its stream). */
+void spi_destroy(spi_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPI_H */

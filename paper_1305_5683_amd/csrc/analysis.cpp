@@ -1,0 +1,351 @@
+// Host symbolic analysis (Sect. 3.2.1 of Bouchet et al.: ordering, symbolic
+// factorisation, elimination/assembly tree).
+//
+// The ordering is chosen for the structure the coded-mask model gives.  An
+// unknown whose measurement rows contain no other selected unknown can be
+// eliminated first: such "leaf" unknowns are pairwise uncoupled in
+// A = H^T W H (they share no row), so each is a leaf of the elimination tree
+// whose row structure is the set of remaining unknowns seen in its rows.
+// Leaves are picked greedily by increasing work (the total length of their
+// rows, a bound on their degree in A), which selects the per-detector,
+// per-time-bin background unknowns before any sky pixel.  Consecutive
+// leaves with overlapping structure are amalgamated into one front
+// (supernode) while the dense panel stays dense enough; every other unknown
+// goes into one dense root front, in its original order.  The result is a
+// two-level assembly tree: independent leaf fronts, all children of the root.
+// It is exact for any SPD matrix (with no leaves it is a dense Cholesky).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <sstream>
+#include <thread>
+
+#include "spi_internal.h"
+
+namespace spi {
+
+namespace {
+constexpr int64_t kRowFrontMaxU = 1024;   // row-only fronts: max |U|
+constexpr int64_t kRowFrontMaxRows = 256; // row-only fronts: max rows
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+}  // namespace
+
+std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
+                    const int32_t* col, const spi_opts& o, Analysis& a) {
+  std::ostringstream err;
+  if (m < 1 || n < 1) return "m and n must be >= 1";
+  if (n > INT32_MAX - 1 || m > INT32_MAX - 1) return "m and n must fit int32";
+  if (!rowptr || !col) return "rowptr and col must be non-null host pointers";
+  if (rowptr[0] != 0) return "rowptr[0] must be 0";
+  for (int64_t r = 0; r < m; ++r) {
+    if (rowptr[r + 1] < rowptr[r]) {
+      err << "rowptr decreases at row " << r;
+      return err.str();
+    }
+  }
+  const int64_t nnz = rowptr[m];
+  for (int64_t r = 0; r < m; ++r) {
+    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      int32_t c = col[e];
+      if (c < 0 || c >= n) {
+        err << "column index " << c << " out of range in row " << r;
+        return err.str();
+      }
+      if (e > rowptr[r] && col[e - 1] >= c) {
+        err << "columns not strictly increasing in row " << r;
+        return err.str();
+      }
+    }
+  }
+  a = Analysis();
+  a.m = m;
+  a.n = n;
+  a.nnz = nnz;
+  a.rowptr.assign(rowptr, rowptr + m + 1);
+  a.col.assign(col, col + nnz);
+
+  // ---- transpose of the pattern
+  a.colptr.assign(n + 1, 0);
+  for (int64_t e = 0; e < nnz; ++e) a.colptr[col[e] + 1]++;
+  for (int64_t j = 0; j < n; ++j) {
+    if (a.colptr[j + 1] == 0) {
+      err << "unknown " << j << " appears in no row (A would be singular)";
+      return err.str();
+    }
+    a.colptr[j + 1] += a.colptr[j];
+  }
+  a.csc_pos.resize(nnz);
+  a.csc_row.resize(nnz);
+  {
+    std::vector<int64_t> fill(a.colptr.begin(), a.colptr.end() - 1);
+    for (int64_t r = 0; r < m; ++r)
+      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        int64_t k = fill[col[e]]++;
+        a.csc_pos[k] = e;
+        a.csc_row[k] = (int32_t)r;
+      }
+  }
+
+  // ---- leaf selection: greedy independent set by increasing work
+  std::vector<int64_t> work(n, 0);
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
+      int32_t r = a.csc_row[k];
+      work[j] += rowptr[r + 1] - rowptr[r];
+    }
+  std::vector<int32_t> cand;
+  for (int64_t j = 0; j < n; ++j)
+    if ((double)work[j] <= o.leaf_max_work) cand.push_back((int32_t)j);
+  std::stable_sort(cand.begin(), cand.end(), [&](int32_t x, int32_t y) {
+    return work[x] < work[y];
+  });
+  std::vector<char> claimed(m, 0), is_leaf(n, 0);
+  for (int32_t j : cand) {
+    bool free_rows = true;
+    for (int64_t k = a.colptr[j]; k < a.colptr[j + 1] && free_rows; ++k)
+      if (claimed[a.csc_row[k]]) free_rows = false;
+    if (!free_rows) continue;
+    is_leaf[j] = 1;
+    for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k)
+      claimed[a.csc_row[k]] = 1;
+  }
+
+  // ---- root numbering (original order)
+  a.root_of_col.assign(n, -1);
+  for (int64_t j = 0; j < n; ++j)
+    if (!is_leaf[j]) {
+      a.root_of_col[j] = (int32_t)a.root_cols.size();
+      a.root_cols.push_back((int32_t)j);
+    }
+  a.n_root = (int64_t)a.root_cols.size();
+  a.n_pad = a.n_root ? round_up(a.n_root, kRootPad) : 0;
+
+  // ---- amalgamate consecutive leaves into fronts
+  std::vector<int32_t> leaves;
+  for (int64_t j = 0; j < n; ++j)
+    if (is_leaf[j]) leaves.push_back((int32_t)j);
+  const int64_t nr = std::max<int64_t>(a.n_root, 1);
+  std::vector<int64_t> mark(nr, -1), seen(nr, -1), posmap(nr, -1);
+  a.grp_col_ptr.push_back(0);
+  a.grp_U_ptr.push_back(0);
+  a.grp_panel_off.push_back(0);
+  int64_t front = 0;
+  std::vector<int32_t> curU, curCols;
+  int64_t cur_sum = 0;
+  auto close_front = [&]() {
+    std::sort(curU.begin(), curU.end());
+    for (int32_t j : curCols) {
+      a.leaf_cols.push_back(j);
+      a.leaf_grp.push_back((int32_t)front);
+    }
+    a.U.insert(a.U.end(), curU.begin(), curU.end());
+    a.grp_col_ptr.push_back((int64_t)a.leaf_cols.size());
+    a.grp_U_ptr.push_back((int64_t)a.U.size());
+    a.grp_panel_off.push_back(a.grp_panel_off.back() +
+                              (int64_t)curU.size() * (int64_t)curCols.size());
+    ++front;
+    curU.clear();
+    curCols.clear();
+    cur_sum = 0;
+  };
+  std::vector<int32_t> rj;
+  for (int32_t j : leaves) {
+    rj.clear();
+    for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
+      int32_t r = a.csc_row[k];
+      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        int32_t ri = a.root_of_col[col[e]];
+        if (ri >= 0 && seen[ri] != j) {
+          seen[ri] = j;
+          rj.push_back(ri);
+        }
+      }
+    }
+    if (!curCols.empty()) {
+      int64_t add = 0;
+      for (int32_t u : rj)
+        if (mark[u] != front) ++add;
+      int64_t newU = (int64_t)curU.size() + add;
+      int64_t newp = (int64_t)curCols.size() + 1;
+      bool ok = newp <= o.max_group;
+      if (ok && newU > 0) {
+        double dens = (double)(cur_sum + (int64_t)rj.size()) /
+                      ((double)newU * (double)newp);
+        ok = dens >= o.amalg_density;
+      }
+      if (!ok) close_front();
+    }
+    for (int32_t u : rj)
+      if (mark[u] != front) {
+        mark[u] = front;
+        curU.push_back(u);
+      }
+    curCols.push_back(j);
+    cur_sum += (int64_t)rj.size();
+  }
+  if (!curCols.empty()) close_front();
+  a.n_groups = front;
+
+  // ---- slots of the leaf fronts
+  const int64_t n_leaf = (int64_t)a.leaf_cols.size();
+  a.leaf_slot_ptr.assign(n_leaf + 1, 0);
+  a.grp_slot_ptr.push_back(0);
+  for (int64_t g = 0; g < a.n_groups; ++g) {
+    for (int64_t l = a.grp_col_ptr[g]; l < a.grp_col_ptr[g + 1]; ++l) {
+      int32_t j = a.leaf_cols[l];
+      for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
+        a.slot_row.push_back(a.csc_row[k]);
+        a.slot_leaf_src.push_back(a.csc_pos[k]);
+      }
+      a.leaf_slot_ptr[l + 1] = (int64_t)a.slot_row.size();
+    }
+    a.grp_slot_ptr.push_back((int64_t)a.slot_row.size());
+  }
+
+  // ---- row-only fronts: rows that touch no leaf unknown
+  {
+    int64_t rows_in = 0;
+    for (int64_t r = 0; r < m; ++r) {
+      if (claimed[r]) continue;
+      int64_t add = 0;
+      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        int32_t ri = a.root_of_col[col[e]];
+        if (ri >= 0 && mark[ri] != front) ++add;
+      }
+      if (rows_in > 0 && ((int64_t)curU.size() + add > kRowFrontMaxU ||
+                          rows_in >= kRowFrontMaxRows)) {
+        std::sort(curU.begin(), curU.end());
+        a.U.insert(a.U.end(), curU.begin(), curU.end());
+        a.grp_col_ptr.push_back((int64_t)a.leaf_cols.size());
+        a.grp_U_ptr.push_back((int64_t)a.U.size());
+        a.grp_panel_off.push_back(a.grp_panel_off.back());
+        a.grp_slot_ptr.push_back((int64_t)a.slot_row.size());
+        ++front;
+        curU.clear();
+        rows_in = 0;
+      }
+      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        int32_t ri = a.root_of_col[col[e]];
+        if (ri >= 0 && mark[ri] != front) {
+          mark[ri] = front;
+          curU.push_back(ri);
+        }
+      }
+      a.slot_row.push_back((int32_t)r);
+      a.slot_leaf_src.push_back(-1);
+      ++rows_in;
+    }
+    if (rows_in > 0) {
+      std::sort(curU.begin(), curU.end());
+      a.U.insert(a.U.end(), curU.begin(), curU.end());
+      a.grp_col_ptr.push_back((int64_t)a.leaf_cols.size());
+      a.grp_U_ptr.push_back((int64_t)a.U.size());
+      a.grp_panel_off.push_back(a.grp_panel_off.back());
+      a.grp_slot_ptr.push_back((int64_t)a.slot_row.size());
+      ++front;
+      curU.clear();
+    }
+  }
+  a.n_fronts = front;
+  if ((int64_t)a.slot_row.size() != m) return "internal: slot count mismatch";
+
+  // ---- compact root entries per slot, with U-local positions
+  a.slot_rr_ptr.assign(m + 1, 0);
+  a.rr_lpos.reserve(nnz);
+  a.rr_src.reserve(nnz);
+  std::fill(posmap.begin(), posmap.end(), -1);
+  for (int64_t f = 0; f < a.n_fronts; ++f) {
+    for (int64_t u = a.grp_U_ptr[f]; u < a.grp_U_ptr[f + 1]; ++u)
+      posmap[a.U[u]] = u - a.grp_U_ptr[f];
+    for (int64_t s = a.grp_slot_ptr[f]; s < a.grp_slot_ptr[f + 1]; ++s) {
+      int32_t r = a.slot_row[s];
+      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        int32_t ri = a.root_of_col[col[e]];
+        if (ri < 0) continue;
+        a.rr_lpos.push_back((int32_t)posmap[ri]);
+        a.rr_src.push_back(e);
+      }
+      a.slot_rr_ptr[s + 1] = (int64_t)a.rr_src.size();
+    }
+  }
+
+  // ---- extend-add / selected-inversion tasks
+  a.grp_task_ptr.push_back(0);
+  a.task_part_off.push_back(0);
+  for (int64_t f = 0; f < a.n_fronts; ++f) {
+    int64_t nU = a.grp_U_ptr[f + 1] - a.grp_U_ptr[f];
+    int64_t p = a.grp_col_ptr[f + 1] - a.grp_col_ptr[f];
+    int64_t nt = (nU + kET - 1) / kET;
+    for (int64_t I = 0; I < nt; ++I)
+      for (int64_t J = 0; J <= I; ++J) {
+        a.tasks.push_back((int32_t)f);
+        a.tasks.push_back((int32_t)I);
+        a.tasks.push_back((int32_t)J);
+        a.task_part_off.push_back(a.task_part_off.back() + p);
+      }
+    a.grp_task_ptr.push_back((int64_t)a.tasks.size() / 3);
+  }
+
+  // ---- root incidences of the leaf panels
+  a.rinc_ptr.assign(a.n_root + 1, 0);
+  for (int64_t g = 0; g < a.n_groups; ++g)
+    for (int64_t u = a.grp_U_ptr[g]; u < a.grp_U_ptr[g + 1]; ++u)
+      a.rinc_ptr[a.U[u] + 1]++;
+  for (int64_t i = 0; i < a.n_root; ++i) a.rinc_ptr[i + 1] += a.rinc_ptr[i];
+  a.rinc_grp.resize(a.rinc_ptr[a.n_root]);
+  a.rinc_u.resize(a.rinc_ptr[a.n_root]);
+  {
+    std::vector<int64_t> fill(a.rinc_ptr.begin(), a.rinc_ptr.end() - 1);
+    for (int64_t g = 0; g < a.n_groups; ++g)
+      for (int64_t u = a.grp_U_ptr[g]; u < a.grp_U_ptr[g + 1]; ++u) {
+        int64_t k = fill[a.U[u]]++;
+        a.rinc_grp[k] = (int32_t)g;
+        a.rinc_u[k] = (int32_t)(u - a.grp_U_ptr[g]);
+      }
+  }
+
+  // ---- counters: nnz(A) (both triangles), nnz(L) as stored, flops
+  {
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<int64_t> cnt(nth, 0);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nth; ++t)
+      th.emplace_back([&, t]() {
+        std::vector<int64_t> st(n, -1);
+        int64_t c = 0;
+        for (int64_t j = t; j < n; j += nth)
+          for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
+            int32_t r = a.csc_row[k];
+            for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
+              if (st[col[e]] != j) {
+                st[col[e]] = j;
+                ++c;
+              }
+          }
+        cnt[t] = c;
+      });
+    for (auto& x : th) x.join();
+    a.nnz_a = std::accumulate(cnt.begin(), cnt.end(), (int64_t)0);
+  }
+  double nR = (double)a.n_root;
+  a.nnz_l = n_leaf + a.grp_panel_off[a.n_fronts] +
+            a.n_root * (a.n_root + 1) / 2;
+  a.flops_factor = nR * nR * nR / 3.0;
+  a.flops_selinv = 2.0 * nR * nR * nR / 3.0;
+  for (int64_t g = 0; g < a.n_groups; ++g) {
+    double p = (double)(a.grp_col_ptr[g + 1] - a.grp_col_ptr[g]);
+    double c = (double)(a.grp_U_ptr[g + 1] - a.grp_U_ptr[g]);
+    a.flops_factor += p * p * p / 3.0 + c * p * p + c * c * p;
+    a.flops_selinv += 2.0 * (p * p * p / 3.0 + c * p * p + c * c * p);
+  }
+  a.flops_solve = 4.0 * (double)a.nnz_l;
+  a.flops_asm = 0;
+  for (int64_t r = 0; r < m; ++r) {
+    double len = (double)(rowptr[r + 1] - rowptr[r]);
+    a.flops_asm += 2.0 * len * len;
+  }
+  return std::string();
+}
+
+}  // namespace spi

@@ -1,0 +1,431 @@
+// C ABI entry points of libspi (declared in include/spi.h).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <sstream>
+
+#include "spi_internal.h"
+
+using namespace spi;
+
+struct spi_handle {
+  Handle h;
+};
+
+namespace {
+
+thread_local std::string g_analyze_err;
+
+template <class T>
+hipError_t dev_copy(T*& dst, const std::vector<T>& src, hipStream_t s) {
+  dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)&dst, src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T),
+                        hipMemcpyHostToDevice, s);
+}
+
+template <class T>
+hipError_t dev_alloc(T*& dst, int64_t count) {
+  dst = nullptr;
+  if (count <= 0) return hipSuccess;
+  return hipMalloc((void**)&dst, (size_t)count * sizeof(T));
+}
+
+int fail(Handle& h, int code, hipError_t e, const char* what) {
+  std::ostringstream os;
+  os << what;
+  if (e != hipSuccess) os << ": " << hipGetErrorString(e);
+  h.err = os.str();
+  if (e == hipErrorOutOfMemory) return SPI_E_OOM;
+  return code;
+}
+
+#define SPI_CK(expr, what)                                        \
+  do {                                                            \
+    hipError_t e_ = (expr);                                       \
+    if (e_ != hipSuccess) return fail(h, SPI_E_HIP, e_, what);    \
+  } while (0)
+
+// ---- phase timers: event pairs on the handle's stream
+hipEvent_t take_event(PhaseTimer& t) {
+  if (!t.free_ev.empty()) {
+    hipEvent_t e = t.free_ev.back();
+    t.free_ev.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void collect(PhaseTimer& t) {
+  for (auto& pr : t.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second) == hipSuccess &&
+        hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      t.total_ms += ms;
+      t.count += 1;
+    }
+    t.free_ev.push_back(pr.first);
+    t.free_ev.push_back(pr.second);
+  }
+  t.pending.clear();
+}
+
+void phase_begin(Handle& h, Phase p) {
+  if (!h.opts.timing) return;
+  PhaseTimer& t = h.timer[p];
+  if (t.pending.size() > 4096) collect(t);
+  t.open = take_event(t);
+  if (t.open) (void)hipEventRecord(t.open, h.stream);
+}
+
+void phase_end(Handle& h, Phase p) {
+  if (!h.opts.timing) return;
+  PhaseTimer& t = h.timer[p];
+  if (!t.open) return;
+  hipEvent_t e = take_event(t);
+  if (!e) return;
+  (void)hipEventRecord(e, h.stream);
+  t.pending.emplace_back(t.open, e);
+  t.open = nullptr;
+}
+
+void free_timers(Handle& h) {
+  for (auto& t : h.timer) {
+    collect(t);
+    for (hipEvent_t e : t.free_ev) (void)hipEventDestroy(e);
+    t.free_ev.clear();
+  }
+}
+
+void free_all(Handle& h) {
+  free_timers(h);
+  DevAnalysis& d = h.d;
+  void* ptrs[] = {d.rowptr, d.col, d.colptr, d.csc_pos, d.csc_row, d.leaf_cols,
+                  d.leaf_grp, d.leaf_slot_ptr, d.grp_col_ptr, d.grp_U_ptr, d.U,
+                  d.grp_panel_off, d.grp_slot_ptr, d.slot_row, d.slot_rr_ptr,
+                  d.slot_leaf_src, d.rr_lpos, d.rr_src, d.root_cols, d.rinc_ptr,
+                  d.rinc_grp, d.rinc_u, d.tasks, d.grp_task_ptr, d.task_part_off,
+                  h.val, h.w, h.sw, h.sleaf, h.rrval, h.panel, h.ldiag, h.S,
+                  h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
+                  h.vx, h.vdd, h.vnorm};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+void spi_default_opts(spi_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = SPI_FP64;
+  o->max_group = 32;
+  o->leaf_max_work = 65536.0;
+  o->amalg_density = 0.35;
+  o->refine_steps = 2;
+}
+
+int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
+                const int32_t* col, const spi_opts* opts, void* stream) {
+  g_analyze_err.clear();
+  if (!out) {
+    g_analyze_err = "null handle pointer";
+    return SPI_E_ARG;
+  }
+  *out = nullptr;
+  spi_opts o;
+  spi_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.precision != SPI_FP64 && o.precision != SPI_MIXED) {
+    g_analyze_err = "unknown precision";
+    return SPI_E_ARG;
+  }
+  if (o.max_group < 1 || o.refine_steps < 0 || !(o.amalg_density >= 0.0)) {
+    g_analyze_err = "invalid options";
+    return SPI_E_ARG;
+  }
+  if (o.precision == SPI_MIXED) {
+    g_analyze_err = "SPI_MIXED is not available in this build";
+    return SPI_E_ARG;
+  }
+  spi_handle* H = new (std::nothrow) spi_handle();
+  if (!H) {
+    g_analyze_err = "host allocation failed";
+    return SPI_E_OOM;
+  }
+  Handle& h = H->h;
+  h.opts = o;
+  h.stream = (hipStream_t)stream;
+  (void)hipGetDevice(&h.device);
+  auto t0 = std::chrono::steady_clock::now();
+  std::string e = analyze(m, n, rowptr, col, o, h.an);
+  if (!e.empty()) {
+    g_analyze_err = e;
+    delete H;
+    return SPI_E_ARG;
+  }
+  const Analysis& a = h.an;
+  DevAnalysis& d = h.d;
+  hipError_t he = hipSuccess;
+#define UP(field) \
+  if (he == hipSuccess) he = dev_copy(d.field, a.field, h.stream)
+  UP(rowptr); UP(col); UP(colptr); UP(csc_pos); UP(csc_row); UP(leaf_cols);
+  UP(leaf_grp); UP(leaf_slot_ptr); UP(grp_col_ptr); UP(grp_U_ptr); UP(U);
+  UP(grp_panel_off); UP(grp_slot_ptr); UP(slot_row); UP(slot_rr_ptr);
+  UP(slot_leaf_src); UP(rr_lpos); UP(rr_src); UP(root_cols); UP(rinc_ptr);
+  UP(rinc_grp); UP(rinc_u); UP(tasks); UP(grp_task_ptr); UP(task_part_off);
+#undef UP
+  const int64_t nl = (int64_t)a.leaf_cols.size();
+  const int64_t np = a.n_pad;
+#define AL(ptr, cnt) \
+  if (he == hipSuccess) he = dev_alloc(ptr, cnt)
+  AL(h.val, a.nnz); AL(h.w, a.m); AL(h.sw, a.m); AL(h.sleaf, a.m);
+  AL(h.rrval, (int64_t)a.rr_src.size());
+  AL(h.panel, a.grp_panel_off.back()); AL(h.ldiag, nl);
+  AL(h.S, np * np); AL(h.W, np * np); AL(h.Z, np * np);
+  AL(h.invd, np * kNB); AL(h.part, a.task_part_off.back());
+  AL(h.flag, 1); AL(h.vleaf, nl); AL(h.vroot, np); AL(h.vres, a.n);
+  AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 2);
+#undef AL
+  if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
+  if (he != hipSuccess) {
+    g_analyze_err = std::string("device setup failed: ") + hipGetErrorString(he);
+    free_all(h);
+    delete H;
+    return he == hipErrorOutOfMemory ? SPI_E_OOM : SPI_E_HIP;
+  }
+  h.t_analyze_ms = std::chrono::duration<double, std::milli>(
+                       std::chrono::steady_clock::now() - t0).count();
+  *out = H;
+  return SPI_OK;
+}
+
+int spi_set_values(spi_handle* H, const double* val, const double* w) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = H->h;
+  if (!val || !w) return fail(h, SPI_E_ARG, hipSuccess, "null value pointer");
+  SPI_CK(hipMemcpyAsync(h.val, val, h.an.nnz * sizeof(double),
+                        hipMemcpyDeviceToDevice, h.stream), "copy values");
+  SPI_CK(hipMemcpyAsync(h.w, w, h.an.m * sizeof(double),
+                        hipMemcpyDeviceToDevice, h.stream), "copy weights");
+  SPI_CK(launch_gather_values(h), "gather values");
+  h.have_values = true;
+  h.have_factor = false;
+  return SPI_OK;
+}
+
+int spi_factor(spi_handle* H) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = H->h;
+  if (!h.have_values)
+    return fail(h, SPI_E_STATE, hipSuccess, "spi_factor before spi_set_values");
+  h.have_factor = false;
+  h.failed_col = -1;
+  SPI_CK(hipMemsetAsync(h.flag, 0xff, sizeof(int64_t), h.stream), "flag");
+  phase_begin(h, kPhLeaf);
+  SPI_CK(launch_leaf_assemble(h), "leaf assembly");
+  phase_end(h, kPhLeaf);
+  if (h.an.n_pad) {
+    phase_begin(h, kPhExtend);
+    SPI_CK(launch_root_fill(h), "root fill");
+    SPI_CK(launch_extend_add(h), "extend-add");
+    phase_end(h, kPhExtend);
+    phase_begin(h, kPhPotrf);
+    SPI_CK(root_potrf(h), "root factorisation");
+    phase_end(h, kPhPotrf);
+  }
+  uint64_t f = 0;
+  SPI_CK(hipMemcpyAsync(&f, h.flag, sizeof(f), hipMemcpyDeviceToHost, h.stream),
+         "flag readback");
+  SPI_CK(hipStreamSynchronize(h.stream), "factor");
+  if (f != std::numeric_limits<uint64_t>::max()) {
+    const int64_t nl = (int64_t)h.an.leaf_cols.size();
+    int64_t k = (int64_t)f;
+    if (k < nl) h.failed_col = h.an.leaf_cols[k];
+    else if (k - nl < h.an.n_root) h.failed_col = h.an.root_cols[k - nl];
+    std::ostringstream os;
+    os << "matrix not positive definite: non-positive pivot at column "
+       << h.failed_col;
+    h.err = os.str();
+    return SPI_E_NOT_SPD;
+  }
+  h.have_factor = true;
+  return SPI_OK;
+}
+
+int spi_rhs(spi_handle* H, const double* y, double* b) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = H->h;
+  if (!y || !b) return fail(h, SPI_E_ARG, hipSuccess, "null pointer");
+  if (!h.have_values)
+    return fail(h, SPI_E_STATE, hipSuccess, "spi_rhs before spi_set_values");
+  SPI_CK(launch_rhs(h, y, b), "rhs");
+  return SPI_OK;
+}
+
+int spi_solve(spi_handle* H, const double* b, double* x, int32_t nrhs,
+              int64_t ldb) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = H->h;
+  if (!b || !x || nrhs < 1 || ldb < h.an.n)
+    return fail(h, SPI_E_ARG, hipSuccess, "invalid solve arguments");
+  if (!h.have_factor)
+    return fail(h, SPI_E_STATE, hipSuccess, "spi_solve without a valid factor");
+  phase_begin(h, kPhSolve);
+  for (int32_t c = 0; c < nrhs; ++c) {
+    const double* bc = b + (int64_t)c * ldb;
+    double* xc = x + (int64_t)c * ldb;
+    SPI_CK(launch_solve_pass(h, bc, xc), "solve");
+    for (int s = 0; s < h.opts.refine_steps; ++s) {
+      SPI_CK(launch_residual_dd(h, bc, xc, h.vres), "residual");
+      SPI_CK(launch_solve_pass(h, h.vres, h.vx), "correction");
+      SPI_CK(hipMemsetAsync(h.vnorm, 0, 2 * sizeof(double), h.stream), "norms");
+      SPI_CK(launch_axpy_norms(h, xc, h.vx), "update");
+    }
+  }
+  phase_end(h, kPhSolve);
+  h.refine_done = h.opts.refine_steps;
+  return SPI_OK;
+}
+
+int spi_diag_inv(spi_handle* H, double* d) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = H->h;
+  if (!d) return fail(h, SPI_E_ARG, hipSuccess, "null output");
+  if (!h.have_factor)
+    return fail(h, SPI_E_STATE, hipSuccess, "spi_diag_inv without a valid factor");
+  if (h.an.n_pad) {
+    phase_begin(h, kPhTrtri);
+    SPI_CK(root_trtri(h), "root factor inversion");
+    phase_end(h, kPhTrtri);
+    phase_begin(h, kPhLauum);
+    SPI_CK(root_lauum(h), "root inverse product");
+    phase_end(h, kPhLauum);
+  }
+  phase_begin(h, kPhSelinv);
+  if (h.an.n_pad) SPI_CK(launch_diag_root(h, d), "root diagonal");
+  SPI_CK(launch_selinv_leaves(h, d), "leaf selected inversion");
+  phase_end(h, kPhSelinv);
+  return SPI_OK;
+}
+
+static void fill_analysis_info(const Analysis& a, spi_info_t* info) {
+  info->m = a.m;
+  info->n = a.n;
+  info->nnz_h = a.nnz;
+  info->nnz_a = a.nnz_a;
+  info->nnz_l = a.nnz_l;
+  info->n_leaf = (int64_t)a.leaf_cols.size();
+  info->n_groups = a.n_groups;
+  info->n_root = a.n_root;
+  info->n_root_padded = a.n_pad;
+  info->flops_factor = a.flops_factor;
+  info->flops_selinv = a.flops_selinv;
+  info->flops_solve = a.flops_solve;
+  info->flops_assembly = a.flops_asm;
+}
+
+int spi_symbolic(int64_t m, int64_t n, const int64_t* rowptr,
+                 const int32_t* col, const spi_opts* opts, spi_info_t* info,
+                 int32_t* elim_order, int32_t* col_parent, int32_t* front_of) {
+  g_analyze_err.clear();
+  spi_opts o;
+  spi_default_opts(&o);
+  if (opts) o = *opts;
+  Analysis a;
+  auto t0 = std::chrono::steady_clock::now();
+  std::string e = analyze(m, n, rowptr, col, o, a);
+  if (!e.empty()) {
+    g_analyze_err = e;
+    return SPI_E_ARG;
+  }
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    fill_analysis_info(a, info);
+    info->failed_col = -1;
+    info->precision = o.precision;
+    info->t_analyze_ms = std::chrono::duration<double, std::milli>(
+                             std::chrono::steady_clock::now() - t0).count();
+  }
+  const int64_t nl = (int64_t)a.leaf_cols.size();
+  if (elim_order) {
+    for (int64_t l = 0; l < nl; ++l) elim_order[l] = a.leaf_cols[l];
+    for (int64_t i = 0; i < a.n_root; ++i) elim_order[nl + i] = a.root_cols[i];
+  }
+  if (col_parent) {
+    for (int64_t g = 0; g < a.n_groups; ++g) {
+      int64_t u0 = a.grp_U_ptr[g], u1 = a.grp_U_ptr[g + 1];
+      for (int64_t l = a.grp_col_ptr[g]; l < a.grp_col_ptr[g + 1]; ++l) {
+        // the panel column of a leaf is stored over the whole front structure,
+        // but its own non-zeros are the root unknowns of its own rows
+        int32_t j = a.leaf_cols[l];
+        int32_t best = -1;
+        for (int64_t s = a.leaf_slot_ptr[l]; s < a.leaf_slot_ptr[l + 1]; ++s)
+          for (int64_t k = a.slot_rr_ptr[s]; k < a.slot_rr_ptr[s + 1]; ++k) {
+            int32_t ri = a.U[u0 + a.rr_lpos[k]];
+            if (best < 0 || ri < best) best = ri;
+          }
+        (void)u1;
+        col_parent[j] = best < 0 ? -1 : a.root_cols[best];
+      }
+    }
+    for (int64_t i = 0; i < a.n_root; ++i)
+      col_parent[a.root_cols[i]] = (i + 1 < a.n_root) ? a.root_cols[i + 1] : -1;
+  }
+  if (front_of) {
+    for (int64_t j = 0; j < a.n; ++j) front_of[j] = -1;
+    for (int64_t l = 0; l < nl; ++l) front_of[a.leaf_cols[l]] = a.leaf_grp[l];
+  }
+  return SPI_OK;
+}
+
+int spi_info(const spi_handle* Hc, spi_info_t* info) {
+  if (!Hc || !info) return SPI_E_ARG;
+  // collecting timers mutates the handle's event pools, not its results
+  Handle& h = const_cast<spi_handle*>(Hc)->h;
+  for (auto& t : h.timer) collect(t);
+  const Analysis& a = h.an;
+  std::memset(info, 0, sizeof(*info));
+  fill_analysis_info(a, info);
+  info->failed_col = h.failed_col;
+  info->t_analyze_ms = h.t_analyze_ms;
+  info->precision = h.opts.precision;
+  info->refine_steps_done = h.refine_done;
+  if (h.refine_done > 0 && h.vnorm) {
+    double nv[2] = {0, 0};
+    if (hipMemcpyAsync(nv, h.vnorm, sizeof(nv), hipMemcpyDeviceToHost,
+                       h.stream) == hipSuccess &&
+        hipStreamSynchronize(h.stream) == hipSuccess && nv[1] > 0)
+      info->last_refine_norm = nv[0] / nv[1];
+  }
+  info->t_leaf_ms = h.timer[kPhLeaf].total_ms;
+  info->t_extend_ms = h.timer[kPhExtend].total_ms;
+  info->t_potrf_ms = h.timer[kPhPotrf].total_ms;
+  info->t_solve_ms = h.timer[kPhSolve].total_ms;
+  info->t_trtri_ms = h.timer[kPhTrtri].total_ms;
+  info->t_lauum_ms = h.timer[kPhLauum].total_ms;
+  info->t_selinv_ms = h.timer[kPhSelinv].total_ms;
+  return SPI_OK;
+}
+
+const char* spi_last_error(const spi_handle* H) {
+  if (!H) return g_analyze_err.c_str();
+  return H->h.err.c_str();
+}
+
+void spi_destroy(spi_handle* H) {
+  if (!H) return;
+  (void)hipStreamSynchronize(H->h.stream);
+  free_all(H->h);
+  delete H;
+}
+
+}  // extern "C"

@@ -1,0 +1,575 @@
+// Sparse-side kernels (gfx950): assembly of A = H^T W H into the fronts,
+// extend-add of the leaf contribution blocks into the root, right-hand side,
+// the leaf parts of the triangular solves and of the selected inversion,
+// and the double-double residual of the refinement.
+//
+// Notation: a leaf front g holds p = |G| pivots (unknowns that share no
+// measurement row with any other pivot, so its pivot block is diagonal) and
+// the row structure U_g (root unknowns seen in its rows).  Its panel
+// L_Ug = A_Ug,G L_GG^-T is stored dense, column-major, |U_g| x p.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "spi_internal.h"
+
+namespace spi {
+
+// panel columns staged in LDS at a time by the extend-add / selinv tasks
+constexpr int kQC = 16;
+
+static int grid_for(int64_t items, int per_block) {
+  int64_t g = (items + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 20));
+}
+
+// ------------------------------------------------------------ value layout
+// Gather H values and weights into front (slot) order.
+__global__ void k_gather_slots(const double* __restrict__ val,
+                               const double* __restrict__ w,
+                               const int32_t* __restrict__ slot_row,
+                               const int64_t* __restrict__ slot_leaf_src,
+                               double* __restrict__ sw,
+                               double* __restrict__ sleaf, int64_t m) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    sw[s] = w[slot_row[s]];
+    int64_t e = slot_leaf_src[s];
+    sleaf[s] = e >= 0 ? val[e] : 0.0;
+  }
+}
+
+__global__ void k_gather_rr(const double* __restrict__ val,
+                            const int64_t* __restrict__ rr_src,
+                            double* __restrict__ rrval, int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    rrval[k] = val[rr_src[k]];
+}
+
+hipError_t launch_gather_values(Handle& h) {
+  const Analysis& a = h.an;
+  hipLaunchKernelGGL(k_gather_slots, dim3(grid_for(a.m, 256)), dim3(256), 0,
+                     h.stream, h.val, h.w, h.d.slot_row, h.d.slot_leaf_src,
+                     h.sw, h.sleaf, a.m);
+  int64_t nrr = (int64_t)a.rr_src.size();
+  if (nrr)
+    hipLaunchKernelGGL(k_gather_rr, dim3(grid_for(nrr, 256)), dim3(256), 0,
+                       h.stream, h.val, h.d.rr_src, h.rrval, nrr);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- leaf assembly
+// One wave per leaf unknown l (front g, position q): accumulate
+// A_ll = sum_r w_r h_rl^2 and the panel column A_Ug,l = sum_r w_r h_rl h_rU
+// over the rows of l (sequentially, lanes over a row's entries, which have
+// distinct positions), then L_ll = sqrt(A_ll) and the column / L_ll.
+__global__ __launch_bounds__(256) void k_leaf_assemble(
+    const int32_t* __restrict__ leaf_grp, const int64_t* __restrict__ leaf_slot_ptr,
+    const int64_t* __restrict__ grp_col_ptr, const int64_t* __restrict__ grp_U_ptr,
+    const int64_t* __restrict__ grp_panel_off, const int64_t* __restrict__ slot_rr_ptr,
+    const int32_t* __restrict__ rr_lpos, const double* __restrict__ rrval,
+    const double* __restrict__ sw, const double* __restrict__ sleaf,
+    double* panel, double* __restrict__ ldiag, int64_t* fail, int64_t n_leaf) {
+  const int lane = threadIdx.x & 63;
+  const int64_t l = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (l >= n_leaf) return;
+  const int g = leaf_grp[l];
+  const int64_t q = l - grp_col_ptr[g];
+  const int64_t nU = grp_U_ptr[g + 1] - grp_U_ptr[g];
+  double* P = panel + grp_panel_off[g] + q * nU;
+  for (int64_t u = lane; u < nU; u += 64) P[u] = 0.0;
+  __threadfence_block();
+  double d = 0.0;
+  for (int64_t s = leaf_slot_ptr[l]; s < leaf_slot_ptr[l + 1]; ++s) {
+    const double t = sw[s] * sleaf[s];
+    d += t * sleaf[s];
+    for (int64_t k = slot_rr_ptr[s] + lane; k < slot_rr_ptr[s + 1]; k += 64)
+      P[rr_lpos[k]] += t * rrval[k];
+    __threadfence_block();
+  }
+  bool bad = !(d > 0.0) || !isfinite(d);
+  const double lll = bad ? 1.0 : sqrt(d);
+  if (lane == 0) {
+    ldiag[l] = lll;
+    if (bad) atomicMin((unsigned long long*)fail, (unsigned long long)l);
+  }
+  const double inv = 1.0 / lll;
+  for (int64_t u = lane; u < nU; u += 64) P[u] *= inv;
+}
+
+hipError_t launch_leaf_assemble(Handle& h) {
+  const Analysis& a = h.an;
+  const int64_t nl = (int64_t)a.leaf_cols.size();
+  if (!nl) return hipSuccess;
+  hipLaunchKernelGGL(k_leaf_assemble, dim3(grid_for(nl, 4)), dim3(256), 0,
+                     h.stream, h.d.leaf_grp, h.d.leaf_slot_ptr, h.d.grp_col_ptr,
+                     h.d.grp_U_ptr, h.d.grp_panel_off, h.d.slot_rr_ptr,
+                     h.d.rr_lpos, h.rrval, h.sw, h.sleaf, h.panel, h.ldiag,
+                     h.flag, nl);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- extend-add
+// Task (g, I, J), I >= J: the block of front g's contribution on positions
+// I*kET.. x J*kET.. of U_g,
+//   C = sum_{rows r of g} w_r h_rU h_rU^T  -  L_Ug L_Ug^T,
+// accumulated in LDS, then added into the root front (lower triangle) at
+// (U[a], U[b]).  The row part of a row only touches the positions of its
+// own entries: the entries whose positions fall in each range are found by
+// binary search (positions are sorted within a row).
+__device__ inline int64_t lower_bound_pos(const int32_t* p, int64_t lo,
+                                          int64_t hi, int32_t v) {
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (p[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_extend_add(
+    const int32_t* __restrict__ tasks, const int64_t* __restrict__ grp_U_ptr,
+    const int32_t* __restrict__ U, const int64_t* __restrict__ grp_col_ptr,
+    const int64_t* __restrict__ grp_panel_off, const int64_t* __restrict__ grp_slot_ptr,
+    const int64_t* __restrict__ slot_rr_ptr, const int32_t* __restrict__ rr_lpos,
+    const double* __restrict__ rrval, const double* __restrict__ sw,
+    const double* __restrict__ panel, double* S, int64_t ld) {
+  __shared__ double C[kET][kET + 1];
+  __shared__ double PI[kQC][kET];
+  __shared__ double PJ[kQC][kET];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = tasks[3 * blockIdx.x], I = tasks[3 * blockIdx.x + 1],
+            J = tasks[3 * blockIdx.x + 2];
+  const int64_t nU = grp_U_ptr[g + 1] - grp_U_ptr[g];
+  const int32_t* Ug = U + grp_U_ptr[g];
+  const int I0 = I * kET, J0 = J * kET;
+  const int na = (int)min<int64_t>(kET, nU - I0), nb = (int)min<int64_t>(kET, nU - J0);
+  const int p = (int)(grp_col_ptr[g + 1] - grp_col_ptr[g]);
+  for (int e = t; e < kET * kET; e += 256) C[e % kET][e / kET] = 0.0;
+  __syncthreads();
+  // row part: one wave per row
+  for (int64_t s = grp_slot_ptr[g] + wave; s < grp_slot_ptr[g + 1]; s += 4) {
+    const int64_t b0 = slot_rr_ptr[s], b1 = slot_rr_ptr[s + 1];
+    int64_t ia = 0, ib = 0, ja = 0, jb = 0;
+    if (lane == 0) ia = lower_bound_pos(rr_lpos, b0, b1, I0);
+    if (lane == 1) ib = lower_bound_pos(rr_lpos, b0, b1, I0 + kET);
+    if (lane == 2) ja = lower_bound_pos(rr_lpos, b0, b1, J0);
+    if (lane == 3) jb = lower_bound_pos(rr_lpos, b0, b1, J0 + kET);
+    ia = __shfl(ia, 0, 64);
+    ib = __shfl(ib, 1, 64);
+    ja = __shfl(ja, 2, 64);
+    jb = __shfl(jb, 3, 64);
+    const int ni = (int)(ib - ia), nj = (int)(jb - ja);
+    const double ws = sw[s];
+    for (int pr = lane; pr < ni * nj; pr += 64) {
+      const int x = pr / nj, y = pr % nj;
+      const int pa = rr_lpos[ia + x] - I0, pb = rr_lpos[ja + y] - J0;
+      if (I == J && pa < pb) continue;
+      atomicAdd(&C[pa][pb], ws * rrval[ia + x] * rrval[ja + y]);
+    }
+  }
+  // leaf part: C -= L_I L_J^T, kQC panel columns at a time
+  const double* Pg = panel + grp_panel_off[g];
+  for (int q0 = 0; q0 < p; q0 += kQC) {
+    const int pc = min(kQC, p - q0);
+    __syncthreads();
+    for (int e = t; e < kQC * kET; e += 256) {
+      int a = e % kET, q = e / kET;
+      PI[q][a] = (q < pc && a < na) ? Pg[(int64_t)(q0 + q) * nU + I0 + a] : 0.0;
+      PJ[q][a] = (q < pc && a < nb) ? Pg[(int64_t)(q0 + q) * nU + J0 + a] : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < kET * kET; e += 256) {
+      const int a = e % kET, b = e / kET;
+      double s = 0.0;
+      for (int q = 0; q < pc; ++q) s += PI[q][a] * PJ[q][b];
+      C[a][b] -= s;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < kET * kET; e += 256) {
+    const int a = e % kET, b = e / kET;
+    if (a >= na || b >= nb) continue;
+    if (I == J && a < b) continue;
+    const double v = C[a][b];
+    if (v == 0.0) continue;
+    atomicAdd(&S[(int64_t)Ug[I0 + a] + (int64_t)Ug[J0 + b] * ld], v);
+  }
+}
+
+hipError_t launch_extend_add(Handle& h) {
+  const Analysis& a = h.an;
+  const int64_t nt = (int64_t)a.tasks.size() / 3;
+  if (!nt || !a.n_pad) return hipSuccess;
+  const int64_t chunk = 1 << 20;
+  for (int64_t t0 = 0; t0 < nt; t0 += chunk) {
+    int64_t c = std::min(chunk, nt - t0);
+    hipLaunchKernelGGL(k_extend_add, dim3((unsigned)c), dim3(256), 0, h.stream,
+                       h.d.tasks + 3 * t0, h.d.grp_U_ptr, h.d.U, h.d.grp_col_ptr,
+                       h.d.grp_panel_off, h.d.grp_slot_ptr, h.d.slot_rr_ptr,
+                       h.d.rr_lpos, h.rrval, h.sw, h.panel, h.S, a.n_pad);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ rhs
+// b_c = sum_{r} h_rc w_r y_r over the column's entries (one wave per column).
+__global__ __launch_bounds__(256) void k_rhs(const int64_t* __restrict__ colptr,
+                                             const int64_t* __restrict__ csc_pos,
+                                             const int32_t* __restrict__ csc_row,
+                                             const double* __restrict__ val,
+                                             const double* __restrict__ w,
+                                             const double* __restrict__ y,
+                                             double* __restrict__ b, int64_t n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  double s = 0.0;
+  for (int64_t k = colptr[c] + lane; k < colptr[c + 1]; k += 64) {
+    int32_t r = csc_row[k];
+    s += val[csc_pos[k]] * (w[r] * y[r]);
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) b[c] = s;
+}
+
+hipError_t launch_rhs(Handle& h, const double* y, double* b) {
+  hipLaunchKernelGGL(k_rhs, dim3(grid_for(h.an.n, 4)), dim3(256), 0, h.stream,
+                     h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.w, y, b,
+                     h.an.n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ double-double residual
+// r = b - H^T W H x with every product and sum in double-double
+// (error-free transformations: two_sum, two_prod by fma), rounded once.
+struct dd {
+  double hi, lo;
+};
+__device__ inline dd two_sum(double a, double b) {
+  double s = a + b, bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ inline dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  double lo = s.lo + a.lo + b.lo;
+  return two_sum(s.hi, lo);
+}
+__device__ inline dd dd_mul_d(dd a, double b) {
+  double p = a.hi * b;
+  double e = fma(a.hi, b, -p);
+  return two_sum(p, e + a.lo * b);
+}
+__device__ inline dd prod_dd(double a, double b) {
+  double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+__device__ inline dd shfl_down_dd(dd v, int off) {
+  return {__shfl_down(v.hi, off, 64), __shfl_down(v.lo, off, 64)};
+}
+
+// t_r = w_r * (H x)_r in double-double (one wave per row).
+__global__ __launch_bounds__(256) void k_hx_dd(const int64_t* __restrict__ rowptr,
+                                               const int32_t* __restrict__ col,
+                                               const double* __restrict__ val,
+                                               const double* __restrict__ w,
+                                               const double* __restrict__ x,
+                                               double* __restrict__ t, int64_t m) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= m) return;
+  dd s{0.0, 0.0};
+  for (int64_t e = rowptr[r] + lane; e < rowptr[r + 1]; e += 64)
+    s = dd_add(s, prod_dd(val[e], x[col[e]]));
+  for (int off = 32; off > 0; off >>= 1) s = dd_add(s, shfl_down_dd(s, off));
+  if (lane == 0) {
+    dd v = dd_mul_d(s, w[r]);
+    t[2 * r] = v.hi;
+    t[2 * r + 1] = v.lo;
+  }
+}
+
+// r_c = b_c - sum_r h_rc t_r in double-double (one wave per column).
+__global__ __launch_bounds__(256) void k_htt_dd(const int64_t* __restrict__ colptr,
+                                                const int64_t* __restrict__ csc_pos,
+                                                const int32_t* __restrict__ csc_row,
+                                                const double* __restrict__ val,
+                                                const double* __restrict__ t,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ r, int64_t n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  dd s{0.0, 0.0};
+  for (int64_t k = colptr[c] + lane; k < colptr[c + 1]; k += 64) {
+    const int32_t row = csc_row[k];
+    const double h = val[csc_pos[k]];
+    dd tr{t[2 * row], t[2 * row + 1]};
+    s = dd_add(s, dd_mul_d(tr, h));
+  }
+  for (int off = 32; off > 0; off >>= 1) s = dd_add(s, shfl_down_dd(s, off));
+  if (lane == 0) {
+    dd v = dd_add(dd{b[c], 0.0}, dd{-s.hi, -s.lo});
+    r[c] = v.hi + v.lo;
+  }
+}
+
+hipError_t launch_residual_dd(Handle& h, const double* b, const double* x,
+                              double* r) {
+  const Analysis& a = h.an;
+  hipLaunchKernelGGL(k_hx_dd, dim3(grid_for(a.m, 4)), dim3(256), 0, h.stream,
+                     h.d.rowptr, h.d.col, h.val, h.w, x, h.vdd, a.m);
+  hipLaunchKernelGGL(k_htt_dd, dim3(grid_for(a.n, 4)), dim3(256), 0, h.stream,
+                     h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.vdd, b, r,
+                     a.n);
+  return hipGetLastError();
+}
+
+// x += dx; norms[0] = max |dx|, norms[1] = max |x| (as ordered bit patterns
+// of non-negative doubles, reduced with atomicMax).
+__global__ void k_axpy_norms(double* __restrict__ x, const double* __restrict__ dx,
+                             unsigned long long* norms, int64_t n) {
+  double mdx = 0.0, mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = x[i] + dx[i];
+    x[i] = v;
+    mdx = fmax(mdx, fabs(dx[i]));
+    mx = fmax(mx, fabs(v));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mdx = fmax(mdx, __shfl_down(mdx, off, 64));
+    mx = fmax(mx, __shfl_down(mx, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&norms[0], (unsigned long long)__double_as_longlong(mdx));
+    atomicMax(&norms[1], (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+hipError_t launch_axpy_norms(Handle& h, double* x, const double* dx) {
+  hipLaunchKernelGGL(k_axpy_norms, dim3(grid_for(h.an.n, 256)), dim3(256), 0,
+                     h.stream, x, dx, (unsigned long long*)h.vnorm, h.an.n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- solves
+// Permute into the elimination order: leaf values y_l = b[leaf_col] / L_ll
+// (forward substitution at the leaves), root values z_i = b[root_col].
+__global__ void k_fwd_leaf(const double* __restrict__ b,
+                           const int32_t* __restrict__ leaf_cols,
+                           const double* __restrict__ ldiag,
+                           double* __restrict__ vleaf, int64_t n_leaf) {
+  for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n_leaf;
+       l += (int64_t)gridDim.x * blockDim.x)
+    vleaf[l] = b[leaf_cols[l]] / ldiag[l];
+}
+
+// z_i = b[root_col_i] - sum over the leaf panels that contain i of
+// (L_Ug y_g)_i : one wave per root unknown, over its incidences.
+__global__ __launch_bounds__(256) void k_fwd_root_gather(
+    const double* __restrict__ b, const int32_t* __restrict__ root_cols,
+    const int64_t* __restrict__ rinc_ptr, const int32_t* __restrict__ rinc_grp,
+    const int32_t* __restrict__ rinc_u, const int64_t* __restrict__ grp_U_ptr,
+    const int64_t* __restrict__ grp_col_ptr, const int64_t* __restrict__ grp_panel_off,
+    const double* __restrict__ panel, const double* __restrict__ vleaf,
+    double* __restrict__ z, int64_t n_root, int64_t n_pad) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n_pad) return;
+  if (i >= n_root) {
+    if (lane == 0) z[i] = 0.0;
+    return;
+  }
+  double s = 0.0;
+  for (int64_t k = rinc_ptr[i] + lane; k < rinc_ptr[i + 1]; k += 64) {
+    const int g = rinc_grp[k];
+    const int64_t u = rinc_u[k];
+    const int64_t nU = grp_U_ptr[g + 1] - grp_U_ptr[g];
+    const int64_t c0 = grp_col_ptr[g], p = grp_col_ptr[g + 1] - c0;
+    const double* P = panel + grp_panel_off[g] + u;
+    for (int64_t q = 0; q < p; ++q) s += P[q * nU] * vleaf[c0 + q];
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) z[i] = b[root_cols[i]] - s;
+}
+
+// Backward at the leaves: x_l = (y_l - L_Ul^T x_U) / L_ll (one wave per
+// leaf), then scatter root and leaf values to the original order.
+__global__ __launch_bounds__(256) void k_bwd_leaf(
+    const int32_t* __restrict__ leaf_grp, const int64_t* __restrict__ grp_col_ptr,
+    const int64_t* __restrict__ grp_U_ptr, const int32_t* __restrict__ U,
+    const int64_t* __restrict__ grp_panel_off, const double* __restrict__ panel,
+    const double* __restrict__ ldiag, const int32_t* __restrict__ leaf_cols,
+    const double* __restrict__ vleaf, const double* __restrict__ z,
+    double* __restrict__ x, int64_t n_leaf) {
+  const int lane = threadIdx.x & 63;
+  const int64_t l = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (l >= n_leaf) return;
+  const int g = leaf_grp[l];
+  const int64_t q = l - grp_col_ptr[g];
+  const int64_t u0 = grp_U_ptr[g], nU = grp_U_ptr[g + 1] - u0;
+  const double* P = panel + grp_panel_off[g] + q * nU;
+  double s = 0.0;
+  for (int64_t u = lane; u < nU; u += 64) s += P[u] * z[U[u0 + u]];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) x[leaf_cols[l]] = (vleaf[l] - s) / ldiag[l];
+}
+
+__global__ void k_scatter_root(const double* __restrict__ z,
+                               const int32_t* __restrict__ root_cols,
+                               double* __restrict__ x, int64_t n_root) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_root;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[root_cols[i]] = z[i];
+}
+
+hipError_t launch_solve_pass(Handle& h, const double* b, double* x) {
+  const Analysis& a = h.an;
+  const int64_t nl = (int64_t)a.leaf_cols.size();
+  hipError_t e;
+  if (nl)
+    hipLaunchKernelGGL(k_fwd_leaf, dim3(grid_for(nl, 256)), dim3(256), 0,
+                       h.stream, b, h.d.leaf_cols, h.ldiag, h.vleaf, nl);
+  if (a.n_pad) {
+    hipLaunchKernelGGL(k_fwd_root_gather, dim3(grid_for(a.n_pad, 4)), dim3(256),
+                       0, h.stream, b, h.d.root_cols, h.d.rinc_ptr, h.d.rinc_grp,
+                       h.d.rinc_u, h.d.grp_U_ptr, h.d.grp_col_ptr,
+                       h.d.grp_panel_off, h.panel, h.vleaf, h.vroot, a.n_root,
+                       a.n_pad);
+    if ((e = root_trsv_fwd(h, h.vroot)) != hipSuccess) return e;
+    if ((e = root_trsv_bwd(h, h.vroot)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter_root, dim3(grid_for(a.n_root, 256)), dim3(256),
+                       0, h.stream, h.vroot, h.d.root_cols, x, a.n_root);
+  }
+  if (nl)
+    hipLaunchKernelGGL(k_bwd_leaf, dim3(grid_for(nl, 4)), dim3(256), 0,
+                       h.stream, h.d.leaf_grp, h.d.grp_col_ptr, h.d.grp_U_ptr,
+                       h.d.U, h.d.grp_panel_off, h.panel, h.ldiag, h.d.leaf_cols,
+                       h.vleaf, h.vroot, x, nl);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- selected inversion
+// Root: d[root_col_i] = Z_ii.
+__global__ void k_diag_root(const double* __restrict__ Z, int64_t ld,
+                            const int32_t* __restrict__ root_cols,
+                            double* __restrict__ d, int64_t n_root) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_root;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[root_cols[i]] = Z[i + i * ld];
+}
+
+hipError_t launch_diag_root(Handle& h, double* d) {
+  if (!h.an.n_root) return hipSuccess;
+  hipLaunchKernelGGL(k_diag_root, dim3(grid_for(h.an.n_root, 256)), dim3(256),
+                     0, h.stream, h.Z, h.an.n_pad, h.d.root_cols, d,
+                     h.an.n_root);
+  return hipGetLastError();
+}
+
+// Leaves (Takahashi: Z L = L^-T): for pivot l of front g with panel column
+// c = L_Ul, Z_Ul = -Z_UU c / L_ll and Z_ll = (1 + c^T Z_UU c) / L_ll^2.
+// Task (g, I, J) adds its block of the quadratic forms c^T Z_UU c for all
+// pivots of g: the full square block for I == J, twice the block for I > J.
+__global__ __launch_bounds__(256) void k_selinv_leaf(
+    const int32_t* __restrict__ tasks, const int64_t* __restrict__ grp_U_ptr,
+    const int32_t* __restrict__ U, const int64_t* __restrict__ grp_col_ptr,
+    const int64_t* __restrict__ grp_panel_off, const double* __restrict__ panel,
+    const double* __restrict__ Z, int64_t ld,
+    const int64_t* __restrict__ task_part_off, double* __restrict__ part) {
+  __shared__ double Zt[kET][kET + 1];
+  __shared__ double PI[kQC][kET];
+  __shared__ double PJ[kQC][kET];
+  __shared__ double red[4][kQC / 4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = tasks[3 * blockIdx.x], I = tasks[3 * blockIdx.x + 1],
+            J = tasks[3 * blockIdx.x + 2];
+  const int p = (int)(grp_col_ptr[g + 1] - grp_col_ptr[g]);
+  if (p == 0) return;
+  const int64_t nU = grp_U_ptr[g + 1] - grp_U_ptr[g];
+  const int32_t* Ug = U + grp_U_ptr[g];
+  const int I0 = I * kET, J0 = J * kET;
+  const int na = (int)min<int64_t>(kET, nU - I0), nb = (int)min<int64_t>(kET, nU - J0);
+  // gather Z_UU block (lower storage: Z[max, min])
+  for (int e = t; e < kET * kET; e += 256) {
+    const int a = e % kET, b = e / kET;
+    double v = 0.0;
+    if (a < na && b < nb) {
+      int64_t ua = Ug[I0 + a], ub = Ug[J0 + b];
+      v = ua >= ub ? Z[ua + ub * ld] : Z[ub + ua * ld];
+    }
+    Zt[a][b] = v;
+  }
+  const double* Pg = panel + grp_panel_off[g];
+  const double fac = (I == J) ? 1.0 : 2.0;
+  for (int q0 = 0; q0 < p; q0 += kQC) {
+    const int pc = min(kQC, p - q0);
+    __syncthreads();
+    for (int e = t; e < kQC * kET; e += 256) {
+      int a = e % kET, q = e / kET;
+      PI[q][a] = (q < pc && a < na) ? Pg[(int64_t)(q0 + q) * nU + I0 + a] : 0.0;
+      PJ[q][a] = (q < pc && a < nb) ? Pg[(int64_t)(q0 + q) * nU + J0 + a] : 0.0;
+    }
+    __syncthreads();
+    // thread (b = lane, q = wave + 4k): y_b = sum_a PI[q][a] Zt[a][b]; s_q += y_b PJ[q][b]
+    for (int q = wave; q < kQC; q += 4) {
+      double s = 0.0;
+      if (q < pc) {
+        double y = 0.0;
+        for (int a = 0; a < kET; ++a) y += PI[q][a] * Zt[a][lane];
+        s = y * PJ[q][lane];
+      }
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+      if (lane == 0) red[wave][q / 4] = s;
+    }
+    __syncthreads();
+    if (t < pc) part[task_part_off[blockIdx.x] + q0 + t] = fac * red[t % 4][t / 4];
+  }
+}
+
+// d[leaf_col_l] = (1 + sum over the front's tasks of the partial sums) / L_ll^2
+__global__ void k_selinv_reduce(const int32_t* __restrict__ leaf_grp,
+                                const int64_t* __restrict__ grp_col_ptr,
+                                const int64_t* __restrict__ grp_task_ptr,
+                                const int64_t* __restrict__ task_part_off,
+                                const double* __restrict__ part,
+                                const double* __restrict__ ldiag,
+                                const int32_t* __restrict__ leaf_cols,
+                                double* __restrict__ d, int64_t n_leaf) {
+  for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n_leaf;
+       l += (int64_t)gridDim.x * blockDim.x) {
+    const int g = leaf_grp[l];
+    const int64_t q = l - grp_col_ptr[g];
+    double s = 0.0;
+    for (int64_t tk = grp_task_ptr[g]; tk < grp_task_ptr[g + 1]; ++tk)
+      s += part[task_part_off[tk] + q];
+    const double L = ldiag[l];
+    d[leaf_cols[l]] = (1.0 + s) / (L * L);
+  }
+}
+
+hipError_t launch_selinv_leaves(Handle& h, double* d) {
+  const Analysis& a = h.an;
+  const int64_t nl = (int64_t)a.leaf_cols.size();
+  if (!nl) return hipSuccess;
+  const int64_t n_lt = a.grp_task_ptr[a.n_groups];  // tasks of leaf fronts
+  if (n_lt && a.n_pad) {
+    const int64_t chunk = 1 << 20;
+    for (int64_t t0 = 0; t0 < n_lt; t0 += chunk) {
+      int64_t c = std::min(chunk, n_lt - t0);
+      hipLaunchKernelGGL(k_selinv_leaf, dim3((unsigned)c), dim3(256), 0,
+                         h.stream, h.d.tasks + 3 * t0, h.d.grp_U_ptr, h.d.U,
+                         h.d.grp_col_ptr, h.d.grp_panel_off, h.panel, h.Z,
+                         a.n_pad, h.d.task_part_off + t0, h.part);
+    }
+  }
+  hipLaunchKernelGGL(k_selinv_reduce, dim3(grid_for(nl, 256)), dim3(256), 0,
+                     h.stream, h.d.leaf_grp, h.d.grp_col_ptr, h.d.grp_task_ptr,
+                     h.d.task_part_off, h.part, h.ldiag, h.d.leaf_cols, d, nl);
+  return hipGetLastError();
+}
+
+}  // namespace spi

@@ -1,0 +1,187 @@
+// Internal declarations of libspi: handle layout, host analysis, kernel
+// launchers.  Not part of the public ABI (that is include/spi.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/spi.h"
+
+namespace spi {
+
+// Root front is padded to a multiple of this (identity on the padding), so
+// every dense kernel works on whole tiles.
+constexpr int kRootPad = 128;
+// Block size of the root POTRF / TRTRI sweeps and of the stored inverse
+// diagonal blocks.
+constexpr int kNB = 64;
+// Tile edge of the extend-add and leaf selected-inversion tasks, in
+// positions of a front's row structure U.
+constexpr int kET = 64;
+// Rows of the dense root triangular-solve chunks.
+constexpr int kTrsvChunk = 512;
+
+// ---------------------------------------------------------------- analysis
+// Host result of the symbolic analysis.  "slot" = a measurement row in
+// front order: rows of front 0, rows of front 1, ...; within a leaf front
+// the rows of its first leaf column, then its second, and so on.
+struct Analysis {
+  int64_t m = 0, n = 0, nnz = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  // transpose of the pattern
+  std::vector<int64_t> colptr;    // n + 1
+  std::vector<int64_t> csc_pos;   // CSR position of each CSC entry
+  std::vector<int32_t> csc_row;   // row of each CSC entry
+  // leaves (eliminated first), in front order
+  std::vector<int32_t> leaf_cols;       // original column of leaf l
+  std::vector<int32_t> leaf_grp;        // front of leaf l
+  std::vector<int64_t> leaf_slot_ptr;   // n_leaf + 1, slots of leaf l
+  // fronts: leaf fronts first, then row-only fronts (no pivot, rows that
+  // touch no leaf column: they only contribute to the root)
+  int64_t n_groups = 0;         // leaf fronts
+  int64_t n_fronts = 0;         // leaf fronts + row-only fronts
+  std::vector<int64_t> grp_col_ptr;    // n_fronts + 1 into leaf_cols
+  std::vector<int64_t> grp_U_ptr;      // n_fronts + 1 into U
+  std::vector<int32_t> U;              // root indices, sorted per front
+  std::vector<int64_t> grp_panel_off;  // n_fronts + 1, dense |U| x p panels
+  std::vector<int64_t> grp_slot_ptr;   // n_fronts + 1 into slots
+  // slots
+  std::vector<int32_t> slot_row;       // original row
+  std::vector<int64_t> slot_rr_ptr;    // m + 1 into the compact root entries
+  std::vector<int64_t> slot_leaf_src;  // CSR position of the leaf entry or -1
+  std::vector<int32_t> rr_lpos;        // U-local position of each root entry
+  std::vector<int64_t> rr_src;         // CSR position of each root entry
+  // root
+  int64_t n_root = 0, n_pad = 0;
+  std::vector<int32_t> root_cols;      // original column of root index i
+  std::vector<int32_t> root_of_col;    // n, root index or -1
+  // root incidences (transpose of the U lists): for root index i the
+  // (front, U-local position) pairs, as global panel row offsets
+  std::vector<int64_t> rinc_ptr;       // n_root + 1
+  std::vector<int32_t> rinc_grp;
+  std::vector<int32_t> rinc_u;
+  // extend-add / selected-inversion tasks: (front, I, J), I >= J, tiles of
+  // kET positions of the front's U
+  std::vector<int32_t> tasks;          // 3 per task
+  std::vector<int64_t> grp_task_ptr;   // n_fronts + 1
+  std::vector<int64_t> task_part_off;  // n_tasks + 1 (selinv partial sums)
+  // counters
+  int64_t nnz_a = 0, nnz_l = 0;
+  double flops_factor = 0, flops_selinv = 0, flops_solve = 0, flops_asm = 0;
+};
+
+// Returns an empty string on success, else the error text.
+std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
+                    const int32_t* col, const spi_opts& opts, Analysis& out);
+
+// ------------------------------------------------------------ device side
+struct DevAnalysis {
+  // pattern
+  int64_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  int64_t* colptr = nullptr;
+  int64_t* csc_pos = nullptr;
+  int32_t* csc_row = nullptr;
+  // fronts
+  int32_t* leaf_cols = nullptr;
+  int32_t* leaf_grp = nullptr;
+  int64_t* leaf_slot_ptr = nullptr;
+  int64_t* grp_col_ptr = nullptr;
+  int64_t* grp_U_ptr = nullptr;
+  int32_t* U = nullptr;
+  int64_t* grp_panel_off = nullptr;
+  int64_t* grp_slot_ptr = nullptr;
+  int32_t* slot_row = nullptr;
+  int64_t* slot_rr_ptr = nullptr;
+  int64_t* slot_leaf_src = nullptr;
+  int32_t* rr_lpos = nullptr;
+  int64_t* rr_src = nullptr;
+  int32_t* root_cols = nullptr;
+  int64_t* rinc_ptr = nullptr;
+  int32_t* rinc_grp = nullptr;
+  int32_t* rinc_u = nullptr;
+  int32_t* tasks = nullptr;
+  int64_t* grp_task_ptr = nullptr;
+  int64_t* task_part_off = nullptr;
+};
+
+enum Phase { kPhLeaf = 0, kPhExtend, kPhPotrf, kPhSolve, kPhTrtri, kPhLauum,
+             kPhSelinv, kNumPhases };
+
+struct PhaseTimer {
+  std::vector<hipEvent_t> free_ev;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  hipEvent_t open = nullptr;
+  double total_ms = 0;
+  int64_t count = 0;
+};
+
+struct Handle {
+  spi_opts opts{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Analysis an;
+  DevAnalysis d;
+  // values in front (slot) order
+  double* val = nullptr;     // H values, CSR order (copy)
+  double* w = nullptr;       // weights, original row order (copy)
+  double* sw = nullptr;      // weight per slot
+  double* sleaf = nullptr;   // leaf coefficient per slot (0 for row-only)
+  double* rrval = nullptr;   // root entries in compact slot order
+  // factor
+  double* panel = nullptr;   // leaf panels L_UG, dense column-major per front
+  double* ldiag = nullptr;   // leaf pivots L_ll
+  double* S = nullptr;       // root front n_pad x n_pad, column-major; L after factor
+  double* invd = nullptr;    // inverses of the kNB diagonal blocks of L_RR
+  double* W = nullptr;       // L_RR^-1 (selected inversion scratch)
+  double* Z = nullptr;       // A^-1 restricted to the root (lower triangle)
+  double* part = nullptr;    // selected-inversion partial sums
+  int64_t* flag = nullptr;   // first failing pivot in elimination order
+  // solve scratch
+  double* vleaf = nullptr;   // n_leaf
+  double* vroot = nullptr;   // n_pad
+  double* vres = nullptr;    // n (residual / correction)
+  double* vx = nullptr;      // n (iterate)
+  double* vdd = nullptr;     // 2 m (double-double row values)
+  double* vnorm = nullptr;   // 2 (norm reductions)
+  // phase timing (opts.timing): HIP event pairs recorded on the stream,
+  // accumulated lazily (spi_info synchronises and sums them)
+  PhaseTimer timer[kNumPhases];
+  bool have_values = false, have_factor = false;
+  int64_t failed_col = -1;
+  double t_analyze_ms = 0;
+  int refine_done = 0;
+  double last_refine_norm = 0;
+  std::string err;
+};
+
+// kernel launchers (stream-ordered); return hipError_t of the launch
+hipError_t launch_gather_values(Handle& h);
+hipError_t launch_leaf_assemble(Handle& h);
+hipError_t launch_root_fill(Handle& h);
+hipError_t launch_extend_add(Handle& h);
+hipError_t launch_rhs(Handle& h, const double* y, double* b);
+hipError_t root_potrf(Handle& h);
+hipError_t root_trsv_fwd(Handle& h, double* z);
+hipError_t root_trsv_bwd(Handle& h, double* z);
+hipError_t root_trtri(Handle& h);
+hipError_t root_lauum(Handle& h);
+hipError_t launch_solve_pass(Handle& h, const double* b, double* x);
+hipError_t launch_residual_dd(Handle& h, const double* b, const double* x,
+                              double* r);
+hipError_t launch_axpy_norms(Handle& h, double* x, const double* dx);
+hipError_t launch_selinv_leaves(Handle& h, double* d);
+hipError_t launch_diag_root(Handle& h, double* d);
+
+// dense kernels, exposed for tests of the root-front building blocks
+enum GemmOp { kXC = 0, kKC = 1 };  // operand access, see k_dense.hip
+hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
+                const double* A, int64_t lda, const double* B, int64_t ldb,
+                double* C, int64_t ldc, int M, int N, int K, double alpha,
+                double beta, bool lower, bool kstart_diag);
+
+}  // namespace spi

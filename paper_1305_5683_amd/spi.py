@@ -1,0 +1,213 @@
+"""Thin ctypes binding of libspi (include/spi.h).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  PyTorch supplies device memory (tensors) and the HIP stream.
+There is no CPU fallback: if ``libspi.so`` is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libspi.so")
+
+SPI_OK, SPI_E_ARG, SPI_E_STATE, SPI_E_NOT_SPD, SPI_E_OOM, SPI_E_HIP, SPI_E_NOCONV = range(7)
+SPI_FP64, SPI_MIXED = 0, 1
+_STATUS = {0: "SPI_OK", 1: "SPI_E_ARG", 2: "SPI_E_STATE", 3: "SPI_E_NOT_SPD",
+           4: "SPI_E_OOM", 5: "SPI_E_HIP", 6: "SPI_E_NOCONV"}
+
+EXPORTED = ["spi_default_opts", "spi_analyze", "spi_set_values", "spi_factor",
+            "spi_rhs", "spi_solve", "spi_diag_inv", "spi_symbolic", "spi_info",
+            "spi_last_error", "spi_destroy"]
+
+
+class spi_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("max_group", C.c_int32),
+                ("leaf_max_work", C.c_double), ("amalg_density", C.c_double),
+                ("refine_steps", C.c_int32), ("timing", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
+
+
+class spi_info_t(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz_h", C.c_int64),
+                ("nnz_a", C.c_int64), ("nnz_l", C.c_int64),
+                ("n_leaf", C.c_int64), ("n_groups", C.c_int64),
+                ("n_root", C.c_int64), ("n_root_padded", C.c_int64),
+                ("failed_col", C.c_int64), ("flops_factor", C.c_double),
+                ("flops_selinv", C.c_double), ("flops_solve", C.c_double),
+                ("flops_assembly", C.c_double), ("t_analyze_ms", C.c_double),
+                ("precision", C.c_int32), ("refine_steps_done", C.c_int32),
+                ("last_refine_norm", C.c_double), ("t_leaf_ms", C.c_double),
+                ("t_extend_ms", C.c_double), ("t_potrf_ms", C.c_double),
+                ("t_solve_ms", C.c_double), ("t_trtri_ms", C.c_double),
+                ("t_lauum_ms", C.c_double), ("t_selinv_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SpiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libspi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with "
+                           "`python -m paper_1305_5683_amd.build`")
+    lib = C.CDLL(path)
+    P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    lib.spi_default_opts.argtypes = [C.POINTER(spi_opts)]
+    lib.spi_default_opts.restype = None
+    lib.spi_analyze.argtypes = [C.POINTER(C.c_void_p), I64, I64, P, P,
+                                C.POINTER(spi_opts), P]
+    lib.spi_set_values.argtypes = [P, P, P]
+    lib.spi_factor.argtypes = [P]
+    lib.spi_rhs.argtypes = [P, P, P]
+    lib.spi_solve.argtypes = [P, P, P, I32, I64]
+    lib.spi_diag_inv.argtypes = [P, P]
+    lib.spi_symbolic.argtypes = [I64, I64, P, P, C.POINTER(spi_opts),
+                                 C.POINTER(spi_info_t), P, P, P]
+    lib.spi_info.argtypes = [P, C.POINTER(spi_info_t)]
+    lib.spi_last_error.argtypes = [P]
+    lib.spi_last_error.restype = C.c_char_p
+    lib.spi_destroy.argtypes = [P]
+    lib.spi_destroy.restype = None
+    for name in EXPORTED:
+        if name not in ("spi_default_opts", "spi_last_error", "spi_destroy"):
+            getattr(lib, name).restype = C.c_int
+    del I64, I32, D
+    _lib = lib
+    return lib
+
+
+def default_opts(**kw) -> spi_opts:
+    lib = load_library()
+    o = spi_opts()
+    lib.spi_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _pattern(rowptr, col):
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    return rp, cl
+
+
+def symbolic(m, n, rowptr, col, **opts):
+    """Host-only analysis: (info dict, elim_order, col_parent, front_of)."""
+    lib = load_library()
+    rp, cl = _pattern(rowptr, col)
+    info = spi_info_t()
+    order = np.empty(n, dtype=np.int32)
+    parent = np.empty(n, dtype=np.int32)
+    front = np.empty(n, dtype=np.int32)
+    o = default_opts(**opts)
+    st = lib.spi_symbolic(m, n, rp.ctypes.data, cl.ctypes.data, C.byref(o),
+                          C.byref(info), order.ctypes.data, parent.ctypes.data,
+                          front.ctypes.data)
+    if st != SPI_OK:
+        raise SpiError(st, lib.spi_last_error(None).decode())
+    return info.as_dict(), order, parent, front
+
+
+def _ptr(t, n=None, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device (cuda/hip) torch tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"tensor too small: {t.numel()} < {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+class SpiSolver:
+    """One analysed pattern; values, factor and results live on the GPU."""
+
+    def __init__(self, m, n, rowptr, col, stream=None, **opts):
+        import torch
+        self.lib = load_library()
+        self.m, self.n = int(m), int(n)
+        rp, cl = _pattern(rowptr, col)
+        self.nnz = int(rp[-1])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        o = default_opts(**opts)
+        st = self.lib.spi_analyze(C.byref(h), self.m, self.n, rp.ctypes.data,
+                                  cl.ctypes.data, C.byref(o),
+                                  C.c_void_p(stream.cuda_stream))
+        if st != SPI_OK:
+            raise SpiError(st, self.lib.spi_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st):
+        if st != SPI_OK:
+            raise SpiError(st, self.lib.spi_last_error(self.h).decode())
+
+    def set_values(self, val, w):
+        import torch
+        self._check(self.lib.spi_set_values(
+            self.h, _ptr(val, self.nnz, torch.float64),
+            _ptr(w, self.m, torch.float64)))
+
+    def factor(self):
+        self._check(self.lib.spi_factor(self.h))
+
+    def rhs(self, y, out=None):
+        import torch
+        b = out if out is not None else torch.empty(self.n, dtype=torch.float64,
+                                                    device=y.device)
+        self._check(self.lib.spi_rhs(self.h, _ptr(y, self.m, torch.float64),
+                                     _ptr(b, self.n, torch.float64)))
+        return b
+
+    def solve(self, b, out=None):
+        """x = A^-1 b; ``b`` of shape (n,) or (nrhs, n) (column-major n x nrhs)."""
+        import torch
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        x = out if out is not None else torch.empty_like(b)
+        self._check(self.lib.spi_solve(self.h, _ptr(b, nrhs * self.n, torch.float64),
+                                       _ptr(x, nrhs * self.n, torch.float64),
+                                       nrhs, self.n))
+        return x
+
+    def diag_inv(self, out=None):
+        import torch
+        d = out if out is not None else torch.empty(
+            self.n, dtype=torch.float64, device=torch.device("cuda"))
+        self._check(self.lib.spi_diag_inv(self.h, _ptr(d, self.n, torch.float64)))
+        return d
+
+    def info(self) -> dict:
+        i = spi_info_t()
+        self._check(self.lib.spi_info(self.h, C.byref(i)))
+        return i.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.spi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

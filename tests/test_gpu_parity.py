@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances (plain FP64 path): solution ``||x - x_o|| / ||x_o|| <= 1e-12``
+and variances ``max_i |d_i - d_o,i| / d_o,i <= 1e-12``; the oracle's x is
+certified by refinement with long-double residuals, so its own error is far
+below the bound.  Integer-valued inputs make ``b = H^T W y`` exact, so it is
+compared bit for bit.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import spi_synth as synth
+from oracle import oracle_solve, normal_equations_bruteforce
+from oracle.certify import refine_inverse_column, apply_normal_ld
+
+pytestmark = pytest.mark.gpu
+
+TOL_X = 1e-12
+TOL_D = 1e-12
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(p, want_diag=True, y=None, **opts):
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver
+    dev = torch.device("cuda")
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col, **opts)
+    s.set_values(torch.from_numpy(p.val).to(dev), torch.from_numpy(p.w).to(dev))
+    s.factor()
+    yy = torch.from_numpy(p.y if y is None else y).to(dev)
+    b = s.rhs(yy)
+    x = s.solve(b)
+    d = s.diag_inv() if want_diag else None
+    torch.cuda.synchronize()
+    out = {"b": b.cpu().numpy(), "x": x.cpu().numpy(),
+           "d": None if d is None else d.cpu().numpy(), "info": s.info()}
+    s.close()
+    return out
+
+
+def rel_x(x, xo):
+    return np.linalg.norm(x - xo) / np.linalg.norm(xo)
+
+
+def rel_d(d, do):
+    return np.max(np.abs(d - do) / np.abs(do))
+
+
+def _check(p, g, o, idx=None):
+    ex = rel_x(g["x"], o["x"])
+    bo = o["b"]
+    eb = np.max(np.abs(g["b"] - bo)) / np.max(np.abs(bo))
+    dg = g["d"] if idx is None else g["d"][idx]
+    ed = rel_d(dg, o["diag"])
+    _say(f"  {p.name}: n={p.n} err_x={ex:.2e} err_d={ed:.2e} err_b={eb:.2e}")
+    assert eb <= 1e-14
+    assert ex <= TOL_X
+    assert ed <= TOL_D
+    assert np.all(g["d"] > 0)
+
+
+def test_tiny_config_parity():
+    p = synth.make_config(0)
+    _say(f"case tiny config seed={p.seed} m={p.m} n={p.n}")
+    g = run_gpu(p)
+    o = oracle_solve(p)
+    _check(p, g, o)
+    assert g["info"]["n_leaf"] == 380 and g["info"]["n_root"] == 400
+
+
+LEAFY = [
+    # (groups, leaf/group, root, rows/leaf, root/row, extra rows, seed, opts)
+    (9, 5, 70, 3, 8, 12, 0, {}),            # ragged U, row-only fronts, pad 128
+    (4, 23, 150, 2, 20, 40, 1, {}),         # fronts wider than 16 columns
+    (30, 3, 200, 4, 30, 0, 2, {}),          # U spanning several 64-tiles
+    (6, 4, 260, 2, 60, 300, 3, {"max_group": 1}),  # one pivot per front
+    (5, 6, 90, 3, 10, 20, 4, {"leaf_max_work": 0.0}),  # no leaves: dense root
+]
+
+
+@pytest.mark.parametrize("case", LEAFY, ids=[f"leafy{i}" for i in range(len(LEAFY))])
+def test_leafy_structure_parity(case):
+    ng, lpg, nr, rpl, rpr, ex, seed, opts = case
+    p = synth.make_random_leafy(ng, lpg, nr, rpl, rpr, ex, seed)
+    _say(f"case leafy seed={seed} m={p.m} n={p.n} opts={opts}")
+    g = run_gpu(p, **opts)
+    o = oracle_solve(p)
+    _check(p, g, o)
+
+
+def test_all_leaves_no_root():
+    """Every unknown has rows of its own: A is diagonal, no root front."""
+    rng = np.random.default_rng(5)
+    n, k = 37, 3
+    rowptr = np.arange(n * k + 1, dtype=np.int64)
+    col = np.repeat(np.arange(n, dtype=np.int32), k)
+    val = 0.1 + rng.random(n * k)
+    w = 0.5 + rng.random(n * k)
+    y = rng.random(n * k) * 10
+    p = synth.Problem(m=n * k, n=n, n_bg=n, rowptr=rowptr, col=col, val=val,
+                      w=w, y=y, x_true=np.ones(n), name="diag")
+    _say("case all-leaves n=37")
+    g = run_gpu(p)
+    assert g["info"]["n_root"] == 0
+    a = np.bincount(col, weights=w * val * val, minlength=n)
+    bb = np.bincount(col, weights=w * val * y, minlength=n)
+    assert np.allclose(g["x"], bb / a, rtol=1e-14)
+    assert np.allclose(g["d"], 1.0 / a, rtol=1e-14)
+
+
+def test_rhs_is_exact_on_integer_inputs():
+    p = synth.make_random_leafy(6, 4, 40, 2, 6, 10, seed=7, integer=True)
+    _say(f"case integer rhs m={p.m} n={p.n}")
+    g = run_gpu(p, want_diag=False)
+    _, bb = normal_equations_bruteforce(p.rowptr, p.col, p.val, p.w, p.y, p.n)
+    assert np.array_equal(g["b"], bb)
+
+
+def test_multiple_right_hand_sides():
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver
+    p = synth.make_random_leafy(8, 5, 80, 3, 9, 15, seed=8)
+    _say(f"case multi-rhs m={p.m} n={p.n}")
+    o = oracle_solve(p, want_diag=False, refine_steps=0)
+    f = o["factor"]
+    rng = np.random.default_rng(0)
+    B = rng.standard_normal((3, p.n))
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col)
+    dev = torch.device("cuda")
+    s.set_values(torch.from_numpy(p.val).to(dev), torch.from_numpy(p.w).to(dev))
+    s.factor()
+    X = s.solve(torch.from_numpy(B).to(dev)).cpu().numpy()
+    s.close()
+    for c in range(3):
+        xo = f.solve(B[c]).astype(np.longdouble)
+        for _ in range(2):     # certify with long-double residuals from H
+            r = B[c].astype(np.longdouble) - apply_normal_ld(
+                p.rowptr, p.col, p.val, p.w, xo)
+            xo = xo + f.solve(r.astype(np.float64))
+        assert rel_x(X[c], xo.astype(np.float64)) <= TOL_X
+
+
+def test_not_spd_is_reported_with_column():
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiError
+    p = synth.make_config(0)
+    dev = torch.device("cuda")
+    # a negative weight on every row of background unknown 7: pivot < 0
+    w = p.w.copy()
+    w[p.col[p.rowptr[:-1]] == 7] = -1.0
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col)
+    s.set_values(torch.from_numpy(p.val).to(dev), torch.from_numpy(w).to(dev))
+    _say("case not-spd leaf")
+    with pytest.raises(SpiError) as ei:
+        s.factor()
+    assert ei.value.status == 3 and s.info()["failed_col"] == 7
+    with pytest.raises(SpiError) as ei:       # no factor: state error
+        s.diag_inv()
+    assert ei.value.status == 2
+    # root: weights scaled negative on all rows -> first root pivot fails
+    s.set_values(torch.from_numpy(p.val).to(dev),
+                 torch.from_numpy(-p.w).to(dev))
+    _say("case not-spd all")
+    with pytest.raises(SpiError) as ei:
+        s.factor()
+    assert ei.value.status == 3
+    s.close()
+
+
+def test_state_errors():
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiError
+    p = synth.make_config(0)
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col)
+    with pytest.raises(SpiError) as ei:
+        s.factor()
+    assert ei.value.status == 2
+    s.close()
+
+
+@pytest.mark.timeout(900)
+def test_medium_config_parity():
+    """The benchmark workload (100x100 sky, 5000 pointings, 33,750 unknowns):
+    full x against the certified oracle, diag(A^-1) on a sample checked both
+    against the oracle's block factor and against certified inverse columns."""
+    p = synth.make_config(1)
+    _say(f"case medium config m={p.m} n={p.n}")
+    g = run_gpu(p)
+    rng = np.random.default_rng(1)
+    idx = np.sort(np.concatenate([rng.choice(p.n_bg, 96, replace=False),
+                                  p.n_bg + rng.choice(p.n - p.n_bg, 96,
+                                                      replace=False)]))
+    o = oracle_solve(p, diag_idx=idx)
+    _check(p, g, o, idx=idx)
+    f = o["factor"]
+    for j in idx[::24]:
+        zc = refine_inverse_column(p, f.solve, int(j))
+        assert abs(g["d"][j] - float(zc[j])) <= TOL_D * float(zc[j])
