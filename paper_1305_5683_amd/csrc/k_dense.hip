@@ -199,9 +199,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       for (int a = 0; a < MI; ++a) fa[a] = frag_a(ks + lk, wm * WM + a * 16 + lx);
 #pragma unroll
       for (int b = 0; b < NI; ++b) fb[b] = frag_b(ks + lk, wn * WN + b * 16 + lx);
-      // D = Bfrag^T * Afrag: lane (lx, lk) of the result holds the output
-      // row i = lx and columns j = 4 * lk + v, which keeps the stores of a
-      // column-major C contiguous over 16 rows.
+      // D = Bfrag^T * Afrag.  The 16x16 result D[r][c] sits in lane
+      // c + 16 * (r % 4), item r / 4; with the operands swapped, lane
+      // (lx, lk) item v holds output row i = lx and column j = 4 * v + lk,
+      // which keeps the stores of a column-major C contiguous over 16 rows.
 #pragma unroll
       for (int a = 0; a < MI; ++a)
 #pragma unroll
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int i = i0 + wm * WM + a * 16 + lx;
-        int j = j0 + wn * WN + b * 16 + lk * 4 + v;
+        int j = j0 + wn * WN + b * 16 + v * 4 + lk;
         if (g.lower && I == J && i < j) continue;
         double* c = g.C + (int64_t)i + (int64_t)j * g.ldc;
         double r = g.alpha * acc[a][b][v];
