@@ -77,7 +77,12 @@ typedef struct spi_opts {
                                double-double residual; default 2 */
     int32_t timing;         /* 1: time the phases with HIP events on the
                                handle's stream (see spi_info); default 0 */
-    int32_t reserved[6];    /* must be zero */
+    int32_t root_inverse;   /* 1: spi_factor also forms the inverse of the
+                               root factor, L_RR^-1, which spi_solve then
+                               applies as two products and spi_diag_inv
+                               reuses; 0: it is formed by spi_diag_inv and
+                               spi_solve substitutes.  Default 1 */
+    int32_t reserved[5];    /* must be zero */
 } spi_opts;
 
 typedef struct spi_info_t {

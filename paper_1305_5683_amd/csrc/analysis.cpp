@@ -14,7 +14,16 @@
 // goes into one dense root front, in its original order.  The result is a
 // two-level assembly tree: independent leaf fronts, all children of the root.
 // It is exact for any SPD matrix (with no leaves it is a dense Cholesky).
+//
+// The root front is assembled output-stationary: its original entries
+// (sum over rows of w h h^T, grouped into dense "row panels") and the leaf
+// contribution blocks (-L_Ug L_Ug^T) are all weighted panel products
+// Q diag(w) Q^T on an index set U.  For every 64 x 64 lower tile of the root
+// the analysis lists the panels that touch it ("incidences", with the
+// positions of U inside the tile's row and column ranges), so one workgroup
+// per tile sums its contributions and writes the tile once.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <numeric>
 #include <sstream>
@@ -25,10 +34,23 @@
 namespace spi {
 
 namespace {
-constexpr int64_t kRowFrontMaxU = 1024;   // row-only fronts: max |U|
-constexpr int64_t kRowFrontMaxRows = 256; // row-only fronts: max rows
+constexpr int kTile = 64;  // root assembly tile
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Runs of a sorted index list by tile: (tile, first position, end position).
+void tile_runs(const int32_t* U, int64_t nU,
+               std::vector<std::array<int32_t, 3>>& runs) {
+  runs.clear();
+  int64_t a = 0;
+  while (a < nU) {
+    const int32_t t = U[a] / kTile;
+    int64_t b = a + 1;
+    while (b < nU && U[b] / kTile == t) ++b;
+    runs.push_back({t, (int32_t)a, (int32_t)b});
+    a = b;
+  }
+}
 }  // namespace
 
 std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
@@ -187,93 +209,171 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   if (!curCols.empty()) close_front();
   a.n_groups = front;
 
-  // ---- slots of the leaf fronts
+  // ---- slots (rows of the leaf fronts, by leaf unknown) and their compact
+  // root entries with U-local positions
   const int64_t n_leaf = (int64_t)a.leaf_cols.size();
   a.leaf_slot_ptr.assign(n_leaf + 1, 0);
   a.grp_slot_ptr.push_back(0);
+  a.slot_rr_ptr.push_back(0);
+  std::fill(posmap.begin(), posmap.end(), -1);
   for (int64_t g = 0; g < a.n_groups; ++g) {
+    for (int64_t u = a.grp_U_ptr[g]; u < a.grp_U_ptr[g + 1]; ++u)
+      posmap[a.U[u]] = u - a.grp_U_ptr[g];
     for (int64_t l = a.grp_col_ptr[g]; l < a.grp_col_ptr[g + 1]; ++l) {
       int32_t j = a.leaf_cols[l];
       for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
-        a.slot_row.push_back(a.csc_row[k]);
+        const int32_t r = a.csc_row[k];
+        a.slot_row.push_back(r);
         a.slot_leaf_src.push_back(a.csc_pos[k]);
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          int32_t ri = a.root_of_col[col[e]];
+          if (ri < 0) continue;
+          a.rr_lpos.push_back((int32_t)posmap[ri]);
+          a.rr_src.push_back(e);
+        }
+        a.slot_rr_ptr.push_back((int64_t)a.rr_src.size());
       }
       a.leaf_slot_ptr[l + 1] = (int64_t)a.slot_row.size();
     }
     a.grp_slot_ptr.push_back((int64_t)a.slot_row.size());
   }
+  a.n_slots = (int64_t)a.slot_row.size();
 
-  // ---- row-only fronts: rows that touch no leaf unknown
+  // ---- row panels: consecutive rows (original order) with overlapping
+  // root structure; rows without root entries contribute nothing to A_RR
+  a.rp_U_base = (int64_t)a.U.size();
+  a.rp_row_ptr.push_back(0);
+  a.rp_U_ptr.push_back(0);
+  a.rp_val_off.push_back(0);
+  a.rpe_ptr.push_back(0);
+  std::fill(mark.begin(), mark.end(), -1);
   {
-    int64_t rows_in = 0;
-    for (int64_t r = 0; r < m; ++r) {
-      if (claimed[r]) continue;
-      int64_t add = 0;
-      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        int32_t ri = a.root_of_col[col[e]];
-        if (ri >= 0 && mark[ri] != front) ++add;
-      }
-      if (rows_in > 0 && ((int64_t)curU.size() + add > kRowFrontMaxU ||
-                          rows_in >= kRowFrontMaxRows)) {
-        std::sort(curU.begin(), curU.end());
-        a.U.insert(a.U.end(), curU.begin(), curU.end());
-        a.grp_col_ptr.push_back((int64_t)a.leaf_cols.size());
-        a.grp_U_ptr.push_back((int64_t)a.U.size());
-        a.grp_panel_off.push_back(a.grp_panel_off.back());
-        a.grp_slot_ptr.push_back((int64_t)a.slot_row.size());
-        ++front;
-        curU.clear();
-        rows_in = 0;
-      }
-      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        int32_t ri = a.root_of_col[col[e]];
-        if (ri >= 0 && mark[ri] != front) {
-          mark[ri] = front;
-          curU.push_back(ri);
+    int64_t panel = 0, rows_in = 0, sum = 0;
+    std::vector<int32_t> pU, pRows;
+    auto close_panel = [&]() {
+      std::sort(pU.begin(), pU.end());
+      for (size_t x = 0; x < pU.size(); ++x) posmap[pU[x]] = (int64_t)x;
+      const int64_t nU = (int64_t)pU.size();
+      for (size_t q = 0; q < pRows.size(); ++q) {
+        const int32_t r = pRows[q];
+        a.rp_rows.push_back(r);
+        a.rp_rowbase.push_back(a.rp_val_off.back() + (int64_t)q * nU);
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          int32_t ri = a.root_of_col[col[e]];
+          if (ri < 0) continue;
+          a.rpe_pos.push_back((int32_t)posmap[ri]);
+          a.rpe_src.push_back(e);
         }
+        a.rpe_ptr.push_back((int64_t)a.rpe_src.size());
       }
-      a.slot_row.push_back((int32_t)r);
-      a.slot_leaf_src.push_back(-1);
-      ++rows_in;
-    }
-    if (rows_in > 0) {
-      std::sort(curU.begin(), curU.end());
-      a.U.insert(a.U.end(), curU.begin(), curU.end());
-      a.grp_col_ptr.push_back((int64_t)a.leaf_cols.size());
-      a.grp_U_ptr.push_back((int64_t)a.U.size());
-      a.grp_panel_off.push_back(a.grp_panel_off.back());
-      a.grp_slot_ptr.push_back((int64_t)a.slot_row.size());
-      ++front;
-      curU.clear();
-    }
-  }
-  a.n_fronts = front;
-  if ((int64_t)a.slot_row.size() != m) return "internal: slot count mismatch";
-
-  // ---- compact root entries per slot, with U-local positions
-  a.slot_rr_ptr.assign(m + 1, 0);
-  a.rr_lpos.reserve(nnz);
-  a.rr_src.reserve(nnz);
-  std::fill(posmap.begin(), posmap.end(), -1);
-  for (int64_t f = 0; f < a.n_fronts; ++f) {
-    for (int64_t u = a.grp_U_ptr[f]; u < a.grp_U_ptr[f + 1]; ++u)
-      posmap[a.U[u]] = u - a.grp_U_ptr[f];
-    for (int64_t s = a.grp_slot_ptr[f]; s < a.grp_slot_ptr[f + 1]; ++s) {
-      int32_t r = a.slot_row[s];
+      a.U.insert(a.U.end(), pU.begin(), pU.end());
+      a.rp_row_ptr.push_back((int64_t)a.rp_rows.size());
+      a.rp_U_ptr.push_back((int64_t)a.U.size() - a.rp_U_base);
+      a.rp_val_off.push_back(a.rp_val_off.back() + nU * (int64_t)pRows.size());
+      ++panel;
+      pU.clear();
+      pRows.clear();
+      rows_in = 0;
+      sum = 0;
+    };
+    for (int64_t r = 0; r < m; ++r) {
+      int64_t len = 0, add = 0;
       for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
         int32_t ri = a.root_of_col[col[e]];
         if (ri < 0) continue;
-        a.rr_lpos.push_back((int32_t)posmap[ri]);
-        a.rr_src.push_back(e);
+        ++len;
+        if (mark[ri] != panel) ++add;
       }
-      a.slot_rr_ptr[s + 1] = (int64_t)a.rr_src.size();
+      if (len == 0) continue;
+      if (rows_in > 0) {
+        const int64_t newU = (int64_t)pU.size() + add;
+        const double dens = (double)(sum + len) / ((double)newU * (double)(rows_in + 1));
+        if (rows_in + 1 > o.max_group || dens < o.amalg_density) close_panel();
+      }
+      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        int32_t ri = a.root_of_col[col[e]];
+        if (ri >= 0 && mark[ri] != panel) {
+          mark[ri] = panel;
+          pU.push_back(ri);
+        }
+      }
+      pRows.push_back((int32_t)r);
+      ++rows_in;
+      sum += len;
     }
+    if (rows_in > 0) close_panel();
+    a.n_rp = panel;
   }
 
-  // ---- extend-add / selected-inversion tasks
+  // ---- update-panel descriptors: leaf fronts (weight -1), row panels
+  const int64_t leaf_panel_total = a.grp_panel_off[a.n_groups];
+  for (int64_t g = 0; g < a.n_groups; ++g) {
+    a.up_U_off.push_back(a.grp_U_ptr[g]);
+    a.up_Q_off.push_back(a.grp_panel_off[g]);
+    a.up_nU.push_back((int32_t)(a.grp_U_ptr[g + 1] - a.grp_U_ptr[g]));
+    a.up_k.push_back((int32_t)(a.grp_col_ptr[g + 1] - a.grp_col_ptr[g]));
+    a.up_w_off.push_back(-1);
+  }
+  for (int64_t p = 0; p < a.n_rp; ++p) {
+    a.up_U_off.push_back(a.rp_U_base + a.rp_U_ptr[p]);
+    a.up_Q_off.push_back(leaf_panel_total + a.rp_val_off[p]);
+    a.up_nU.push_back((int32_t)(a.rp_U_ptr[p + 1] - a.rp_U_ptr[p]));
+    a.up_k.push_back((int32_t)(a.rp_row_ptr[p + 1] - a.rp_row_ptr[p]));
+    a.up_w_off.push_back((int32_t)a.rp_row_ptr[p]);
+  }
+  a.n_up = a.n_groups + a.n_rp;
+
+  // ---- incidences on the 64 x 64 lower tiles of the root
+  if (a.n_pad) {
+    const int64_t T = a.n_pad / kTile;
+    a.n_tiles = T * (T + 1) / 2;
+    std::vector<int64_t> cnt(a.n_tiles + 1, 0);
+    std::vector<std::array<int32_t, 3>> runs;
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<int64_t> fillp;
+      if (pass == 1) {
+        a.inc_ptr.assign(a.n_tiles + 1, 0);
+        for (int64_t t = 0; t < a.n_tiles; ++t) a.inc_ptr[t + 1] = a.inc_ptr[t] + cnt[t];
+        a.inc.resize(4 * a.inc_ptr[a.n_tiles]);
+        fillp.assign(a.inc_ptr.begin(), a.inc_ptr.end() - 1);
+      }
+      for (int64_t u = 0; u < a.n_up; ++u) {
+        if (a.up_k[u] == 0) continue;
+        tile_runs(a.U.data() + a.up_U_off[u], a.up_nU[u], runs);
+        for (size_t x = 0; x < runs.size(); ++x)
+          for (size_t y = 0; y <= x; ++y) {
+            const int64_t I = runs[x][0], J = runs[y][0];
+            const int64_t t = I * (I + 1) / 2 + J;
+            if (pass == 0) {
+              cnt[t]++;
+            } else {
+              int32_t* p = a.inc.data() + 4 * fillp[t]++;
+              p[0] = (int32_t)u;
+              p[1] = runs[x][1];
+              p[2] = runs[y][1];
+              p[3] = (runs[x][2] - runs[x][1]) | ((runs[y][2] - runs[y][1]) << 16);
+            }
+          }
+      }
+    }
+    // tiles with the most work first
+    std::vector<double> tw(a.n_tiles, 0.0);
+    for (int64_t t = 0; t < a.n_tiles; ++t)
+      for (int64_t q = a.inc_ptr[t]; q < a.inc_ptr[t + 1]; ++q) {
+        const int32_t* p = a.inc.data() + 4 * q;
+        const int nI = p[3] & 0xffff, nJ = p[3] >> 16;
+        tw[t] += (double)((nI + 15) / 16) * ((nJ + 15) / 16) * (a.up_k[p[0]] + 3) / 4 + 1.0;
+      }
+    a.tile_order.resize(a.n_tiles);
+    std::iota(a.tile_order.begin(), a.tile_order.end(), 0);
+    std::stable_sort(a.tile_order.begin(), a.tile_order.end(),
+                     [&](int32_t x, int32_t y) { return tw[x] > tw[y]; });
+  }
+
+  // ---- selected-inversion tasks of the leaf fronts
   a.grp_task_ptr.push_back(0);
   a.task_part_off.push_back(0);
-  for (int64_t f = 0; f < a.n_fronts; ++f) {
+  for (int64_t f = 0; f < a.n_groups; ++f) {
     int64_t nU = a.grp_U_ptr[f + 1] - a.grp_U_ptr[f];
     int64_t p = a.grp_col_ptr[f + 1] - a.grp_col_ptr[f];
     int64_t nt = (nU + kET - 1) / kET;
@@ -286,8 +386,26 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
       }
     a.grp_task_ptr.push_back((int64_t)a.tasks.size() / 3);
   }
+  // launch order: by 2-D block of the root front at the task's first row /
+  // column, then by task index
+  {
+    constexpr int kOrderBlock = 2048;
+    const int64_t nt = (int64_t)a.tasks.size() / 3;
+    std::vector<int64_t> key(nt);
+    for (int64_t t = 0; t < nt; ++t) {
+      const int64_t f = a.tasks[3 * t], I = a.tasks[3 * t + 1],
+                    J = a.tasks[3 * t + 2];
+      const int32_t* Uf = a.U.data() + a.grp_U_ptr[f];
+      const int64_t bi = Uf[I * kET] / kOrderBlock, bj = Uf[J * kET] / kOrderBlock;
+      key[t] = (bj << 20) | bi;
+    }
+    a.sel_order.resize(nt);
+    std::iota(a.sel_order.begin(), a.sel_order.end(), 0);
+    std::stable_sort(a.sel_order.begin(), a.sel_order.end(),
+                     [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+  }
 
-  // ---- root incidences of the leaf panels
+  // ---- root incidences of the leaf panels (forward solve)
   a.rinc_ptr.assign(a.n_root + 1, 0);
   for (int64_t g = 0; g < a.n_groups; ++g)
     for (int64_t u = a.grp_U_ptr[g]; u < a.grp_U_ptr[g + 1]; ++u)
@@ -308,29 +426,28 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   // ---- counters: nnz(A) (both triangles), nnz(L) as stored, flops
   {
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    std::vector<int64_t> cnt(nth, 0);
+    std::vector<int64_t> c(nth, 0);
     std::vector<std::thread> th;
     for (unsigned t = 0; t < nth; ++t)
       th.emplace_back([&, t]() {
         std::vector<int64_t> st(n, -1);
-        int64_t c = 0;
+        int64_t s = 0;
         for (int64_t j = t; j < n; j += nth)
           for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
             int32_t r = a.csc_row[k];
             for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
               if (st[col[e]] != j) {
                 st[col[e]] = j;
-                ++c;
+                ++s;
               }
           }
-        cnt[t] = c;
+        c[t] = s;
       });
     for (auto& x : th) x.join();
-    a.nnz_a = std::accumulate(cnt.begin(), cnt.end(), (int64_t)0);
+    a.nnz_a = std::accumulate(c.begin(), c.end(), (int64_t)0);
   }
   double nR = (double)a.n_root;
-  a.nnz_l = n_leaf + a.grp_panel_off[a.n_fronts] +
-            a.n_root * (a.n_root + 1) / 2;
+  a.nnz_l = n_leaf + a.grp_panel_off[a.n_groups] + a.n_root * (a.n_root + 1) / 2;
   a.flops_factor = nR * nR * nR / 3.0;
   a.flops_selinv = 2.0 * nR * nR * nR / 3.0;
   for (int64_t g = 0; g < a.n_groups; ++g) {

@@ -112,9 +112,12 @@ void free_all(Handle& h) {
                   d.grp_panel_off, d.grp_slot_ptr, d.slot_row, d.slot_rr_ptr,
                   d.slot_leaf_src, d.rr_lpos, d.rr_src, d.root_cols, d.rinc_ptr,
                   d.rinc_grp, d.rinc_u, d.tasks, d.grp_task_ptr, d.task_part_off,
+                  d.sel_order, d.rp_rows, d.rp_rowbase, d.rpe_ptr, d.rpe_pos,
+                  d.rpe_src, d.up_U_off, d.up_Q_off, d.up_nU, d.up_k,
+                  d.up_w_off, d.tile_order, d.inc_ptr, d.inc, h.rpw,
                   h.val, h.w, h.sw, h.sleaf, h.rrval, h.panel, h.ldiag, h.S,
                   h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
-                  h.vx, h.vdd, h.vnorm};
+                  h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -131,6 +134,7 @@ void spi_default_opts(spi_opts* o) {
   o->leaf_max_work = 65536.0;
   o->amalg_density = 0.35;
   o->refine_steps = 2;
+  o->root_inverse = 1;
 }
 
 int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
@@ -182,18 +186,24 @@ int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
   UP(grp_panel_off); UP(grp_slot_ptr); UP(slot_row); UP(slot_rr_ptr);
   UP(slot_leaf_src); UP(rr_lpos); UP(rr_src); UP(root_cols); UP(rinc_ptr);
   UP(rinc_grp); UP(rinc_u); UP(tasks); UP(grp_task_ptr); UP(task_part_off);
+  UP(sel_order); UP(rp_rows); UP(rp_rowbase); UP(rpe_ptr); UP(rpe_pos);
+  UP(rpe_src); UP(up_U_off); UP(up_Q_off); UP(up_nU); UP(up_k); UP(up_w_off);
+  UP(tile_order); UP(inc_ptr); UP(inc);
 #undef UP
   const int64_t nl = (int64_t)a.leaf_cols.size();
   const int64_t np = a.n_pad;
 #define AL(ptr, cnt) \
   if (he == hipSuccess) he = dev_alloc(ptr, cnt)
-  AL(h.val, a.nnz); AL(h.w, a.m); AL(h.sw, a.m); AL(h.sleaf, a.m);
+  AL(h.val, a.nnz); AL(h.w, a.m); AL(h.sw, a.n_slots);
+  AL(h.sleaf, a.n_slots); AL(h.rpw, (int64_t)a.rp_rows.size());
   AL(h.rrval, (int64_t)a.rr_src.size());
-  AL(h.panel, a.grp_panel_off.back()); AL(h.ldiag, nl);
+  AL(h.panel, a.grp_panel_off.back() + a.rp_val_off.back());
+  AL(h.ldiag, nl);
   AL(h.S, np * np); AL(h.W, np * np); AL(h.Z, np * np);
   AL(h.invd, np * kNB); AL(h.part, a.task_part_off.back());
   AL(h.flag, 1); AL(h.vleaf, nl); AL(h.vroot, np); AL(h.vres, a.n);
   AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 2);
+  AL(h.vroot2, np); AL(h.vpart, root_inv_part_size(np));
 #undef AL
   if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
   if (he != hipSuccess) {
@@ -217,8 +227,10 @@ int spi_set_values(spi_handle* H, const double* val, const double* w) {
   SPI_CK(hipMemcpyAsync(h.w, w, h.an.m * sizeof(double),
                         hipMemcpyDeviceToDevice, h.stream), "copy weights");
   SPI_CK(launch_gather_values(h), "gather values");
+  SPI_CK(launch_fill_rowpanels(h), "row panels");
   h.have_values = true;
   h.have_factor = false;
+  h.have_inv = false;
   return SPI_OK;
 }
 
@@ -228,6 +240,7 @@ int spi_factor(spi_handle* H) {
   if (!h.have_values)
     return fail(h, SPI_E_STATE, hipSuccess, "spi_factor before spi_set_values");
   h.have_factor = false;
+  h.have_inv = false;
   h.failed_col = -1;
   SPI_CK(hipMemsetAsync(h.flag, 0xff, sizeof(int64_t), h.stream), "flag");
   phase_begin(h, kPhLeaf);
@@ -235,12 +248,16 @@ int spi_factor(spi_handle* H) {
   phase_end(h, kPhLeaf);
   if (h.an.n_pad) {
     phase_begin(h, kPhExtend);
-    SPI_CK(launch_root_fill(h), "root fill");
-    SPI_CK(launch_extend_add(h), "extend-add");
+    SPI_CK(launch_assemble_root(h), "root assembly");
     phase_end(h, kPhExtend);
     phase_begin(h, kPhPotrf);
     SPI_CK(root_potrf(h), "root factorisation");
     phase_end(h, kPhPotrf);
+    if (h.opts.root_inverse) {
+      phase_begin(h, kPhTrtri);
+      SPI_CK(root_trtri(h), "root factor inversion");
+      phase_end(h, kPhTrtri);
+    }
   }
   uint64_t f = 0;
   SPI_CK(hipMemcpyAsync(&f, h.flag, sizeof(f), hipMemcpyDeviceToHost, h.stream),
@@ -258,6 +275,7 @@ int spi_factor(spi_handle* H) {
     return SPI_E_NOT_SPD;
   }
   h.have_factor = true;
+  h.have_inv = h.an.n_pad > 0 && h.opts.root_inverse;
   return SPI_OK;
 }
 
@@ -303,9 +321,12 @@ int spi_diag_inv(spi_handle* H, double* d) {
   if (!h.have_factor)
     return fail(h, SPI_E_STATE, hipSuccess, "spi_diag_inv without a valid factor");
   if (h.an.n_pad) {
-    phase_begin(h, kPhTrtri);
-    SPI_CK(root_trtri(h), "root factor inversion");
-    phase_end(h, kPhTrtri);
+    if (!h.have_inv) {
+      phase_begin(h, kPhTrtri);
+      SPI_CK(root_trtri(h), "root factor inversion");
+      phase_end(h, kPhTrtri);
+      h.have_inv = true;
+    }
     phase_begin(h, kPhLauum);
     SPI_CK(root_lauum(h), "root inverse product");
     phase_end(h, kPhLauum);

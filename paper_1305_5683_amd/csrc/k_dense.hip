@@ -19,310 +19,146 @@ namespace spi {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// ----------------------------------------------------------------- GEMM
-// C[i, j] = beta * C[i, j] + alpha * sum_k opA(i, k) * opB(k, j)
-// Operand access:
-//   A, kXC: A(i, k) = A[i + k * lda]   (i contiguous)
-//   A, kKC: A(i, k) = A[k + i * lda]   (k contiguous)
-//   B, kXC: B(k, j) = B[j + k * ldb]   (j contiguous)
-//   B, kKC: B(k, j) = B[k + j * ldb]   (k contiguous)
-// Tiles are BM x BN, 256 threads = 4 waves in a 2 x 2 grid, each wave owns a
-// (BM/2) x (BN/2) block of 16 x 16 MFMA accumulators.  K advances in slabs
-// of kKT = 16 staged through LDS (register prefetch of the next slab).
-// `lower`: only tiles with I >= J are enumerated (square tiles) and the
-// diagonal tiles write their lower triangle only.  `kstart_diag`: the K
-// range of tile (I, J) starts at I * BM (products with a lower-triangular
-// left factor whose upper part is stored as zeros).
-constexpr int kKT = 16;
-
-struct GemmArgs {
-  const double* A;
-  const double* B;
-  double* C;
-  int64_t lda, ldb, ldc;
-  int M, N, K;
-  double alpha, beta;
-  int lower, kstart_diag;
-  int tiles_m, tiles_n, n_tiles;
-};
-
-__device__ inline void tile_of(const GemmArgs& g, int t, int& I, int& J) {
-  if (g.lower) {
-    // t = I (I + 1) / 2 + J, J <= I
-    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    while (i * (i + 1) / 2 > t) --i;
-    I = i;
-    J = t - i * (i + 1) / 2;
-  } else {
-    I = t % g.tiles_m;
-    J = t / g.tiles_m;
-  }
-}
-
-// Map the hardware workgroup index to a logical tile so that consecutive
-// logical tiles (which share operand panels) run on the same XCD, whose L2
-// they then share.  Workgroups are dispatched round-robin over 8 XCDs.
-__device__ inline int xcd_remap(int w, int n) {
-  const int nx = 8;
-  int per = n / nx, rem = n % nx;
-  int x = w % nx, local = w / nx;
-  return x * per + min(x, rem) + local;
-}
-
-template <int BM, int BN, int OPA, int OPB>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  constexpr int WM = BM / 2, WN = BN / 2;
-  constexpr int MI = WM / 16, NI = WN / 16;
-  // LDS layouts: kXC operands as [k][x], kKC operands as [x][k] (+1 pad)
-  constexpr int A_SZ = (OPA == kXC) ? kKT * BM : BM * (kKT + 1);
-  constexpr int B_SZ = (OPB == kXC) ? kKT * BN : BN * (kKT + 1);
-  __shared__ double As[A_SZ];
-  __shared__ double Bs[B_SZ];
-
-  const int wg = xcd_remap(blockIdx.x, g.n_tiles);
-  int I, J;
-  tile_of(g, wg, I, J);
-  const int i0 = I * BM, j0 = J * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  int kbeg = g.kstart_diag ? i0 : 0;
-  const int kend = g.K;
-
-  // global -> register staging: each thread moves EA (EB) doubles per slab
-  constexpr int EA = BM * kKT / 256, EB = BN * kKT / 256;
-  double ra[EA], rb[EB];
-
-  auto load_a = [&](int k0) {
-    if (OPA == kXC) {  // rows of the slab: kKT rows of BM contiguous doubles
-      constexpr int TPR = BM / EA;  // threads per k-row
-      int kk = tid / TPR, x = (tid % TPR) * EA;
-      const double* p = g.A + (int64_t)(i0 + x) + (int64_t)(k0 + kk) * g.lda;
-#pragma unroll
-      for (int e = 0; e < EA; e += 2) {
-        double2 v = *reinterpret_cast<const double2*>(p + e);
-        ra[e] = v.x;
-        ra[e + 1] = v.y;
-      }
-    } else {  // for each x: kKT contiguous k
-      constexpr int TPX = kKT / EA;  // threads per x
-      int x = tid / TPX, kk = (tid % TPX) * EA;
-      const double* p = g.A + (int64_t)(k0 + kk) + (int64_t)(i0 + x) * g.lda;
-#pragma unroll
-      for (int e = 0; e < EA; e += 2) {
-        double2 v = *reinterpret_cast<const double2*>(p + e);
-        ra[e] = v.x;
-        ra[e + 1] = v.y;
-      }
-    }
-  };
-  auto store_a = [&]() {
-    if (OPA == kXC) {
-      constexpr int TPR = BM / EA;
-      int kk = tid / TPR, x = (tid % TPR) * EA;
-#pragma unroll
-      for (int e = 0; e < EA; ++e) As[kk * BM + x + e] = ra[e];
-    } else {
-      constexpr int TPX = kKT / EA;
-      int x = tid / TPX, kk = (tid % TPX) * EA;
-#pragma unroll
-      for (int e = 0; e < EA; ++e) As[x * (kKT + 1) + kk + e] = ra[e];
-    }
-  };
-  auto load_b = [&](int k0) {
-    if (OPB == kXC) {
-      constexpr int TPR = BN / EB;
-      int kk = tid / TPR, x = (tid % TPR) * EB;
-      const double* p = g.B + (int64_t)(j0 + x) + (int64_t)(k0 + kk) * g.ldb;
-#pragma unroll
-      for (int e = 0; e < EB; e += 2) {
-        double2 v = *reinterpret_cast<const double2*>(p + e);
-        rb[e] = v.x;
-        rb[e + 1] = v.y;
-      }
-    } else {
-      constexpr int TPX = kKT / EB;
-      int x = tid / TPX, kk = (tid % TPX) * EB;
-      const double* p = g.B + (int64_t)(k0 + kk) + (int64_t)(j0 + x) * g.ldb;
-#pragma unroll
-      for (int e = 0; e < EB; e += 2) {
-        double2 v = *reinterpret_cast<const double2*>(p + e);
-        rb[e] = v.x;
-        rb[e + 1] = v.y;
-      }
-    }
-  };
-  auto store_b = [&]() {
-    if (OPB == kXC) {
-      constexpr int TPR = BN / EB;
-      int kk = tid / TPR, x = (tid % TPR) * EB;
-#pragma unroll
-      for (int e = 0; e < EB; ++e) Bs[kk * BN + x + e] = rb[e];
-    } else {
-      constexpr int TPX = kKT / EB;
-      int x = tid / TPX, kk = (tid % TPX) * EB;
-#pragma unroll
-      for (int e = 0; e < EB; ++e) Bs[x * (kKT + 1) + kk + e] = rb[e];
-    }
-  };
-  auto frag_a = [&](int kk, int x) -> double {  // A(x, kk), x tile-local
-    return (OPA == kXC) ? As[kk * BM + x] : As[x * (kKT + 1) + kk];
-  };
-  auto frag_b = [&](int kk, int x) -> double {  // B(kk, x)
-    return (OPB == kXC) ? Bs[kk * BN + x] : Bs[x * (kKT + 1) + kk];
-  };
-
-  v4d acc[MI][NI];
-#pragma unroll
-  for (int a = 0; a < MI; ++a)
-#pragma unroll
-    for (int b = 0; b < NI; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-
-  if (kbeg < kend) {
-    load_a(kbeg);
-    load_b(kbeg);
-  }
-  for (int k0 = kbeg; k0 < kend; k0 += kKT) {
-    __syncthreads();
-    store_a();
-    store_b();
-    __syncthreads();
-    if (k0 + kKT < kend) {
-      load_a(k0 + kKT);
-      load_b(k0 + kKT);
-    }
-    const int lx = lane & 15, lk = lane >> 4;
-#pragma unroll
-    for (int ks = 0; ks < kKT; ks += 4) {
-      double fa[MI], fb[NI];
-#pragma unroll
-      for (int a = 0; a < MI; ++a) fa[a] = frag_a(ks + lk, wm * WM + a * 16 + lx);
-#pragma unroll
-      for (int b = 0; b < NI; ++b) fb[b] = frag_b(ks + lk, wn * WN + b * 16 + lx);
-      // D = Bfrag^T * Afrag.  The 16x16 result D[r][c] sits in lane
-      // c + 16 * (r % 4), item r / 4; with the operands swapped, lane
-      // (lx, lk) item v holds output row i = lx and column j = 4 * v + lk,
-      // which keeps the stores of a column-major C contiguous over 16 rows.
-#pragma unroll
-      for (int a = 0; a < MI; ++a)
-#pragma unroll
-        for (int b = 0; b < NI; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[b], fa[a],
-                                                           acc[a][b], 0, 0, 0);
-    }
-  }
-
-  // epilogue
-  const int lx = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int a = 0; a < MI; ++a)
-#pragma unroll
-    for (int b = 0; b < NI; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        int i = i0 + wm * WM + a * 16 + lx;
-        int j = j0 + wn * WN + b * 16 + v * 4 + lk;
-        if (g.lower && I == J && i < j) continue;
-        double* c = g.C + (int64_t)i + (int64_t)j * g.ldc;
-        double r = g.alpha * acc[a][b][v];
-        if (g.beta != 0.0) r += g.beta * (*c);
-        *c = r;
-      }
-}
-
-template <int BM, int BN, int OPA, int OPB>
-static hipError_t gemm_t(hipStream_t s, const GemmArgs& a0) {
-  GemmArgs a = a0;
-  a.tiles_m = a.M / BM;
-  a.tiles_n = a.N / BN;
-  a.n_tiles = a.lower ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n;
-  if (a.n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm<BM, BN, OPA, OPB>), dim3(a.n_tiles), dim3(256), 0,
-                     s, a);
-  return hipGetLastError();
-}
-
-hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
-                const double* A, int64_t lda, const double* B, int64_t ldb,
-                double* C, int64_t ldc, int M, int N, int K, double alpha,
-                double beta, bool lower, bool kstart_diag) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  if (M % bm || N % bn || K % kKT || (lower && (bm != bn || M != N)))
-    return hipErrorInvalidValue;
-  GemmArgs a{A, B, C, lda, ldb, ldc, M, N, K, alpha, beta, lower ? 1 : 0,
-             kstart_diag ? 1 : 0, 0, 0, 0};
-#define SPI_GEMM_CASE(BM_, BN_, OA, OB)                                   \
-  if (bm == BM_ && bn == BN_ && opA == OA && opB == OB)                  \
-    return gemm_t<BM_, BN_, OA, OB>(s, a);
-#define SPI_GEMM_OPS(BM_, BN_)          \
-  SPI_GEMM_CASE(BM_, BN_, kXC, kXC)     \
-  SPI_GEMM_CASE(BM_, BN_, kXC, kKC)     \
-  SPI_GEMM_CASE(BM_, BN_, kKC, kKC)
-  SPI_GEMM_OPS(128, 128)
-  SPI_GEMM_OPS(128, 64)
-  SPI_GEMM_OPS(64, 128)
-  SPI_GEMM_OPS(64, 64)
-#undef SPI_GEMM_OPS
-#undef SPI_GEMM_CASE
-  return hipErrorInvalidValue;
-}
-
 // ------------------------------------------------ diagonal block kernels
-// Cholesky of the kNB x kNB diagonal block at (k0, k0) in LDS, then its
-// triangular inverse.  Writes L back (lower triangle incl. diagonal) and the
-// inverse, column-major with explicit zeros above the diagonal, to `inv`.
-// A pivot that is not positive and finite records its elimination index
-// (base + k0 + k) with atomicMin in `fail` and continues with pivot 1.
+// Cholesky of the kNB x kNB diagonal block at (k0, k0), right-looking, one
+// column per step.  Thread (ti, tg) keeps row ti, columns j = tg + 4q, in
+// registers; the current column is exchanged through LDS (double-buffered
+// by step parity, so one barrier per step).  Writes L back (lower triangle
+// incl. diagonal).  A pivot that is not positive and finite records its
+// elimination index (base + k0 + k) with atomicMin in `fail` and continues
+// with pivot 1.
 __global__ __launch_bounds__(256) void k_potrf_diag(double* S, int64_t ld,
-                                                    int k0, double* inv,
-                                                    int64_t* fail,
+                                                    int k0, int64_t* fail,
                                                     int64_t base) {
-  __shared__ double T[kNB][kNB + 1];
-  __shared__ double X[kNB][kNB + 1];
+  constexpr int Q = kNB / 4;
+  __shared__ double colk[2][kNB];
+  const int t = threadIdx.x, ti = t % kNB, tg = t / kNB;
+  double r[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int j = tg + 4 * q;
+    r[q] = (ti >= j) ? S[(int64_t)(k0 + ti) + (int64_t)(k0 + j) * ld] : 0.0;
+  }
+  for (int k = 0; k < kNB; ++k) {
+    const int par = k & 1;
+    if (tg == (k & 3)) {  // owner of column k publishes it (updated values)
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (q == (k >> 2)) colk[par][ti] = r[q];
+    }
+    __syncthreads();
+    const double d = colk[par][k];
+    const bool bad = !(d > 0.0) || !isfinite(d);
+    const double lkk = bad ? 1.0 : sqrt(d);
+    const double rk = 1.0 / lkk;
+    const double lik = colk[par][ti] * rk;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int j = tg + 4 * q;
+      if (j > k && j <= ti) r[q] -= lik * (colk[par][j] * rk);
+      if (j == k) {
+        if (ti == k) r[q] = lkk;
+        else if (ti > k) r[q] = lik;
+      }
+    }
+    if (t == 0 && bad)
+      atomicMin((unsigned long long*)fail, (unsigned long long)(base + k0 + k));
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int j = tg + 4 * q;
+    if (ti >= j) S[(int64_t)(k0 + ti) + (int64_t)(k0 + j) * ld] = r[q];
+  }
+}
+
+// Panel solve P := P L_kk^-T for the rows below the diagonal block.  Four
+// threads per row (adjacent lanes): thread g keeps the row's columns
+// c = g + 4q in registers; at step c the owner divides by L_cc and the four
+// lanes exchange x_c by shuffle, then update their later columns.
+__global__ __launch_bounds__(256) void k_trsm_panel(double* S, int64_t ld,
+                                                    int k0, int rows) {
+  constexpr int Q = kNB / 4;
+  __shared__ double L[kNB][kNB + 1];
+  __shared__ double rdiag[kNB];
   const int t = threadIdx.x;
   for (int e = t; e < kNB * kNB; e += 256) {
     int i = e % kNB, j = e / kNB;
-    T[i][j] = (i >= j) ? S[(int64_t)(k0 + i) + (int64_t)(k0 + j) * ld] : 0.0;
+    L[i][j] = S[(int64_t)(k0 + i) + (int64_t)(k0 + j) * ld];
+  }
+  __syncthreads();
+  if (t < kNB) rdiag[t] = 1.0 / L[t][t];
+  __syncthreads();
+  const int g = t & 3;
+  const int r = blockIdx.x * 64 + (t >> 2);
+  const bool live = r < rows;
+  double* P = S + (int64_t)(k0 + kNB + (live ? r : 0)) + (int64_t)k0 * ld;
+  double x[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) x[q] = live ? P[(int64_t)(g + 4 * q) * ld] : 0.0;
+#pragma unroll
+  for (int c = 0; c < kNB; ++c) {
+    const int owner = c & 3, qc = c >> 2;
+    double xc = 0.0;
+    if (g == owner) {
+      x[qc] *= rdiag[c];
+      xc = x[qc];
+    }
+    xc = __shfl(xc, (threadIdx.x & ~3) + owner, 64);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int cq = g + 4 * q;
+      if (cq > c) x[q] -= L[cq][c] * xc;
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) P[(int64_t)(g + 4 * q) * ld] = x[q];
+  }
+}
+
+// Inverses of all kNB x kNB diagonal blocks of the factor, one block per
+// workgroup: X = L_kk^-1 by right-looking elimination on the identity,
+// stored column-major with explicit zeros above the diagonal.
+__global__ __launch_bounds__(256) void k_invert_diag_blocks(const double* S,
+                                                            int64_t ld,
+                                                            double* invd) {
+  __shared__ double L[kNB][kNB + 1];
+  __shared__ double X[kNB][kNB + 1];
+  const int k0 = blockIdx.x * kNB;
+  const int t = threadIdx.x, ti = t % kNB, tg = t / kNB;
+  for (int j = tg; j < kNB; j += 4) {
+    L[ti][j] = (ti >= j) ? S[(int64_t)(k0 + ti) + (int64_t)(k0 + j) * ld] : 0.0;
+    X[ti][j] = (ti == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   for (int k = 0; k < kNB; ++k) {
-    double d = T[k][k];
-    bool bad = !(d > 0.0) || !isfinite(d);
-    double lkk = bad ? 1.0 : sqrt(d);
-    __syncthreads();
-    if (t == 0) {
-      if (bad) atomicMin((unsigned long long*)fail,
-                         (unsigned long long)(base + k0 + k));
-      T[k][k] = lkk;
-    }
-    if (t > k && t < kNB) T[t][k] /= lkk;
-    __syncthreads();
-    const int nt = kNB - 1 - k;
-    for (int e = t; e < nt * nt; e += 256) {
-      int i = k + 1 + e % nt, j = k + 1 + e / nt;
-      if (i >= j) T[i][j] -= T[i][k] * T[j][k];
+    // row k of X is final after dividing by L_kk; rows below eliminate it
+    const double rk = 1.0 / L[k][k];
+    double xk[kNB / 4];
+#pragma unroll
+    for (int q = 0; q < kNB / 4; ++q) {
+      int j = tg + 4 * q;
+      xk[q] = (j <= k) ? X[k][j] * rk : 0.0;
     }
     __syncthreads();
-  }
-  // X = T^-1 row by row: X[i][j] = (delta_ij - sum_{j<=q<i} T[i][q] X[q][j]) / T[i][i]
-  for (int i = 0; i < kNB; ++i) {
-    if (t < kNB) {
-      int j = t;
-      double v = 0.0;
-      if (j <= i) {
-        double s = (i == j) ? 1.0 : 0.0;
-        for (int q = j; q < i; ++q) s -= T[i][q] * X[q][j];
-        v = s / T[i][i];
+    if (ti == k) {
+#pragma unroll
+      for (int q = 0; q < kNB / 4; ++q) {
+        int j = tg + 4 * q;
+        if (j <= k) X[k][j] = xk[q];
       }
-      X[i][j] = v;
+    } else if (ti > k) {
+      const double lik = L[ti][k];
+#pragma unroll
+      for (int q = 0; q < kNB / 4; ++q) {
+        int j = tg + 4 * q;
+        if (j <= k) X[ti][j] -= lik * xk[q];
+      }
     }
     __syncthreads();
   }
-  for (int e = t; e < kNB * kNB; e += 256) {
-    int i = e % kNB, j = e / kNB;
-    if (i >= j) S[(int64_t)(k0 + i) + (int64_t)(k0 + j) * ld] = T[i][j];
-    inv[i + j * kNB] = X[i][j];
-  }
+  double* out = invd + (int64_t)blockIdx.x * kNB * kNB;
+  for (int j = tg; j < kNB; j += 4) out[ti + j * kNB] = (ti >= j) ? X[ti][j] : 0.0;
 }
 
 // Copy a kNB x kNB column-major block (with its zeros) into a matrix.
@@ -368,32 +204,33 @@ hipError_t launch_root_fill(Handle& h) {
 
 static int pick_bm(int M) { return (M % 128 == 0) ? 128 : 64; }
 
-// Right-looking blocked Cholesky of the root front, block kNB.
+// Right-looking blocked Cholesky of the root front, block kNB, then the
+// inverses of all its diagonal blocks (used by the factor inversion).
 hipError_t root_potrf(Handle& h) {
   const int np = (int)h.an.n_pad;
   const int64_t ld = np;
   hipError_t e = hipSuccess;
   const int64_t base = (int64_t)h.an.leaf_cols.size();
   for (int k0 = 0; k0 < np; k0 += kNB) {
-    double* inv = h.invd + (int64_t)(k0 / kNB) * kNB * kNB;
     hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, h.stream, h.S, ld,
-                       k0, inv, h.flag, base);
+                       k0, h.flag, base);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int rest = np - k0 - kNB;
     if (rest <= 0) break;
-    double* P = h.S + (int64_t)(k0 + kNB) + (int64_t)k0 * ld;
-    // panel: P := P * inv^T  (each tile owns whole rows of the panel)
-    e = gemm(h.stream, pick_bm(rest), 64, kXC, kXC, P, ld, inv, kNB, P, ld,
-             rest, kNB, kNB, 1.0, 0.0, false, false);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_trsm_panel, dim3((rest + 63) / 64), dim3(256), 0,
+                       h.stream, h.S, ld, k0, rest);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     // trailing update, lower triangle: S22 -= P P^T
+    double* P = h.S + (int64_t)(k0 + kNB) + (int64_t)k0 * ld;
     double* C = h.S + (int64_t)(k0 + kNB) * (ld + 1);
     int t = (rest % 128 == 0) ? 128 : 64;
     e = gemm(h.stream, t, t, kXC, kXC, P, ld, P, ld, C, ld, rest, rest, kNB,
              -1.0, 1.0, true, false);
     if (e != hipSuccess) return e;
   }
-  return e;
+  hipLaunchKernelGGL(k_invert_diag_blocks, dim3(np / kNB), dim3(256), 0,
+                     h.stream, h.S, ld, h.invd);
+  return hipGetLastError();
 }
 
 // Inverse of the root factor (W = L^-1, in place on a copy of L) followed
@@ -535,6 +372,76 @@ __global__ __launch_bounds__(256) void k_gemv_t(const double* L, int64_t ld,
   for (int j = c0 + lane; j < c1; j += 64) s += L[(int64_t)j + (int64_t)i * ld] * z[j];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) z[i] -= s;
+}
+
+// ------------------------------------- solves with the inverse root factor
+// With W = L^-1 available (lower triangular, zeros stored above the
+// diagonal) the two root substitutions are the products z = W v and
+// x = W^T z, read once from HBM at full width instead of a serial sweep.
+constexpr int kMvChunk = 512;
+
+// part[C][r] = sum_{j in chunk C} W[r, j] v[j] for the 64 rows of block I
+__global__ __launch_bounds__(256) void k_trmv_lower_part(const double* __restrict__ W,
+                                                         int64_t ld,
+                                                         const double* __restrict__ v,
+                                                         double* __restrict__ part,
+                                                         int np) {
+  __shared__ double red[4][kNB];
+  const int I = blockIdx.x, C = blockIdx.y;
+  const int c0 = C * kMvChunk;
+  if (c0 > I * kNB + kNB - 1) return;  // chunk entirely above the diagonal
+  const int t = threadIdx.x, i = t % kNB, g = t / kNB;
+  const int r = I * kNB + i;
+  const int c1 = min(np, c0 + kMvChunk);
+  double s = 0.0;
+  for (int j = c0 + g; j < c1; j += 4) s += W[(int64_t)r + (int64_t)j * ld] * v[j];
+  red[g][i] = s;
+  __syncthreads();
+  if (t < kNB)
+    part[(int64_t)C * np + I * kNB + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+}
+
+__global__ void k_trmv_lower_reduce(const double* __restrict__ part,
+                                    double* __restrict__ z, int np) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np;
+       r += gridDim.x * blockDim.x) {
+    const int last = (r / kNB * kNB + kNB - 1) / kMvChunk;
+    double s = 0.0;
+    for (int C = 0; C <= last; ++C) s += part[(int64_t)C * np + r];
+    z[r] = s;
+  }
+}
+
+// x[j] = sum_{i >= j} W[i, j] z[i]: one wave per column.
+__global__ __launch_bounds__(256) void k_trmv_upper_t(const double* __restrict__ W,
+                                                      int64_t ld,
+                                                      const double* __restrict__ z,
+                                                      double* __restrict__ x, int np) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= np) return;
+  const double* col = W + (int64_t)j * ld;
+  double s = 0.0;
+  for (int i = j + lane; i < np; i += 64) s += col[i] * z[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) x[j] = s;
+}
+
+// z (in/out, length n_pad): z := W^T (W z), using tmp (n_pad) and part.
+hipError_t root_inv_apply(Handle& h, double* z, double* tmp) {
+  const int np = (int)h.an.n_pad;
+  const int nch = (np + kMvChunk - 1) / kMvChunk;
+  hipLaunchKernelGGL(k_trmv_lower_part, dim3(np / kNB, nch), dim3(256), 0,
+                     h.stream, h.W, (int64_t)np, z, h.vpart, np);
+  hipLaunchKernelGGL(k_trmv_lower_reduce, dim3((np + 255) / 256), dim3(256), 0,
+                     h.stream, h.vpart, tmp, np);
+  hipLaunchKernelGGL(k_trmv_upper_t, dim3((np + 3) / 4), dim3(256), 0, h.stream,
+                     h.W, (int64_t)np, tmp, z, np);
+  return hipGetLastError();
+}
+
+int64_t root_inv_part_size(int64_t np) {
+  return ((np + kMvChunk - 1) / kMvChunk) * np;
 }
 
 hipError_t root_trsv_fwd(Handle& h, double* z) {

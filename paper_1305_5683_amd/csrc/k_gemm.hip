@@ -1,0 +1,256 @@
+// Tiled FP64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// The bulk of the root front's Cholesky factorisation, of the inversion of
+// its factor and of the product giving the root block of A^-1 are dense
+// contractions; they all go through this one kernel.
+//
+// C[i, j] = beta * C[i, j] + alpha * sum_k opA(i, k) * opB(k, j)
+// Operand access:
+//   A, kXC: A(i, k) = A[i + k * lda]   (i contiguous)
+//   A, kKC: A(i, k) = A[k + i * lda]   (k contiguous)
+//   B, kXC: B(k, j) = B[j + k * ldb]   (j contiguous)
+//   B, kKC: B(k, j) = B[k + j * ldb]   (k contiguous)
+// Tiles are BM x BN, 256 threads = 4 waves in a 2 x 2 grid; each wave owns
+// a (BM/2) x (BN/2) block of 16 x 16 accumulators.  K advances in slabs of
+// kKT = 32, staged through LDS with a register prefetch of the next slab.
+// `lower`: only tiles with I >= J are enumerated (square tiles) and the
+// diagonal tiles write their lower triangle only.  `kstart_diag`: the K
+// range of tile (I, J) starts at I * BM (products whose left factor is lower
+// triangular with zeros stored above the diagonal).
+#include <hip/hip_runtime.h>
+
+#include "spi_internal.h"
+
+namespace spi {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kKT = 32;
+constexpr int kGroup = 8;      // tile rows per group of the launch order
+// LDS row strides (doubles): kXC slabs [k][x] padded by 16 so the four
+// 16-lane groups of a fragment read fall in different bank halves; kKC
+// slabs [x][k] with stride kKT + 2 (16 bytes mod 256) so the 32 lanes of a
+// half-wave read distinct banks.
+constexpr int kPadXC = 16;
+constexpr int kStrKC = kKT + 2;
+
+struct GemmArgs {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t lda, ldb, ldc;
+  int M, N, K;
+  double alpha, beta;
+  int lower, kstart_diag;
+  int tiles_m, tiles_n, n_tiles;
+};
+
+// Logical tile t -> (I, J).  Tiles are visited in groups of kGroup tile
+// rows, column by column inside a group, so that the tiles running together
+// share kGroup row panels of A and one column panel of B.
+__device__ inline void tile_of(const GemmArgs& g, int t, int& I, int& J) {
+  const int G = kGroup;
+  if (!g.lower) {
+    const int grp = t / (G * g.tiles_n);
+    const int local = t - grp * G * g.tiles_n;
+    const int gs = min(G, g.tiles_m - grp * G);
+    I = grp * G + local % gs;
+    J = local / gs;
+    return;
+  }
+  // lower triangle: group grp holds rows [grp*G, grp*G + gs); columns
+  // J < grp*G have gs tiles each, the diagonal block a triangle.
+  int grp = 0, base = 0;
+  for (;;) {
+    const int gs = min(G, g.tiles_m - grp * G);
+    const int cnt = grp * G * gs + gs * (gs + 1) / 2;
+    if (t < base + cnt) break;
+    base += cnt;
+    ++grp;
+  }
+  const int gs = min(G, g.tiles_m - grp * G);
+  int local = t - base;
+  if (local < grp * G * gs) {
+    J = local / gs;
+    I = grp * G + local % gs;
+    return;
+  }
+  local -= grp * G * gs;
+  int d = 0;
+  while (local >= gs - d) {
+    local -= gs - d;
+    ++d;
+  }
+  J = grp * G + d;
+  I = J + local;
+}
+
+// Map the hardware workgroup index to a logical tile so that consecutive
+// logical tiles (which share operand panels) run on the same XCD, whose L2
+// they then share.  Workgroups are dispatched round-robin over 8 XCDs.
+__device__ inline int xcd_remap(int w, int n) {
+  const int nx = 8;
+  int per = n / nx, rem = n % nx;
+  int x = w % nx, local = w / nx;
+  return x * per + min(x, rem) + local;
+}
+
+template <int BM, int BN, int OPA, int OPB>
+__global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int MI = WM / 16, NI = WN / 16;
+  constexpr int A_SZ = (OPA == kXC) ? kKT * (BM + kPadXC) : BM * kStrKC;
+  constexpr int B_SZ = (OPB == kXC) ? kKT * (BN + kPadXC) : BN * kStrKC;
+  __shared__ double As[A_SZ];
+  __shared__ double Bs[B_SZ];
+
+  int I, J;
+  tile_of(g, xcd_remap(blockIdx.x, g.n_tiles), I, J);
+  const int i0 = I * BM, j0 = J * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int kbeg = g.kstart_diag ? i0 : 0;
+  const int kend = g.K;
+
+  // global -> register staging: each thread moves EA (EB) doubles per slab
+  constexpr int EA = BM * kKT / 256, EB = BN * kKT / 256;
+  double ra[EA], rb[EB];
+
+  auto load = [&](const double* base, int64_t ld, int x0, int k0, int op,
+                  int X, int E, double* r) {
+    if (op == kXC) {  // kKT rows of X contiguous doubles
+      const int tpr = X / E;
+      const int kk = tid / tpr, x = (tid % tpr) * E;
+      const double* p = base + (int64_t)(x0 + x) + (int64_t)(k0 + kk) * ld;
+#pragma unroll
+      for (int e = 0; e < E; e += 2) {
+        double2 v = *reinterpret_cast<const double2*>(p + e);
+        r[e] = v.x;
+        r[e + 1] = v.y;
+      }
+    } else {  // for each x: kKT contiguous k
+      const int tpx = kKT / E;
+      const int x = tid / tpx, kk = (tid % tpx) * E;
+      const double* p = base + (int64_t)(k0 + kk) + (int64_t)(x0 + x) * ld;
+#pragma unroll
+      for (int e = 0; e < E; e += 2) {
+        double2 v = *reinterpret_cast<const double2*>(p + e);
+        r[e] = v.x;
+        r[e + 1] = v.y;
+      }
+    }
+  };
+  auto store = [&](double* L, int op, int X, int E, const double* r) {
+    if (op == kXC) {
+      const int tpr = X / E;
+      const int kk = tid / tpr, x = (tid % tpr) * E;
+#pragma unroll
+      for (int e = 0; e < E; ++e) L[kk * (X + kPadXC) + x + e] = r[e];
+    } else {
+      const int tpx = kKT / E;
+      const int x = tid / tpx, kk = (tid % tpx) * E;
+#pragma unroll
+      for (int e = 0; e < E; ++e) L[x * kStrKC + kk + e] = r[e];
+    }
+  };
+
+  v4d acc[MI][NI];
+#pragma unroll
+  for (int a = 0; a < MI; ++a)
+#pragma unroll
+    for (int b = 0; b < NI; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  if (kbeg < kend) {
+    load(g.A, g.lda, i0, kbeg, OPA, BM, EA, ra);
+    load(g.B, g.ldb, j0, kbeg, OPB, BN, EB, rb);
+  }
+  const int lx = lane & 15, lk = lane >> 4;
+  for (int k0 = kbeg; k0 < kend; k0 += kKT) {
+    __syncthreads();
+    store(As, OPA, BM, EA, ra);
+    store(Bs, OPB, BN, EB, rb);
+    __syncthreads();
+    if (k0 + kKT < kend) {
+      load(g.A, g.lda, i0, k0 + kKT, OPA, BM, EA, ra);
+      load(g.B, g.ldb, j0, k0 + kKT, OPB, BN, EB, rb);
+    }
+#pragma unroll
+    for (int ks = 0; ks < kKT; ks += 4) {
+      double fa[MI], fb[NI];
+#pragma unroll
+      for (int a = 0; a < MI; ++a) {
+        const int x = wm * WM + a * 16 + lx, kk = ks + lk;
+        fa[a] = (OPA == kXC) ? As[kk * (BM + kPadXC) + x] : As[x * kStrKC + kk];
+      }
+#pragma unroll
+      for (int b = 0; b < NI; ++b) {
+        const int x = wn * WN + b * 16 + lx, kk = ks + lk;
+        fb[b] = (OPB == kXC) ? Bs[kk * (BN + kPadXC) + x] : Bs[x * kStrKC + kk];
+      }
+      // D = Bfrag^T * Afrag.  The 16x16 result D[r][c] sits in lane
+      // c + 16 * (r % 4), item r / 4; with the operands swapped, lane
+      // (lx, lk) item v holds output row i = lx and column j = 4 * v + lk,
+      // which keeps the stores of a column-major C contiguous over 16 rows.
+#pragma unroll
+      for (int a = 0; a < MI; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[b], fa[a],
+                                                           acc[a][b], 0, 0, 0);
+    }
+  }
+
+#pragma unroll
+  for (int a = 0; a < MI; ++a)
+#pragma unroll
+    for (int b = 0; b < NI; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wm * WM + a * 16 + lx;
+        const int j = j0 + wn * WN + b * 16 + v * 4 + lk;
+        if (g.lower && I == J && i < j) continue;
+        double* c = g.C + (int64_t)i + (int64_t)j * g.ldc;
+        double r = g.alpha * acc[a][b][v];
+        if (g.beta != 0.0) r += g.beta * (*c);
+        *c = r;
+      }
+}
+
+template <int BM, int BN, int OPA, int OPB>
+static hipError_t gemm_t(hipStream_t s, const GemmArgs& a0) {
+  GemmArgs a = a0;
+  a.tiles_m = a.M / BM;
+  a.tiles_n = a.N / BN;
+  a.n_tiles = a.lower ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n;
+  if (a.n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gemm<BM, BN, OPA, OPB>), dim3(a.n_tiles), dim3(256), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
+                const double* A, int64_t lda, const double* B, int64_t ldb,
+                double* C, int64_t ldc, int M, int N, int K, double alpha,
+                double beta, bool lower, bool kstart_diag) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (M % bm || N % bn || K % kKT || (lower && (bm != bn || M != N)))
+    return hipErrorInvalidValue;
+  GemmArgs a{A, B, C, lda, ldb, ldc, M, N, K, alpha, beta, lower ? 1 : 0,
+             kstart_diag ? 1 : 0, 0, 0, 0};
+#define SPI_GEMM_CASE(BM_, BN_, OA, OB)                                   \
+  if (bm == BM_ && bn == BN_ && opA == OA && opB == OB)                  \
+    return gemm_t<BM_, BN_, OA, OB>(s, a);
+#define SPI_GEMM_OPS(BM_, BN_)          \
+  SPI_GEMM_CASE(BM_, BN_, kXC, kXC)     \
+  SPI_GEMM_CASE(BM_, BN_, kXC, kKC)     \
+  SPI_GEMM_CASE(BM_, BN_, kKC, kKC)
+  SPI_GEMM_OPS(128, 128)
+  SPI_GEMM_OPS(128, 64)
+  SPI_GEMM_OPS(64, 128)
+  SPI_GEMM_OPS(64, 64)
+#undef SPI_GEMM_OPS
+#undef SPI_GEMM_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace spi

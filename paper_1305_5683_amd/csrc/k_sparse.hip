@@ -16,7 +16,9 @@
 
 namespace spi {
 
-// panel columns staged in LDS at a time by the extend-add / selinv tasks
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// panel columns staged in LDS at a time by the selected-inversion tasks
 constexpr int kQC = 16;
 
 static int grid_for(int64_t items, int per_block) {
@@ -50,9 +52,10 @@ __global__ void k_gather_rr(const double* __restrict__ val,
 
 hipError_t launch_gather_values(Handle& h) {
   const Analysis& a = h.an;
-  hipLaunchKernelGGL(k_gather_slots, dim3(grid_for(a.m, 256)), dim3(256), 0,
-                     h.stream, h.val, h.w, h.d.slot_row, h.d.slot_leaf_src,
-                     h.sw, h.sleaf, a.m);
+  if (a.n_slots)
+    hipLaunchKernelGGL(k_gather_slots, dim3(grid_for(a.n_slots, 256)), dim3(256),
+                       0, h.stream, h.val, h.w, h.d.slot_row, h.d.slot_leaf_src,
+                       h.sw, h.sleaf, a.n_slots);
   int64_t nrr = (int64_t)a.rr_src.size();
   if (nrr)
     hipLaunchKernelGGL(k_gather_rr, dim3(grid_for(nrr, 256)), dim3(256), 0,
@@ -111,106 +114,128 @@ hipError_t launch_leaf_assemble(Handle& h) {
   return hipGetLastError();
 }
 
-// -------------------------------------------------------------- extend-add
-// Task (g, I, J), I >= J: the block of front g's contribution on positions
-// I*kET.. x J*kET.. of U_g,
-//   C = sum_{rows r of g} w_r h_rU h_rU^T  -  L_Ug L_Ug^T,
-// accumulated in LDS, then added into the root front (lower triangle) at
-// (U[a], U[b]).  The row part of a row only touches the positions of its
-// own entries: the entries whose positions fall in each range are found by
-// binary search (positions are sorted within a row).
-__device__ inline int64_t lower_bound_pos(const int32_t* p, int64_t lo,
-                                          int64_t hi, int32_t v) {
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (p[mid] < v) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
+// ------------------------------------------------------------ row panels
+// Dense row panels for the assembly of A_RR: column q of a panel holds the
+// root entries of its q-th row (zeros elsewhere); the row weights are kept
+// apart.  Filled once per set of values.
+__global__ void k_zero(double* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_extend_add(
-    const int32_t* __restrict__ tasks, const int64_t* __restrict__ grp_U_ptr,
-    const int32_t* __restrict__ U, const int64_t* __restrict__ grp_col_ptr,
-    const int64_t* __restrict__ grp_panel_off, const int64_t* __restrict__ grp_slot_ptr,
-    const int64_t* __restrict__ slot_rr_ptr, const int32_t* __restrict__ rr_lpos,
-    const double* __restrict__ rrval, const double* __restrict__ sw,
-    const double* __restrict__ panel, double* S, int64_t ld) {
-  __shared__ double C[kET][kET + 1];
-  __shared__ double PI[kQC][kET];
-  __shared__ double PJ[kQC][kET];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int g = tasks[3 * blockIdx.x], I = tasks[3 * blockIdx.x + 1],
-            J = tasks[3 * blockIdx.x + 2];
-  const int64_t nU = grp_U_ptr[g + 1] - grp_U_ptr[g];
-  const int32_t* Ug = U + grp_U_ptr[g];
-  const int I0 = I * kET, J0 = J * kET;
-  const int na = (int)min<int64_t>(kET, nU - I0), nb = (int)min<int64_t>(kET, nU - J0);
-  const int p = (int)(grp_col_ptr[g + 1] - grp_col_ptr[g]);
-  for (int e = t; e < kET * kET; e += 256) C[e % kET][e / kET] = 0.0;
-  __syncthreads();
-  // row part: one wave per row
-  for (int64_t s = grp_slot_ptr[g] + wave; s < grp_slot_ptr[g + 1]; s += 4) {
-    const int64_t b0 = slot_rr_ptr[s], b1 = slot_rr_ptr[s + 1];
-    int64_t ia = 0, ib = 0, ja = 0, jb = 0;
-    if (lane == 0) ia = lower_bound_pos(rr_lpos, b0, b1, I0);
-    if (lane == 1) ib = lower_bound_pos(rr_lpos, b0, b1, I0 + kET);
-    if (lane == 2) ja = lower_bound_pos(rr_lpos, b0, b1, J0);
-    if (lane == 3) jb = lower_bound_pos(rr_lpos, b0, b1, J0 + kET);
-    ia = __shfl(ia, 0, 64);
-    ib = __shfl(ib, 1, 64);
-    ja = __shfl(ja, 2, 64);
-    jb = __shfl(jb, 3, 64);
-    const int ni = (int)(ib - ia), nj = (int)(jb - ja);
-    const double ws = sw[s];
-    for (int pr = lane; pr < ni * nj; pr += 64) {
-      const int x = pr / nj, y = pr % nj;
-      const int pa = rr_lpos[ia + x] - I0, pb = rr_lpos[ja + y] - J0;
-      if (I == J && pa < pb) continue;
-      atomicAdd(&C[pa][pb], ws * rrval[ia + x] * rrval[ja + y]);
-    }
-  }
-  // leaf part: C -= L_I L_J^T, kQC panel columns at a time
-  const double* Pg = panel + grp_panel_off[g];
-  for (int q0 = 0; q0 < p; q0 += kQC) {
-    const int pc = min(kQC, p - q0);
-    __syncthreads();
-    for (int e = t; e < kQC * kET; e += 256) {
-      int a = e % kET, q = e / kET;
-      PI[q][a] = (q < pc && a < na) ? Pg[(int64_t)(q0 + q) * nU + I0 + a] : 0.0;
-      PJ[q][a] = (q < pc && a < nb) ? Pg[(int64_t)(q0 + q) * nU + J0 + a] : 0.0;
-    }
-    __syncthreads();
-    for (int e = t; e < kET * kET; e += 256) {
-      const int a = e % kET, b = e / kET;
-      double s = 0.0;
-      for (int q = 0; q < pc; ++q) s += PI[q][a] * PJ[q][b];
-      C[a][b] -= s;
-    }
-  }
-  __syncthreads();
-  for (int e = t; e < kET * kET; e += 256) {
-    const int a = e % kET, b = e / kET;
-    if (a >= na || b >= nb) continue;
-    if (I == J && a < b) continue;
-    const double v = C[a][b];
-    if (v == 0.0) continue;
-    atomicAdd(&S[(int64_t)Ug[I0 + a] + (int64_t)Ug[J0 + b] * ld], v);
-  }
+__global__ __launch_bounds__(256) void k_fill_rowpanels(
+    const double* __restrict__ val, const double* __restrict__ w,
+    const int32_t* __restrict__ rp_rows, const int64_t* __restrict__ rp_rowbase,
+    const int64_t* __restrict__ rpe_ptr, const int32_t* __restrict__ rpe_pos,
+    const int64_t* __restrict__ rpe_src, double* __restrict__ rpbuf,
+    double* __restrict__ rpw, int64_t nrows) {
+  const int lane = threadIdx.x & 63;
+  const int64_t pr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pr >= nrows) return;
+  double* col = rpbuf + rp_rowbase[pr];
+  for (int64_t e = rpe_ptr[pr] + lane; e < rpe_ptr[pr + 1]; e += 64)
+    col[rpe_pos[e]] = val[rpe_src[e]];
+  if (lane == 0) rpw[pr] = w[rp_rows[pr]];
 }
 
-hipError_t launch_extend_add(Handle& h) {
+hipError_t launch_fill_rowpanels(Handle& h) {
   const Analysis& a = h.an;
-  const int64_t nt = (int64_t)a.tasks.size() / 3;
-  if (!nt || !a.n_pad) return hipSuccess;
-  const int64_t chunk = 1 << 20;
-  for (int64_t t0 = 0; t0 < nt; t0 += chunk) {
-    int64_t c = std::min(chunk, nt - t0);
-    hipLaunchKernelGGL(k_extend_add, dim3((unsigned)c), dim3(256), 0, h.stream,
-                       h.d.tasks + 3 * t0, h.d.grp_U_ptr, h.d.U, h.d.grp_col_ptr,
-                       h.d.grp_panel_off, h.d.grp_slot_ptr, h.d.slot_rr_ptr,
-                       h.d.rr_lpos, h.rrval, h.sw, h.panel, h.S, a.n_pad);
+  const int64_t nrows = (int64_t)a.rp_rows.size();
+  if (!nrows) return hipSuccess;
+  double* rpbuf = h.panel + a.grp_panel_off[a.n_groups];
+  const int64_t total = a.rp_val_off[a.n_rp];
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(total, 256 * 8)), dim3(256), 0,
+                     h.stream, rpbuf, total);
+  hipLaunchKernelGGL(k_fill_rowpanels, dim3(grid_for(nrows, 4)), dim3(256), 0,
+                     h.stream, h.val, h.w, h.d.rp_rows, h.d.rp_rowbase,
+                     h.d.rpe_ptr, h.d.rpe_pos, h.d.rpe_src, rpbuf, h.rpw, nrows);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------- root assembly
+// One workgroup per 64 x 64 lower tile (I, J) of the root front.  The tile
+// is the sum of its incidences: update panel u (a leaf front's panel L_Ug
+// with weight -1, or a row panel with the row weights) restricted to the
+// positions of U that fall in the tile's rows (aI0 .. aI0 + nI) and columns
+// (aJ0 .. aJ0 + nJ):  C[U[a] - 64 I][U[b] - 64 J] += sum_q w_q Q[a][q] Q[b][q].
+// Each wave takes one incidence at a time and computes it in 16 x 16 blocks
+// on the FP64 matrix cores, adding into the LDS tile (LDS atomics, since
+// waves work on different incidences); the tile is then written once.
+__global__ __launch_bounds__(256) void k_assemble_root(
+    const int32_t* __restrict__ tile_order, const int64_t* __restrict__ inc_ptr,
+    const int32_t* __restrict__ inc, const int64_t* __restrict__ up_U_off,
+    const int64_t* __restrict__ up_Q_off, const int32_t* __restrict__ up_nU,
+    const int32_t* __restrict__ up_k, const int32_t* __restrict__ up_w_off,
+    const int32_t* __restrict__ U, const double* __restrict__ panel,
+    const double* __restrict__ rpw, double* __restrict__ S, int64_t ld,
+    int64_t n_root) {
+  __shared__ double C[kET][kET + 1];
+  const int t = tile_order[blockIdx.x];
+  int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int64_t i0 = (int64_t)I * kET, j0 = (int64_t)J * kET;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < kET * kET; e += 256) {
+    const int a = e % kET, b = e / kET;
+    C[a][b] = (I == J && a == b && i0 + a >= n_root) ? 1.0 : 0.0;
   }
+  __syncthreads();
+  const int lx = lane & 15, lk = lane >> 4;
+  for (int64_t q = inc_ptr[t] + wave; q < inc_ptr[t + 1]; q += 4) {
+    const int32_t* p = inc + 4 * q;
+    const int u = p[0], aI0 = p[1], aJ0 = p[2];
+    const int nI = p[3] & 0xffff, nJ = p[3] >> 16;
+    const int32_t* Uu = U + up_U_off[u];
+    const double* Q = panel + up_Q_off[u];
+    const int64_t nU = up_nU[u];
+    const int k = up_k[u], woff = up_w_off[u];
+    for (int sa = 0; sa < nI; sa += 16)
+      for (int sb = 0; sb < nJ; sb += 16) {
+        const int a = sa + lx, b = sb + lx;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int ks = 0; ks < k; ks += 4) {
+          const int qq = ks + lk;
+          double av = 0.0, bv = 0.0;
+          if (qq < k) {
+            const double wq = woff < 0 ? -1.0 : rpw[woff + qq];
+            if (a < nI) av = Q[aI0 + a + qq * nU] * wq;
+            if (b < nJ) bv = Q[aJ0 + b + qq * nU];
+          }
+          // lane (lx, lk) item v of the result: row sa + lx, column
+          // sb + 4 v + lk (operand order as in the root GEMM)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av, acc, 0, 0, 0);
+        }
+        if (a < nI) {
+          const int ra = Uu[aI0 + a] - (int)i0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int bb = sb + 4 * v + lk;
+            if (bb < nJ) {
+              const int rb = Uu[aJ0 + bb] - (int)j0;
+              if (I != J || ra >= rb) atomicAdd(&C[ra][rb], acc[v]);
+            }
+          }
+        }
+      }
+  }
+  __syncthreads();
+  for (int e = tid; e < kET * kET; e += 256) {
+    const int a = e % kET, b = e / kET;
+    if (I == J && a < b) continue;
+    S[(i0 + a) + (j0 + b) * ld] = C[a][b];
+  }
+}
+
+hipError_t launch_assemble_root(Handle& h) {
+  const Analysis& a = h.an;
+  if (!a.n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_assemble_root, dim3((unsigned)a.n_tiles), dim3(256), 0,
+                     h.stream, h.d.tile_order, h.d.inc_ptr, h.d.inc, h.d.up_U_off,
+                     h.d.up_Q_off, h.d.up_nU, h.d.up_k, h.d.up_w_off, h.d.U,
+                     h.panel, h.rpw, h.S, a.n_pad, a.n_root);
   return hipGetLastError();
 }
 
@@ -439,8 +464,12 @@ hipError_t launch_solve_pass(Handle& h, const double* b, double* x) {
                        h.d.rinc_u, h.d.grp_U_ptr, h.d.grp_col_ptr,
                        h.d.grp_panel_off, h.panel, h.vleaf, h.vroot, a.n_root,
                        a.n_pad);
-    if ((e = root_trsv_fwd(h, h.vroot)) != hipSuccess) return e;
-    if ((e = root_trsv_bwd(h, h.vroot)) != hipSuccess) return e;
+    if (h.have_inv) {
+      if ((e = root_inv_apply(h, h.vroot, h.vroot2)) != hipSuccess) return e;
+    } else {
+      if ((e = root_trsv_fwd(h, h.vroot)) != hipSuccess) return e;
+      if ((e = root_trsv_bwd(h, h.vroot)) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_scatter_root, dim3(grid_for(a.n_root, 256)), dim3(256),
                        0, h.stream, h.vroot, h.d.root_cols, x, a.n_root);
   }
@@ -475,7 +504,8 @@ hipError_t launch_diag_root(Handle& h, double* d) {
 // Task (g, I, J) adds its block of the quadratic forms c^T Z_UU c for all
 // pivots of g: the full square block for I == J, twice the block for I > J.
 __global__ __launch_bounds__(256) void k_selinv_leaf(
-    const int32_t* __restrict__ tasks, const int64_t* __restrict__ grp_U_ptr,
+    const int32_t* __restrict__ tasks, const int32_t* __restrict__ order,
+    const int64_t* __restrict__ grp_U_ptr,
     const int32_t* __restrict__ U, const int64_t* __restrict__ grp_col_ptr,
     const int64_t* __restrict__ grp_panel_off, const double* __restrict__ panel,
     const double* __restrict__ Z, int64_t ld,
@@ -485,8 +515,8 @@ __global__ __launch_bounds__(256) void k_selinv_leaf(
   __shared__ double PJ[kQC][kET];
   __shared__ double red[4][kQC / 4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int g = tasks[3 * blockIdx.x], I = tasks[3 * blockIdx.x + 1],
-            J = tasks[3 * blockIdx.x + 2];
+  const int tk = order[blockIdx.x];
+  const int g = tasks[3 * tk], I = tasks[3 * tk + 1], J = tasks[3 * tk + 2];
   const int p = (int)(grp_col_ptr[g + 1] - grp_col_ptr[g]);
   if (p == 0) return;
   const int64_t nU = grp_U_ptr[g + 1] - grp_U_ptr[g];
@@ -526,7 +556,7 @@ __global__ __launch_bounds__(256) void k_selinv_leaf(
       if (lane == 0) red[wave][q / 4] = s;
     }
     __syncthreads();
-    if (t < pc) part[task_part_off[blockIdx.x] + q0 + t] = fac * red[t % 4][t / 4];
+    if (t < pc) part[task_part_off[tk] + q0 + t] = fac * red[t % 4][t / 4];
   }
 }
 
@@ -561,9 +591,10 @@ hipError_t launch_selinv_leaves(Handle& h, double* d) {
     for (int64_t t0 = 0; t0 < n_lt; t0 += chunk) {
       int64_t c = std::min(chunk, n_lt - t0);
       hipLaunchKernelGGL(k_selinv_leaf, dim3((unsigned)c), dim3(256), 0,
-                         h.stream, h.d.tasks + 3 * t0, h.d.grp_U_ptr, h.d.U,
+                         h.stream, h.d.tasks, h.d.sel_order + t0, h.d.grp_U_ptr,
+                         h.d.U,
                          h.d.grp_col_ptr, h.d.grp_panel_off, h.panel, h.Z,
-                         a.n_pad, h.d.task_part_off + t0, h.part);
+                         a.n_pad, h.d.task_part_off, h.part);
     }
   }
   hipLaunchKernelGGL(k_selinv_reduce, dim3(grid_for(nl, 256)), dim3(256), 0,

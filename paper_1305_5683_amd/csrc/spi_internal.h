@@ -40,21 +40,46 @@ struct Analysis {
   std::vector<int32_t> leaf_cols;       // original column of leaf l
   std::vector<int32_t> leaf_grp;        // front of leaf l
   std::vector<int64_t> leaf_slot_ptr;   // n_leaf + 1, slots of leaf l
-  // fronts: leaf fronts first, then row-only fronts (no pivot, rows that
-  // touch no leaf column: they only contribute to the root)
-  int64_t n_groups = 0;         // leaf fronts
-  int64_t n_fronts = 0;         // leaf fronts + row-only fronts
-  std::vector<int64_t> grp_col_ptr;    // n_fronts + 1 into leaf_cols
-  std::vector<int64_t> grp_U_ptr;      // n_fronts + 1 into U
-  std::vector<int32_t> U;              // root indices, sorted per front
-  std::vector<int64_t> grp_panel_off;  // n_fronts + 1, dense |U| x p panels
-  std::vector<int64_t> grp_slot_ptr;   // n_fronts + 1 into slots
-  // slots
+  // leaf fronts (supernodes of leaf unknowns)
+  int64_t n_groups = 0;
+  std::vector<int64_t> grp_col_ptr;    // n_groups + 1 into leaf_cols
+  std::vector<int64_t> grp_U_ptr;      // n_groups + 1 into U
+  std::vector<int32_t> U;              // root indices, sorted per front; the
+                                       // row panels' lists follow (rp_U_base)
+  std::vector<int64_t> grp_panel_off;  // n_groups + 1, dense |U| x p panels
+  std::vector<int64_t> grp_slot_ptr;   // n_groups + 1 into slots
+  // slots: the rows of the leaf fronts, by leaf unknown
+  int64_t n_slots = 0;
   std::vector<int32_t> slot_row;       // original row
-  std::vector<int64_t> slot_rr_ptr;    // m + 1 into the compact root entries
-  std::vector<int64_t> slot_leaf_src;  // CSR position of the leaf entry or -1
+  std::vector<int64_t> slot_rr_ptr;    // n_slots + 1 into the compact root entries
+  std::vector<int64_t> slot_leaf_src;  // CSR position of the leaf entry
   std::vector<int32_t> rr_lpos;        // U-local position of each root entry
   std::vector<int64_t> rr_src;         // CSR position of each root entry
+  // row panels: consecutive rows with overlapping root structure, stored
+  // dense |U| x rows (values h, weights w kept per row) for the assembly of
+  // A_RR = sum_r w_r h_rR h_rR^T
+  int64_t n_rp = 0;
+  int64_t rp_U_base = 0;               // offset of the row panels' U lists
+  std::vector<int64_t> rp_row_ptr;     // n_rp + 1 into rp_rows
+  std::vector<int32_t> rp_rows;        // original rows, panel order
+  std::vector<int64_t> rp_U_ptr;       // n_rp + 1 (relative to rp_U_base)
+  std::vector<int64_t> rp_val_off;     // n_rp + 1, offsets of the dense panels
+  std::vector<int64_t> rp_rowbase;     // per panel row: offset of its column
+  std::vector<int64_t> rpe_ptr;        // per panel row + 1: its root entries
+  std::vector<int32_t> rpe_pos;        // U-local position
+  std::vector<int64_t> rpe_src;        // CSR position
+  // update panels (leaf fronts, then row panels): descriptors
+  int64_t n_up = 0;
+  std::vector<int64_t> up_U_off;       // into U
+  std::vector<int64_t> up_Q_off;       // into the panel buffer (leaf | rows)
+  std::vector<int32_t> up_nU;
+  std::vector<int32_t> up_k;
+  std::vector<int32_t> up_w_off;       // into the row weights, -1: weight -1
+  // incidences of the update panels on the 64 x 64 lower tiles of the root
+  int64_t n_tiles = 0;                 // T (T + 1) / 2, T = n_pad / 64
+  std::vector<int32_t> tile_order;     // tiles by decreasing work
+  std::vector<int64_t> inc_ptr;        // n_tiles + 1
+  std::vector<int32_t> inc;            // 4 per incidence: up, aI0, aJ0, nI|nJ<<16
   // root
   int64_t n_root = 0, n_pad = 0;
   std::vector<int32_t> root_cols;      // original column of root index i
@@ -64,11 +89,14 @@ struct Analysis {
   std::vector<int64_t> rinc_ptr;       // n_root + 1
   std::vector<int32_t> rinc_grp;
   std::vector<int32_t> rinc_u;
-  // extend-add / selected-inversion tasks: (front, I, J), I >= J, tiles of
-  // kET positions of the front's U
+  // selected-inversion tasks of the leaf fronts: (front, I, J), I >= J,
+  // tiles of kET positions of the front's U
   std::vector<int32_t> tasks;          // 3 per task
-  std::vector<int64_t> grp_task_ptr;   // n_fronts + 1
-  std::vector<int64_t> task_part_off;  // n_tasks + 1 (selinv partial sums)
+  std::vector<int64_t> grp_task_ptr;   // n_groups + 1
+  std::vector<int64_t> task_part_off;  // n_tasks + 1 (partial sums)
+  // launch order of the tasks: grouped by the 2-D block of the root front
+  // they read, so that tasks running together share a region of it
+  std::vector<int32_t> sel_order;
   // counters
   int64_t nnz_a = 0, nnz_l = 0;
   double flops_factor = 0, flops_selinv = 0, flops_solve = 0, flops_asm = 0;
@@ -107,6 +135,21 @@ struct DevAnalysis {
   int32_t* tasks = nullptr;
   int64_t* grp_task_ptr = nullptr;
   int64_t* task_part_off = nullptr;
+  int32_t* sel_order = nullptr;
+  // row panels and root assembly
+  int32_t* rp_rows = nullptr;
+  int64_t* rp_rowbase = nullptr;
+  int64_t* rpe_ptr = nullptr;
+  int32_t* rpe_pos = nullptr;
+  int64_t* rpe_src = nullptr;
+  int64_t* up_U_off = nullptr;
+  int64_t* up_Q_off = nullptr;
+  int32_t* up_nU = nullptr;
+  int32_t* up_k = nullptr;
+  int32_t* up_w_off = nullptr;
+  int32_t* tile_order = nullptr;
+  int64_t* inc_ptr = nullptr;
+  int32_t* inc = nullptr;
 };
 
 enum Phase { kPhLeaf = 0, kPhExtend, kPhPotrf, kPhSolve, kPhTrtri, kPhLauum,
@@ -130,10 +173,12 @@ struct Handle {
   double* val = nullptr;     // H values, CSR order (copy)
   double* w = nullptr;       // weights, original row order (copy)
   double* sw = nullptr;      // weight per slot
-  double* sleaf = nullptr;   // leaf coefficient per slot (0 for row-only)
+  double* sleaf = nullptr;   // leaf coefficient per slot
   double* rrval = nullptr;   // root entries in compact slot order
+  double* rpw = nullptr;     // row weights in row-panel order
   // factor
-  double* panel = nullptr;   // leaf panels L_UG, dense column-major per front
+  double* panel = nullptr;   // leaf panels L_UG, dense column-major per front,
+                             // followed by the dense row panels
   double* ldiag = nullptr;   // leaf pivots L_ll
   double* S = nullptr;       // root front n_pad x n_pad, column-major; L after factor
   double* invd = nullptr;    // inverses of the kNB diagonal blocks of L_RR
@@ -148,6 +193,9 @@ struct Handle {
   double* vx = nullptr;      // n (iterate)
   double* vdd = nullptr;     // 2 m (double-double row values)
   double* vnorm = nullptr;   // 2 (norm reductions)
+  double* vroot2 = nullptr;  // n_pad
+  double* vpart = nullptr;   // partial products of the root GEMV
+  bool have_inv = false;     // W = L_RR^-1 is valid
   // phase timing (opts.timing): HIP event pairs recorded on the stream,
   // accumulated lazily (spi_info synchronises and sums them)
   PhaseTimer timer[kNumPhases];
@@ -162,12 +210,14 @@ struct Handle {
 // kernel launchers (stream-ordered); return hipError_t of the launch
 hipError_t launch_gather_values(Handle& h);
 hipError_t launch_leaf_assemble(Handle& h);
-hipError_t launch_root_fill(Handle& h);
-hipError_t launch_extend_add(Handle& h);
+hipError_t launch_fill_rowpanels(Handle& h);
+hipError_t launch_assemble_root(Handle& h);
 hipError_t launch_rhs(Handle& h, const double* y, double* b);
 hipError_t root_potrf(Handle& h);
 hipError_t root_trsv_fwd(Handle& h, double* z);
 hipError_t root_trsv_bwd(Handle& h, double* z);
+hipError_t root_inv_apply(Handle& h, double* z, double* tmp);
+int64_t root_inv_part_size(int64_t np);
 hipError_t root_trtri(Handle& h);
 hipError_t root_lauum(Handle& h);
 hipError_t launch_solve_pass(Handle& h, const double* b, double* x);

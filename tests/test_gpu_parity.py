@@ -89,6 +89,8 @@ LEAFY = [
     (30, 3, 200, 4, 30, 0, 2, {}),          # U spanning several 64-tiles
     (6, 4, 260, 2, 60, 300, 3, {"max_group": 1}),  # one pivot per front
     (5, 6, 90, 3, 10, 20, 4, {"leaf_max_work": 0.0}),  # no leaves: dense root
+    (12, 7, 600, 3, 25, 50, 5, {"root_inverse": 0}),   # substitution solves
+    (12, 7, 600, 3, 25, 50, 5, {"refine_steps": 0}),   # no refinement
 ]
 
 
