@@ -106,6 +106,9 @@ void free_timers(Handle& h) {
 
 void free_all(Handle& h) {
   free_timers(h);
+  if (h.ev_next) (void)hipEventDestroy(h.ev_next);
+  if (h.ev_panel) (void)hipEventDestroy(h.ev_panel);
+  if (h.side) (void)hipStreamDestroy(h.side);
   DevAnalysis& d = h.d;
   void* ptrs[] = {d.rowptr, d.col, d.colptr, d.csc_pos, d.csc_row, d.leaf_cols,
                   d.leaf_grp, d.leaf_slot_ptr, d.grp_col_ptr, d.grp_U_ptr, d.U,
@@ -117,7 +120,7 @@ void free_all(Handle& h) {
                   d.up_w_off, d.tile_order, d.inc_ptr, d.inc, h.rpw,
                   h.val, h.w, h.sw, h.sleaf, h.rrval, h.panel, h.ldiag, h.S,
                   h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
-                  h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart};
+                  h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2, h.scratch};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -204,6 +207,7 @@ int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
   AL(h.flag, 1); AL(h.vleaf, nl); AL(h.vroot, np); AL(h.vres, a.n);
   AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 2);
   AL(h.vroot2, np); AL(h.vpart, root_inv_part_size(np));
+  AL(h.invd2, ((np + 255) / 256) * 256 * 256); AL(h.scratch, np * 256);
 #undef AL
   if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
   if (he != hipSuccess) {

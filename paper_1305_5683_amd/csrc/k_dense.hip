@@ -20,54 +20,80 @@ namespace spi {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------ diagonal block kernels
-// Cholesky of the kNB x kNB diagonal block at (k0, k0), right-looking, one
-// column per step.  Thread (ti, tg) keeps row ti, columns j = tg + 4q, in
-// registers; the current column is exchanged through LDS (double-buffered
-// by step parity, so one barrier per step).  Writes L back (lower triangle
-// incl. diagonal).  A pivot that is not positive and finite records its
-// elimination index (base + k0 + k) with atomicMin in `fail` and continues
-// with pivot 1.
+// Cholesky of the kNB x kNB diagonal block at (k0, k0) and, in the same
+// sweep, its inverse.  Right-looking, one column per step, the step loop
+// fully unrolled so that every register index is a compile-time constant.
+// Thread (ti, tg) keeps row ti of the block, columns j = tg + 4q, in
+// registers (r: the factor, x: the inverse being formed by the same
+// elimination applied to the identity).  Per step the owners publish
+// column k of the factor and row k of the inverse through LDS
+// (double-buffered by step parity: one barrier per step).  Row k of the
+// inverse is scaled by 1 / L_kk at the end, so no thread writes a row that
+// others read in the same step.
+// Writes L (lower triangle incl. diagonal) back to S and L_kk^-1,
+// column-major with zeros above the diagonal, to `inv`.  A pivot that is
+// not positive and finite records its elimination index (base + k0 + k)
+// with atomicMin in `fail` and continues with pivot 1.
 __global__ __launch_bounds__(256) void k_potrf_diag(double* S, int64_t ld,
-                                                    int k0, int64_t* fail,
+                                                    int k0, double* inv,
+                                                    int64_t* fail,
                                                     int64_t base) {
   constexpr int Q = kNB / 4;
-  __shared__ double colk[2][kNB];
+  __shared__ double colk[2][kNB];   // column k of the factor (unscaled)
+  __shared__ double xrow[2][kNB];   // row k of the inverse (unscaled)
+  __shared__ double rdiag[kNB];
   const int t = threadIdx.x, ti = t % kNB, tg = t / kNB;
-  double r[Q];
+  double r[Q], x[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int j = tg + 4 * q;
     r[q] = (ti >= j) ? S[(int64_t)(k0 + ti) + (int64_t)(k0 + j) * ld] : 0.0;
+    x[q] = (ti == j) ? 1.0 : 0.0;
   }
+#pragma clang loop unroll(full)
   for (int k = 0; k < kNB; ++k) {
-    const int par = k & 1;
-    if (tg == (k & 3)) {  // owner of column k publishes it (updated values)
+    const int par = k & 1, qk = k >> 2, gk = k & 3;
+    if (tg == gk) colk[par][ti] = r[qk];
+    if (ti == k) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q)
-        if (q == (k >> 2)) colk[par][ti] = r[q];
+      for (int q = 0; q < Q; ++q) xrow[par][tg + 4 * q] = x[q];
     }
     __syncthreads();
+    double ck[Q], xk[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      ck[q] = colk[par][tg + 4 * q];
+      xk[q] = xrow[par][tg + 4 * q];
+    }
     const double d = colk[par][k];
     const bool bad = !(d > 0.0) || !isfinite(d);
     const double lkk = bad ? 1.0 : sqrt(d);
     const double rk = 1.0 / lkk;
     const double lik = colk[par][ti] * rk;
+    if (ti > k) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int j = tg + 4 * q;
-      if (j > k && j <= ti) r[q] -= lik * (colk[par][j] * rk);
-      if (j == k) {
-        if (ti == k) r[q] = lkk;
-        else if (ti > k) r[q] = lik;
+      for (int q = 0; q < Q; ++q) {
+        const int j = tg + 4 * q;
+        if (j > k && j <= ti) r[q] -= lik * (ck[q] * rk);   // trailing update
+        if (j <= k) x[q] -= lik * (xk[q] * rk);            // inverse rows
       }
     }
-    if (t == 0 && bad)
-      atomicMin((unsigned long long*)fail, (unsigned long long)(base + k0 + k));
+    if (tg == gk) {  // column k of the factor is final
+      if (ti == k) r[qk] = lkk;
+      else if (ti > k) r[qk] = lik;
+    }
+    if (t == 0) {
+      rdiag[k] = rk;
+      if (bad) atomicMin((unsigned long long*)fail, (unsigned long long)(base + k0 + k));
+    }
   }
+  __syncthreads();
+  const double rs = rdiag[ti];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int j = tg + 4 * q;
     if (ti >= j) S[(int64_t)(k0 + ti) + (int64_t)(k0 + j) * ld] = r[q];
+    inv[ti + j * kNB] = (ti >= j) ? x[q] * rs : 0.0;
   }
 }
 
@@ -104,10 +130,13 @@ __global__ __launch_bounds__(256) void k_trsm_panel(double* S, int64_t ld,
       xc = x[qc];
     }
     xc = __shfl(xc, (threadIdx.x & ~3) + owner, 64);
+    double lc[Q];  // column c of L_kk at this thread's columns, one batch
+#pragma unroll
+    for (int q = 0; q < Q; ++q) lc[q] = L[g + 4 * q][c];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int cq = g + 4 * q;
-      if (cq > c) x[q] -= L[cq][c] * xc;
+      if (cq > c) x[q] -= lc[q] * xc;
     }
   }
   if (live) {
@@ -161,6 +190,92 @@ __global__ __launch_bounds__(256) void k_invert_diag_blocks(const double* S,
   for (int j = tg; j < kNB; j += 4) out[ti + j * kNB] = (ti >= j) ? X[ti][j] : 0.0;
 }
 
+// Inverses of the kNBO x kNBO diagonal blocks of the factor (the last one
+// may be narrower), one block per workgroup, from the inverses of their
+// kNB x kNB diagonal sub-blocks:  X_ii = L_ii^-1 and, column by column,
+// X_ij = -X_ii sum_{j<=k<i} L_ik X_kj  for i > j.  Output column-major with
+// leading dimension kNBO and zeros above the diagonal.
+__global__ __launch_bounds__(256) void k_invert_outer_blocks(const double* S,
+                                                             int64_t ld,
+                                                             const double* invd,
+                                                             double* out,
+                                                             int np) {
+  constexpr int NBO = 256, NS = NBO / kNB;
+  __shared__ double La[kNB][kNB + 1];
+  __shared__ double Xb[kNB][kNB + 1];
+  const int K0 = blockIdx.x * NBO;
+  const int ns = min(NS, (np - K0) / kNB);
+  double* X = out + (int64_t)blockIdx.x * NBO * NBO;
+  const int t = threadIdx.x;
+  const int ri = (t % 16) * 4, cj = (t / 16) * 4;  // this thread's 4 x 4 block
+  // diagonal sub-blocks and zeros above
+  for (int bj = 0; bj < NS; ++bj)
+    for (int bi = 0; bi < NS; ++bi)
+      for (int e = t; e < kNB * kNB; e += 256) {
+        const int i = e % kNB, j = e / kNB;
+        double v = 0.0;
+        if (bi == bj && bi < ns)
+          v = invd[(int64_t)(K0 / kNB + bi) * kNB * kNB + i + j * kNB];
+        if (bi <= bj || bi >= ns || bj >= ns)
+          X[(bi * kNB + i) + (int64_t)(bj * kNB + j) * NBO] = v;
+      }
+  __syncthreads();
+  for (int bj = 0; bj < ns; ++bj)
+    for (int bi = bj + 1; bi < ns; ++bi) {
+      double acc[4][4] = {};
+      for (int bk = bj; bk < bi; ++bk) {  // acc += L_ik X_kj
+        for (int e = t; e < kNB * kNB; e += 256) {
+          const int i = e % kNB, j = e / kNB;
+          La[i][j] = S[(int64_t)(K0 + bi * kNB + i) + (int64_t)(K0 + bk * kNB + j) * ld];
+          Xb[i][j] = X[(bk * kNB + i) + (int64_t)(bj * kNB + j) * NBO];
+        }
+        __syncthreads();
+        for (int q = 0; q < kNB; ++q) {
+          double a[4], b[4];
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            a[x] = La[ri + x][q];
+            b[x] = Xb[q][cj + x];
+          }
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+        }
+        __syncthreads();
+      }
+      // X_ij = -X_ii acc
+      for (int e = t; e < kNB * kNB; e += 256) {
+        const int i = e % kNB, j = e / kNB;
+        La[i][j] = X[(bi * kNB + i) + (int64_t)(bi * kNB + j) * NBO];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) Xb[ri + x][cj + y] = acc[x][y];
+      __syncthreads();
+      double r[4][4] = {};
+      for (int q = 0; q < kNB; ++q) {
+        double a[4], b[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          a[x] = La[ri + x][q];
+          b[x] = Xb[q][cj + x];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) r[x][y] += a[x] * b[y];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          X[(bi * kNB + ri + x) + (int64_t)(bj * kNB + cj + y) * NBO] = -r[x][y];
+      __syncthreads();
+    }
+}
+
 // Copy a kNB x kNB column-major block (with its zeros) into a matrix.
 __global__ void k_put_block(double* W, int64_t ld, int k0, const double* blk) {
   for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) {
@@ -204,46 +319,135 @@ hipError_t launch_root_fill(Handle& h) {
 
 static int pick_bm(int M) { return (M % 128 == 0) ? 128 : 64; }
 
-// Right-looking blocked Cholesky of the root front, block kNB, then the
-// inverses of all its diagonal blocks (used by the factor inversion).
-hipError_t root_potrf(Handle& h) {
+// Outer block of the root POTRF / TRTRI sweeps: the bulk updates run with
+// K = kNBO (a quarter of the C traffic of kNB steps); the panels inside an
+// outer block are factored in kNB steps.
+constexpr int kNBO = 256;
+
+// Factor the outer panel [K0, K0 + KB) of the root (all rows below K0):
+// kNB diagonal blocks, their panel solves, and the updates of the panel's
+// remaining columns.
+static hipError_t factor_panel(Handle& h, hipStream_t s, int K0, int KB) {
   const int np = (int)h.an.n_pad;
   const int64_t ld = np;
-  hipError_t e = hipSuccess;
   const int64_t base = (int64_t)h.an.leaf_cols.size();
-  for (int k0 = 0; k0 < np; k0 += kNB) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, h.stream, h.S, ld,
-                       k0, h.flag, base);
+  hipError_t e;
+  for (int k0 = K0; k0 < K0 + KB; k0 += kNB) {
+    double* inv = h.invd + (int64_t)(k0 / kNB) * kNB * kNB;
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, h.S, ld, k0,
+                       inv, h.flag, base);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int rest = np - k0 - kNB;
     if (rest <= 0) break;
-    hipLaunchKernelGGL(k_trsm_panel, dim3((rest + 63) / 64), dim3(256), 0,
-                       h.stream, h.S, ld, k0, rest);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // trailing update, lower triangle: S22 -= P P^T
-    double* P = h.S + (int64_t)(k0 + kNB) + (int64_t)k0 * ld;
-    double* C = h.S + (int64_t)(k0 + kNB) * (ld + 1);
-    int t = (rest % 128 == 0) ? 128 : 64;
-    e = gemm(h.stream, t, t, kXC, kXC, P, ld, P, ld, C, ld, rest, rest, kNB,
-             -1.0, 1.0, true, false);
+    // panel solve P := P L_kk^-T as a product with the inverse (each tile
+    // owns whole rows of the 64-wide panel, so it is safe in place)
+    double* Pp = h.S + (int64_t)(k0 + kNB) + (int64_t)k0 * ld;
+    e = gemm(s, pick_bm(rest), 64, kXC, kXC, Pp, ld, inv, kNB, Pp, ld, rest,
+             kNB, kNB, 1.0, 0.0, false, false);
     if (e != hipSuccess) return e;
+    const int ncols = K0 + KB - k0 - kNB;  // panel columns still to update
+    if (ncols > 0) {
+      double* P = h.S + (int64_t)(k0 + kNB) + (int64_t)k0 * ld;
+      double* C = h.S + (int64_t)(k0 + kNB) * (ld + 1);
+      e = gemm(s, pick_bm(rest), 64, kXC, kXC, P, ld, P, ld, C, ld, rest, ncols,
+               kNB, -1.0, 1.0, false, false, true);
+      if (e != hipSuccess) return e;
+    }
   }
-  hipLaunchKernelGGL(k_invert_diag_blocks, dim3(np / kNB), dim3(256), 0,
-                     h.stream, h.S, ld, h.invd);
+  return hipSuccess;
+}
+
+static hipError_t ensure_side_stream(Handle& h) {
+  hipError_t e;
+  if (!h.side) {
+    if ((e = hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking)) != hipSuccess)
+      return e;
+  }
+  if (!h.ev_next) {
+    if ((e = hipEventCreateWithFlags(&h.ev_next, hipEventDisableTiming)) != hipSuccess)
+      return e;
+  }
+  if (!h.ev_panel) {
+    if ((e = hipEventCreateWithFlags(&h.ev_panel, hipEventDisableTiming)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+// Right-looking blocked Cholesky of the root front with a one-panel
+// lookahead: after outer step K0 has updated the next panel's columns (T1),
+// the side stream factors that panel while the main stream applies the rest
+// of the trailing update (T2); the two touch disjoint columns.  Then the
+// inverses of all kNB diagonal blocks (used by the factor inversion).
+hipError_t root_potrf(Handle& h) {
+  const int np = (int)h.an.n_pad;
+  const int64_t ld = np;
+  hipError_t e;
+  if ((e = ensure_side_stream(h)) != hipSuccess) return e;
+  if ((e = factor_panel(h, h.stream, 0, std::min(kNBO, np))) != hipSuccess)
+    return e;
+  for (int K0 = 0; K0 < np; K0 += kNBO) {
+    const int KB = std::min(kNBO, np - K0), K1 = K0 + KB;
+    const int rest = np - K1;
+    if (rest <= 0) break;
+    const int KB2 = std::min(kNBO, rest);
+    double* P = h.S + (int64_t)K1 + (int64_t)K0 * ld;  // rows >= K1 of the panel
+    // T1: next panel's columns [K1, K1 + KB2), all rows >= K1
+    e = gemm(h.stream, pick_bm(rest), (KB2 % 128 == 0) ? 128 : 64, kXC, kXC, P,
+             ld, P, ld, h.S + (int64_t)K1 * (ld + 1), ld, rest, KB2, KB, -1.0,
+             1.0, false, false, true);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(h.ev_next, h.stream)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(h.side, h.ev_next, 0)) != hipSuccess) return e;
+    if ((e = factor_panel(h, h.side, K1, KB2)) != hipSuccess) return e;
+    if ((e = hipEventRecord(h.ev_panel, h.side)) != hipSuccess) return e;
+    // T2: trailing square beyond the next panel, lower triangle
+    const int r2 = rest - KB2;
+    if (r2 > 0) {
+      const int t = (r2 % 128 == 0) ? 128 : 64;
+      e = gemm(h.stream, t, t, kXC, kXC, P + KB2, ld, P + KB2, ld,
+               h.S + (int64_t)(K1 + KB2) * (ld + 1), ld, r2, r2, KB, -1.0, 1.0,
+               true, false);
+      if (e != hipSuccess) return e;
+    }
+    if ((e = hipStreamWaitEvent(h.stream, h.ev_panel, 0)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_invert_outer_blocks, dim3((np + kNBO - 1) / kNBO),
+                     dim3(256), 0, h.stream, h.S, ld, h.invd, h.invd2, np);
   return hipGetLastError();
 }
 
-// Inverse of the root factor (W = L^-1, in place on a copy of L) followed
-// by Z = W^T W, the root block of A^-1 (lower triangle).
-//
-// Inversion by block columns, left to right.  With the first block columns
-// already inverted, row block k to the left holds L_k,<k X_<k and the block
-// rows below hold L_>k,<k X_<k.  Step k, with X_kk = L_kk^-1 (kept from the
-// factorisation):
-//   T      = L_>k,k X_kk              (becomes the state of block column k)
+// 2-D copy of a rows x cols column-major block.
+__global__ void k_copy2d(const double* __restrict__ src, int64_t lds,
+                         double* __restrict__ dst, int64_t ldd, int rows,
+                         int cols) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % rows, j = e / rows;
+    dst[i + j * ldd] = src[i + j * lds];
+  }
+}
+
+static hipError_t copy2d(hipStream_t s, const double* src, int64_t lds,
+                         double* dst, int64_t ldd, int rows, int cols) {
+  const int64_t total = (int64_t)rows * cols;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy2d, dim3(fill_grid(total)), dim3(256), 0, s, src,
+                     lds, dst, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+// Inverse of the root factor, W = L^-1, in place on a copy of L, by outer
+// block columns left to right.  With the first block columns already
+// inverted, row block k to the left holds L_k,<k X_<k and the block rows
+// below hold L_>k,<k X_<k.  Step k, with X_kk = L_kk^-1 (from the batched
+// diagonal-block inversion):
+//   T       = L_>k,k X_kk             (becomes the state of block column k)
 //   S_>k,<k -= T * S_k,<k
-//   S_k,<k  = -X_kk * S_k,<k          (final row block k of L^-1)
-//   S_kk    = X_kk
+//   S_k,<k   = -X_kk * S_k,<k         (final row block k of L^-1)
+//   S_kk     = X_kk
+// The two in-place products read their input from a scratch copy.
 hipError_t root_trtri(Handle& h) {
   const int np = (int)h.an.n_pad;
   const int64_t ld = np;
@@ -251,31 +455,36 @@ hipError_t root_trtri(Handle& h) {
   hipLaunchKernelGGL(k_copy_lower, dim3(fill_grid((int64_t)np * np)), dim3(256),
                      0, h.stream, h.S, h.W, (int64_t)np);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  for (int k0 = 0; k0 < np; k0 += kNB) {
-    const double* inv = h.invd + (int64_t)(k0 / kNB) * kNB * kNB;
-    const int rest = np - k0 - kNB;
-    double* W21 = h.W + (int64_t)(k0 + kNB) + (int64_t)k0 * ld;
-    double* W10 = h.W + (int64_t)k0;
-    double* W20 = h.W + (int64_t)(k0 + kNB);
+  for (int K0 = 0; K0 < np; K0 += kNBO) {
+    const int KB = std::min(kNBO, np - K0), K1 = K0 + KB;
+    const int rest = np - K1;
+    const double* X11 = h.invd2 + (int64_t)(K0 / kNBO) * kNBO * kNBO;
+    double* W21 = h.W + (int64_t)K1 + (int64_t)K0 * ld;
+    double* W10 = h.W + (int64_t)K0;
+    double* W20 = h.W + (int64_t)K1;
+    const int bk = (KB % 128 == 0) ? 128 : 64;
     if (rest > 0) {
-      e = gemm(h.stream, pick_bm(rest), 64, kXC, kKC, W21, ld, inv, kNB, W21,
-               ld, rest, kNB, kNB, 1.0, 0.0, false, false);
+      if ((e = copy2d(h.stream, W21, ld, h.scratch, ld, rest, KB)) != hipSuccess)
+        return e;
+      e = gemm(h.stream, pick_bm(rest), bk, kXC, kKC, h.scratch, ld, X11, kNBO,
+               W21, ld, rest, KB, KB, 1.0, 0.0, false, false);
       if (e != hipSuccess) return e;
-      if (k0 > 0) {
-        e = gemm(h.stream, pick_bm(rest), (k0 % 128 == 0) ? 128 : 64, kXC, kKC,
-                 W21, ld, W10, ld, W20, ld, rest, k0, kNB, -1.0, 1.0, false,
-                 false);
+      if (K0 > 0) {
+        e = gemm(h.stream, pick_bm(rest), 128, kXC, kKC, W21, ld, W10, ld, W20,
+                 ld, rest, K0, KB, -1.0, 1.0, false, false);
         if (e != hipSuccess) return e;
       }
     }
-    if (k0 > 0) {
-      e = gemm(h.stream, 64, (k0 % 128 == 0) ? 128 : 64, kXC, kKC, inv, kNB,
-               W10, ld, W10, ld, kNB, k0, kNB, -1.0, 0.0, false, false);
+    if (K0 > 0) {
+      if ((e = copy2d(h.stream, W10, ld, h.scratch, kNBO, KB, K0)) != hipSuccess)
+        return e;
+      e = gemm(h.stream, bk, 128, kXC, kKC, X11, kNBO, h.scratch, kNBO, W10, ld,
+               KB, K0, KB, -1.0, 0.0, false, false);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_put_block, dim3(1), dim3(256), 0, h.stream, h.W, ld,
-                       k0, inv);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = copy2d(h.stream, X11, kNBO, h.W + (int64_t)K0 * (ld + 1), ld, KB,
+                    KB)) != hipSuccess)
+      return e;
   }
   return hipSuccess;
 }

@@ -16,7 +16,9 @@
 // `lower`: only tiles with I >= J are enumerated (square tiles) and the
 // diagonal tiles write their lower triangle only.  `kstart_diag`: the K
 // range of tile (I, J) starts at I * BM (products whose left factor is lower
-// triangular with zeros stored above the diagonal).
+// triangular with zeros stored above the diagonal).  `diag_mask`: C's
+// origin lies on the matrix diagonal and only its lower part (i >= j) is
+// written; tiles entirely above the diagonal do nothing.
 #include <hip/hip_runtime.h>
 
 #include "spi_internal.h"
@@ -41,7 +43,7 @@ struct GemmArgs {
   int64_t lda, ldb, ldc;
   int M, N, K;
   double alpha, beta;
-  int lower, kstart_diag;
+  int lower, kstart_diag, diag_mask;
   int tiles_m, tiles_n, n_tiles;
 };
 
@@ -85,14 +87,16 @@ __device__ inline void tile_of(const GemmArgs& g, int t, int& I, int& J) {
   I = J + local;
 }
 
-// Map the hardware workgroup index to a logical tile so that consecutive
-// logical tiles (which share operand panels) run on the same XCD, whose L2
-// they then share.  Workgroups are dispatched round-robin over 8 XCDs.
+// Map the hardware workgroup index to a logical tile.  Workgroups are
+// dispatched round-robin over the 8 XCDs (w % 8).  Within every block of 64
+// logical tiles, XCD x takes the chunk of 8 consecutive tiles [8x, 8x + 8):
+// a chunk shares its operand panels in that XCD's L2, and every XCD gets an
+// equal share of every part of the launch (tiles whose K range shrinks with
+// the tile index stay balanced).  The last partial block maps to itself.
 __device__ inline int xcd_remap(int w, int n) {
-  const int nx = 8;
-  int per = n / nx, rem = n % nx;
-  int x = w % nx, local = w / nx;
-  return x * per + min(x, rem) + local;
+  if (w >= (n & ~63)) return w;
+  const int r = w & 63;
+  return (w & ~63) + 8 * (r & 7) + (r >> 3);
 }
 
 template <int BM, int BN, int OPA, int OPB>
@@ -107,6 +111,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   int I, J;
   tile_of(g, xcd_remap(blockIdx.x, g.n_tiles), I, J);
   const int i0 = I * BM, j0 = J * BN;
+  if (g.diag_mask && i0 + BM - 1 < j0) return;  // tile above the diagonal
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int kbeg = g.kstart_diag ? i0 : 0;
@@ -208,7 +213,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + wm * WM + a * 16 + lx;
         const int j = j0 + wn * WN + b * 16 + v * 4 + lk;
-        if (g.lower && I == J && i < j) continue;
+        if (((g.lower && I == J) || g.diag_mask) && i < j) continue;
         double* c = g.C + (int64_t)i + (int64_t)j * g.ldc;
         double r = g.alpha * acc[a][b][v];
         if (g.beta != 0.0) r += g.beta * (*c);
@@ -231,12 +236,12 @@ static hipError_t gemm_t(hipStream_t s, const GemmArgs& a0) {
 hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* C, int64_t ldc, int M, int N, int K, double alpha,
-                double beta, bool lower, bool kstart_diag) {
+                double beta, bool lower, bool kstart_diag, bool diag_mask) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (M % bm || N % bn || K % kKT || (lower && (bm != bn || M != N)))
     return hipErrorInvalidValue;
   GemmArgs a{A, B, C, lda, ldb, ldc, M, N, K, alpha, beta, lower ? 1 : 0,
-             kstart_diag ? 1 : 0, 0, 0, 0};
+             kstart_diag ? 1 : 0, diag_mask ? 1 : 0, 0, 0, 0};
 #define SPI_GEMM_CASE(BM_, BN_, OA, OB)                                   \
   if (bm == BM_ && bn == BN_ && opA == OA && opB == OB)                  \
     return gemm_t<BM_, BN_, OA, OB>(s, a);

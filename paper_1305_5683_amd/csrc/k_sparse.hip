@@ -20,6 +20,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 // panel columns staged in LDS at a time by the selected-inversion tasks
 constexpr int kQC = 16;
+// panel columns loaded at once per 16 x 16 block of the root assembly
+constexpr int kAsmK = 32;
 
 static int grid_for(int64_t items, int per_block) {
   int64_t g = (items + per_block - 1) / per_block;
@@ -195,6 +197,14 @@ __global__ __launch_bounds__(256) void k_assemble_root(
     for (int sa = 0; sa < nI; sa += 16)
       for (int sb = 0; sb < nJ; sb += 16) {
         const int a = sa + lx, b = sb + lx;
+        // all loads of the block first (one round trip), then the MFMAs
+        const int ra = (a < nI) ? Uu[aI0 + a] - (int)i0 : -1;
+        int rb[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int bb = sb + 4 * v + lk;
+          rb[v] = (bb < nJ) ? Uu[aJ0 + bb] - (int)j0 : -1;
+        }
         v4d acc = {0.0, 0.0, 0.0, 0.0};
         for (int ks = 0; ks < k; ks += 4) {
           const int qq = ks + lk;
@@ -208,16 +218,10 @@ __global__ __launch_bounds__(256) void k_assemble_root(
           // sb + 4 v + lk (operand order as in the root GEMM)
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av, acc, 0, 0, 0);
         }
-        if (a < nI) {
-          const int ra = Uu[aI0 + a] - (int)i0;
+        if (ra >= 0) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int bb = sb + 4 * v + lk;
-            if (bb < nJ) {
-              const int rb = Uu[aJ0 + bb] - (int)j0;
-              if (I != J || ra >= rb) atomicAdd(&C[ra][rb], acc[v]);
-            }
-          }
+          for (int v = 0; v < 4; ++v)
+            if (rb[v] >= 0 && (I != J || ra >= rb[v])) atomicAdd(&C[ra][rb[v]], acc[v]);
         }
       }
   }

@@ -183,6 +183,10 @@ struct Handle {
   double* S = nullptr;       // root front n_pad x n_pad, column-major; L after factor
   double* invd = nullptr;    // inverses of the kNB diagonal blocks of L_RR
   double* W = nullptr;       // L_RR^-1 (selected inversion scratch)
+  double* invd2 = nullptr;   // inverses of the 256 x 256 diagonal blocks
+  double* scratch = nullptr; // n_pad x 256 staging for in-place products
+  hipStream_t side = nullptr;       // lookahead stream of the root POTRF
+  hipEvent_t ev_next = nullptr, ev_panel = nullptr;
   double* Z = nullptr;       // A^-1 restricted to the root (lower triangle)
   double* part = nullptr;    // selected-inversion partial sums
   int64_t* flag = nullptr;   // first failing pivot in elimination order
@@ -232,6 +236,7 @@ enum GemmOp { kXC = 0, kKC = 1 };  // operand access, see k_dense.hip
 hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* C, int64_t ldc, int M, int N, int K, double alpha,
-                double beta, bool lower, bool kstart_diag);
+                double beta, bool lower, bool kstart_diag,
+                bool diag_mask = false);
 
 }  // namespace spi
