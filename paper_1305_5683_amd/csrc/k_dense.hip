@@ -20,80 +20,171 @@ namespace spi {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------ diagonal block kernels
-// Cholesky of the kNB x kNB diagonal block at (k0, k0) and, in the same
-// sweep, its inverse.  Right-looking, one column per step, the step loop
-// fully unrolled so that every register index is a compile-time constant.
-// Thread (ti, tg) keeps row ti of the block, columns j = tg + 4q, in
-// registers (r: the factor, x: the inverse being formed by the same
-// elimination applied to the identity).  Per step the owners publish
-// column k of the factor and row k of the inverse through LDS
-// (double-buffered by step parity: one barrier per step).  Row k of the
-// inverse is scaled by 1 / L_kk at the end, so no thread writes a row that
-// others read in the same step.
-// Writes L (lower triangle incl. diagonal) back to S and L_kk^-1,
-// column-major with zeros above the diagonal, to `inv`.  A pivot that is
-// not positive and finite records its elimination index (base + k0 + k)
-// with atomicMin in `fail` and continues with pivot 1.
-__global__ __launch_bounds__(256) void k_potrf_diag(double* S, int64_t ld,
-                                                    int k0, double* inv,
-                                                    int64_t* fail,
-                                                    int64_t base) {
-  constexpr int Q = kNB / 4;
-  __shared__ double colk[2][kNB];   // column k of the factor (unscaled)
-  __shared__ double xrow[2][kNB];   // row k of the inverse (unscaled)
-  __shared__ double rdiag[kNB];
+// 1 / sqrt(d) for d > 0: hardware estimate refined by two Newton steps
+// (quadratic convergence from the estimate to full binary64 accuracy), a
+// much shorter dependent chain than a rounded square root and division.
+__device__ inline double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  return y;
+}
+
+// Cholesky of the kNB x kNB diagonal block at (k0, k0) and its inverse, in
+// one right-looking sweep over column blocks of 4, by 1024 threads.
+// Thread (ti, tg) keeps row ti, columns j = tg + 16q (q < 4), of the factor
+// (r) and of the inverse (x) in registers; the block loop is fully unrolled
+// so every register index is a compile-time constant.  Per block the four
+// column values of every row and the block's four rows of the (partially
+// eliminated) inverse are published through LDS (double-buffered by parity:
+// one barrier per block); every thread then factors the 4x4 diagonal block
+// redundantly, scales its row, applies the rank-4 update to its remaining
+// columns and eliminates the block from its row of the inverse (the same
+// operations applied to the identity).  A pivot that is not positive and
+// finite records its elimination index (base + k0 + k) with atomicMin in
+// `fail` and continues with pivot 1.  Writes L (lower triangle incl.
+// diagonal) back to S and L_kk^-1, column-major with zeros above the
+// diagonal, to `inv`.
+__global__ __launch_bounds__(1024) void k_potrf_diag(double* S, int64_t ld,
+                                                     int k0, double* inv,
+                                                     int64_t* fail,
+                                                     int64_t base) {
+  constexpr int G = 16, Q = kNB / G;
+  __shared__ double blk[2][kNB][4];   // block columns of every row
+  __shared__ double xb[2][4][kNB];    // block rows of the inverse
   const int t = threadIdx.x, ti = t % kNB, tg = t / kNB;
   double r[Q], x[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int j = tg + 4 * q;
+    const int j = tg + G * q;
     r[q] = (ti >= j) ? S[(int64_t)(k0 + ti) + (int64_t)(k0 + j) * ld] : 0.0;
     x[q] = (ti == j) ? 1.0 : 0.0;
   }
 #pragma clang loop unroll(full)
-  for (int k = 0; k < kNB; ++k) {
-    const int par = k & 1, qk = k >> 2, gk = k & 3;
-    if (tg == gk) colk[par][ti] = r[qk];
-    if (ti == k) {
+  for (int kb = 0; kb < kNB / 4; ++kb) {
+    const int k = 4 * kb, par = kb & 1, qk = kb / 4;
+    const bool owner = (tg >> 2) == (kb & 3);   // owns column k + (tg & 3)
+    if (owner) blk[par][ti][tg & 3] = r[qk];
+    if (ti >= k && ti < k + 4) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) xrow[par][tg + 4 * q] = x[q];
+      for (int q = 0; q < Q; ++q) xb[par][ti - k][tg + G * q] = x[q];
     }
     __syncthreads();
-    double ck[Q], xk[Q];
+    // 4x4 diagonal block: D = Lb Lb^T (Li = Lb^-1), redundantly per thread
+    double Lb[4][4] = {}, Li[4][4] = {};
+    bool badany = false;
+    int badc = 0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      ck[q] = colk[par][tg + 4 * q];
-      xk[q] = xrow[par][tg + 4 * q];
-    }
-    const double d = colk[par][k];
-    const bool bad = !(d > 0.0) || !isfinite(d);
-    const double lkk = bad ? 1.0 : sqrt(d);
-    const double rk = 1.0 / lkk;
-    const double lik = colk[par][ti] * rk;
-    if (ti > k) {
+    for (int c = 0; c < 4; ++c) {
+      double d = blk[par][k + c][c];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int j = tg + 4 * q;
-        if (j > k && j <= ti) r[q] -= lik * (ck[q] * rk);   // trailing update
-        if (j <= k) x[q] -= lik * (xk[q] * rk);            // inverse rows
+      for (int e = 0; e < c; ++e) d -= Lb[c][e] * Lb[c][e];
+      const bool bad = !(d > 0.0) || !isfinite(d);
+      if (bad && !badany) { badany = true; badc = c; }
+      const double dd = bad ? 1.0 : d;
+      const double rc = rsqrt_nr(dd);
+      Lb[c][c] = dd * rc;
+      Li[c][c] = rc;
+#pragma unroll
+      for (int a = c + 1; a < 4; ++a) {
+        double v = blk[par][k + a][c];
+#pragma unroll
+        for (int e = 0; e < c; ++e) v -= Lb[a][e] * Lb[c][e];
+        Lb[a][c] = v * rc;
       }
     }
-    if (tg == gk) {  // column k of the factor is final
-      if (ti == k) r[qk] = lkk;
-      else if (ti > k) r[qk] = lik;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int a = c + 1; a < 4; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int e = c; e < a; ++e) v -= Lb[a][e] * Li[e][c];
+        Li[a][c] = v * Li[a][a];
+      }
+    if (t == 0 && badany)
+      atomicMin((unsigned long long*)fail, (unsigned long long)(base + k0 + k + badc));
+    // this row's block entries: l = Li v (rows below the block)
+    double l[4] = {0.0, 0.0, 0.0, 0.0};
+    if (ti >= k + 4) {
+      double v[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = blk[par][ti][c];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int e = 0; e <= c; ++e) sacc += Li[c][e] * v[e];
+        l[c] = sacc;
+      }
     }
-    if (t == 0) {
-      rdiag[k] = rk;
-      if (bad) atomicMin((unsigned long long*)fail, (unsigned long long)(base + k0 + k));
+    // rank-4 update of this row's later columns (lower part only)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int j = tg + G * q;
+      if (ti >= k + 4 && j > k + 3 && j <= ti) {
+        double w[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) w[c] = blk[par][j][c];
+        double sacc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double ljc = 0.0;
+#pragma unroll
+          for (int e = 0; e <= c; ++e) ljc += Li[c][e] * w[e];
+          sacc += l[c] * ljc;
+        }
+        r[q] -= sacc;
+      }
+    }
+    // the block column of the factor is final
+    if (owner) {
+      const int c = tg & 3;
+      double v = r[qk];
+      if (ti >= k + 4) {
+        v = (c == 0) ? l[0] : (c == 1) ? l[1] : (c == 2) ? l[2] : l[3];
+      } else if (ti >= k) {
+        v = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int cc = 0; cc <= a; ++cc)
+            if (a == ti - k && cc == c) v = Lb[a][cc];
+      }
+      r[qk] = v;
+    }
+    // inverse: X_b = Li Xtilde_b; rows of the block take it, rows below
+    // eliminate it (only columns j <= k + 3 are non-zero)
+    if (ti >= k) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int j = tg + G * q;
+        if (j <= k + 3) {
+          double xt[4], xf[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) xt[c] = xb[par][c][j];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int e = 0; e <= c; ++e) sacc += Li[c][e] * xt[e];
+            xf[c] = sacc;
+          }
+          if (ti >= k + 4) {
+            x[q] -= l[0] * xf[0] + l[1] * xf[1] + l[2] * xf[2] + l[3] * xf[3];
+          } else {
+            const int a = ti - k;
+            x[q] = (a == 0) ? xf[0] : (a == 1) ? xf[1] : (a == 2) ? xf[2] : xf[3];
+          }
+        }
+      }
     }
   }
-  __syncthreads();
-  const double rs = rdiag[ti];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int j = tg + 4 * q;
+    const int j = tg + G * q;
     if (ti >= j) S[(int64_t)(k0 + ti) + (int64_t)(k0 + j) * ld] = r[q];
-    inv[ti + j * kNB] = (ti >= j) ? x[q] * rs : 0.0;
+    inv[ti + j * kNB] = (ti >= j) ? x[q] : 0.0;
   }
 }
 
@@ -334,7 +425,7 @@ static hipError_t factor_panel(Handle& h, hipStream_t s, int K0, int KB) {
   hipError_t e;
   for (int k0 = K0; k0 < K0 + KB; k0 += kNB) {
     double* inv = h.invd + (int64_t)(k0 / kNB) * kNB * kNB;
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, h.S, ld, k0,
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(1024), 0, s, h.S, ld, k0,
                        inv, h.flag, base);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int rest = np - k0 - kNB;
