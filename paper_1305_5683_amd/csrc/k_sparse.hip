@@ -20,8 +20,9 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 // panel columns staged in LDS at a time by the selected-inversion tasks
 constexpr int kQC = 16;
-// panel columns loaded at once per 16 x 16 block of the root assembly
-constexpr int kAsmK = 32;
+// threads of a root-assembly workgroup (8 waves share one LDS tile, so that
+// up to 8 waves per SIMD hide the latency of the small panel loads)
+constexpr int kAsmThreads = 512;
 
 static int grid_for(int64_t items, int per_block) {
   int64_t g = (items + per_block - 1) / per_block;
@@ -164,7 +165,7 @@ hipError_t launch_fill_rowpanels(Handle& h) {
 // Each wave takes one incidence at a time and computes it in 16 x 16 blocks
 // on the FP64 matrix cores, adding into the LDS tile (LDS atomics, since
 // waves work on different incidences); the tile is then written once.
-__global__ __launch_bounds__(256) void k_assemble_root(
+__global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
     const int32_t* __restrict__ tile_order, const int64_t* __restrict__ inc_ptr,
     const int32_t* __restrict__ inc, const int64_t* __restrict__ up_U_off,
     const int64_t* __restrict__ up_Q_off, const int32_t* __restrict__ up_nU,
@@ -180,13 +181,14 @@ __global__ __launch_bounds__(256) void k_assemble_root(
   const int J = t - I * (I + 1) / 2;
   const int64_t i0 = (int64_t)I * kET, j0 = (int64_t)J * kET;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < kET * kET; e += 256) {
+  constexpr int NW = kAsmThreads / 64;
+  for (int e = tid; e < kET * kET; e += kAsmThreads) {
     const int a = e % kET, b = e / kET;
     C[a][b] = (I == J && a == b && i0 + a >= n_root) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int lx = lane & 15, lk = lane >> 4;
-  for (int64_t q = inc_ptr[t] + wave; q < inc_ptr[t + 1]; q += 4) {
+  for (int64_t q = inc_ptr[t] + wave; q < inc_ptr[t + 1]; q += NW) {
     const int32_t* p = inc + 4 * q;
     const int u = p[0], aI0 = p[1], aJ0 = p[2];
     const int nI = p[3] & 0xffff, nJ = p[3] >> 16;
@@ -226,7 +228,7 @@ __global__ __launch_bounds__(256) void k_assemble_root(
       }
   }
   __syncthreads();
-  for (int e = tid; e < kET * kET; e += 256) {
+  for (int e = tid; e < kET * kET; e += kAsmThreads) {
     const int a = e % kET, b = e / kET;
     if (I == J && a < b) continue;
     S[(i0 + a) + (j0 + b) * ld] = C[a][b];
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(256) void k_assemble_root(
 hipError_t launch_assemble_root(Handle& h) {
   const Analysis& a = h.an;
   if (!a.n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_assemble_root, dim3((unsigned)a.n_tiles), dim3(256), 0,
+  hipLaunchKernelGGL(k_assemble_root, dim3((unsigned)a.n_tiles), dim3(kAsmThreads), 0,
                      h.stream, h.d.tile_order, h.d.inc_ptr, h.d.inc, h.d.up_U_off,
                      h.d.up_Q_off, h.d.up_nU, h.d.up_k, h.d.up_w_off, h.d.U,
                      h.panel, h.rpw, h.S, a.n_pad, a.n_root);
