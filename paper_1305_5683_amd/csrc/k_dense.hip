@@ -188,99 +188,6 @@ __global__ __launch_bounds__(1024) void k_potrf_diag(double* S, int64_t ld,
   }
 }
 
-// Panel solve P := P L_kk^-T for the rows below the diagonal block.  Four
-// threads per row (adjacent lanes): thread g keeps the row's columns
-// c = g + 4q in registers; at step c the owner divides by L_cc and the four
-// lanes exchange x_c by shuffle, then update their later columns.
-__global__ __launch_bounds__(256) void k_trsm_panel(double* S, int64_t ld,
-                                                    int k0, int rows) {
-  constexpr int Q = kNB / 4;
-  __shared__ double L[kNB][kNB + 1];
-  __shared__ double rdiag[kNB];
-  const int t = threadIdx.x;
-  for (int e = t; e < kNB * kNB; e += 256) {
-    int i = e % kNB, j = e / kNB;
-    L[i][j] = S[(int64_t)(k0 + i) + (int64_t)(k0 + j) * ld];
-  }
-  __syncthreads();
-  if (t < kNB) rdiag[t] = 1.0 / L[t][t];
-  __syncthreads();
-  const int g = t & 3;
-  const int r = blockIdx.x * 64 + (t >> 2);
-  const bool live = r < rows;
-  double* P = S + (int64_t)(k0 + kNB + (live ? r : 0)) + (int64_t)k0 * ld;
-  double x[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) x[q] = live ? P[(int64_t)(g + 4 * q) * ld] : 0.0;
-#pragma unroll
-  for (int c = 0; c < kNB; ++c) {
-    const int owner = c & 3, qc = c >> 2;
-    double xc = 0.0;
-    if (g == owner) {
-      x[qc] *= rdiag[c];
-      xc = x[qc];
-    }
-    xc = __shfl(xc, (threadIdx.x & ~3) + owner, 64);
-    double lc[Q];  // column c of L_kk at this thread's columns, one batch
-#pragma unroll
-    for (int q = 0; q < Q; ++q) lc[q] = L[g + 4 * q][c];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int cq = g + 4 * q;
-      if (cq > c) x[q] -= lc[q] * xc;
-    }
-  }
-  if (live) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) P[(int64_t)(g + 4 * q) * ld] = x[q];
-  }
-}
-
-// Inverses of all kNB x kNB diagonal blocks of the factor, one block per
-// workgroup: X = L_kk^-1 by right-looking elimination on the identity,
-// stored column-major with explicit zeros above the diagonal.
-__global__ __launch_bounds__(256) void k_invert_diag_blocks(const double* S,
-                                                            int64_t ld,
-                                                            double* invd) {
-  __shared__ double L[kNB][kNB + 1];
-  __shared__ double X[kNB][kNB + 1];
-  const int k0 = blockIdx.x * kNB;
-  const int t = threadIdx.x, ti = t % kNB, tg = t / kNB;
-  for (int j = tg; j < kNB; j += 4) {
-    L[ti][j] = (ti >= j) ? S[(int64_t)(k0 + ti) + (int64_t)(k0 + j) * ld] : 0.0;
-    X[ti][j] = (ti == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int k = 0; k < kNB; ++k) {
-    // row k of X is final after dividing by L_kk; rows below eliminate it
-    const double rk = 1.0 / L[k][k];
-    double xk[kNB / 4];
-#pragma unroll
-    for (int q = 0; q < kNB / 4; ++q) {
-      int j = tg + 4 * q;
-      xk[q] = (j <= k) ? X[k][j] * rk : 0.0;
-    }
-    __syncthreads();
-    if (ti == k) {
-#pragma unroll
-      for (int q = 0; q < kNB / 4; ++q) {
-        int j = tg + 4 * q;
-        if (j <= k) X[k][j] = xk[q];
-      }
-    } else if (ti > k) {
-      const double lik = L[ti][k];
-#pragma unroll
-      for (int q = 0; q < kNB / 4; ++q) {
-        int j = tg + 4 * q;
-        if (j <= k) X[ti][j] -= lik * xk[q];
-      }
-    }
-    __syncthreads();
-  }
-  double* out = invd + (int64_t)blockIdx.x * kNB * kNB;
-  for (int j = tg; j < kNB; j += 4) out[ti + j * kNB] = (ti >= j) ? X[ti][j] : 0.0;
-}
-
 // Inverses of the kNBO x kNBO diagonal blocks of the factor (the last one
 // may be narrower), one block per workgroup, from the inverses of their
 // kNB x kNB diagonal sub-blocks:  X_ii = L_ii^-1 and, column by column,
@@ -367,24 +274,6 @@ __global__ __launch_bounds__(256) void k_invert_outer_blocks(const double* S,
     }
 }
 
-// Copy a kNB x kNB column-major block (with its zeros) into a matrix.
-__global__ void k_put_block(double* W, int64_t ld, int k0, const double* blk) {
-  for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) {
-    int i = e % kNB, j = e / kNB;
-    W[(int64_t)(k0 + i) + (int64_t)(k0 + j) * ld] = blk[e];
-  }
-}
-
-// Zero the whole root front and put 1 on the padded diagonal.
-__global__ void k_root_fill(double* S, int64_t n_pad, int64_t n_root) {
-  int64_t total = n_pad * n_pad;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t i = e % n_pad, j = e / n_pad;
-    S[e] = (i == j && i >= n_root) ? 1.0 : 0.0;
-  }
-}
-
 // Copy the lower triangle (and zeros above) of S into W.
 __global__ void k_copy_lower(const double* __restrict__ S, double* __restrict__ W,
                              int64_t n_pad) {
@@ -399,13 +288,6 @@ __global__ void k_copy_lower(const double* __restrict__ S, double* __restrict__ 
 static int fill_grid(int64_t total) {
   int64_t g = (total + 255) / 256;
   return (int)std::min<int64_t>(g, 65536);
-}
-
-hipError_t launch_root_fill(Handle& h) {
-  if (!h.an.n_pad) return hipSuccess;
-  hipLaunchKernelGGL(k_root_fill, dim3(fill_grid(h.an.n_pad * h.an.n_pad)),
-                     dim3(256), 0, h.stream, h.S, h.an.n_pad, h.an.n_root);
-  return hipGetLastError();
 }
 
 static int pick_bm(int M) { return (M % 128 == 0) ? 128 : 64; }

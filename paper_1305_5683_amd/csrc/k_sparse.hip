@@ -162,9 +162,25 @@ hipError_t launch_fill_rowpanels(Handle& h) {
 // with weight -1, or a row panel with the row weights) restricted to the
 // positions of U that fall in the tile's rows (aI0 .. aI0 + nI) and columns
 // (aJ0 .. aJ0 + nJ):  C[U[a] - 64 I][U[b] - 64 J] += sum_q w_q Q[a][q] Q[b][q].
-// Each wave takes one incidence at a time and computes it in 16 x 16 blocks
-// on the FP64 matrix cores, adding into the LDS tile (LDS atomics, since
-// waves work on different incidences); the tile is then written once.
+// The tile's incidences are staged in LDS in chunks, with their panel and
+// index offsets resolved, so a wave's work on an incidence starts with no
+// dependent descriptor loads.  Each wave takes one incidence at a time and
+// computes it in 16 x 16 blocks on the FP64 matrix cores; all loads of a
+// block (indices, kAsmKC panel columns of both operands, row weights) are
+// issued together before its MFMAs.  Results are added into the LDS tile
+// (LDS atomics, since waves work on different incidences); the tile is then
+// written once.
+constexpr int kAsmChunk = 128;  // incidences staged per pass
+constexpr int kAsmKC = 32;      // panel columns per batch of loads
+
+// A wave-uniform 64-bit value moved to scalar registers.
+__device__ inline int64_t uniform64(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
     const int32_t* __restrict__ tile_order, const int64_t* __restrict__ inc_ptr,
     const int32_t* __restrict__ inc, const int64_t* __restrict__ up_U_off,
@@ -174,6 +190,10 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
     const double* __restrict__ rpw, double* __restrict__ S, int64_t ld,
     int64_t n_root) {
   __shared__ double C[kET][kET + 1];
+  __shared__ int64_t s_qa[kAsmChunk], s_qb[kAsmChunk];
+  __shared__ int64_t s_ua[kAsmChunk], s_ub[kAsmChunk];
+  __shared__ int32_t s_nU[kAsmChunk], s_k[kAsmChunk], s_w[kAsmChunk],
+      s_n[kAsmChunk];
   const int t = tile_order[blockIdx.x];
   int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -186,46 +206,84 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
     const int a = e % kET, b = e / kET;
     C[a][b] = (I == J && a == b && i0 + a >= n_root) ? 1.0 : 0.0;
   }
-  __syncthreads();
   const int lx = lane & 15, lk = lane >> 4;
-  for (int64_t q = inc_ptr[t] + wave; q < inc_ptr[t + 1]; q += NW) {
-    const int32_t* p = inc + 4 * q;
-    const int u = p[0], aI0 = p[1], aJ0 = p[2];
-    const int nI = p[3] & 0xffff, nJ = p[3] >> 16;
-    const int32_t* Uu = U + up_U_off[u];
-    const double* Q = panel + up_Q_off[u];
-    const int64_t nU = up_nU[u];
-    const int k = up_k[u], woff = up_w_off[u];
-    for (int sa = 0; sa < nI; sa += 16)
-      for (int sb = 0; sb < nJ; sb += 16) {
-        const int a = sa + lx, b = sb + lx;
-        // all loads of the block first (one round trip), then the MFMAs
-        const int ra = (a < nI) ? Uu[aI0 + a] - (int)i0 : -1;
-        int rb[4];
+  const int64_t q_beg = inc_ptr[t], q_end = inc_ptr[t + 1];
+  for (int64_t c0 = q_beg; c0 < q_end; c0 += kAsmChunk) {
+    const int nc = (int)min((int64_t)kAsmChunk, q_end - c0);
+    __syncthreads();  // previous chunk consumed (and C initialised)
+    if (tid < nc) {
+      const int32_t* p = inc + 4 * (c0 + tid);
+      const int u = p[0];
+      const int64_t qo = up_Q_off[u], uo = up_U_off[u];
+      s_qa[tid] = qo + p[1];
+      s_qb[tid] = qo + p[2];
+      s_ua[tid] = uo + p[1];
+      s_ub[tid] = uo + p[2];
+      s_nU[tid] = up_nU[u];
+      s_k[tid] = up_k[u];
+      s_w[tid] = up_w_off[u];
+      s_n[tid] = p[3];
+    }
+    __syncthreads();
+    for (int q = wave; q < nc; q += NW) {
+      // per-incidence values are wave-uniform: keep them in scalar registers
+      const double* Qa = panel + uniform64(s_qa[q]);
+      const double* Qb = panel + uniform64(s_qb[q]);
+      const int32_t* Ua = U + uniform64(s_ua[q]);
+      const int32_t* Ub = U + uniform64(s_ub[q]);
+      const int nU = __builtin_amdgcn_readfirstlane(s_nU[q]);
+      const int k = __builtin_amdgcn_readfirstlane(s_k[q]);
+      const int woff = __builtin_amdgcn_readfirstlane(s_w[q]);
+      const int nn = __builtin_amdgcn_readfirstlane(s_n[q]);
+      const int nI = nn & 0xffff, nJ = nn >> 16;
+      for (int sa = 0; sa < nI; sa += 16)
+        for (int sb = 0; sb < nJ; sb += 16) {
+          // Addresses are clamped into the incidence (and the panel) and the
+          // out-of-range values replaced afterwards, so every load is issued
+          // unconditionally and the whole batch is in flight at once.
+          const int a = sa + lx, b = sb + lx;
+          const bool va = a < nI, vb = b < nJ;
+          const int ac = va ? a : nI - 1, bc = vb ? b : nJ - 1;
+          int ra = Ua[ac];
+          int rb[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int bb = sb + 4 * v + lk;
-          rb[v] = (bb < nJ) ? Uu[aJ0 + bb] - (int)j0 : -1;
-        }
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int ks = 0; ks < k; ks += 4) {
-          const int qq = ks + lk;
-          double av = 0.0, bv = 0.0;
-          if (qq < k) {
-            const double wq = woff < 0 ? -1.0 : rpw[woff + qq];
-            if (a < nI) av = Q[aI0 + a + qq * nU] * wq;
-            if (b < nJ) bv = Q[aJ0 + b + qq * nU];
-          }
-          // lane (lx, lk) item v of the result: row sa + lx, column
-          // sb + 4 v + lk (operand order as in the root GEMM)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av, acc, 0, 0, 0);
-        }
-        if (ra >= 0) {
+          for (int v = 0; v < 4; ++v) rb[v] = Ub[min(sb + 4 * v + lk, nJ - 1)];
+          ra = va ? ra - (int)i0 : -1;
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (rb[v] >= 0 && (I != J || ra >= rb[v])) atomicAdd(&C[ra][rb[v]], acc[v]);
+            rb[v] = (sb + 4 * v + lk < nJ) ? rb[v] - (int)j0 : -1;
+          v4d acc = {0.0, 0.0, 0.0, 0.0};
+          for (int kc = 0; kc < k; kc += kAsmKC) {
+            double av[kAsmKC / 4], bv[kAsmKC / 4], wv[kAsmKC / 4];
+#pragma unroll
+            for (int s = 0; s < kAsmKC / 4; ++s) {
+              const int qc = min(kc + 4 * s + lk, k - 1);
+              av[s] = Qa[ac + qc * nU];
+              bv[s] = Qb[bc + qc * nU];
+              wv[s] = woff >= 0 ? rpw[woff + qc] : -1.0;  // uniform branch
+            }
+#pragma unroll
+            for (int s = 0; s < kAsmKC / 4; ++s) {
+              const bool vq = kc + 4 * s + lk < k;
+              av[s] = (vq && va) ? av[s] * wv[s] : 0.0;
+              bv[s] = (vq && vb) ? bv[s] : 0.0;
+            }
+            // lane (lx, lk) item v of the result: row sa + lx, column
+            // sb + 4 v + lk (operand order as in the root GEMM)
+#pragma unroll
+            for (int s = 0; s < kAsmKC / 4; ++s)
+              if (kc + 4 * s < k)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[s], av[s], acc, 0,
+                                                           0, 0);
+          }
+          if (ra >= 0) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (rb[v] >= 0 && (I != J || ra >= rb[v]))
+                atomicAdd(&C[ra][rb[v]], acc[v]);
+          }
         }
-      }
+    }
   }
   __syncthreads();
   for (int e = tid; e < kET * kET; e += kAsmThreads) {
