@@ -62,7 +62,13 @@ enum spi_status {
 
 enum spi_precision {
     SPI_FP64 = 0,       /* every stage in binary64 */
-    SPI_MIXED = 1       /* binary32 root bulk, binary64 pivot tiles + refinement */
+    SPI_MIXED = 1       /* root front factorisation and factor inversion
+                           with binary32 matrix-core products (each launch
+                           sums at most 256 terms in binary32, partial
+                           results are combined in binary64); binary64
+                           storage, diagonal 64-blocks, leaf fronts,
+                           refinement residuals, and the selected-inversion
+                           sums (root block of A^-1 and leaf terms) */
 };
 
 typedef struct spi_opts {
@@ -82,7 +88,20 @@ typedef struct spi_opts {
                                applies as two products and spi_diag_inv
                                reuses; 0: it is formed by spi_diag_inv and
                                spi_solve substitutes.  Default 1 */
-    int32_t reserved[5];    /* must be zero */
+    int32_t equilibrate;    /* 1: factor S A S with S = diag(s), s_c the power
+                               of two 2^-floor(log2(A_cc)/2) (scaled diagonal
+                               in [1, 4)); exact, so FP64 results do not
+                               change, and it keeps the FP32 stages of
+                               SPI_MIXED in range; 0: no scaling.  Default 1 */
+    double refine_tol;      /* > 0: spi_solve stops refining once the
+                               max-norm of the correction is <= refine_tol
+                               times the max-norm of x (reading the norms
+                               back synchronises the stream after each step)
+                               and returns SPI_E_NOCONV if refine_steps steps
+                               do not get there; 0: exactly refine_steps
+                               steps.  Default 0; SPI_MIXED uses 1e-14 and at
+                               least 10 steps when this is 0 */
+    int32_t reserved[2];    /* must be zero */
 } spi_opts;
 
 typedef struct spi_info_t {

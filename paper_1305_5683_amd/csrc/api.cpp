@@ -120,7 +120,8 @@ void free_all(Handle& h) {
                   d.up_w_off, d.tile_order, d.inc_ptr, d.inc, h.rpw,
                   h.val, h.w, h.sw, h.sleaf, h.rrval, h.panel, h.ldiag, h.S,
                   h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
-                  h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2, h.scratch};
+                  h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2, h.scratch,
+                  h.colscale, h.vbh, h.vxh};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -138,6 +139,8 @@ void spi_default_opts(spi_opts* o) {
   o->amalg_density = 0.35;
   o->refine_steps = 2;
   o->root_inverse = 1;
+  o->equilibrate = 1;
+  o->refine_tol = 0.0;
 }
 
 int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
@@ -155,13 +158,15 @@ int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
     g_analyze_err = "unknown precision";
     return SPI_E_ARG;
   }
-  if (o.max_group < 1 || o.refine_steps < 0 || !(o.amalg_density >= 0.0)) {
+  if (o.max_group < 1 || o.refine_steps < 0 || !(o.amalg_density >= 0.0) ||
+      !(o.refine_tol >= 0.0)) {
     g_analyze_err = "invalid options";
     return SPI_E_ARG;
   }
-  if (o.precision == SPI_MIXED) {
-    g_analyze_err = "SPI_MIXED is not available in this build";
-    return SPI_E_ARG;
+  if (o.precision == SPI_MIXED && o.refine_tol == 0.0) {
+    // the FP32 root factor needs refinement to reach FP64 accuracy in x
+    o.refine_tol = 1e-14;
+    o.refine_steps = std::max(o.refine_steps, 10);
   }
   spi_handle* H = new (std::nothrow) spi_handle();
   if (!H) {
@@ -208,6 +213,7 @@ int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
   AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 2);
   AL(h.vroot2, np); AL(h.vpart, root_inv_part_size(np));
   AL(h.invd2, ((np + 255) / 256) * 256 * 256); AL(h.scratch, np * 256);
+  AL(h.colscale, a.n); AL(h.vbh, a.n); AL(h.vxh, a.n);
 #undef AL
   if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
   if (he != hipSuccess) {
@@ -230,6 +236,7 @@ int spi_set_values(spi_handle* H, const double* val, const double* w) {
                         hipMemcpyDeviceToDevice, h.stream), "copy values");
   SPI_CK(hipMemcpyAsync(h.w, w, h.an.m * sizeof(double),
                         hipMemcpyDeviceToDevice, h.stream), "copy weights");
+  if (h.opts.equilibrate) SPI_CK(launch_equilibrate(h), "equilibration");
   SPI_CK(launch_gather_values(h), "gather values");
   SPI_CK(launch_fill_rowpanels(h), "row panels");
   h.have_values = true;
@@ -246,7 +253,7 @@ int spi_factor(spi_handle* H) {
   h.have_factor = false;
   h.have_inv = false;
   h.failed_col = -1;
-  SPI_CK(hipMemsetAsync(h.flag, 0xff, sizeof(int64_t), h.stream), "flag");
+  SPI_CK(fill_i64(h.stream, h.flag, -1, 1), "flag");
   phase_begin(h, kPhLeaf);
   SPI_CK(launch_leaf_assemble(h), "leaf assembly");
   phase_end(h, kPhLeaf);
@@ -301,20 +308,52 @@ int spi_solve(spi_handle* H, const double* b, double* x, int32_t nrhs,
     return fail(h, SPI_E_ARG, hipSuccess, "invalid solve arguments");
   if (!h.have_factor)
     return fail(h, SPI_E_STATE, hipSuccess, "spi_solve without a valid factor");
+  // With equilibration the factor is that of S A S: solve (S A S) x' = S b
+  // and return x = S x'.  The refinement residual S b - (H S)^T W (H S) x'
+  // is S (b - A x) exactly (powers of two).
+  const bool eq = h.opts.equilibrate != 0;
+  const double tol = h.opts.refine_tol;
+  int status = SPI_OK, done_max = 0;
   phase_begin(h, kPhSolve);
   for (int32_t c = 0; c < nrhs; ++c) {
     const double* bc = b + (int64_t)c * ldb;
     double* xc = x + (int64_t)c * ldb;
-    SPI_CK(launch_solve_pass(h, bc, xc), "solve");
-    for (int s = 0; s < h.opts.refine_steps; ++s) {
-      SPI_CK(launch_residual_dd(h, bc, xc, h.vres), "residual");
-      SPI_CK(launch_solve_pass(h, h.vres, h.vx), "correction");
-      SPI_CK(hipMemsetAsync(h.vnorm, 0, 2 * sizeof(double), h.stream), "norms");
-      SPI_CK(launch_axpy_norms(h, xc, h.vx), "update");
+    const double* src = bc;
+    double* dst = xc;
+    if (eq) {
+      SPI_CK(launch_scale_vec(h, bc, h.vbh, 0), "scale rhs");
+      src = h.vbh;
+      dst = h.vxh;
     }
+    SPI_CK(launch_solve_pass(h, src, dst), "solve");
+    bool converged = tol <= 0.0;
+    int done = 0;
+    for (int s = 0; s < h.opts.refine_steps; ++s) {
+      SPI_CK(launch_residual_dd(h, src, dst, h.vres), "residual");
+      SPI_CK(launch_solve_pass(h, h.vres, h.vx), "correction");
+      SPI_CK(fill_f64(h.stream, h.vnorm, 0.0, 2), "norms");
+      SPI_CK(launch_axpy_norms(h, dst, h.vx), "update");
+      ++done;
+      if (tol > 0.0) {
+        double nv[2];
+        SPI_CK(hipMemcpyAsync(nv, h.vnorm, sizeof(nv), hipMemcpyDeviceToHost,
+                              h.stream), "norm readback");
+        SPI_CK(hipStreamSynchronize(h.stream), "refinement");
+        if (nv[0] <= tol * nv[1]) {
+          converged = true;
+          break;
+        }
+      }
+    }
+    if (eq) SPI_CK(launch_scale_vec(h, h.vxh, xc, 0), "scale solution");
+    done_max = std::max(done_max, done);
+    if (!converged) status = SPI_E_NOCONV;
   }
   phase_end(h, kPhSolve);
-  h.refine_done = h.opts.refine_steps;
+  h.refine_done = done_max;
+  if (status != SPI_OK)
+    return fail(h, status, hipSuccess,
+                "iterative refinement did not reach refine_tol");
   return SPI_OK;
 }
 
@@ -338,6 +377,8 @@ int spi_diag_inv(spi_handle* H, double* d) {
   phase_begin(h, kPhSelinv);
   if (h.an.n_pad) SPI_CK(launch_diag_root(h, d), "root diagonal");
   SPI_CK(launch_selinv_leaves(h, d), "leaf selected inversion");
+  // (S A S)^-1 = S^-1 A^-1 S^-1: undo the scaling, d_i = s_i^2 d'_i
+  if (h.opts.equilibrate) SPI_CK(launch_scale_vec(h, d, d, 2), "scale variances");
   phase_end(h, kPhSelinv);
   return SPI_OK;
 }

@@ -301,6 +301,7 @@ constexpr int kNBO = 256;
 // kNB diagonal blocks, their panel solves, and the updates of the panel's
 // remaining columns.
 static hipError_t factor_panel(Handle& h, hipStream_t s, int K0, int KB) {
+  const bool f32 = h.opts.precision == SPI_MIXED;
   const int np = (int)h.an.n_pad;
   const int64_t ld = np;
   const int64_t base = (int64_t)h.an.leaf_cols.size();
@@ -316,14 +317,14 @@ static hipError_t factor_panel(Handle& h, hipStream_t s, int K0, int KB) {
     // owns whole rows of the 64-wide panel, so it is safe in place)
     double* Pp = h.S + (int64_t)(k0 + kNB) + (int64_t)k0 * ld;
     e = gemm(s, pick_bm(rest), 64, kXC, kXC, Pp, ld, inv, kNB, Pp, ld, rest,
-             kNB, kNB, 1.0, 0.0, false, false);
+             kNB, kNB, 1.0, 0.0, false, false, false, f32);
     if (e != hipSuccess) return e;
     const int ncols = K0 + KB - k0 - kNB;  // panel columns still to update
     if (ncols > 0) {
       double* P = h.S + (int64_t)(k0 + kNB) + (int64_t)k0 * ld;
       double* C = h.S + (int64_t)(k0 + kNB) * (ld + 1);
       e = gemm(s, pick_bm(rest), 64, kXC, kXC, P, ld, P, ld, C, ld, rest, ncols,
-               kNB, -1.0, 1.0, false, false, true);
+               kNB, -1.0, 1.0, false, false, true, f32);
       if (e != hipSuccess) return e;
     }
   }
@@ -353,6 +354,7 @@ static hipError_t ensure_side_stream(Handle& h) {
 // of the trailing update (T2); the two touch disjoint columns.  Then the
 // inverses of all kNB diagonal blocks (used by the factor inversion).
 hipError_t root_potrf(Handle& h) {
+  const bool f32 = h.opts.precision == SPI_MIXED;
   const int np = (int)h.an.n_pad;
   const int64_t ld = np;
   hipError_t e;
@@ -368,7 +370,7 @@ hipError_t root_potrf(Handle& h) {
     // T1: next panel's columns [K1, K1 + KB2), all rows >= K1
     e = gemm(h.stream, pick_bm(rest), (KB2 % 128 == 0) ? 128 : 64, kXC, kXC, P,
              ld, P, ld, h.S + (int64_t)K1 * (ld + 1), ld, rest, KB2, KB, -1.0,
-             1.0, false, false, true);
+             1.0, false, false, true, f32);
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(h.ev_next, h.stream)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(h.side, h.ev_next, 0)) != hipSuccess) return e;
@@ -380,7 +382,7 @@ hipError_t root_potrf(Handle& h) {
       const int t = (r2 % 128 == 0) ? 128 : 64;
       e = gemm(h.stream, t, t, kXC, kXC, P + KB2, ld, P + KB2, ld,
                h.S + (int64_t)(K1 + KB2) * (ld + 1), ld, r2, r2, KB, -1.0, 1.0,
-               true, false);
+               true, false, false, f32);
       if (e != hipSuccess) return e;
     }
     if ((e = hipStreamWaitEvent(h.stream, h.ev_panel, 0)) != hipSuccess) return e;
@@ -422,6 +424,7 @@ static hipError_t copy2d(hipStream_t s, const double* src, int64_t lds,
 //   S_kk     = X_kk
 // The two in-place products read their input from a scratch copy.
 hipError_t root_trtri(Handle& h) {
+  const bool f32 = h.opts.precision == SPI_MIXED;
   const int np = (int)h.an.n_pad;
   const int64_t ld = np;
   hipError_t e;
@@ -440,11 +443,11 @@ hipError_t root_trtri(Handle& h) {
       if ((e = copy2d(h.stream, W21, ld, h.scratch, ld, rest, KB)) != hipSuccess)
         return e;
       e = gemm(h.stream, pick_bm(rest), bk, kXC, kKC, h.scratch, ld, X11, kNBO,
-               W21, ld, rest, KB, KB, 1.0, 0.0, false, false);
+               W21, ld, rest, KB, KB, 1.0, 0.0, false, false, false, f32);
       if (e != hipSuccess) return e;
       if (K0 > 0) {
         e = gemm(h.stream, pick_bm(rest), 128, kXC, kKC, W21, ld, W10, ld, W20,
-                 ld, rest, K0, KB, -1.0, 1.0, false, false);
+                 ld, rest, K0, KB, -1.0, 1.0, false, false, false, f32);
         if (e != hipSuccess) return e;
       }
     }
@@ -452,7 +455,7 @@ hipError_t root_trtri(Handle& h) {
       if ((e = copy2d(h.stream, W10, ld, h.scratch, kNBO, KB, K0)) != hipSuccess)
         return e;
       e = gemm(h.stream, bk, 128, kXC, kKC, X11, kNBO, h.scratch, kNBO, W10, ld,
-               KB, K0, KB, -1.0, 0.0, false, false);
+               KB, K0, KB, -1.0, 0.0, false, false, false, f32);
       if (e != hipSuccess) return e;
     }
     if ((e = copy2d(h.stream, X11, kNBO, h.W + (int64_t)K0 * (ld + 1), ld, KB,
@@ -463,7 +466,10 @@ hipError_t root_trtri(Handle& h) {
 }
 
 // Z = W^T W (lower tiles); tile (I, J) sums over K >= I since W is lower
-// triangular with stored zeros above the diagonal.
+// triangular with stored zeros above the diagonal.  Always FP64: these sums
+// are the diagonal accumulation of the selected inversion, and an FP32
+// accumulation over n_R terms would cost about sqrt(n_R / 4) binary32
+// roundings of relative error in the variances.
 hipError_t root_lauum(Handle& h) {
   const int np = (int)h.an.n_pad;
   return gemm(h.stream, 128, 128, kKC, kKC, h.W, np, h.W, np, h.Z, np, np, np,

@@ -1,8 +1,13 @@
-// Tiled FP64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4f64).
+// Tiled GEMM on the gfx950 matrix cores, FP64 data in and out.
 //
 // The bulk of the root front's Cholesky factorisation, of the inversion of
 // its factor and of the product giving the root block of A^-1 are dense
-// contractions; they all go through this one kernel.
+// contractions; they all go through this one kernel.  The compute type T is
+// double (v_mfma_f64_16x16x4f64) or, for the mixed-precision path, float
+// (v_mfma_f32_16x16x4f32): operands are rounded to T when staged in LDS and
+// accumulated in T over the K range of one launch; the epilogue combines
+// the result with C in FP64, so sums across launches (the panels of a
+// blocked factorisation) are FP64.
 //
 // C[i, j] = beta * C[i, j] + alpha * sum_k opA(i, k) * opB(k, j)
 // Operand access:
@@ -26,6 +31,18 @@
 namespace spi {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef v4d type; };
+template <> struct Acc<float> { typedef v4f type; };
+
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
 constexpr int kKT = 32;
 constexpr int kGroup = 8;      // tile rows per group of the launch order
@@ -99,14 +116,14 @@ __device__ inline int xcd_remap(int w, int n) {
   return (w & ~63) + 8 * (r & 7) + (r >> 3);
 }
 
-template <int BM, int BN, int OPA, int OPB>
+template <int BM, int BN, int OPA, int OPB, typename T>
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int MI = WM / 16, NI = WN / 16;
   constexpr int A_SZ = (OPA == kXC) ? kKT * (BM + kPadXC) : BM * kStrKC;
   constexpr int B_SZ = (OPB == kXC) ? kKT * (BN + kPadXC) : BN * kStrKC;
-  __shared__ double As[A_SZ];
-  __shared__ double Bs[B_SZ];
+  __shared__ T As[A_SZ];
+  __shared__ T Bs[B_SZ];
 
   int I, J;
   tile_of(g, xcd_remap(blockIdx.x, g.n_tiles), I, J);
@@ -145,25 +162,26 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
       }
     }
   };
-  auto store = [&](double* L, int op, int X, int E, const double* r) {
+  auto store = [&](T* L, int op, int X, int E, const double* r) {
     if (op == kXC) {
       const int tpr = X / E;
       const int kk = tid / tpr, x = (tid % tpr) * E;
 #pragma unroll
-      for (int e = 0; e < E; ++e) L[kk * (X + kPadXC) + x + e] = r[e];
+      for (int e = 0; e < E; ++e) L[kk * (X + kPadXC) + x + e] = (T)r[e];
     } else {
       const int tpx = kKT / E;
       const int x = tid / tpx, kk = (tid % tpx) * E;
 #pragma unroll
-      for (int e = 0; e < E; ++e) L[x * kStrKC + kk + e] = r[e];
+      for (int e = 0; e < E; ++e) L[x * kStrKC + kk + e] = (T)r[e];
     }
   };
 
-  v4d acc[MI][NI];
+  typedef typename Acc<T>::type VA;
+  VA acc[MI][NI];
 #pragma unroll
   for (int a = 0; a < MI; ++a)
 #pragma unroll
-    for (int b = 0; b < NI; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NI; ++b) acc[a][b] = VA{0, 0, 0, 0};
 
   if (kbeg < kend) {
     load(g.A, g.lda, i0, kbeg, OPA, BM, EA, ra);
@@ -181,7 +199,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
     }
 #pragma unroll
     for (int ks = 0; ks < kKT; ks += 4) {
-      double fa[MI], fb[NI];
+      T fa[MI], fb[NI];
 #pragma unroll
       for (int a = 0; a < MI; ++a) {
         const int x = wm * WM + a * 16 + lx, kk = ks + lk;
@@ -192,16 +210,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
         const int x = wn * WN + b * 16 + lx, kk = ks + lk;
         fb[b] = (OPB == kXC) ? Bs[kk * (BN + kPadXC) + x] : Bs[x * kStrKC + kk];
       }
-      // D = Bfrag^T * Afrag.  The 16x16 result D[r][c] sits in lane
-      // c + 16 * (r % 4), item r / 4; with the operands swapped, lane
-      // (lx, lk) item v holds output row i = lx and column j = 4 * v + lk,
-      // which keeps the stores of a column-major C contiguous over 16 rows.
+      // D = Bfrag^T * Afrag, so lane (lx, lk) holds output row i = lx of
+      // the 16 x 16 block (column-major stores of C stay contiguous over 16
+      // rows).  Its column for item v follows the instruction's result
+      // layout: FP64 puts D[r][c] in lane c + 16 (r % 4), item r / 4, so
+      // j = 4 v + lk; FP32 puts it in lane c + 16 (r / 4), item r % 4, so
+      // j = 4 lk + v.
 #pragma unroll
       for (int a = 0; a < MI; ++a)
 #pragma unroll
-        for (int b = 0; b < NI; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[b], fa[a],
-                                                           acc[a][b], 0, 0, 0);
+        for (int b = 0; b < NI; ++b) acc[a][b] = mfma16(fb[b], fa[a], acc[a][b]);
     }
   }
 
@@ -212,23 +230,24 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + wm * WM + a * 16 + lx;
-        const int j = j0 + wn * WN + b * 16 + v * 4 + lk;
+        const int j = j0 + wn * WN + b * 16 +
+                      (sizeof(T) == 8 ? v * 4 + lk : lk * 4 + v);
         if (((g.lower && I == J) || g.diag_mask) && i < j) continue;
         double* c = g.C + (int64_t)i + (int64_t)j * g.ldc;
-        double r = g.alpha * acc[a][b][v];
+        double r = g.alpha * (double)acc[a][b][v];
         if (g.beta != 0.0) r += g.beta * (*c);
         *c = r;
       }
 }
 
-template <int BM, int BN, int OPA, int OPB>
+template <int BM, int BN, int OPA, int OPB, typename T>
 static hipError_t gemm_t(hipStream_t s, const GemmArgs& a0) {
   GemmArgs a = a0;
   a.tiles_m = a.M / BM;
   a.tiles_n = a.N / BN;
   a.n_tiles = a.lower ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n;
   if (a.n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm<BM, BN, OPA, OPB>), dim3(a.n_tiles), dim3(256), 0,
+  hipLaunchKernelGGL((k_gemm<BM, BN, OPA, OPB, T>), dim3(a.n_tiles), dim3(256), 0,
                      s, a);
   return hipGetLastError();
 }
@@ -236,7 +255,8 @@ static hipError_t gemm_t(hipStream_t s, const GemmArgs& a0) {
 hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* C, int64_t ldc, int M, int N, int K, double alpha,
-                double beta, bool lower, bool kstart_diag, bool diag_mask) {
+                double beta, bool lower, bool kstart_diag, bool diag_mask,
+                bool f32) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (M % bm || N % bn || K % kKT || (lower && (bm != bn || M != N)))
     return hipErrorInvalidValue;
@@ -244,7 +264,8 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
              kstart_diag ? 1 : 0, diag_mask ? 1 : 0, 0, 0, 0};
 #define SPI_GEMM_CASE(BM_, BN_, OA, OB)                                   \
   if (bm == BM_ && bn == BN_ && opA == OA && opB == OB)                  \
-    return gemm_t<BM_, BN_, OA, OB>(s, a);
+    return f32 ? gemm_t<BM_, BN_, OA, OB, float>(s, a)                   \
+               : gemm_t<BM_, BN_, OA, OB, double>(s, a);
 #define SPI_GEMM_OPS(BM_, BN_)          \
   SPI_GEMM_CASE(BM_, BN_, kXC, kXC)     \
   SPI_GEMM_CASE(BM_, BN_, kXC, kKC)     \

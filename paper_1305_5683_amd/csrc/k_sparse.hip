@@ -303,6 +303,101 @@ hipError_t launch_assemble_root(Handle& h) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ equilibration
+// Symmetric diagonal scaling A -> S A S with S = diag(s), applied as a column
+// scaling of H (H -> H S).  s_c is the power of two 2^-floor(log2(A_cc) / 2),
+// A_cc = sum_r w_r h_rc^2, so the scaled diagonal lies in [1, 4).  Powers of
+// two make the scaling exact: every product, sum, square root and quotient
+// of the factorisation of S A S is the scaled image of the same operation
+// on A, so it changes no rounding; what it buys is range (the FP32
+// intermediates of the mixed-precision path stay finite whatever the
+// column scales of H).  Columns with a zero or non-finite diagonal keep
+// s_c = 1 and fail at their pivot as before.
+__global__ __launch_bounds__(256) void k_col_scale(
+    const int64_t* __restrict__ colptr, const int64_t* __restrict__ csc_pos,
+    const int32_t* __restrict__ csc_row, const double* __restrict__ val,
+    const double* __restrict__ w, double* __restrict__ scale, int64_t n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  double d = 0.0;
+  for (int64_t k = colptr[c] + lane; k < colptr[c + 1]; k += 64) {
+    const double v = val[csc_pos[k]];
+    d += w[csc_row[k]] * v * v;
+  }
+  for (int off = 32; off > 0; off >>= 1) d += __shfl_down(d, off, 64);
+  if (lane == 0) {
+    double s = 1.0;
+    if (d > 0.0 && d <= 1.7976931348623157e308) {
+      const int e = ilogb(d);     // d = m 2^e, 1 <= m < 2
+      s = ldexp(1.0, -(e >> 1));  // arithmetic shift: floor(e / 2)
+    }
+    scale[c] = s;
+  }
+}
+
+__global__ void k_scale_vals(double* __restrict__ val, const int32_t* __restrict__ col,
+                             const double* __restrict__ scale, int64_t nnz) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x)
+    val[e] *= scale[col[e]];
+}
+
+// y = s x (mode 0), x / s (mode 1), s^2 x (mode 2); exact for powers of two.
+__global__ void k_scale_vec(const double* x, const double* __restrict__ s, double* y,
+                            int64_t n, int mode) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double si = s[i];
+    y[i] = mode == 0 ? x[i] * si : (mode == 1 ? x[i] / si : x[i] * si * si);
+  }
+}
+
+hipError_t launch_equilibrate(Handle& h) {
+  const Analysis& a = h.an;
+  hipLaunchKernelGGL(k_col_scale, dim3(grid_for(a.n, 4)), dim3(256), 0, h.stream,
+                     h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.w, h.colscale,
+                     a.n);
+  if (a.nnz)
+    hipLaunchKernelGGL(k_scale_vals, dim3((unsigned)std::min<int64_t>(
+                                         (a.nnz + 255) / 256, 16384)),
+                       dim3(256), 0, h.stream, h.val, h.d.col, h.colscale, a.nnz);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_vec(Handle& h, const double* x, double* y, int mode) {
+  const int64_t n = h.an.n;
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_vec, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)),
+                     dim3(256), 0, h.stream, x, h.colscale, y, n, mode);
+  return hipGetLastError();
+}
+
+// Fill kernels (used instead of hipMemsetAsync so that a captured graph
+// holds only kernel nodes).
+__global__ void k_fill_i64(int64_t* p, int64_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_f64(double* p, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+hipError_t fill_i64(hipStream_t s, int64_t* p, int64_t v, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)),
+                     dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t fill_f64(hipStream_t s, double* p, double v, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)),
+                     dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ rhs
 // b_c = sum_{r} h_rc w_r y_r over the column's entries (one wave per column).
 __global__ __launch_bounds__(256) void k_rhs(const int64_t* __restrict__ colptr,
@@ -311,6 +406,7 @@ __global__ __launch_bounds__(256) void k_rhs(const int64_t* __restrict__ colptr,
                                              const double* __restrict__ val,
                                              const double* __restrict__ w,
                                              const double* __restrict__ y,
+                                             const double* __restrict__ scale,
                                              double* __restrict__ b, int64_t n) {
   const int lane = threadIdx.x & 63;
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -321,13 +417,14 @@ __global__ __launch_bounds__(256) void k_rhs(const int64_t* __restrict__ colptr,
     s += val[csc_pos[k]] * (w[r] * y[r]);
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) b[c] = s;
+  // val holds H S: undo the (power-of-two, exact) column scale
+  if (lane == 0) b[c] = scale ? s / scale[c] : s;
 }
 
 hipError_t launch_rhs(Handle& h, const double* y, double* b) {
   hipLaunchKernelGGL(k_rhs, dim3(grid_for(h.an.n, 4)), dim3(256), 0, h.stream,
-                     h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.w, y, b,
-                     h.an.n);
+                     h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.w, y,
+                     h.opts.equilibrate ? h.colscale : nullptr, b, h.an.n);
   return hipGetLastError();
 }
 

@@ -199,6 +199,9 @@ struct Handle {
   double* vnorm = nullptr;   // 2 (norm reductions)
   double* vroot2 = nullptr;  // n_pad
   double* vpart = nullptr;   // partial products of the root GEMV
+  double* colscale = nullptr;  // equilibration: power-of-two column scales s
+  double* vbh = nullptr;     // n: scaled right-hand side S b
+  double* vxh = nullptr;     // n: solution of the scaled system
   bool have_inv = false;     // W = L_RR^-1 is valid
   // phase timing (opts.timing): HIP event pairs recorded on the stream,
   // accumulated lazily (spi_info synchronises and sums them)
@@ -230,6 +233,11 @@ hipError_t launch_residual_dd(Handle& h, const double* b, const double* x,
 hipError_t launch_axpy_norms(Handle& h, double* x, const double* dx);
 hipError_t launch_selinv_leaves(Handle& h, double* d);
 hipError_t launch_diag_root(Handle& h, double* d);
+hipError_t launch_equilibrate(Handle& h);
+// y = s x (mode 0), x / s (mode 1), s^2 x (mode 2) with the column scales
+hipError_t launch_scale_vec(Handle& h, const double* x, double* y, int mode);
+hipError_t fill_i64(hipStream_t s, int64_t* p, int64_t v, int64_t n);
+hipError_t fill_f64(hipStream_t s, double* p, double v, int64_t n);
 
 // dense kernels, exposed for tests of the root-front building blocks
 enum GemmOp { kXC = 0, kKC = 1 };  // operand access, see k_dense.hip
@@ -237,6 +245,6 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* C, int64_t ldc, int M, int N, int K, double alpha,
                 double beta, bool lower, bool kstart_diag,
-                bool diag_mask = false);
+                bool diag_mask = false, bool f32 = false);
 
 }  // namespace spi

@@ -28,7 +28,8 @@ class spi_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_group", C.c_int32),
                 ("leaf_max_work", C.c_double), ("amalg_density", C.c_double),
                 ("refine_steps", C.c_int32), ("timing", C.c_int32),
-                ("root_inverse", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("root_inverse", C.c_int32), ("equilibrate", C.c_int32),
+                ("refine_tol", C.c_double), ("reserved", C.c_int32 * 2)]
 
 
 class spi_info_t(C.Structure):
