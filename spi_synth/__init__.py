@@ -322,3 +322,18 @@ def make_random_leafy(n_groups: int, leaf_per_group: int, n_root: int,
     return Problem(m=mm, n=n, n_bg=n_leaf, rowptr=rowptr, col=col, val=val,
                    w=w, y=y, x_true=x_true, seed=seed,
                    name=f"leafy{n_groups}x{leaf_per_group}+{n_root}")
+
+
+def lp_init_params(hidden: int, seed: int = 0) -> np.ndarray:
+    """Seeded initial weights of the learned-preconditioner network (float32,
+    flat layout [W1 (H x 3), b1, W2 (H x H), b2, w3, b3, wl (3)]):
+    Gaussian weights scaled by 1/sqrt(fan-in), zero biases, zero skip.
+    Only random draws: the network itself is defined elsewhere."""
+    rng = np.random.default_rng(seed)
+    H, F = hidden, 3
+    W1 = rng.standard_normal((H, F)) / np.sqrt(F)
+    W2 = rng.standard_normal((H, H)) / np.sqrt(H)
+    w3 = rng.standard_normal(H) / np.sqrt(H) * 0.1
+    p = np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), w3,
+                        [0.0], np.zeros(F)])
+    return p.astype(np.float32)
