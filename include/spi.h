@@ -233,6 +233,94 @@ const char* spi_last_error(const spi_handle* h);
 /* Free the handle and all its device memory (synchronises its stream). */
 void spi_destroy(spi_handle* h);
 
+/* ------------------------------------------------------------------------
+ * Learned preconditioner for many bands on one pattern
+ * ------------------------------------------------------------------------
+ * The energy bands of one observation share the pattern of H and differ in
+ * W and y (Sect. 2.2.3).  Iterative methods need a good preconditioner to
+ * converge (Sect. 3.1).  Here the direct factor of a reference band r
+ * (a handle after spi_factor) preconditions conjugate gradients on a later
+ * band b.  A small network corrects it with a per-unknown diagonal:
+ *
+ *     M^-1 = D A_r^-1 D,   D = diag(d),   d_j = exp(g(f_j))
+ *
+ * Features of unknown j:
+ *     f0 = log(A_b,jj / A_r,jj)
+ *     f1 = 1 for a root-front unknown, else 0
+ *     f2 = mean of f0 over the unknowns of the same kind
+ * Network (hidden width HID in {8, 16, 32}, binary32, shared by all unknowns):
+ *     h1 = tanh(W1 f + b1),  h2 = tanh(W2 h1 + b2),  g = w3.h2 + b3 + wl.f
+ * Parameters are stored flat, in binary32, in this order:
+ *     W1 (HID x 3, row-major), b1 (HID), W2 (HID x HID, row-major),
+ *     b2 (HID), w3 (HID), b3 (1), wl (3)
+ * Training loss on a band with direct solution x of A_b x = rhs:
+ *     L = e^T A_b e / (2 x^T rhs),   e = M^-1 rhs - x
+ * The forward and backward passes and the Adam update run on the GPU.
+ * Every call below runs on the band handle's stream.  The reference handle
+ * must use the same stream and the same pattern.
+ */
+typedef struct spi_lp spi_lp;
+
+/* Number of parameters for hidden width `hidden`, or -1 if unsupported. */
+int64_t spi_lp_param_count(int32_t hidden);
+
+/* New network with the given initial parameters (host, binary32,
+ * spi_lp_param_count(hidden) values, layout above); Adam state zero. */
+int spi_lp_create(spi_lp** lp, int32_t hidden, const float* params);
+
+/* Copy the current parameters to `params` (host, binary32). */
+int spi_lp_get_params(const spi_lp* lp, float* params);
+
+/*
+ * Training loss of one band, and optionally its gradient.
+ *  band  handle with the band's values (spi_set_values)
+ *  ref   factored reference handle
+ *  rhs   device, float64[n]: right-hand side of the band
+ *  x     device, float64[n]: its direct solution
+ *  loss  host, written
+ *  grad  host, float64[param_count] or NULL: dL/dparams (synchronises)
+ * Costs two solves with the reference factor and one product with A_b.
+ */
+int spi_lp_loss_grad(spi_lp* lp, spi_handle* band, spi_handle* ref,
+                     const double* rhs, const double* x, double* loss,
+                     double* grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on one band's loss, with
+ * learning rate lr; `loss` (host) receives the loss before the step. */
+int spi_lp_train_step(spi_lp* lp, spi_handle* band, spi_handle* ref,
+                      const double* rhs, const double* x, double lr,
+                      double* loss);
+
+void spi_lp_destroy(spi_lp* lp);
+
+typedef struct spi_pcg_info {
+    int32_t iterations;     /* inner binary32 CG iterations, all passes */
+    int32_t outer;          /* binary64 residual passes */
+    int32_t fell_back;      /* 1: tolerance not met, solved by spi_factor +
+                               spi_solve on the band instead */
+    int32_t reserved;
+    double rel_residual;    /* ||b - A x||_2 / ||b||_2 of the returned x, binary64 */
+} spi_pcg_info;
+
+/*
+ * Solve A_b x = b by preconditioned conjugate gradients with M^-1 above
+ * (lp = NULL: no correction, d = 1).  The method is iterative refinement in
+ * binary64: each pass takes the true residual r = b - A_b x, accumulated in
+ * double-double from H.  Within a pass, conjugate gradients in binary32
+ * solve A_b e = r to a relative residual of 1e-5, with products by H and
+ * H^T in binary32; the preconditioner applies the reference factor's
+ * binary64 solves.  Then x += e.
+ * Stops when ||b - A_b x|| <= tol ||b|| (binary64).
+ * If `maxit` inner iterations do not get there, the band is factored and
+ * solved directly (its own multifrontal factor) and `fell_back` is set.
+ *  b, x  device, float64[n];  tol > 0;  maxit >= 1
+ *  info  host, may be NULL
+ * Synchronises the stream (the scalars of CG are read back every iteration).
+ */
+int spi_pcg_solve(spi_handle* band, spi_handle* ref, const spi_lp* lp,
+                  const double* b, double* x, double tol, int32_t maxit,
+                  spi_pcg_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,10 +11,6 @@
 
 using namespace spi;
 
-struct spi_handle {
-  Handle h;
-};
-
 namespace {
 
 thread_local std::string g_analyze_err;
@@ -36,20 +32,6 @@ hipError_t dev_alloc(T*& dst, int64_t count) {
   return hipMalloc((void**)&dst, (size_t)count * sizeof(T));
 }
 
-int fail(Handle& h, int code, hipError_t e, const char* what) {
-  std::ostringstream os;
-  os << what;
-  if (e != hipSuccess) os << ": " << hipGetErrorString(e);
-  h.err = os.str();
-  if (e == hipErrorOutOfMemory) return SPI_E_OOM;
-  return code;
-}
-
-#define SPI_CK(expr, what)                                        \
-  do {                                                            \
-    hipError_t e_ = (expr);                                       \
-    if (e_ != hipSuccess) return fail(h, SPI_E_HIP, e_, what);    \
-  } while (0)
 
 // ---- phase timers: event pairs on the handle's stream
 hipEvent_t take_event(PhaseTimer& t) {
@@ -121,7 +103,8 @@ void free_all(Handle& h) {
                   h.val, h.w, h.sw, h.sleaf, h.rrval, h.panel, h.ldiag, h.S,
                   h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
                   h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2, h.scratch,
-                  h.colscale, h.vbh, h.vxh};
+                  h.colscale, h.vbh, h.vxh, h.diagA, d.root_of_col};
+  free_lp_work(h);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -196,7 +179,7 @@ int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
   UP(rinc_grp); UP(rinc_u); UP(tasks); UP(grp_task_ptr); UP(task_part_off);
   UP(sel_order); UP(rp_rows); UP(rp_rowbase); UP(rpe_ptr); UP(rpe_pos);
   UP(rpe_src); UP(up_U_off); UP(up_Q_off); UP(up_nU); UP(up_k); UP(up_w_off);
-  UP(tile_order); UP(inc_ptr); UP(inc);
+  UP(tile_order); UP(inc_ptr); UP(inc); UP(root_of_col);
 #undef UP
   const int64_t nl = (int64_t)a.leaf_cols.size();
   const int64_t np = a.n_pad;
@@ -213,7 +196,7 @@ int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
   AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 2);
   AL(h.vroot2, np); AL(h.vpart, root_inv_part_size(np));
   AL(h.invd2, ((np + 255) / 256) * 256 * 256); AL(h.scratch, np * 256);
-  AL(h.colscale, a.n); AL(h.vbh, a.n); AL(h.vxh, a.n);
+  AL(h.colscale, a.n); AL(h.vbh, a.n); AL(h.vxh, a.n); AL(h.diagA, a.n);
 #undef AL
   if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
   if (he != hipSuccess) {
@@ -236,7 +219,8 @@ int spi_set_values(spi_handle* H, const double* val, const double* w) {
                         hipMemcpyDeviceToDevice, h.stream), "copy values");
   SPI_CK(hipMemcpyAsync(h.w, w, h.an.m * sizeof(double),
                         hipMemcpyDeviceToDevice, h.stream), "copy weights");
-  if (h.opts.equilibrate) SPI_CK(launch_equilibrate(h), "equilibration");
+  SPI_CK(launch_equilibrate(h), "diagonal / equilibration");
+  h.val32_ok = false;
   SPI_CK(launch_gather_values(h), "gather values");
   SPI_CK(launch_fill_rowpanels(h), "row panels");
   h.have_values = true;

@@ -316,7 +316,8 @@ hipError_t launch_assemble_root(Handle& h) {
 __global__ __launch_bounds__(256) void k_col_scale(
     const int64_t* __restrict__ colptr, const int64_t* __restrict__ csc_pos,
     const int32_t* __restrict__ csc_row, const double* __restrict__ val,
-    const double* __restrict__ w, double* __restrict__ scale, int64_t n) {
+    const double* __restrict__ w, double* __restrict__ diag,
+    double* __restrict__ scale, int64_t n) {
   const int lane = threadIdx.x & 63;
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= n) return;
@@ -327,12 +328,13 @@ __global__ __launch_bounds__(256) void k_col_scale(
   }
   for (int off = 32; off > 0; off >>= 1) d += __shfl_down(d, off, 64);
   if (lane == 0) {
+    diag[c] = d;
     double s = 1.0;
     if (d > 0.0 && d <= 1.7976931348623157e308) {
       const int e = ilogb(d);     // d = m 2^e, 1 <= m < 2
       s = ldexp(1.0, -(e >> 1));  // arithmetic shift: floor(e / 2)
     }
-    scale[c] = s;
+    if (scale) scale[c] = s;
   }
 }
 
@@ -353,12 +355,15 @@ __global__ void k_scale_vec(const double* x, const double* __restrict__ s, doubl
   }
 }
 
+// diag(A) into h.diagA, and with opts.equilibrate the column scales and
+// the scaled values of H.
 hipError_t launch_equilibrate(Handle& h) {
   const Analysis& a = h.an;
+  const bool eq = h.opts.equilibrate != 0;
   hipLaunchKernelGGL(k_col_scale, dim3(grid_for(a.n, 4)), dim3(256), 0, h.stream,
-                     h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.w, h.colscale,
-                     a.n);
-  if (a.nnz)
+                     h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.w, h.diagA,
+                     eq ? h.colscale : nullptr, a.n);
+  if (eq && a.nnz)
     hipLaunchKernelGGL(k_scale_vals, dim3((unsigned)std::min<int64_t>(
                                          (a.nnz + 255) / 256, 16384)),
                        dim3(256), 0, h.stream, h.val, h.d.col, h.colscale, a.nnz);
@@ -497,7 +502,7 @@ __global__ __launch_bounds__(256) void k_htt_dd(const int64_t* __restrict__ colp
   }
   for (int off = 32; off > 0; off >>= 1) s = dd_add(s, shfl_down_dd(s, off));
   if (lane == 0) {
-    dd v = dd_add(dd{b[c], 0.0}, dd{-s.hi, -s.lo});
+    dd v = dd_add(dd{b ? b[c] : 0.0, 0.0}, dd{-s.hi, -s.lo});
     r[c] = v.hi + v.lo;
   }
 }

@@ -150,6 +150,7 @@ struct DevAnalysis {
   int32_t* tile_order = nullptr;
   int64_t* inc_ptr = nullptr;
   int32_t* inc = nullptr;
+  int32_t* root_of_col = nullptr;  // n: root index of a column, -1 for leaves
 };
 
 enum Phase { kPhLeaf = 0, kPhExtend, kPhPotrf, kPhSolve, kPhTrtri, kPhLauum,
@@ -202,6 +203,18 @@ struct Handle {
   double* colscale = nullptr;  // equilibration: power-of-two column scales s
   double* vbh = nullptr;     // n: scaled right-hand side S b
   double* vxh = nullptr;     // n: solution of the scaled system
+  double* diagA = nullptr;   // n: diagonal of A = H^T W H (unscaled)
+  // scratch of the learned preconditioner and of PCG, allocated on first use
+  struct LpWork {
+    float* v32 = nullptr;                   // nnz: H in binary32
+    float *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
+          *e = nullptr, *t = nullptr;       // n (t: m)
+    double *d = nullptr, *x = nullptr, *r64 = nullptr, *u = nullptr,
+           *v = nullptr, *w = nullptr, *g = nullptr, *part = nullptr;
+    float* phi = nullptr;                   // 3 n features
+    double* fpart = nullptr;                // feature partial sums
+  } lp;
+  bool val32_ok = false;
   bool have_inv = false;     // W = L_RR^-1 is valid
   // phase timing (opts.timing): HIP event pairs recorded on the stream,
   // accumulated lazily (spi_info synchronises and sums them)
@@ -213,6 +226,22 @@ struct Handle {
   double last_refine_norm = 0;
   std::string err;
 };
+
+// Failure helper of the entry points: records the text, maps OOM.
+inline int fail(Handle& h, int code, hipError_t e, const char* what) {
+  h.err = what;
+  if (e != hipSuccess) h.err += std::string(": ") + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory) return SPI_E_OOM;
+  return code;
+}
+
+#define SPI_CK(expr, what)                                               \
+  do {                                                                   \
+    hipError_t e_ = (expr);                                              \
+    if (e_ != hipSuccess) return ::spi::fail(h, SPI_E_HIP, e_, what);    \
+  } while (0)
+
+void free_lp_work(Handle& h);
 
 // kernel launchers (stream-ordered); return hipError_t of the launch
 hipError_t launch_gather_values(Handle& h);
@@ -247,4 +276,48 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 double beta, bool lower, bool kstart_diag,
                 bool diag_mask = false, bool f32 = false);
 
+// learned preconditioner and PCG (k_learned.hip)
+int64_t lp_param_count(int hidden);
+hipError_t lp_features(hipStream_t s, const double* diag_b, const double* diag_r,
+                       const int32_t* root_of_col, float* phi, double* part,
+                       int64_t n);
+int lp_backward_blocks(int64_t n);
+hipError_t lp_forward(hipStream_t s, int hidden, const float* params,
+                      const float* phi, double* d, int64_t n);
+hipError_t lp_backward(hipStream_t s, int hidden, const float* params,
+                       const float* phi, const double* dLdd, const double* d,
+                       double* part, double* grad, int64_t n);
+hipError_t lp_adam(hipStream_t s, float* params, const double* grad, float* m,
+                   float* v, int P, float lr, int step);
+hipError_t vec_mul(hipStream_t s, const double* a, const double* b, double* out,
+                   int64_t n);
+hipError_t lp_err(hipStream_t s, const double* d, const double* v, const double* x,
+                  double* e, int64_t n);
+hipError_t lp_u(hipStream_t s, const double* d, const double* q, double sc,
+                double* u, int64_t n);
+hipError_t lp_dldd(hipStream_t s, const double* q, double sc, const double* v,
+                   const double* rhs, const double* w, double* out, int64_t n);
+hipError_t vec_neg(hipStream_t s, const double* x, double* y, int64_t n);
+hipError_t vec_ones(hipStream_t s, double* x, int64_t n);
+hipError_t dot_partials64(hipStream_t s, const double* a, const double* b,
+                          double* part, int64_t n);
+hipError_t dot_partials32(hipStream_t s, const float* a, const float* b,
+                          double* part, int64_t n);
+int dot_blocks();
+hipError_t pcg_val32(Handle& h, float* v32);
+hipError_t pcg_spmv32(Handle& h, const float* v32, const float* p, float* t,
+                      float* q);
+hipError_t vec_to64(hipStream_t s, const float* in, const double* d, double* out,
+                    int64_t n);
+hipError_t vec_to32(hipStream_t s, const double* in, const double* d, float* out,
+                    int64_t n);
+hipError_t vec_axpy32(hipStream_t s, float a, const float* x, float* y, int64_t n);
+hipError_t vec_xpby32(hipStream_t s, const float* x, float b, float* y, int64_t n);
+hipError_t vec_acc64(hipStream_t s, const float* e, double* x, int64_t n);
+hipError_t vec_zero32(hipStream_t s, float* e, int64_t n);
+
 }  // namespace spi
+
+struct spi_handle {
+  spi::Handle h;
+};

@@ -21,7 +21,9 @@ _STATUS = {0: "SPI_OK", 1: "SPI_E_ARG", 2: "SPI_E_STATE", 3: "SPI_E_NOT_SPD",
 
 EXPORTED = ["spi_default_opts", "spi_analyze", "spi_set_values", "spi_factor",
             "spi_rhs", "spi_solve", "spi_diag_inv", "spi_symbolic", "spi_info",
-            "spi_last_error", "spi_destroy"]
+            "spi_last_error", "spi_destroy", "spi_lp_param_count",
+            "spi_lp_create", "spi_lp_get_params", "spi_lp_loss_grad",
+            "spi_lp_train_step", "spi_lp_destroy", "spi_pcg_solve"]
 
 
 class spi_opts(C.Structure):
@@ -48,6 +50,15 @@ class spi_info_t(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class spi_pcg_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("outer", C.c_int32),
+                ("fell_back", C.c_int32), ("reserved", C.c_int32),
+                ("rel_residual", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class SpiError(RuntimeError):
@@ -85,9 +96,19 @@ def load_library(path: str = LIB_PATH):
     lib.spi_last_error.restype = C.c_char_p
     lib.spi_destroy.argtypes = [P]
     lib.spi_destroy.restype = None
+    lib.spi_lp_param_count.argtypes = [I32]
+    lib.spi_lp_create.argtypes = [C.POINTER(C.c_void_p), I32, P]
+    lib.spi_lp_get_params.argtypes = [P, P]
+    lib.spi_lp_loss_grad.argtypes = [P, P, P, P, P, C.POINTER(D), P]
+    lib.spi_lp_train_step.argtypes = [P, P, P, P, P, D, C.POINTER(D)]
+    lib.spi_lp_destroy.argtypes = [P]
+    lib.spi_lp_destroy.restype = None
+    lib.spi_pcg_solve.argtypes = [P, P, P, P, P, D, I32, C.POINTER(spi_pcg_info)]
     for name in EXPORTED:
-        if name not in ("spi_default_opts", "spi_last_error", "spi_destroy"):
+        if name not in ("spi_default_opts", "spi_last_error", "spi_destroy",
+                        "spi_lp_destroy", "spi_lp_param_count"):
             getattr(lib, name).restype = C.c_int
+    lib.spi_lp_param_count.restype = C.c_int64
     del I64, I32, D
     _lib = lib
     return lib
@@ -212,3 +233,75 @@ class SpiSolver:
             self.close()
         except Exception:
             pass
+
+
+class SpiLearnedPrecond:
+    """The learned diagonal correction of a reference factor (see spi.h):
+    a small network on the GPU, trained by the library's own kernels."""
+
+    def __init__(self, hidden, params):
+        self.lib = load_library()
+        self.hidden = int(hidden)
+        self.P = int(self.lib.spi_lp_param_count(self.hidden))
+        if self.P < 0:
+            raise ValueError("hidden width must be 8, 16 or 32")
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.P:
+            raise ValueError(f"expected {self.P} parameters, got {p.size}")
+        h = C.c_void_p()
+        st = self.lib.spi_lp_create(C.byref(h), self.hidden, p.ctypes.data)
+        if st != SPI_OK:
+            raise SpiError(st, "spi_lp_create failed")
+        self.h = h
+
+    def params(self):
+        out = np.empty(self.P, dtype=np.float32)
+        st = self.lib.spi_lp_get_params(self.h, out.ctypes.data)
+        if st != SPI_OK:
+            raise SpiError(st, "spi_lp_get_params failed")
+        return out
+
+    def loss_grad(self, band: "SpiSolver", ref: "SpiSolver", rhs, x, grad=True):
+        import torch
+        loss = C.c_double()
+        g = np.empty(self.P, dtype=np.float64) if grad else None
+        band._check(self.lib.spi_lp_loss_grad(
+            self.h, band.h, ref.h, _ptr(rhs, band.n, torch.float64),
+            _ptr(x, band.n, torch.float64), C.byref(loss),
+            None if g is None else g.ctypes.data))
+        return loss.value, g
+
+    def train_step(self, band: "SpiSolver", ref: "SpiSolver", rhs, x, lr):
+        import torch
+        loss = C.c_double()
+        band._check(self.lib.spi_lp_train_step(
+            self.h, band.h, ref.h, _ptr(rhs, band.n, torch.float64),
+            _ptr(x, band.n, torch.float64), float(lr), C.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.spi_lp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pcg_solve(band: "SpiSolver", ref: "SpiSolver", b, lp=None, tol=1e-10,
+              maxit=500, out=None):
+    """x = A_band^-1 b by FP32 PCG with the reference factor (and the learned
+    correction ``lp``, if given), FP64 outer residuals, direct fallback.
+    Returns (x, info dict)."""
+    import torch
+    lib = load_library()
+    x = out if out is not None else torch.empty_like(b)
+    info = spi_pcg_info()
+    band._check(lib.spi_pcg_solve(
+        band.h, ref.h, None if lp is None else lp.h,
+        _ptr(b, band.n, torch.float64), _ptr(x, band.n, torch.float64),
+        float(tol), int(maxit), C.byref(info)))
+    return x, info.as_dict()
