@@ -106,7 +106,10 @@ typedef struct spi_opts {
 
 typedef struct spi_info_t {
     int64_t m, n, nnz_h;        /* shape of H and its non-zeros */
-    int64_t nnz_a;              /* non-zeros of A = H^T W H (both triangles) */
+    int64_t nnz_a;              /* non-zeros of A = H^T W H (both triangles);
+                                   -1 when counting them would cost more
+                                   than 2e10 visits (sum of squared row
+                                   lengths of H) */
     int64_t nnz_l;              /* non-zeros of L (lower, incl. diagonal, as stored) */
     int64_t n_leaf;             /* unknowns eliminated in leaf fronts */
     int64_t n_groups;           /* leaf fronts (amalgamated supernodes) */
@@ -221,6 +224,17 @@ int spi_symbolic(int64_t m, int64_t n, const int64_t* rowptr,
                  const int32_t* col, const spi_opts* opts, spi_info_t* info,
                  int32_t* elim_order, int32_t* col_parent, int32_t* front_of);
 
+/*
+ * A new handle on the same pattern as `src` (another energy band, Sect.
+ * 2.2.3): the host analysis of `src` is copied instead of recomputed, then
+ * uploaded and the device buffers sized as in spi_analyze.
+ *  opts    may be NULL (src's options); the analysis options (max_group,
+ *          leaf_max_work, amalg_density) must equal src's
+ *  stream  hipStream_t of the new handle
+ */
+int spi_analyze_like(spi_handle** h, const spi_handle* src, const spi_opts* opts,
+                     void* stream);
+
 /* Counters of the analysis and of the last calls; with opts.timing the
  * accumulated phase times since spi_analyze (synchronises the stream).
  * Host struct. */
@@ -320,6 +334,55 @@ typedef struct spi_pcg_info {
 int spi_pcg_solve(spi_handle* band, spi_handle* ref, const spi_lp* lp,
                   const double* b, double* x, double tol, int32_t maxit,
                   spi_pcg_info* info);
+
+/* ------------------------------------------------------------------------
+ * Batches: many systems in flight together
+ * ------------------------------------------------------------------------
+ * The paper solves its energy bands one after the other (Sect. 4.2).  A
+ * batch takes k handles of any patterns, each on its own stream (bands
+ * from spi_analyze_like, independent sub-problems from spi_analyze).  It
+ * enqueues each system's whole pipeline and synchronises once per stream
+ * at the end, so the systems overlap on the GPU.
+ */
+typedef struct spi_batch spi_batch;
+
+/* Group k distinct handles.  use_graphs = 1: on its first run, each
+ * handle's pipeline is captured into a HIP graph.  Later runs with the
+ * same buffer pointers replay the graph; new pointers re-capture it.  This
+ * needs non-NULL streams.  The handles stay owned by the caller and must
+ * outlive the batch. */
+int spi_batch_create(spi_batch** b, spi_handle* const* hs, int32_t k,
+                     int32_t use_graphs);
+
+/*
+ * For each system i (values already set with spi_set_values):
+ *  - spi_factor;
+ *  - rhs[i] = H^T W y[i];
+ *  - x[i] = A^-1 rhs[i], with exactly opts.refine_steps refinement steps
+ *    (no refine_tol read-back inside a batch);
+ *  - d[i] = diag(A^-1).
+ * y, rhs, x, d: host arrays of k device pointers.  d may be NULL, as may
+ * any d[i], to skip the variances.  status: host int32[k] or NULL, each
+ * system's status (SPI_E_NOT_SPD etc.).  Returns SPI_OK, or the first
+ * failing status.  All systems are finished on return.
+ */
+int spi_batch_run(spi_batch* b, const double* const* y, double* const* rhs,
+                  double* const* x, double* const* d, int32_t* status);
+
+void spi_batch_destroy(spi_batch* b);
+
+/*
+ * Autotuner of the root POTRF's outer block (128, 256 or 512 columns per
+ * trailing update with one-panel lookahead).  It times spi_factor on the
+ * handle's current values with each candidate, keeps the fastest, and
+ * leaves a factor computed with it.
+ *  chosen  host, may be NULL
+ */
+int spi_autotune(spi_handle* h, int32_t* chosen);
+/* Current outer block of the root POTRF, or -1 for a NULL handle. */
+int spi_get_potrf_block(const spi_handle* h);
+/* Set the outer block by hand: 128, 256 or 512. */
+int spi_set_potrf_block(spi_handle* h, int32_t block);
 
 #ifdef __cplusplus
 }

@@ -423,8 +423,17 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
       }
   }
 
-  // ---- counters: nnz(A) (both triangles), nnz(L) as stored, flops
-  {
+  // ---- counters: nnz(A) (both triangles), nnz(L) as stored, flops.
+  // The exact structural count of A costs sum over rows of len^2 scattered
+  // visits; above kNnzACountCap of them it is not taken (nnz_a = -1).
+  constexpr double kNnzACountCap = 2e10;
+  double visits = 0.0;
+  for (int64_t r = 0; r < m; ++r) {
+    const double len = (double)(rowptr[r + 1] - rowptr[r]);
+    visits += len * len;
+  }
+  a.nnz_a = -1;
+  if (visits <= kNnzACountCap) {
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<int64_t> c(nth, 0);
     std::vector<std::thread> th;

@@ -109,64 +109,29 @@ void free_all(Handle& h) {
     if (p) (void)hipFree(p);
 }
 
-}  // namespace
 
-extern "C" {
-
-void spi_default_opts(spi_opts* o) {
-  if (!o) return;
-  std::memset(o, 0, sizeof(*o));
-  o->precision = SPI_FP64;
-  o->max_group = 32;
-  o->leaf_max_work = 65536.0;
-  o->amalg_density = 0.35;
-  o->refine_steps = 2;
-  o->root_inverse = 1;
-  o->equilibrate = 1;
-  o->refine_tol = 0.0;
-}
-
-int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
-                const int32_t* col, const spi_opts* opts, void* stream) {
-  g_analyze_err.clear();
-  if (!out) {
-    g_analyze_err = "null handle pointer";
-    return SPI_E_ARG;
-  }
-  *out = nullptr;
-  spi_opts o;
-  spi_default_opts(&o);
-  if (opts) o = *opts;
+bool check_opts(spi_opts& o) {
   if (o.precision != SPI_FP64 && o.precision != SPI_MIXED) {
     g_analyze_err = "unknown precision";
-    return SPI_E_ARG;
+    return false;
   }
   if (o.max_group < 1 || o.refine_steps < 0 || !(o.amalg_density >= 0.0) ||
       !(o.refine_tol >= 0.0)) {
     g_analyze_err = "invalid options";
-    return SPI_E_ARG;
+    return false;
   }
   if (o.precision == SPI_MIXED && o.refine_tol == 0.0) {
     // the FP32 root factor needs refinement to reach FP64 accuracy in x
     o.refine_tol = 1e-14;
     o.refine_steps = std::max(o.refine_steps, 10);
   }
-  spi_handle* H = new (std::nothrow) spi_handle();
-  if (!H) {
-    g_analyze_err = "host allocation failed";
-    return SPI_E_OOM;
-  }
+  return true;
+}
+
+// Upload the analysis and size every buffer of a handle whose h.an is set;
+// deletes H on failure.
+int setup_device(spi_handle* H) {
   Handle& h = H->h;
-  h.opts = o;
-  h.stream = (hipStream_t)stream;
-  (void)hipGetDevice(&h.device);
-  auto t0 = std::chrono::steady_clock::now();
-  std::string e = analyze(m, n, rowptr, col, o, h.an);
-  if (!e.empty()) {
-    g_analyze_err = e;
-    delete H;
-    return SPI_E_ARG;
-  }
   const Analysis& a = h.an;
   DevAnalysis& d = h.d;
   hipError_t he = hipSuccess;
@@ -205,6 +170,184 @@ int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
     delete H;
     return he == hipErrorOutOfMemory ? SPI_E_OOM : SPI_E_HIP;
   }
+  return SPI_OK;
+}
+
+}  // namespace
+
+// ---- stream-ordered pieces of the entry points (also used by batches)
+namespace spi {
+
+int factor_enqueue(Handle& h) {
+  h.have_factor = false;
+  h.have_inv = false;
+  h.failed_col = -1;
+  SPI_CK(fill_i64(h.stream, h.flag, -1, 1), "flag");
+  phase_begin(h, kPhLeaf);
+  SPI_CK(launch_leaf_assemble(h), "leaf assembly");
+  phase_end(h, kPhLeaf);
+  if (h.an.n_pad) {
+    phase_begin(h, kPhExtend);
+    SPI_CK(launch_assemble_root(h), "root assembly");
+    phase_end(h, kPhExtend);
+    phase_begin(h, kPhPotrf);
+    SPI_CK(root_potrf(h), "root factorisation");
+    phase_end(h, kPhPotrf);
+    if (h.opts.root_inverse) {
+      phase_begin(h, kPhTrtri);
+      SPI_CK(root_trtri(h), "root factor inversion");
+      phase_end(h, kPhTrtri);
+    }
+  }
+  // work enqueued after this point may use the inverse (stream order);
+  // factor_finish withdraws it if a pivot failed
+  h.have_inv = h.an.n_pad > 0 && h.opts.root_inverse;
+  return SPI_OK;
+}
+
+// Interpret the pivot flag read back after factor_enqueue's work completed.
+int factor_finish(Handle& h, uint64_t f) {
+  if (f != std::numeric_limits<uint64_t>::max()) {
+    const int64_t nl = (int64_t)h.an.leaf_cols.size();
+    int64_t k = (int64_t)f;
+    if (k < nl) h.failed_col = h.an.leaf_cols[k];
+    else if (k - nl < h.an.n_root) h.failed_col = h.an.root_cols[k - nl];
+    std::ostringstream os;
+    os << "matrix not positive definite: non-positive pivot at column "
+       << h.failed_col;
+    h.err = os.str();
+    h.have_inv = false;
+    return SPI_E_NOT_SPD;
+  }
+  h.have_factor = true;
+  return SPI_OK;
+}
+
+// One right-hand side with exactly `steps` refinement steps (no readback).
+int solve_enqueue(Handle& h, const double* bc, double* xc, int steps) {
+  const bool eq = h.opts.equilibrate != 0;
+  const double* src = bc;
+  double* dst = xc;
+  if (eq) {
+    SPI_CK(launch_scale_vec(h, bc, h.vbh, 0), "scale rhs");
+    src = h.vbh;
+    dst = h.vxh;
+  }
+  SPI_CK(launch_solve_pass(h, src, dst), "solve");
+  for (int s = 0; s < steps; ++s) {
+    SPI_CK(launch_residual_dd(h, src, dst, h.vres), "residual");
+    SPI_CK(launch_solve_pass(h, h.vres, h.vx), "correction");
+    SPI_CK(fill_f64(h.stream, h.vnorm, 0.0, 2), "norms");
+    SPI_CK(launch_axpy_norms(h, dst, h.vx), "update");
+  }
+  if (eq) SPI_CK(launch_scale_vec(h, h.vxh, xc, 0), "scale solution");
+  return SPI_OK;
+}
+
+int diag_enqueue(Handle& h, double* d) {
+  if (h.an.n_pad) {
+    if (!h.have_inv) {
+      phase_begin(h, kPhTrtri);
+      SPI_CK(root_trtri(h), "root factor inversion");
+      phase_end(h, kPhTrtri);
+      h.have_inv = true;
+    }
+    phase_begin(h, kPhLauum);
+    SPI_CK(root_lauum(h), "root inverse product");
+    phase_end(h, kPhLauum);
+  }
+  phase_begin(h, kPhSelinv);
+  if (h.an.n_pad) SPI_CK(launch_diag_root(h, d), "root diagonal");
+  SPI_CK(launch_selinv_leaves(h, d), "leaf selected inversion");
+  // (S A S)^-1 = S^-1 A^-1 S^-1: undo the scaling, d_i = s_i^2 d'_i
+  if (h.opts.equilibrate) SPI_CK(launch_scale_vec(h, d, d, 2), "scale variances");
+  phase_end(h, kPhSelinv);
+  return SPI_OK;
+}
+
+}  // namespace spi
+
+extern "C" {
+
+void spi_default_opts(spi_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = SPI_FP64;
+  o->max_group = 32;
+  o->leaf_max_work = 65536.0;
+  o->amalg_density = 0.35;
+  o->refine_steps = 2;
+  o->root_inverse = 1;
+  o->equilibrate = 1;
+  o->refine_tol = 0.0;
+}
+
+int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
+                const int32_t* col, const spi_opts* opts, void* stream) {
+  g_analyze_err.clear();
+  if (!out) {
+    g_analyze_err = "null handle pointer";
+    return SPI_E_ARG;
+  }
+  *out = nullptr;
+  spi_opts o;
+  spi_default_opts(&o);
+  if (opts) o = *opts;
+  if (!check_opts(o)) return SPI_E_ARG;
+  spi_handle* H = new (std::nothrow) spi_handle();
+  if (!H) {
+    g_analyze_err = "host allocation failed";
+    return SPI_E_OOM;
+  }
+  Handle& h = H->h;
+  h.opts = o;
+  h.stream = (hipStream_t)stream;
+  (void)hipGetDevice(&h.device);
+  auto t0 = std::chrono::steady_clock::now();
+  std::string e = analyze(m, n, rowptr, col, o, h.an);
+  if (!e.empty()) {
+    g_analyze_err = e;
+    delete H;
+    return SPI_E_ARG;
+  }
+  const int st = setup_device(H);
+  if (st != SPI_OK) return st;
+  h.t_analyze_ms = std::chrono::duration<double, std::milli>(
+                       std::chrono::steady_clock::now() - t0).count();
+  *out = H;
+  return SPI_OK;
+}
+
+int spi_analyze_like(spi_handle** out, const spi_handle* src, const spi_opts* opts,
+                     void* stream) {
+  g_analyze_err.clear();
+  if (!out || !src) {
+    g_analyze_err = "null handle pointer";
+    return SPI_E_ARG;
+  }
+  *out = nullptr;
+  spi_opts o = src->h.opts;
+  if (opts) o = *opts;
+  if (!check_opts(o)) return SPI_E_ARG;
+  if (o.max_group != src->h.opts.max_group ||
+      o.leaf_max_work != src->h.opts.leaf_max_work ||
+      o.amalg_density != src->h.opts.amalg_density) {
+    g_analyze_err = "analysis options must match the source handle";
+    return SPI_E_ARG;
+  }
+  spi_handle* H = new (std::nothrow) spi_handle();
+  if (!H) {
+    g_analyze_err = "host allocation failed";
+    return SPI_E_OOM;
+  }
+  Handle& h = H->h;
+  h.opts = o;
+  h.stream = (hipStream_t)stream;
+  (void)hipGetDevice(&h.device);
+  auto t0 = std::chrono::steady_clock::now();
+  h.an = src->h.an;  // host copy of the analysis: no re-analysis
+  const int st = setup_device(H);
+  if (st != SPI_OK) return st;
   h.t_analyze_ms = std::chrono::duration<double, std::milli>(
                        std::chrono::steady_clock::now() - t0).count();
   *out = H;
@@ -234,44 +377,13 @@ int spi_factor(spi_handle* H) {
   Handle& h = H->h;
   if (!h.have_values)
     return fail(h, SPI_E_STATE, hipSuccess, "spi_factor before spi_set_values");
-  h.have_factor = false;
-  h.have_inv = false;
-  h.failed_col = -1;
-  SPI_CK(fill_i64(h.stream, h.flag, -1, 1), "flag");
-  phase_begin(h, kPhLeaf);
-  SPI_CK(launch_leaf_assemble(h), "leaf assembly");
-  phase_end(h, kPhLeaf);
-  if (h.an.n_pad) {
-    phase_begin(h, kPhExtend);
-    SPI_CK(launch_assemble_root(h), "root assembly");
-    phase_end(h, kPhExtend);
-    phase_begin(h, kPhPotrf);
-    SPI_CK(root_potrf(h), "root factorisation");
-    phase_end(h, kPhPotrf);
-    if (h.opts.root_inverse) {
-      phase_begin(h, kPhTrtri);
-      SPI_CK(root_trtri(h), "root factor inversion");
-      phase_end(h, kPhTrtri);
-    }
-  }
+  int st = factor_enqueue(h);
+  if (st != SPI_OK) return st;
   uint64_t f = 0;
   SPI_CK(hipMemcpyAsync(&f, h.flag, sizeof(f), hipMemcpyDeviceToHost, h.stream),
          "flag readback");
   SPI_CK(hipStreamSynchronize(h.stream), "factor");
-  if (f != std::numeric_limits<uint64_t>::max()) {
-    const int64_t nl = (int64_t)h.an.leaf_cols.size();
-    int64_t k = (int64_t)f;
-    if (k < nl) h.failed_col = h.an.leaf_cols[k];
-    else if (k - nl < h.an.n_root) h.failed_col = h.an.root_cols[k - nl];
-    std::ostringstream os;
-    os << "matrix not positive definite: non-positive pivot at column "
-       << h.failed_col;
-    h.err = os.str();
-    return SPI_E_NOT_SPD;
-  }
-  h.have_factor = true;
-  h.have_inv = h.an.n_pad > 0 && h.opts.root_inverse;
-  return SPI_OK;
+  return factor_finish(h, f);
 }
 
 int spi_rhs(spi_handle* H, const double* y, double* b) {
@@ -347,24 +459,7 @@ int spi_diag_inv(spi_handle* H, double* d) {
   if (!d) return fail(h, SPI_E_ARG, hipSuccess, "null output");
   if (!h.have_factor)
     return fail(h, SPI_E_STATE, hipSuccess, "spi_diag_inv without a valid factor");
-  if (h.an.n_pad) {
-    if (!h.have_inv) {
-      phase_begin(h, kPhTrtri);
-      SPI_CK(root_trtri(h), "root factor inversion");
-      phase_end(h, kPhTrtri);
-      h.have_inv = true;
-    }
-    phase_begin(h, kPhLauum);
-    SPI_CK(root_lauum(h), "root inverse product");
-    phase_end(h, kPhLauum);
-  }
-  phase_begin(h, kPhSelinv);
-  if (h.an.n_pad) SPI_CK(launch_diag_root(h, d), "root diagonal");
-  SPI_CK(launch_selinv_leaves(h, d), "leaf selected inversion");
-  // (S A S)^-1 = S^-1 A^-1 S^-1: undo the scaling, d_i = s_i^2 d'_i
-  if (h.opts.equilibrate) SPI_CK(launch_scale_vec(h, d, d, 2), "scale variances");
-  phase_end(h, kPhSelinv);
-  return SPI_OK;
+  return diag_enqueue(h, d);
 }
 
 static void fill_analysis_info(const Analysis& a, spi_info_t* info) {

@@ -1,0 +1,209 @@
+// C ABI of batched runs over many handles and of the POTRF autotuner
+// (declared in include/spi.h).
+//
+// Energy bands share the pattern of H and differ in W and y (Sect. 2.2.3);
+// the paper solves them one after the other (Sect. 4.2).  A batch enqueues
+// the whole pipeline of every system (factorisation, right-hand side, solve,
+// variances) on each handle's own stream before synchronising once, so
+// systems run concurrently and fill the gaps of each other's dependency
+// chains (the diagonal-block chain of a root POTRF leaves most of the GPU
+// idle).  With graphs, each handle's pipeline is captured into a HIP graph
+// on first use and replayed afterwards: one launch per system instead of
+// about a thousand.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <new>
+#include <vector>
+
+#include "spi_internal.h"
+
+using namespace spi;
+
+namespace {
+
+struct Captured {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+void drop(Captured& c) {
+  if (c.exec) (void)hipGraphExecDestroy(c.exec);
+  if (c.graph) (void)hipGraphDestroy(c.graph);
+  c = Captured{};
+}
+
+// The whole pipeline of one system, stream-ordered, no host synchronisation.
+int enqueue_system(Handle& h, const double* y, double* b, double* x, double* d) {
+  int st = factor_enqueue(h);
+  if (st != SPI_OK) return st;
+  SPI_CK(launch_rhs(h, y, b), "rhs");
+  if ((st = solve_enqueue(h, b, x, h.opts.refine_steps)) != SPI_OK) return st;
+  if (d && (st = diag_enqueue(h, d)) != SPI_OK) return st;
+  return SPI_OK;
+}
+
+}  // namespace
+
+struct spi_batch {
+  std::vector<spi_handle*> hs;
+  std::vector<Captured> graphs;
+  bool use_graphs = false;
+};
+
+extern "C" {
+
+int spi_batch_create(spi_batch** out, spi_handle* const* hs, int32_t k,
+                     int32_t use_graphs) {
+  if (!out || !hs || k < 1) return SPI_E_ARG;
+  *out = nullptr;
+  for (int32_t i = 0; i < k; ++i) {
+    if (!hs[i]) return SPI_E_ARG;
+    if (use_graphs && !hs[i]->h.stream) return SPI_E_ARG;  // NULL stream: no capture
+    for (int32_t j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return SPI_E_ARG;
+  }
+  spi_batch* b = new (std::nothrow) spi_batch();
+  if (!b) return SPI_E_OOM;
+  b->hs.assign(hs, hs + k);
+  b->graphs.resize(k);
+  b->use_graphs = use_graphs != 0;
+  *out = b;
+  return SPI_OK;
+}
+
+int spi_batch_run(spi_batch* B, const double* const* y, double* const* rhs,
+                  double* const* x, double* const* d, int32_t* status) {
+  if (!B || !y || !rhs || !x) return SPI_E_ARG;
+  const int k = (int)B->hs.size();
+  int first_bad = SPI_OK;
+  auto note = [&](int i, int st) {
+    if (status) status[i] = st;
+    if (st != SPI_OK && first_bad == SPI_OK) first_bad = st;
+  };
+  std::vector<bool> launched(k, false);
+  for (int i = 0; i < k; ++i) {
+    Handle& h = B->hs[i]->h;
+    if (!y[i] || !rhs[i] || !x[i]) {
+      note(i, fail(h, SPI_E_ARG, hipSuccess, "null pointer in batch"));
+      continue;
+    }
+    if (!h.have_values) {
+      note(i, fail(h, SPI_E_STATE, hipSuccess, "batch run before spi_set_values"));
+      continue;
+    }
+    const int timing = h.opts.timing;
+    h.opts.timing = 0;  // no host-side event bookkeeping inside a batch
+    int st = SPI_OK;
+    hipError_t he = hipSuccess;
+    if (!B->use_graphs) {
+      st = enqueue_system(h, y[i], rhs[i], x[i], d ? d[i] : nullptr);
+    } else {
+      Captured& c = B->graphs[i];
+      const void* key[4] = {y[i], rhs[i], x[i], d ? d[i] : nullptr};
+      if (c.exec && !std::equal(key, key + 4, c.key)) drop(c);
+      if (!c.exec) {
+        // everything that allocates or creates must exist before capture
+        he = ensure_side_stream(h);
+        if (he == hipSuccess)
+          he = hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal);
+        if (he == hipSuccess) {
+          st = enqueue_system(h, y[i], rhs[i], x[i], d ? d[i] : nullptr);
+          hipGraph_t g = nullptr;
+          const hipError_t he2 = hipStreamEndCapture(h.stream, &g);
+          if (st == SPI_OK) he = he2;
+          if (he == hipSuccess && st == SPI_OK) {
+            he = hipGraphInstantiate(&c.exec, g, nullptr, nullptr, 0);
+            c.graph = g;
+            std::copy(key, key + 4, c.key);
+          } else if (g) {
+            (void)hipGraphDestroy(g);
+          }
+        }
+      }
+      if (he == hipSuccess && st == SPI_OK) {
+        // state the captured pipeline leaves behind on the handle
+        h.have_inv = h.an.n_pad > 0 && h.opts.root_inverse;
+        he = hipGraphLaunch(c.exec, h.stream);
+      }
+    }
+    h.opts.timing = timing;
+    if (he != hipSuccess) st = fail(h, SPI_E_HIP, he, "batch graph");
+    if (st != SPI_OK) {
+      note(i, st);
+      continue;
+    }
+    launched[i] = true;
+  }
+  // one synchronisation per stream; pivot flags decide each status
+  for (int i = 0; i < k; ++i) {
+    if (!launched[i]) continue;
+    Handle& h = B->hs[i]->h;
+    uint64_t f = 0;
+    hipError_t he = hipMemcpyAsync(&f, h.flag, sizeof(f), hipMemcpyDeviceToHost,
+                                   h.stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
+    if (he != hipSuccess) {
+      note(i, fail(h, SPI_E_HIP, he, "batch"));
+      continue;
+    }
+    note(i, factor_finish(h, f));
+    h.refine_done = h.opts.refine_steps;
+  }
+  return first_bad;
+}
+
+void spi_batch_destroy(spi_batch* B) {
+  if (!B) return;
+  for (auto& c : B->graphs) drop(c);
+  delete B;
+}
+
+int spi_autotune(spi_handle* H, int32_t* chosen) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = H->h;
+  if (!h.have_values)
+    return fail(h, SPI_E_STATE, hipSuccess, "spi_autotune before spi_set_values");
+  const int cand[3] = {128, 256, 512};
+  double best = 1e300;
+  int best_b = h.potrf_block;
+  const int timing = h.opts.timing;
+  h.opts.timing = 0;
+  for (int c : cand) {
+    if (h.an.n_pad > 0 && c > h.an.n_pad) continue;
+    h.potrf_block = c;
+    double t_min = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+      SPI_CK(hipStreamSynchronize(h.stream), "autotune");
+      const auto t0 = std::chrono::steady_clock::now();
+      const int st = spi_factor(H);
+      if (st != SPI_OK) {
+        h.opts.timing = timing;
+        return st;
+      }
+      const double ms = std::chrono::duration<double, std::milli>(
+                            std::chrono::steady_clock::now() - t0).count();
+      t_min = std::min(t_min, ms);
+    }
+    if (t_min < best) {
+      best = t_min;
+      best_b = c;
+    }
+  }
+  h.potrf_block = best_b;
+  h.opts.timing = timing;
+  if (chosen) *chosen = best_b;
+  return spi_factor(H);  // leave a factor made with the chosen block
+}
+
+int spi_get_potrf_block(const spi_handle* H) { return H ? H->h.potrf_block : -1; }
+
+int spi_set_potrf_block(spi_handle* H, int32_t block) {
+  if (!H || (block != 128 && block != 256 && block != 512)) return SPI_E_ARG;
+  H->h.potrf_block = block;
+  return SPI_OK;
+}
+
+}  // extern "C"

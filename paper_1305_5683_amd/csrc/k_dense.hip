@@ -331,7 +331,7 @@ static hipError_t factor_panel(Handle& h, hipStream_t s, int K0, int KB) {
   return hipSuccess;
 }
 
-static hipError_t ensure_side_stream(Handle& h) {
+hipError_t ensure_side_stream(Handle& h) {
   hipError_t e;
   if (!h.side) {
     if ((e = hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking)) != hipSuccess)
@@ -359,13 +359,14 @@ hipError_t root_potrf(Handle& h) {
   const int64_t ld = np;
   hipError_t e;
   if ((e = ensure_side_stream(h)) != hipSuccess) return e;
-  if ((e = factor_panel(h, h.stream, 0, std::min(kNBO, np))) != hipSuccess)
+  const int NBO = h.potrf_block;  // outer block: 128, 256 or 512
+  if ((e = factor_panel(h, h.stream, 0, std::min(NBO, np))) != hipSuccess)
     return e;
-  for (int K0 = 0; K0 < np; K0 += kNBO) {
-    const int KB = std::min(kNBO, np - K0), K1 = K0 + KB;
+  for (int K0 = 0; K0 < np; K0 += NBO) {
+    const int KB = std::min(NBO, np - K0), K1 = K0 + KB;
     const int rest = np - K1;
     if (rest <= 0) break;
-    const int KB2 = std::min(kNBO, rest);
+    const int KB2 = std::min(NBO, rest);
     double* P = h.S + (int64_t)K1 + (int64_t)K0 * ld;  // rows >= K1 of the panel
     // T1: next panel's columns [K1, K1 + KB2), all rows >= K1
     e = gemm(h.stream, pick_bm(rest), (KB2 % 128 == 0) ? 128 : 64, kXC, kXC, P,

@@ -215,6 +215,7 @@ struct Handle {
     double* fpart = nullptr;                // feature partial sums
   } lp;
   bool val32_ok = false;
+  int potrf_block = 256;     // outer block of the root POTRF (autotuned)
   bool have_inv = false;     // W = L_RR^-1 is valid
   // phase timing (opts.timing): HIP event pairs recorded on the stream,
   // accumulated lazily (spi_info synchronises and sums them)
@@ -242,6 +243,15 @@ inline int fail(Handle& h, int code, hipError_t e, const char* what) {
   } while (0)
 
 void free_lp_work(Handle& h);
+
+// Stream-ordered pieces of the entry points (api.cpp): enqueue the work
+// with no host synchronisation; factor_finish interprets the pivot flag
+// once the factorisation has completed.
+int factor_enqueue(Handle& h);
+int factor_finish(Handle& h, uint64_t flag);
+int solve_enqueue(Handle& h, const double* b, double* x, int steps);
+int diag_enqueue(Handle& h, double* d);
+hipError_t ensure_side_stream(Handle& h);
 
 // kernel launchers (stream-ordered); return hipError_t of the launch
 hipError_t launch_gather_values(Handle& h);

@@ -23,7 +23,10 @@ EXPORTED = ["spi_default_opts", "spi_analyze", "spi_set_values", "spi_factor",
             "spi_rhs", "spi_solve", "spi_diag_inv", "spi_symbolic", "spi_info",
             "spi_last_error", "spi_destroy", "spi_lp_param_count",
             "spi_lp_create", "spi_lp_get_params", "spi_lp_loss_grad",
-            "spi_lp_train_step", "spi_lp_destroy", "spi_pcg_solve"]
+            "spi_lp_train_step", "spi_lp_destroy", "spi_pcg_solve",
+            "spi_analyze_like", "spi_batch_create", "spi_batch_run",
+            "spi_batch_destroy", "spi_autotune", "spi_get_potrf_block",
+            "spi_set_potrf_block"]
 
 
 class spi_opts(C.Structure):
@@ -104,9 +107,19 @@ def load_library(path: str = LIB_PATH):
     lib.spi_lp_destroy.argtypes = [P]
     lib.spi_lp_destroy.restype = None
     lib.spi_pcg_solve.argtypes = [P, P, P, P, P, D, I32, C.POINTER(spi_pcg_info)]
+    lib.spi_analyze_like.argtypes = [C.POINTER(C.c_void_p), P,
+                                     C.POINTER(spi_opts), P]
+    lib.spi_batch_create.argtypes = [C.POINTER(C.c_void_p), P, I32, I32]
+    lib.spi_batch_run.argtypes = [P, P, P, P, P, P]
+    lib.spi_batch_destroy.argtypes = [P]
+    lib.spi_batch_destroy.restype = None
+    lib.spi_autotune.argtypes = [P, C.POINTER(I32)]
+    lib.spi_get_potrf_block.argtypes = [P]
+    lib.spi_set_potrf_block.argtypes = [P, I32]
     for name in EXPORTED:
         if name not in ("spi_default_opts", "spi_last_error", "spi_destroy",
-                        "spi_lp_destroy", "spi_lp_param_count"):
+                        "spi_lp_destroy", "spi_lp_param_count",
+                        "spi_batch_destroy"):
             getattr(lib, name).restype = C.c_int
     lib.spi_lp_param_count.restype = C.c_int64
     del I64, I32, D
@@ -180,9 +193,41 @@ class SpiSolver:
             raise SpiError(st, self.lib.spi_last_error(None).decode())
         self.h = h
 
+    @classmethod
+    def like(cls, src: "SpiSolver", stream=None, **opts):
+        """A handle on ``src``'s pattern with a copy of its analysis."""
+        import torch
+        self = cls.__new__(cls)
+        self.lib = src.lib
+        self.m, self.n, self.nnz = src.m, src.n, src.nnz
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        o = default_opts(**opts) if opts else None
+        st = self.lib.spi_analyze_like(C.byref(h), src.h,
+                                       None if o is None else C.byref(o),
+                                       C.c_void_p(self.stream.cuda_stream))
+        if st != SPI_OK:
+            raise SpiError(st, self.lib.spi_last_error(None).decode())
+        self.h = h
+        return self
+
     def _check(self, st):
         if st != SPI_OK:
             raise SpiError(st, self.lib.spi_last_error(self.h).decode())
+
+    def autotune(self) -> int:
+        """Pick the root POTRF outer block by timing; returns it."""
+        c = C.c_int32()
+        self._check(self.lib.spi_autotune(self.h, C.byref(c)))
+        return c.value
+
+    @property
+    def potrf_block(self) -> int:
+        return int(self.lib.spi_get_potrf_block(self.h))
+
+    @potrf_block.setter
+    def potrf_block(self, v):
+        self._check(self.lib.spi_set_potrf_block(self.h, int(v)))
 
     def set_values(self, val, w):
         import torch
@@ -305,3 +350,50 @@ def pcg_solve(band: "SpiSolver", ref: "SpiSolver", b, lp=None, tol=1e-10,
         _ptr(b, band.n, torch.float64), _ptr(x, band.n, torch.float64),
         float(tol), int(maxit), C.byref(info)))
     return x, info.as_dict()
+
+
+class SpiBatch:
+    """Several handles run together (see spi_batch_run in spi.h)."""
+
+    def __init__(self, solvers, use_graphs=True):
+        self.lib = load_library()
+        self.solvers = list(solvers)
+        arr = (C.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        h = C.c_void_p()
+        st = self.lib.spi_batch_create(C.byref(h), arr, len(self.solvers),
+                                       1 if use_graphs else 0)
+        if st != SPI_OK:
+            raise SpiError(st, "spi_batch_create failed")
+        self.h = h
+
+    def run(self, y, rhs, x, d=None):
+        """Lists of device tensors, one per system; returns per-system status."""
+        import torch
+        k = len(self.solvers)
+
+        def arr(ts, cnt, allow_none=False):
+            a = (C.c_void_p * k)()
+            for i, (t, s) in enumerate(zip(ts, self.solvers)):
+                if t is None and allow_none:
+                    a[i] = None
+                else:
+                    a[i] = _ptr(t, cnt(s), torch.float64).value
+            return a
+        st = (C.c_int32 * k)()
+        ya = arr(y, lambda s: s.m)
+        ra = arr(rhs, lambda s: s.n)
+        xa = arr(x, lambda s: s.n)
+        da = None if d is None else arr(d, lambda s: s.n, allow_none=True)
+        self.lib.spi_batch_run(self.h, ya, ra, xa, da, st)
+        return [int(v) for v in st]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.spi_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -56,7 +56,8 @@ class SkyConfig:
     x_hi: float = 50.0
 
 
-# Workload shapes (see the design doc for the recipe and the readings behind it).
+# Workload shapes: tiny, medium and large coded-mask systems (fixed or
+# random time-bin lengths).
 CONFIGS = {
     0: SkyConfig("tiny-fp64", sky=20, n_point=200, fov=9, bin_len=10),
     1: SkyConfig("medium-fp64", sky=100, n_point=5000, fov=17, bin_len=4),
@@ -337,3 +338,17 @@ def lp_init_params(hidden: int, seed: int = 0) -> np.ndarray:
     p = np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), w3,
                         [0.0], np.zeros(F)])
     return p.astype(np.float32)
+
+
+def subproblem_configs(k: int, seed: int = 0, side_lo: int = 30,
+                       side_hi: int = 120) -> list:
+    """Shapes of ``k`` independent sub-problems of uneven size: sky side
+    s ~ U{side_lo..side_hi}, FoV 17, 50% mask, bins of 4 pointings and
+    4 * ceil(0.1 s^2) pointings (about 2.9 s^2 unknowns)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(k):
+        s = int(rng.integers(side_lo, side_hi + 1))
+        n_p = 4 * int(np.ceil(0.1 * s * s))
+        out.append(SkyConfig(f"sub{i}-s{s}", s, n_p, 17, 4))
+    return out

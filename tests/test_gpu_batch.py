@@ -1,0 +1,157 @@
+"""GPU: batches of systems, shared analyses and the POTRF autotuner.
+
+Every system of a batch must give what it gives alone: x and diag(A^-1)
+against the FP64 oracle at the FP64 tolerance (1e-12), for both eager and
+graph runs, with graphs replayed on new values.  A failing pivot in one
+system is reported for that system only.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import spi_synth as synth
+from oracle import oracle_solve
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _set(s, p):
+    torch = _torch()
+    s.set_values(torch.from_numpy(p.val).cuda(), torch.from_numpy(p.w).cuda())
+
+
+def _systems():
+    base = synth.make_config(0)
+    bands = [synth.make_band(base, *synth.band_scales_drift(b, 64), seed=2000 + b)
+             for b in (0, 21, 42)]
+    subs = [synth.make_problem(c, seed=7 + i) for i, c in
+            enumerate(synth.subproblem_configs(3, seed=3, side_lo=12, side_hi=24))]
+    return base, bands, subs
+
+
+def test_analyze_like_matches_fresh_analysis():
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver
+    p = synth.make_config(0)
+    _say("case analyze_like tiny")
+    a = SpiSolver(p.m, p.n, p.rowptr, p.col)
+    b = SpiSolver.like(a)
+    out = []
+    for s in (a, b):
+        _set(s, p)
+        s.factor()
+        rhs = s.rhs(torch.from_numpy(p.y).cuda())
+        out.append((s.solve(rhs).cpu().numpy(), s.diag_inv().cpu().numpy()))
+    # the root assembly sums with LDS atomics, so two runs agree to
+    # rounding, not bit for bit
+    assert _rel(out[0][0], out[1][0]) <= 1e-13
+    assert np.max(np.abs(out[0][1] - out[1][1]) / out[1][1]) <= 1e-13
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_batch_matches_oracle(graphs):
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiBatch
+    base, bands, subs = _systems()
+    _say(f"case batch graphs={graphs}: 3 bands + 3 sub-problems")
+    first = SpiSolver(base.m, base.n, base.rowptr, base.col,
+                      stream=torch.cuda.Stream())
+    solvers = [first] + [SpiSolver.like(first, stream=torch.cuda.Stream())
+                         for _ in bands[1:]]
+    solvers += [SpiSolver(q.m, q.n, q.rowptr, q.col, stream=torch.cuda.Stream())
+                for q in subs]
+    probs = bands + subs
+    batch = SpiBatch(solvers, use_graphs=bool(graphs))
+    y = [torch.from_numpy(q.y).cuda() for q in probs]
+    rhs = [torch.empty(q.n, dtype=torch.float64, device="cuda") for q in probs]
+    x = [torch.empty_like(r) for r in rhs]
+    d = [torch.empty_like(r) for r in rhs]
+    for rnd in range(2):
+        if rnd == 1:   # new values on the same buffers: graphs are replayed
+            probs = [synth.make_band(base, *synth.band_scales_drift(b, 64),
+                                     seed=3000 + b) for b in (5, 26, 47)] + subs
+            for i, q in enumerate(probs[:3]):
+                y[i].copy_(torch.from_numpy(q.y))
+        for s, q in zip(solvers, probs):
+            _set(s, q)
+        torch.cuda.synchronize()
+        st = batch.run(y, rhs, x, d)
+        assert st == [0] * len(probs)
+        for i, q in enumerate(probs):
+            o = oracle_solve(q)
+            ex = _rel(x[i].cpu().numpy(), o["x"])
+            ed = np.max(np.abs(d[i].cpu().numpy() - o["diag"]) / o["diag"])
+            _say(f"  round {rnd} system {i} n={q.n}: err_x={ex:.2e} err_d={ed:.2e}")
+            assert ex <= TOL and ed <= TOL
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_reports_failing_system_only():
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiBatch
+    base, bands, subs = _systems()
+    _say("case batch with one non-SPD system")
+    solvers = [SpiSolver(q.m, q.n, q.rowptr, q.col, stream=torch.cuda.Stream())
+               for q in (bands[0], subs[0])]
+    _set(solvers[0], bands[0])
+    bad = subs[0]
+    solvers[1].set_values(torch.from_numpy(bad.val).cuda(),
+                          torch.from_numpy(-bad.w).cuda())
+    batch = SpiBatch(solvers, use_graphs=True)
+    y = [torch.from_numpy(q.y).cuda() for q in (bands[0], bad)]
+    rhs = [torch.empty(q.n, dtype=torch.float64, device="cuda") for q in (bands[0], bad)]
+    x = [torch.empty_like(r) for r in rhs]
+    st = batch.run(y, rhs, x)
+    assert st[0] == 0 and st[1] == 3
+    o = oracle_solve(bands[0], want_diag=False)
+    assert _rel(x[0].cpu().numpy(), o["x"]) <= TOL
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
+def test_autotune_picks_a_block_and_factor_stays_exact():
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver
+    p = synth.make_random_leafy(10, 5, 700, 3, 30, 40, seed=9)
+    _say(f"case autotune n={p.n}")
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col)
+    _set(s, p)
+    blk = s.autotune()
+    _say(f"  chosen block {blk}")
+    assert blk in (128, 256, 512) and s.potrf_block == blk
+    rhs = s.rhs(torch.from_numpy(p.y).cuda())
+    x = s.solve(rhs).cpu().numpy()
+    d = s.diag_inv().cpu().numpy()
+    o = oracle_solve(p)
+    assert _rel(x, o["x"]) <= TOL
+    assert np.max(np.abs(d - o["diag"]) / o["diag"]) <= TOL
+    for blk in (128, 512):
+        s.potrf_block = blk
+        s.factor()
+        x2 = s.solve(rhs).cpu().numpy()
+        assert _rel(x2, o["x"]) <= TOL
+    s.close()
