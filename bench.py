@@ -8,6 +8,17 @@ pointings x 19 detectors, 17x17 field of view, background per detector per
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on
 one GPU.
+
+Other workloads (``--workload``), each printing its own JSON line:
+  batch    64 energy bands on the medium pattern (response scale
+           U(0.5, 1.5) per band, fresh Poisson counts) plus 32 independent
+           sub-problems of uneven size (sky 30..120), mixed precision: each
+           system alone, one after the other, against batched runs
+           (concurrent streams, HIP graphs);
+  learned  256 drifting bands on the medium pattern (+-20% response and
+           background scale): direct solves of bands 0..31, the network
+           trained on them, then FP32 PCG on a sample of bands 32..255 with
+           and without the learned correction.
 """
 from __future__ import annotations
 
@@ -34,6 +45,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("medium", "batch", "learned"),
+                    default="medium")
+    ap.add_argument("--bands", type=int, default=64,
+                    help="batch: number of bands; learned: PCG sample size")
+    ap.add_argument("--subproblems", type=int, default=32)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="fp64: every stage in binary64; mixed: binary32 "
                          "matrix-core products on the root front, binary64 "
@@ -112,6 +128,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "this build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "learned":
+        return run_learned(args)
     import torch
     import spi_synth
     from paper_1305_5683_amd import SpiSolver
@@ -201,6 +221,195 @@ def main():
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out))
+
+
+def _say(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def _mixed_opts():
+    # binary32 root products, 3 fixed refinement steps (batches do not read
+    # norms back)
+    return dict(precision=1, refine_tol=1e-14, refine_steps=3)
+
+
+def run_batch(args):
+    import torch
+    import spi_synth
+    from paper_1305_5683_amd import SpiSolver, SpiBatch
+    torch.cuda.set_device(0)
+    base = spi_synth.make_config(1)
+    rng = np.random.default_rng(3000)
+    nb, ns = args.bands, args.subproblems
+    _say(f"generating {nb} bands")
+    bands = [spi_synth.make_band(base, float(rng.uniform(0.5, 1.5)), 1.0,
+                                 seed=3000 + b) for b in range(nb)]
+    _say(f"generating {ns} sub-problems")
+    subs = [spi_synth.make_problem(c, seed=3500 + i) for i, c in
+            enumerate(spi_synth.subproblem_configs(ns, seed=3500))]
+    opts = _mixed_opts()
+    slots = 4
+    streams = [torch.cuda.Stream() for _ in range(slots + ns)]
+    _say("analysis")
+    first = SpiSolver(base.m, base.n, base.rowptr, base.col, stream=streams[0], **opts)
+    bslots = [first] + [SpiSolver.like(first, stream=streams[i]) for i in range(1, slots)]
+    sub_s = [SpiSolver(q.m, q.n, q.rowptr, q.col, stream=streams[slots + i], **opts)
+             for i, q in enumerate(subs)]
+    dev = torch.device("cuda")
+    bvals = [(torch.from_numpy(q.val).to(dev), torch.from_numpy(q.w).to(dev),
+              torch.from_numpy(q.y).to(dev)) for q in bands]
+    svals = [(torch.from_numpy(q.val).to(dev), torch.from_numpy(q.w).to(dev),
+              torch.from_numpy(q.y).to(dev)) for q in subs]
+
+    def outs(n):
+        return [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
+    bout = [outs(base.n) for _ in range(slots)]
+    sout = [outs(q.n) for q in subs]
+
+    def alone(s, v, o):
+        s.set_values(v[0], v[1])
+        s.factor()
+        s.rhs(v[2], out=o[0])
+        s.solve(o[0], out=o[1])
+        s.diag_inv(out=o[2])
+    def sequential():
+        for b in range(nb):
+            alone(bslots[0], bvals[b], bout[0])
+        for s, v, o in zip(sub_s, svals, sout):
+            alone(s, v, o)
+        torch.cuda.synchronize()
+    bb = SpiBatch(bslots, use_graphs=True)
+    sb = SpiBatch(sub_s, use_graphs=True)
+    def batched():
+        for c in range(0, nb, slots):
+            grp = list(range(c, min(nb, c + slots)))
+            for k, b in enumerate(grp):
+                bslots[k].set_values(bvals[b][0], bvals[b][1])
+            ys = [bvals[b][2] for b in grp] + [bvals[grp[0]][2]] * (slots - len(grp))
+            st = bb.run(ys, [o[0] for o in bout], [o[1] for o in bout],
+                        [o[2] for o in bout])
+            assert st == [0] * slots, st
+        for s, v in zip(sub_s, svals):
+            s.set_values(v[0], v[1])
+        st = sb.run([v[2] for v in svals], [o[0] for o in sout],
+                    [o[1] for o in sout], [o[2] for o in sout])
+        assert st == [0] * ns, st
+        torch.cuda.synchronize()
+    _say("warm-up")
+    sequential()
+    batched()
+    _say("timing sequential")
+    t0 = time.perf_counter()
+    sequential()
+    t_seq = time.perf_counter() - t0
+    _say("timing batched")
+    t0 = time.perf_counter()
+    batched()
+    t_bat = time.perf_counter() - t0
+    k = nb + ns
+    flops = 0.0
+    for s, cnt in [(bslots[0], nb)] + [(x, 1) for x in sub_s]:
+        i = s.info()
+        flops += cnt * (i["flops_factor"] + i["flops_selinv"] +
+                        4 * i["flops_solve"] + i["flops_assembly"])
+    out = {
+        "metric": "s/system for solve+diag(A^-1)", "value": t_bat / k,
+        "unit": "s/system", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": t_bat * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"batch: {nb} bands on the medium pattern + {ns} "
+                               "sub-problems (sky 30..120), mixed precision",
+                   "systems": k, "sub_problem_n": [q.n for q in subs]},
+        "sequential_s_per_system": t_seq / k,
+        "batched_s_per_system": t_bat / k,
+        "speedup": t_seq / t_bat,
+        "gflops_per_s": flops / t_bat / 1e9,
+    }
+    bb.close()
+    sb.close()
+    print(json.dumps(out))
+
+
+def run_learned(args):
+    import torch
+    import spi_synth
+    from paper_1305_5683_amd import SpiSolver, SpiLearnedPrecond, pcg_solve
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda")
+    base = spi_synth.make_config(1)
+    n_bands = 256
+
+    def band(b):
+        rs, bs = spi_synth.band_scales_drift(b, n_bands)
+        return spi_synth.make_band(base, rs, bs, seed=4000 + b)
+    _say("analysis")
+    ref = SpiSolver(base.m, base.n, base.rowptr, base.col)
+    work = SpiSolver.like(ref)
+    # direct solves of bands 0..31 (training data), reference = band 31
+    _say("direct solves of bands 0..31")
+    data, t_direct = [], []
+    for b in range(32):
+        q = band(b)
+        v = (torch.from_numpy(q.val).to(dev), torch.from_numpy(q.w).to(dev),
+             torch.from_numpy(q.y).to(dev))
+        s = ref if b == 31 else work
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_values(v[0], v[1])
+        s.factor()
+        rhs = s.rhs(v[2])
+        x = s.solve(rhs)
+        torch.cuda.synchronize()
+        t_direct.append(time.perf_counter() - t0)
+        if b < 31:
+            data.append((v, rhs, x))
+    hid = 16
+    lp = SpiLearnedPrecond(hid, spi_synth.lp_init_params(hid, 0))
+    _say("training")
+    t0 = time.perf_counter()
+    losses = []
+    for epoch in range(20):
+        tot = 0.0
+        for v, rhs, x in data:
+            work.set_values(v[0], v[1])
+            tot += lp.train_step(work, ref, rhs, x, lr=0.02)
+        losses.append(tot / len(data))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    sample = np.linspace(32, 255, args.bands).round().astype(int)
+    res = {"with": [], "without": []}
+    _say(f"PCG on {len(sample)} bands")
+    for b in sample:
+        q = band(int(b))
+        v = (torch.from_numpy(q.val).to(dev), torch.from_numpy(q.w).to(dev),
+             torch.from_numpy(q.y).to(dev))
+        work.set_values(v[0], v[1])
+        rhs = work.rhs(v[2])
+        for key, model in (("without", None), ("with", lp)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = pcg_solve(work, ref, rhs, lp=model, tol=1e-10, maxit=300)
+            torch.cuda.synchronize()
+            res[key].append((time.perf_counter() - t0, info["iterations"],
+                             info["fell_back"], info["rel_residual"]))
+    def summ(r):
+        a = np.array([x[:3] for x in r], dtype=float)
+        return {"s_per_band": float(a[:, 0].mean()), "iterations_mean": float(a[:, 1].mean()),
+                "fallbacks": int(a[:, 2].sum()),
+                "max_rel_residual": float(max(x[3] for x in r))}
+    out = {
+        "metric": "s/band for x = A^-1 b (learned-preconditioned FP32 PCG)",
+        "value": summ(res["with"])["s_per_band"], "unit": "s/band", "n_gpus": 1,
+        "higher_is_better": False, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "learned: 256 drifting bands on the medium pattern",
+                   "pcg_bands": [int(b) for b in sample], "hidden": hid},
+        "direct_s_per_band": float(np.median(t_direct)),
+        "train_s": t_train, "train_loss_first_last": [losses[0], losses[-1]],
+        "pcg_with_network": summ(res["with"]),
+        "pcg_without_network": summ(res["without"]),
+    }
+    lp.close()
     print(json.dumps(out))
 
 
