@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--bands", type=int, default=64,
                     help="batch: number of bands; learned: PCG sample size")
     ap.add_argument("--subproblems", type=int, default=32)
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+    ap.add_argument("--precision", choices=("fp64", "mixed", "both"), default="fp64",
                     help="fp64: every stage in binary64; mixed: binary32 "
                          "matrix-core products on the root front, binary64 "
                          "elsewhere, refinement to convergence")
@@ -137,12 +137,41 @@ def main():
     from paper_1305_5683_amd import SpiSolver
 
     print(f"# generating workload config {args.config}", file=sys.stderr, flush=True)
-    p = spi_synth.make_config(args.config)
+    p = spi_synth.make_config(args.config, progress=lambda f: print(
+        f"#   pattern {100 * f:.0f}%", file=sys.stderr, flush=True))
+    torch.cuda.set_device(torch.device("cuda:0"))
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    results = {}
+    for prec in precisions:
+        out, x, d = measure(p, prec, args)
+        results[prec] = (out, x, d)
+    if len(precisions) == 2:
+        # mixed against the FP64 GPU path on the same system
+        _, x64, d64 = results["fp64"]
+        out, xm, dm = results["mixed"]
+        out["mixed_vs_fp64"] = {
+            "x_rel": float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64)),
+            "d_max_rel": float(torch.max(torch.abs(dm - d64) / d64)),
+            "fp64_s_per_system": results["fp64"][0]["value"]}
+        print(json.dumps(results["fp64"][0]))
+        print(json.dumps(out))
+        return
+    out = results[precisions[0]][0]
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out))
+
+
+def measure(p, prec, args):
+    """Time `args.steps` whole systems at one precision; returns the JSON
+    object and the last x and diag(A^-1) (device tensors)."""
+    import torch
+    from paper_1305_5683_amd import SpiSolver
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    mixed = args.precision == "mixed"
+    mixed = prec == "mixed"
     s = SpiSolver(p.m, p.n, p.rowptr, p.col, stream=stream, timing=1,
                   precision=1 if mixed else 0)
     t_an = time.perf_counter() - t0
@@ -160,7 +189,8 @@ def main():
         s.solve(bbuf, out=xbuf)
         s.diag_inv(out=dbuf)
 
-    print(f"# analysis {t_an:.2f}s; warmup {args.warmup}", file=sys.stderr, flush=True)
+    print(f"# {prec}: analysis {t_an:.2f}s; warmup {args.warmup}", file=sys.stderr,
+          flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -206,7 +236,7 @@ def main():
                    "m": p.m, "n": p.n, "nnz_h": int(p.nnz), "n_root": nR,
                    "n_leaf": i1["n_leaf"], "n_fronts": i1["n_groups"],
                    "nnz_a": i1["nnz_a"], "nnz_l": i1["nnz_l"],
-                   "precision": args.precision, "parallelism": "1 GPU"},
+                   "precision": prec, "parallelism": "1 GPU"},
         "gflops_per_s": flops / (ms / 1e3) / 1e9,
         "frac_fp64_peak_path": flops / (ms / 1e3) / (PEAK_FP64_TFLOPS * 1e12),
         "algorithmic_flops": flops,
@@ -218,10 +248,9 @@ def main():
                      "frac": ach / peak, "traffic": None},
     }
     s.close()
-    if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(p)
-    print(json.dumps(out))
+    return out, xbuf, dbuf
+
+
 
 
 def _say(msg):

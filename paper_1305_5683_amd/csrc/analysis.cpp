@@ -27,6 +27,9 @@
 #include <cmath>
 #include <numeric>
 #include <sstream>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <thread>
 
 #include "spi_internal.h"
@@ -37,6 +40,52 @@ namespace {
 constexpr int kTile = 64;  // root assembly tile
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// With SPI_VERBOSE set in the environment the analysis reports the time of
+// each phase on stderr (large patterns take minutes on the host).
+struct PhaseLog {
+  bool on = std::getenv("SPI_VERBOSE") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void operator()(const char* what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[spi analysis] %-30s %8.2f s\n", what,
+                 std::chrono::duration<double>(now - t).count());
+    std::fflush(stderr);
+    t = now;
+  }
+};
+
+unsigned n_threads() {
+  return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+}
+
+// Run f(t) for t in [0, T) on T threads.
+template <class F>
+void parallel(unsigned T, F f) {
+  if (T <= 1) {
+    f(0u);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(T);
+  for (unsigned t = 0; t < T; ++t) th.emplace_back([&f, t]() { f(t); });
+  for (auto& x : th) x.join();
+}
+
+// Split [0, n) into T ranges of about equal weight, weight(i) = w[i+1]-w[i]
+// for a prefix array w (e.g. rowptr).
+std::vector<int64_t> balanced_ranges(const int64_t* w, int64_t n, unsigned T) {
+  std::vector<int64_t> b(T + 1, n);
+  b[0] = 0;
+  const int64_t total = w[n] - w[0];
+  for (unsigned t = 1; t < T; ++t) {
+    const int64_t target = w[0] + total * (int64_t)t / (int64_t)T;
+    b[t] = std::lower_bound(w, w + n + 1, target) - w;
+    b[t] = std::min(std::max(b[t], b[t - 1]), n);
+  }
+  return b;
+}
 
 // Runs of a sorted index list by tile: (tile, first position, end position).
 void tile_runs(const int32_t* U, int64_t nU,
@@ -56,6 +105,7 @@ void tile_runs(const int32_t* U, int64_t nU,
 std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
                     const int32_t* col, const spi_opts& o, Analysis& a) {
   std::ostringstream err;
+  PhaseLog phase;
   if (m < 1 || n < 1) return "m and n must be >= 1";
   if (n > INT32_MAX - 1 || m > INT32_MAX - 1) return "m and n must fit int32";
   if (!rowptr || !col) return "rowptr and col must be non-null host pointers";
@@ -87,35 +137,53 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   a.rowptr.assign(rowptr, rowptr + m + 1);
   a.col.assign(col, col + nnz);
 
-  // ---- transpose of the pattern
-  a.colptr.assign(n + 1, 0);
-  for (int64_t e = 0; e < nnz; ++e) a.colptr[col[e] + 1]++;
-  for (int64_t j = 0; j < n; ++j) {
-    if (a.colptr[j + 1] == 0) {
-      err << "unknown " << j << " appears in no row (A would be singular)";
-      return err.str();
-    }
-    a.colptr[j + 1] += a.colptr[j];
-  }
-  a.csc_pos.resize(nnz);
-  a.csc_row.resize(nnz);
+  // ---- transpose of the pattern (parallel counting sort over row ranges;
+  // rows stay in increasing order within each column)
+  const unsigned NT = n_threads();
   {
-    std::vector<int64_t> fill(a.colptr.begin(), a.colptr.end() - 1);
-    for (int64_t r = 0; r < m; ++r)
-      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        int64_t k = fill[col[e]]++;
-        a.csc_pos[k] = e;
-        a.csc_row[k] = (int32_t)r;
+    const std::vector<int64_t> rb = balanced_ranges(rowptr, m, NT);
+    std::vector<std::vector<int64_t>> off(NT, std::vector<int64_t>(n, 0));
+    parallel(NT, [&](unsigned t) {
+      int64_t* c = off[t].data();
+      for (int64_t e = rowptr[rb[t]]; e < rowptr[rb[t + 1]]; ++e) c[col[e]]++;
+    });
+    a.colptr.assign(n + 1, 0);
+    for (int64_t j = 0; j < n; ++j) {
+      int64_t s = a.colptr[j];
+      for (unsigned t = 0; t < NT; ++t) {
+        const int64_t c = off[t][j];
+        off[t][j] = s;
+        s += c;
       }
+      if (s == a.colptr[j]) {
+        err << "unknown " << j << " appears in no row (A would be singular)";
+        return err.str();
+      }
+      a.colptr[j + 1] = s;
+    }
+    a.csc_pos.resize(nnz);
+    a.csc_row.resize(nnz);
+    parallel(NT, [&](unsigned t) {
+      int64_t* o = off[t].data();
+      for (int64_t r = rb[t]; r < rb[t + 1]; ++r)
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          const int64_t k = o[col[e]]++;
+          a.csc_pos[k] = e;
+          a.csc_row[k] = (int32_t)r;
+        }
+    });
   }
 
+  phase("transpose");
   // ---- leaf selection: greedy independent set by increasing work
   std::vector<int64_t> work(n, 0);
-  for (int64_t j = 0; j < n; ++j)
-    for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
-      int32_t r = a.csc_row[k];
-      work[j] += rowptr[r + 1] - rowptr[r];
-    }
+  parallel(NT, [&](unsigned t) {
+    for (int64_t j = t; j < n; j += NT)
+      for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
+        int32_t r = a.csc_row[k];
+        work[j] += rowptr[r + 1] - rowptr[r];
+      }
+  });
   std::vector<int32_t> cand;
   for (int64_t j = 0; j < n; ++j)
     if ((double)work[j] <= o.leaf_max_work) cand.push_back((int32_t)j);
@@ -133,6 +201,7 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
       claimed[a.csc_row[k]] = 1;
   }
 
+  phase("leaf selection");
   // ---- root numbering (original order)
   a.root_of_col.assign(n, -1);
   for (int64_t j = 0; j < n; ++j)
@@ -143,12 +212,13 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   a.n_root = (int64_t)a.root_cols.size();
   a.n_pad = a.n_root ? round_up(a.n_root, kRootPad) : 0;
 
+  phase("root numbering");
   // ---- amalgamate consecutive leaves into fronts
   std::vector<int32_t> leaves;
   for (int64_t j = 0; j < n; ++j)
     if (is_leaf[j]) leaves.push_back((int32_t)j);
   const int64_t nr = std::max<int64_t>(a.n_root, 1);
-  std::vector<int64_t> mark(nr, -1), seen(nr, -1), posmap(nr, -1);
+  std::vector<int64_t> mark(nr, -1), seen(nr, -1);
   a.grp_col_ptr.push_back(0);
   a.grp_U_ptr.push_back(0);
   a.grp_panel_off.push_back(0);
@@ -209,102 +279,140 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   if (!curCols.empty()) close_front();
   a.n_groups = front;
 
+  phase("amalgamation");
   // ---- slots (rows of the leaf fronts, by leaf unknown) and their compact
-  // root entries with U-local positions
+  // root entries with U-local positions.  Sizes first, then every front
+  // fills its own ranges (in parallel).
   const int64_t n_leaf = (int64_t)a.leaf_cols.size();
-  a.leaf_slot_ptr.assign(n_leaf + 1, 0);
-  a.grp_slot_ptr.push_back(0);
-  a.slot_rr_ptr.push_back(0);
-  std::fill(posmap.begin(), posmap.end(), -1);
-  for (int64_t g = 0; g < a.n_groups; ++g) {
-    for (int64_t u = a.grp_U_ptr[g]; u < a.grp_U_ptr[g + 1]; ++u)
-      posmap[a.U[u]] = u - a.grp_U_ptr[g];
-    for (int64_t l = a.grp_col_ptr[g]; l < a.grp_col_ptr[g + 1]; ++l) {
-      int32_t j = a.leaf_cols[l];
-      for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
-        const int32_t r = a.csc_row[k];
-        a.slot_row.push_back(r);
-        a.slot_leaf_src.push_back(a.csc_pos[k]);
-        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-          int32_t ri = a.root_of_col[col[e]];
-          if (ri < 0) continue;
-          a.rr_lpos.push_back((int32_t)posmap[ri]);
-          a.rr_src.push_back(e);
-        }
-        a.slot_rr_ptr.push_back((int64_t)a.rr_src.size());
-      }
-      a.leaf_slot_ptr[l + 1] = (int64_t)a.slot_row.size();
+  std::vector<int32_t> root_cnt(m, 0);  // root entries per row
+  parallel(NT, [&](unsigned t) {
+    for (int64_t r = t; r < m; r += NT) {
+      int32_t c = 0;
+      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) c += a.root_of_col[col[e]] >= 0;
+      root_cnt[r] = c;
     }
-    a.grp_slot_ptr.push_back((int64_t)a.slot_row.size());
+  });
+  a.leaf_slot_ptr.assign(n_leaf + 1, 0);
+  for (int64_t l = 0; l < n_leaf; ++l) {
+    const int32_t j = a.leaf_cols[l];
+    a.leaf_slot_ptr[l + 1] = a.leaf_slot_ptr[l] + (a.colptr[j + 1] - a.colptr[j]);
   }
-  a.n_slots = (int64_t)a.slot_row.size();
+  a.n_slots = a.leaf_slot_ptr[n_leaf];
+  a.grp_slot_ptr.resize(a.n_groups + 1);
+  for (int64_t g = 0; g <= a.n_groups; ++g) a.grp_slot_ptr[g] = a.leaf_slot_ptr[a.grp_col_ptr[g]];
+  a.slot_row.resize(a.n_slots);
+  a.slot_leaf_src.resize(a.n_slots);
+  a.slot_rr_ptr.assign(a.n_slots + 1, 0);
+  for (int64_t l = 0; l < n_leaf; ++l) {
+    const int32_t j = a.leaf_cols[l];
+    int64_t sl = a.leaf_slot_ptr[l];
+    for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k, ++sl) {
+      a.slot_row[sl] = a.csc_row[k];
+      a.slot_leaf_src[sl] = a.csc_pos[k];
+      a.slot_rr_ptr[sl + 1] = a.slot_rr_ptr[sl] + root_cnt[a.csc_row[k]];
+    }
+  }
+  a.rr_lpos.resize(a.slot_rr_ptr[a.n_slots]);
+  a.rr_src.resize(a.slot_rr_ptr[a.n_slots]);
+  parallel(NT, [&](unsigned t) {
+    std::vector<int64_t> pm(nr, -1);
+    for (int64_t g = t; g < a.n_groups; g += NT) {
+      for (int64_t u = a.grp_U_ptr[g]; u < a.grp_U_ptr[g + 1]; ++u)
+        pm[a.U[u]] = u - a.grp_U_ptr[g];
+      for (int64_t sl = a.grp_slot_ptr[g]; sl < a.grp_slot_ptr[g + 1]; ++sl) {
+        const int32_t r = a.slot_row[sl];
+        int64_t q = a.slot_rr_ptr[sl];
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          const int32_t ri = a.root_of_col[col[e]];
+          if (ri < 0) continue;
+          a.rr_lpos[q] = (int32_t)pm[ri];
+          a.rr_src[q] = e;
+          ++q;
+        }
+      }
+    }
+  });
 
+  phase("slots");
   // ---- row panels: consecutive rows (original order) with overlapping
-  // root structure; rows without root entries contribute nothing to A_RR
+  // root structure; rows without root entries contribute nothing to A_RR.
+  // The grouping is sequential (each decision depends on the open panel);
+  // the per-entry maps are then filled panel by panel in parallel.
   a.rp_U_base = (int64_t)a.U.size();
-  a.rp_row_ptr.push_back(0);
-  a.rp_U_ptr.push_back(0);
-  a.rp_val_off.push_back(0);
-  a.rpe_ptr.push_back(0);
+  a.rp_row_ptr.assign(1, 0);
+  a.rp_U_ptr.assign(1, 0);
+  a.rp_val_off.assign(1, 0);
   std::fill(mark.begin(), mark.end(), -1);
   {
-    int64_t panel = 0, rows_in = 0, sum = 0;
-    std::vector<int32_t> pU, pRows;
+    int64_t panel = 0, rows_in = 0, sum = 0, pU0 = (int64_t)a.U.size();
     auto close_panel = [&]() {
-      std::sort(pU.begin(), pU.end());
-      for (size_t x = 0; x < pU.size(); ++x) posmap[pU[x]] = (int64_t)x;
-      const int64_t nU = (int64_t)pU.size();
-      for (size_t q = 0; q < pRows.size(); ++q) {
-        const int32_t r = pRows[q];
-        a.rp_rows.push_back(r);
-        a.rp_rowbase.push_back(a.rp_val_off.back() + (int64_t)q * nU);
-        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-          int32_t ri = a.root_of_col[col[e]];
-          if (ri < 0) continue;
-          a.rpe_pos.push_back((int32_t)posmap[ri]);
-          a.rpe_src.push_back(e);
-        }
-        a.rpe_ptr.push_back((int64_t)a.rpe_src.size());
-      }
-      a.U.insert(a.U.end(), pU.begin(), pU.end());
+      std::sort(a.U.begin() + pU0, a.U.end());
+      const int64_t nU = (int64_t)a.U.size() - pU0;
       a.rp_row_ptr.push_back((int64_t)a.rp_rows.size());
       a.rp_U_ptr.push_back((int64_t)a.U.size() - a.rp_U_base);
-      a.rp_val_off.push_back(a.rp_val_off.back() + nU * (int64_t)pRows.size());
+      a.rp_val_off.push_back(a.rp_val_off.back() + nU * rows_in);
       ++panel;
-      pU.clear();
-      pRows.clear();
+      pU0 = (int64_t)a.U.size();
       rows_in = 0;
       sum = 0;
     };
     for (int64_t r = 0; r < m; ++r) {
-      int64_t len = 0, add = 0;
-      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        int32_t ri = a.root_of_col[col[e]];
-        if (ri < 0) continue;
-        ++len;
-        if (mark[ri] != panel) ++add;
-      }
+      const int64_t len = root_cnt[r];
       if (len == 0) continue;
       if (rows_in > 0) {
-        const int64_t newU = (int64_t)pU.size() + add;
+        int64_t add = 0;
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          const int32_t ri = a.root_of_col[col[e]];
+          if (ri >= 0 && mark[ri] != panel) ++add;
+        }
+        const int64_t newU = (int64_t)a.U.size() - pU0 + add;
         const double dens = (double)(sum + len) / ((double)newU * (double)(rows_in + 1));
         if (rows_in + 1 > o.max_group || dens < o.amalg_density) close_panel();
       }
       for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        int32_t ri = a.root_of_col[col[e]];
+        const int32_t ri = a.root_of_col[col[e]];
         if (ri >= 0 && mark[ri] != panel) {
           mark[ri] = panel;
-          pU.push_back(ri);
+          a.U.push_back(ri);
         }
       }
-      pRows.push_back((int32_t)r);
+      a.rp_rows.push_back((int32_t)r);
       ++rows_in;
       sum += len;
     }
     if (rows_in > 0) close_panel();
     a.n_rp = panel;
   }
+  {
+    const int64_t nrows = (int64_t)a.rp_rows.size();
+    a.rp_rowbase.resize(nrows);
+    a.rpe_ptr.assign(nrows + 1, 0);
+    for (int64_t q = 0; q < nrows; ++q) a.rpe_ptr[q + 1] = a.rpe_ptr[q] + root_cnt[a.rp_rows[q]];
+    a.rpe_pos.resize(a.rpe_ptr[nrows]);
+    a.rpe_src.resize(a.rpe_ptr[nrows]);
+    parallel(NT, [&](unsigned t) {
+      std::vector<int64_t> pm(nr, -1);
+      for (int64_t p = t; p < a.n_rp; p += NT) {
+        const int32_t* Up = a.U.data() + a.rp_U_base + a.rp_U_ptr[p];
+        const int64_t nU = a.rp_U_ptr[p + 1] - a.rp_U_ptr[p];
+        for (int64_t x = 0; x < nU; ++x) pm[Up[x]] = x;
+        for (int64_t q = a.rp_row_ptr[p]; q < a.rp_row_ptr[p + 1]; ++q) {
+          const int32_t r = a.rp_rows[q];
+          a.rp_rowbase[q] = a.rp_val_off[p] + (q - a.rp_row_ptr[p]) * nU;
+          int64_t z = a.rpe_ptr[q];
+          for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+            const int32_t ri = a.root_of_col[col[e]];
+            if (ri < 0) continue;
+            a.rpe_pos[z] = (int32_t)pm[ri];
+            a.rpe_src[z] = e;
+            ++z;
+          }
+        }
+      }
+    });
+  }
 
+  phase("row panels");
   // ---- update-panel descriptors: leaf fronts (weight -1), row panels
   const int64_t leaf_panel_total = a.grp_panel_off[a.n_groups];
   for (int64_t g = 0; g < a.n_groups; ++g) {
@@ -370,7 +478,18 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
                      [&](int32_t x, int32_t y) { return tw[x] > tw[y]; });
   }
 
+  phase("incidences");
   // ---- selected-inversion tasks of the leaf fronts
+  {
+    int64_t nt_all = 0;
+    for (int64_t f = 0; f < a.n_groups; ++f) {
+      const int64_t nt = (a.grp_U_ptr[f + 1] - a.grp_U_ptr[f] + kET - 1) / kET;
+      nt_all += nt * (nt + 1) / 2;
+    }
+    a.tasks.reserve(3 * nt_all);
+    a.task_part_off.reserve(nt_all + 1);
+    a.grp_task_ptr.reserve(a.n_groups + 1);
+  }
   a.grp_task_ptr.push_back(0);
   a.task_part_off.push_back(0);
   for (int64_t f = 0; f < a.n_groups; ++f) {
@@ -405,6 +524,7 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
                      [&](int32_t x, int32_t y) { return key[x] < key[y]; });
   }
 
+  phase("selected-inversion tasks");
   // ---- root incidences of the leaf panels (forward solve)
   a.rinc_ptr.assign(a.n_root + 1, 0);
   for (int64_t g = 0; g < a.n_groups; ++g)
@@ -423,6 +543,7 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
       }
   }
 
+  phase("root incidences");
   // ---- counters: nnz(A) (both triangles), nnz(L) as stored, flops.
   // The exact structural count of A costs sum over rows of len^2 scattered
   // visits; above kNnzACountCap of them it is not taken (nnz_a = -1).
@@ -471,6 +592,7 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
     double len = (double)(rowptr[r + 1] - rowptr[r]);
     a.flops_asm += 2.0 * len * len;
   }
+  phase("counters");
   return std::string();
 }
 

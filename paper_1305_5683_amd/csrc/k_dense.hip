@@ -414,31 +414,28 @@ static hipError_t copy2d(hipStream_t s, const double* src, int64_t lds,
   return hipGetLastError();
 }
 
-// Inverse of the root factor, W = L^-1, in place on a copy of L, by outer
-// block columns left to right.  With the first block columns already
-// inverted, row block k to the left holds L_k,<k X_<k and the block rows
-// below hold L_>k,<k X_<k.  Step k, with X_kk = L_kk^-1 (from the batched
-// diagonal-block inversion):
+// Right-looking inversion of the diagonal block [off, off + size) of the
+// factor, in place on W (which holds that block of L on entry).  With the
+// first block columns of the block already inverted, row block k to the left
+// holds L_k,<k X_<k and the block rows below hold L_>k,<k X_<k.  Step k, with
+// X_kk = L_kk^-1 (the stored kNBO-block inverses):
 //   T       = L_>k,k X_kk             (becomes the state of block column k)
 //   S_>k,<k -= T * S_k,<k
 //   S_k,<k   = -X_kk * S_k,<k         (final row block k of L^-1)
 //   S_kk     = X_kk
-// The two in-place products read their input from a scratch copy.
-hipError_t root_trtri(Handle& h) {
-  const bool f32 = h.opts.precision == SPI_MIXED;
-  const int np = (int)h.an.n_pad;
-  const int64_t ld = np;
+// The two in-place products read their input from a scratch copy.  Each
+// product sums kNBO terms (binary32 in mixed precision, then binary64).
+static hipError_t trtri_sweep(Handle& h, int off, int size, bool f32) {
+  const int64_t ld = h.an.n_pad;
+  double* Wb = h.W + off + (int64_t)off * ld;
   hipError_t e;
-  hipLaunchKernelGGL(k_copy_lower, dim3(fill_grid((int64_t)np * np)), dim3(256),
-                     0, h.stream, h.S, h.W, (int64_t)np);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  for (int K0 = 0; K0 < np; K0 += kNBO) {
-    const int KB = std::min(kNBO, np - K0), K1 = K0 + KB;
-    const int rest = np - K1;
-    const double* X11 = h.invd2 + (int64_t)(K0 / kNBO) * kNBO * kNBO;
-    double* W21 = h.W + (int64_t)K1 + (int64_t)K0 * ld;
-    double* W10 = h.W + (int64_t)K0;
-    double* W20 = h.W + (int64_t)K1;
+  for (int K0 = 0; K0 < size; K0 += kNBO) {
+    const int KB = std::min(kNBO, size - K0), K1 = K0 + KB;
+    const int rest = size - K1;
+    const double* X11 = h.invd2 + (int64_t)((off + K0) / kNBO) * kNBO * kNBO;
+    double* W21 = Wb + (int64_t)K1 + (int64_t)K0 * ld;
+    double* W10 = Wb + (int64_t)K0;
+    double* W20 = Wb + (int64_t)K1;
     const int bk = (KB % 128 == 0) ? 128 : 64;
     if (rest > 0) {
       if ((e = copy2d(h.stream, W21, ld, h.scratch, ld, rest, KB)) != hipSuccess)
@@ -459,11 +456,58 @@ hipError_t root_trtri(Handle& h) {
                KB, K0, KB, -1.0, 0.0, false, false, false, f32);
       if (e != hipSuccess) return e;
     }
-    if ((e = copy2d(h.stream, X11, kNBO, h.W + (int64_t)K0 * (ld + 1), ld, KB,
+    if ((e = copy2d(h.stream, X11, kNBO, Wb + (int64_t)K0 * (ld + 1), ld, KB,
                     KB)) != hipSuccess)
       return e;
   }
   return hipSuccess;
+}
+
+// Below this order a diagonal block is inverted by the sweep: its GEMMs
+// span all rows below the step and keep the GPU full, where further halving
+// would launch products of a few tiles each.
+constexpr int kTrtriRecMin = 4096;
+
+// FP64: the top of the inversion by halving.  Split at hh (a multiple of
+// kNBO), invert both diagonal halves, then
+//   W21 = -X22 (L21 X11)
+// as two GEMMs with a triangular operand each (the K range of a tile is
+// trimmed to where that operand is non-zero).  These GEMMs have K up to
+// size / 2 and carry most of the flops; the sweep's products have K = kNBO.
+// T = L21 X11 is staged in Z, which holds nothing until the root block of
+// A^-1 is formed.
+static hipError_t trtri_rec(Handle& h, int off, int size) {
+  if (size <= kTrtriRecMin) return trtri_sweep(h, off, size, false);
+  const int64_t ld = h.an.n_pad;
+  hipError_t e;
+  const int hh = ((size / 2 + kNBO - 1) / kNBO) * kNBO;
+  const int r = size - hh;
+  if ((e = trtri_rec(h, off, hh)) != hipSuccess) return e;
+  if ((e = trtri_rec(h, off + hh, r)) != hipSuccess) return e;
+  const double* L21 = h.S + (off + hh) + (int64_t)off * ld;
+  const double* X11 = h.W + off + (int64_t)off * ld;
+  const double* X22 = h.W + (off + hh) + (int64_t)(off + hh) * ld;
+  double* W21 = h.W + (off + hh) + (int64_t)off * ld;
+  double* T = h.Z;
+  e = gemm(h.stream, pick_bm(r), 128, kXC, kKC, L21, ld, X11, ld, T, ld, r, hh, hh,
+           1.0, 0.0, false, false, false, false, kGemmKStartCol);
+  if (e != hipSuccess) return e;
+  return gemm(h.stream, pick_bm(r), 128, kXC, kKC, X22, ld, T, ld, W21, ld, r, hh,
+              r, -1.0, 0.0, false, false, false, false, kGemmKEndRow);
+}
+
+// Inverse of the root factor, W = L^-1.  W starts as a copy of L's lower
+// triangle with zeros above (the zeros matter: later products read whole
+// diagonal tiles).  Mixed precision uses the sweep alone, whose products
+// sum at most kNBO terms in binary32 before the binary64 accumulation.
+hipError_t root_trtri(Handle& h) {
+  const bool f32 = h.opts.precision == SPI_MIXED;
+  const int np = (int)h.an.n_pad;
+  hipLaunchKernelGGL(k_copy_lower, dim3(fill_grid((int64_t)np * np)), dim3(256), 0,
+                     h.stream, h.S, h.W, (int64_t)np);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return f32 ? trtri_sweep(h, 0, np, true) : trtri_rec(h, 0, np);
 }
 
 // Z = W^T W (lower tiles); tile (I, J) sums over K >= I since W is lower

@@ -18,6 +18,8 @@
 // Tiles are BM x BN, 256 threads = 4 waves in a 2 x 2 grid; each wave owns
 // a (BM/2) x (BN/2) block of 16 x 16 accumulators.  K advances in slabs of
 // kKT = 32, staged through LDS with a register prefetch of the next slab.
+// `kmask`: kGemmKStartCol (B lower triangular: k >= j only) and
+// kGemmKEndRow (A lower triangular: k <= i only) trim the K range per tile.
 // `lower`: only tiles with I >= J are enumerated (square tiles) and the
 // diagonal tiles write their lower triangle only.  `kstart_diag`: the K
 // range of tile (I, J) starts at I * BM (products whose left factor is lower
@@ -46,11 +48,14 @@ __device__ inline v4f mfma16(float a, float b, v4f c) {
 
 constexpr int kKT = 32;
 constexpr int kGroup = 8;      // tile rows per group of the launch order
-// LDS row strides (doubles): kXC slabs [k][x] padded by 16 so the four
-// 16-lane groups of a fragment read fall in different bank halves; kKC
-// slabs [x][k] with stride kKT + 2 (16 bytes mod 256) so the 32 lanes of a
-// half-wave read distinct banks.
-constexpr int kPadXC = 16;
+// LDS layouts.  kXC slabs are [k][x] with the row padded so that a row's
+// stride is 64 bytes mod 256: the four 16-lane groups of a fragment read
+// (k = ks .. ks + 3) then start in four different quarters of the banks
+// (8 elements of padding for double, 16 for float).  kKC slabs are [x][k]
+// with stride kKT + 2 so the lanes of a fragment read spread over banks.
+template <typename T> struct PadXC;
+template <> struct PadXC<double> { static constexpr int v = 8; };
+template <> struct PadXC<float> { static constexpr int v = 16; };
 constexpr int kStrKC = kKT + 2;
 
 struct GemmArgs {
@@ -61,6 +66,7 @@ struct GemmArgs {
   int M, N, K;
   double alpha, beta;
   int lower, kstart_diag, diag_mask;
+  int kmask;  // kGemmKStartCol / kGemmKEndRow: triangular operands
   int tiles_m, tiles_n, n_tiles;
 };
 
@@ -120,6 +126,7 @@ template <int BM, int BN, int OPA, int OPB, typename T>
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int MI = WM / 16, NI = WN / 16;
+  constexpr int kPadXC = PadXC<T>::v;
   constexpr int A_SZ = (OPA == kXC) ? kKT * (BM + kPadXC) : BM * kStrKC;
   constexpr int B_SZ = (OPB == kXC) ? kKT * (BN + kPadXC) : BN * kStrKC;
   __shared__ T As[A_SZ];
@@ -131,26 +138,34 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   if (g.diag_mask && i0 + BM - 1 < j0) return;  // tile above the diagonal
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int kbeg = g.kstart_diag ? i0 : 0;
-  const int kend = g.K;
+  // K range of the tile: an upper-triangular A starts at i0 (kstart_diag),
+  // a lower-triangular B starts at j0, a lower-triangular A ends at i0 + BM
+  int kbeg = g.kstart_diag ? i0 : 0;
+  if (g.kmask & kGemmKStartCol) kbeg = max(kbeg, j0);
+  const int kend = (g.kmask & kGemmKEndRow) ? min(g.K, i0 + BM) : g.K;
 
   // global -> register staging: each thread moves EA (EB) doubles per slab
   constexpr int EA = BM * kKT / 256, EB = BN * kKT / 256;
   double ra[EA], rb[EB];
 
+  // kXC: a k-row of the slab is X contiguous doubles; X / 2 threads read it
+  // as double2 (a wave covers whole rows), so both the global read and the
+  // LDS write of one instruction are contiguous.  kKC: every x has kKT
+  // contiguous k; kKT / E threads share one x.
   auto load = [&](const double* base, int64_t ld, int x0, int k0, int op,
                   int X, int E, double* r) {
-    if (op == kXC) {  // kKT rows of X contiguous doubles
-      const int tpr = X / E;
-      const int kk = tid / tpr, x = (tid % tpr) * E;
-      const double* p = base + (int64_t)(x0 + x) + (int64_t)(k0 + kk) * ld;
+    if (op == kXC) {
+      const int tpr = X / 2, rows = 256 / tpr;
+      const int r0 = tid / tpr, x = (tid % tpr) * 2;
 #pragma unroll
-      for (int e = 0; e < E; e += 2) {
-        double2 v = *reinterpret_cast<const double2*>(p + e);
-        r[e] = v.x;
-        r[e + 1] = v.y;
+      for (int i = 0; i < E / 2; ++i) {
+        const int kk = r0 + i * rows;
+        double2 v = *reinterpret_cast<const double2*>(
+            base + (int64_t)(x0 + x) + (int64_t)(k0 + kk) * ld);
+        r[2 * i] = v.x;
+        r[2 * i + 1] = v.y;
       }
-    } else {  // for each x: kKT contiguous k
+    } else {
       const int tpx = kKT / E;
       const int x = tid / tpx, kk = (tid % tpx) * E;
       const double* p = base + (int64_t)(k0 + kk) + (int64_t)(x0 + x) * ld;
@@ -164,10 +179,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   };
   auto store = [&](T* L, int op, int X, int E, const double* r) {
     if (op == kXC) {
-      const int tpr = X / E;
-      const int kk = tid / tpr, x = (tid % tpr) * E;
+      const int tpr = X / 2, rows = 256 / tpr;
+      const int r0 = tid / tpr, x = (tid % tpr) * 2;
 #pragma unroll
-      for (int e = 0; e < E; ++e) L[kk * (X + kPadXC) + x + e] = (T)r[e];
+      for (int i = 0; i < E / 2; ++i) {
+        const int kk = r0 + i * rows;
+        L[kk * (X + kPadXC) + x] = (T)r[2 * i];
+        L[kk * (X + kPadXC) + x + 1] = (T)r[2 * i + 1];
+      }
     } else {
       const int tpx = kKT / E;
       const int x = tid / tpx, kk = (tid % tpx) * E;
@@ -256,12 +275,12 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* C, int64_t ldc, int M, int N, int K, double alpha,
                 double beta, bool lower, bool kstart_diag, bool diag_mask,
-                bool f32) {
+                bool f32, int kmask) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (M % bm || N % bn || K % kKT || (lower && (bm != bn || M != N)))
     return hipErrorInvalidValue;
   GemmArgs a{A, B, C, lda, ldb, ldc, M, N, K, alpha, beta, lower ? 1 : 0,
-             kstart_diag ? 1 : 0, diag_mask ? 1 : 0, 0, 0, 0};
+             kstart_diag ? 1 : 0, diag_mask ? 1 : 0, kmask, 0, 0, 0};
 #define SPI_GEMM_CASE(BM_, BN_, OA, OB)                                   \
   if (bm == BM_ && bn == BN_ && opA == OA && opB == OB)                  \
     return f32 ? gemm_t<BM_, BN_, OA, OB, float>(s, a)                   \

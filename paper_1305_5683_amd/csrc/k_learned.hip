@@ -44,8 +44,14 @@ struct NetLayout {
   static constexpr int P = owl + kF;
 };
 
+// Grid of a grid-stride kernel (capped: the kernel loops).
 int grid_of(int64_t n, int per) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 65535));
+}
+
+// Grid of a one-thread-per-unknown kernel: exact (n < 2^31).
+int grid_exact(int64_t n) {
+  return (int)std::max<int64_t>(1, (n + kLpThreads - 1) / kLpThreads);
 }
 
 }  // namespace
@@ -361,7 +367,7 @@ constexpr int kVecBlocks = 256;
 hipError_t lp_features(hipStream_t s, const double* diag_b, const double* diag_r,
                        const int32_t* root_of_col, float* phi, double* part,
                        int64_t n) {
-  const int nb = grid_of(n, kLpThreads);
+  const int nb = grid_exact(n);
   hipLaunchKernelGGL(k_lp_f0, dim3(nb), dim3(kLpThreads), 0, s, diag_b, diag_r,
                      root_of_col, phi, part, n);
   hipLaunchKernelGGL(k_lp_f2, dim3(nb), dim3(kLpThreads), 0, s, part, nb,
@@ -369,7 +375,7 @@ hipError_t lp_features(hipStream_t s, const double* diag_b, const double* diag_r
   return hipGetLastError();
 }
 
-int lp_backward_blocks(int64_t n) { return grid_of(n, kLpThreads); }
+int lp_backward_blocks(int64_t n) { return grid_exact(n); }
 
 #define SPI_LP_HID(H, call)       \
   switch (H) {                    \
@@ -382,7 +388,7 @@ int lp_backward_blocks(int64_t n) { return grid_of(n, kLpThreads); }
 hipError_t lp_forward(hipStream_t s, int hidden, const float* params,
                       const float* phi, double* d, int64_t n) {
 #define SPI_FWD(H)                                                              \
-  hipLaunchKernelGGL(k_lp_forward<H>, dim3(grid_of(n, kLpThreads)),            \
+  hipLaunchKernelGGL(k_lp_forward<H>, dim3(grid_exact(n)),                    \
                      dim3(kLpThreads), 0, s, params, phi, d, n)
   SPI_LP_HID(hidden, SPI_FWD)
 #undef SPI_FWD
@@ -392,7 +398,7 @@ hipError_t lp_forward(hipStream_t s, int hidden, const float* params,
 hipError_t lp_backward(hipStream_t s, int hidden, const float* params,
                        const float* phi, const double* dLdd, const double* d,
                        double* part, double* grad, int64_t n) {
-  const int nb = grid_of(n, kLpThreads);
+  const int nb = grid_exact(n);
 #define SPI_BWD(H)                                                              \
   hipLaunchKernelGGL(k_lp_backward<H>, dim3(nb), dim3(kLpThreads), 0, s,       \
                      params, phi, dLdd, d, part, n)

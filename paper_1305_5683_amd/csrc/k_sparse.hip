@@ -24,9 +24,16 @@ constexpr int kQC = 16;
 // up to 8 waves per SIMD hide the latency of the small panel loads)
 constexpr int kAsmThreads = 512;
 
+// Grid of a grid-stride kernel (capped: the kernel loops).
 static int grid_for(int64_t items, int per_block) {
   int64_t g = (items + per_block - 1) / per_block;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 20));
+}
+
+// Grid of a one-wave-per-item kernel (4 waves per 256-thread block, no
+// loop): exact.  Items are rows or columns of H (< 2^31), so it fits.
+static unsigned wave_grid(int64_t items) {
+  return (unsigned)std::max<int64_t>(1, (items + 3) / 4);
 }
 
 // ------------------------------------------------------------ value layout
@@ -109,7 +116,7 @@ hipError_t launch_leaf_assemble(Handle& h) {
   const Analysis& a = h.an;
   const int64_t nl = (int64_t)a.leaf_cols.size();
   if (!nl) return hipSuccess;
-  hipLaunchKernelGGL(k_leaf_assemble, dim3(grid_for(nl, 4)), dim3(256), 0,
+  hipLaunchKernelGGL(k_leaf_assemble, dim3(wave_grid(nl)), dim3(256), 0,
                      h.stream, h.d.leaf_grp, h.d.leaf_slot_ptr, h.d.grp_col_ptr,
                      h.d.grp_U_ptr, h.d.grp_panel_off, h.d.slot_rr_ptr,
                      h.d.rr_lpos, h.rrval, h.sw, h.sleaf, h.panel, h.ldiag,
@@ -150,7 +157,7 @@ hipError_t launch_fill_rowpanels(Handle& h) {
   const int64_t total = a.rp_val_off[a.n_rp];
   hipLaunchKernelGGL(k_zero, dim3(grid_for(total, 256 * 8)), dim3(256), 0,
                      h.stream, rpbuf, total);
-  hipLaunchKernelGGL(k_fill_rowpanels, dim3(grid_for(nrows, 4)), dim3(256), 0,
+  hipLaunchKernelGGL(k_fill_rowpanels, dim3(wave_grid(nrows)), dim3(256), 0,
                      h.stream, h.val, h.w, h.d.rp_rows, h.d.rp_rowbase,
                      h.d.rpe_ptr, h.d.rpe_pos, h.d.rpe_src, rpbuf, h.rpw, nrows);
   return hipGetLastError();
@@ -360,7 +367,7 @@ __global__ void k_scale_vec(const double* x, const double* __restrict__ s, doubl
 hipError_t launch_equilibrate(Handle& h) {
   const Analysis& a = h.an;
   const bool eq = h.opts.equilibrate != 0;
-  hipLaunchKernelGGL(k_col_scale, dim3(grid_for(a.n, 4)), dim3(256), 0, h.stream,
+  hipLaunchKernelGGL(k_col_scale, dim3(wave_grid(a.n)), dim3(256), 0, h.stream,
                      h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.w, h.diagA,
                      eq ? h.colscale : nullptr, a.n);
   if (eq && a.nnz)
@@ -427,7 +434,7 @@ __global__ __launch_bounds__(256) void k_rhs(const int64_t* __restrict__ colptr,
 }
 
 hipError_t launch_rhs(Handle& h, const double* y, double* b) {
-  hipLaunchKernelGGL(k_rhs, dim3(grid_for(h.an.n, 4)), dim3(256), 0, h.stream,
+  hipLaunchKernelGGL(k_rhs, dim3(wave_grid(h.an.n)), dim3(256), 0, h.stream,
                      h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.w, y,
                      h.opts.equilibrate ? h.colscale : nullptr, b, h.an.n);
   return hipGetLastError();
@@ -510,9 +517,9 @@ __global__ __launch_bounds__(256) void k_htt_dd(const int64_t* __restrict__ colp
 hipError_t launch_residual_dd(Handle& h, const double* b, const double* x,
                               double* r) {
   const Analysis& a = h.an;
-  hipLaunchKernelGGL(k_hx_dd, dim3(grid_for(a.m, 4)), dim3(256), 0, h.stream,
+  hipLaunchKernelGGL(k_hx_dd, dim3(wave_grid(a.m)), dim3(256), 0, h.stream,
                      h.d.rowptr, h.d.col, h.val, h.w, x, h.vdd, a.m);
-  hipLaunchKernelGGL(k_htt_dd, dim3(grid_for(a.n, 4)), dim3(256), 0, h.stream,
+  hipLaunchKernelGGL(k_htt_dd, dim3(wave_grid(a.n)), dim3(256), 0, h.stream,
                      h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.vdd, b, r,
                      a.n);
   return hipGetLastError();
@@ -625,7 +632,7 @@ hipError_t launch_solve_pass(Handle& h, const double* b, double* x) {
     hipLaunchKernelGGL(k_fwd_leaf, dim3(grid_for(nl, 256)), dim3(256), 0,
                        h.stream, b, h.d.leaf_cols, h.ldiag, h.vleaf, nl);
   if (a.n_pad) {
-    hipLaunchKernelGGL(k_fwd_root_gather, dim3(grid_for(a.n_pad, 4)), dim3(256),
+    hipLaunchKernelGGL(k_fwd_root_gather, dim3(wave_grid(a.n_pad)), dim3(256),
                        0, h.stream, b, h.d.root_cols, h.d.rinc_ptr, h.d.rinc_grp,
                        h.d.rinc_u, h.d.grp_U_ptr, h.d.grp_col_ptr,
                        h.d.grp_panel_off, h.panel, h.vleaf, h.vroot, a.n_root,
@@ -640,7 +647,7 @@ hipError_t launch_solve_pass(Handle& h, const double* b, double* x) {
                        0, h.stream, h.vroot, h.d.root_cols, x, a.n_root);
   }
   if (nl)
-    hipLaunchKernelGGL(k_bwd_leaf, dim3(grid_for(nl, 4)), dim3(256), 0,
+    hipLaunchKernelGGL(k_bwd_leaf, dim3(wave_grid(nl)), dim3(256), 0,
                        h.stream, h.d.leaf_grp, h.d.grp_col_ptr, h.d.grp_U_ptr,
                        h.d.U, h.d.grp_panel_off, h.panel, h.ldiag, h.d.leaf_cols,
                        h.vleaf, h.vroot, x, nl);

@@ -279,12 +279,14 @@ hipError_t fill_i64(hipStream_t s, int64_t* p, int64_t v, int64_t n);
 hipError_t fill_f64(hipStream_t s, double* p, double v, int64_t n);
 
 // dense kernels, exposed for tests of the root-front building blocks
-enum GemmOp { kXC = 0, kKC = 1 };  // operand access, see k_dense.hip
+enum GemmOp { kXC = 0, kKC = 1 };  // operand access, see k_gemm.hip
+enum GemmKMask { kGemmKStartCol = 1, kGemmKEndRow = 2 };
 hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* C, int64_t ldc, int M, int N, int K, double alpha,
                 double beta, bool lower, bool kstart_diag,
-                bool diag_mask = false, bool f32 = false);
+                bool diag_mask = false, bool f32 = false,
+                int kmask = 0);
 
 // learned preconditioner and PCG (k_learned.hip)
 int64_t lp_param_count(int hidden);

@@ -113,7 +113,7 @@ def _bin_lengths(cfg: SkyConfig, rng: np.random.Generator) -> np.ndarray:
     return np.asarray(lens, dtype=np.int64)
 
 
-def _pattern_and_values(cfg: SkyConfig, rng: np.random.Generator):
+def _pattern_and_values(cfg: SkyConfig, rng: np.random.Generator, progress=None):
     S, F, nd, npnt = cfg.sky, cfg.fov, cfg.n_det, cfg.n_point
     lens = _bin_lengths(cfg, rng)
     n_bins = len(lens)
@@ -129,7 +129,10 @@ def _pattern_and_values(cfg: SkyConfig, rng: np.random.Generator):
     rowptr = np.zeros(npnt * nd + 1, dtype=np.int64)
     cols_chunks, vals_chunks = [], []
     pos = 0
-    for p0 in range(0, npnt, _CHUNK):
+    n_chunks = -(-npnt // _CHUNK)
+    for ci, p0 in enumerate(range(0, npnt, _CHUNK)):
+        if progress is not None and ci % max(1, n_chunks // 10) == 0:
+            progress(ci / n_chunks)
         p1 = min(npnt, p0 + _CHUNK)
         cnt = p1 - p0
         u_mask = rng.random((cnt, nd, F * F))
@@ -175,12 +178,13 @@ def _draw_counts(rowptr, col, val, x_true, rng):
     return d, w
 
 
-def make_problem(cfg: SkyConfig, seed: int = 0) -> Problem:
-    """Draw one coded-mask least-squares instance of shape ``cfg``."""
+def make_problem(cfg: SkyConfig, seed: int = 0, progress=None) -> Problem:
+    """Draw one coded-mask least-squares instance of shape ``cfg``.
+    ``progress(fraction)`` (optional) is called as the pattern is drawn."""
     s = seed
     for _ in range(8):
         rng = np.random.default_rng(s)
-        rowptr, col, val, n_bg, n_bins, lens = _pattern_and_values(cfg, rng)
+        rowptr, col, val, n_bg, n_bins, lens = _pattern_and_values(cfg, rng, progress)
         n = n_bg + cfg.sky * cfg.sky
         counts = np.bincount(col, minlength=n)
         if np.all(counts > 0):
@@ -197,9 +201,9 @@ def make_problem(cfg: SkyConfig, seed: int = 0) -> Problem:
                          "n_point": cfg.n_point, "n_det": cfg.n_det})
 
 
-def make_config(i: int, seed: int | None = None) -> Problem:
+def make_config(i: int, seed: int | None = None, progress=None) -> Problem:
     """Workload ``i`` (0 tiny, 1 medium, 2 large); default seed is ``i``."""
-    return make_problem(CONFIGS[i], i if seed is None else seed)
+    return make_problem(CONFIGS[i], i if seed is None else seed, progress)
 
 
 def band_scales_drift(b: int, n_bands: int = 256):
