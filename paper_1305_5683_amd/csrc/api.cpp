@@ -99,7 +99,7 @@ void free_all(Handle& h) {
                   d.rinc_grp, d.rinc_u, d.tasks, d.grp_task_ptr, d.task_part_off,
                   d.sel_order, d.rp_rows, d.rp_rowbase, d.rpe_ptr, d.rpe_pos,
                   d.rpe_src, d.up_U_off, d.up_Q_off, d.up_nU, d.up_k,
-                  d.up_w_off, d.tile_order, d.inc_ptr, d.inc, h.rpw,
+                  d.up_w_off, d.tile_order, d.inc_ptr, d.inc,
                   h.val, h.w, h.sw, h.sleaf, h.rrval, h.panel, h.ldiag, h.S,
                   h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
                   h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2, h.scratch,
@@ -151,7 +151,7 @@ int setup_device(spi_handle* H) {
 #define AL(ptr, cnt) \
   if (he == hipSuccess) he = dev_alloc(ptr, cnt)
   AL(h.val, a.nnz); AL(h.w, a.m); AL(h.sw, a.n_slots);
-  AL(h.sleaf, a.n_slots); AL(h.rpw, (int64_t)a.rp_rows.size());
+  AL(h.sleaf, a.n_slots);
   AL(h.rrval, (int64_t)a.rr_src.size());
   AL(h.panel, a.grp_panel_off.back() + a.rp_val_off.back());
   AL(h.ldiag, nl);

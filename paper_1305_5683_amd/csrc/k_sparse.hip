@@ -139,14 +139,16 @@ __global__ __launch_bounds__(256) void k_fill_rowpanels(
     const int32_t* __restrict__ rp_rows, const int64_t* __restrict__ rp_rowbase,
     const int64_t* __restrict__ rpe_ptr, const int32_t* __restrict__ rpe_pos,
     const int64_t* __restrict__ rpe_src, double* __restrict__ rpbuf,
-    double* __restrict__ rpw, int64_t nrows) {
+    int64_t nrows) {
   const int lane = threadIdx.x & 63;
   const int64_t pr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (pr >= nrows) return;
   double* col = rpbuf + rp_rowbase[pr];
+  // rows are stored scaled by sqrt(w_r): the panel product is then
+  // Q Q^T = sum_r w_r h_r h_r^T with no weights to load in the assembly
+  const double sw = sqrt(w[rp_rows[pr]]);
   for (int64_t e = rpe_ptr[pr] + lane; e < rpe_ptr[pr + 1]; e += 64)
-    col[rpe_pos[e]] = val[rpe_src[e]];
-  if (lane == 0) rpw[pr] = w[rp_rows[pr]];
+    col[rpe_pos[e]] = sw * val[rpe_src[e]];
 }
 
 hipError_t launch_fill_rowpanels(Handle& h) {
@@ -159,26 +161,27 @@ hipError_t launch_fill_rowpanels(Handle& h) {
                      h.stream, rpbuf, total);
   hipLaunchKernelGGL(k_fill_rowpanels, dim3(wave_grid(nrows)), dim3(256), 0,
                      h.stream, h.val, h.w, h.d.rp_rows, h.d.rp_rowbase,
-                     h.d.rpe_ptr, h.d.rpe_pos, h.d.rpe_src, rpbuf, h.rpw, nrows);
+                     h.d.rpe_ptr, h.d.rpe_pos, h.d.rpe_src, rpbuf, nrows);
   return hipGetLastError();
 }
 
 // --------------------------------------------------------- root assembly
 // One workgroup per 64 x 64 lower tile (I, J) of the root front.  The tile
 // is the sum of its incidences: update panel u (a leaf front's panel L_Ug
-// with weight -1, or a row panel with the row weights) restricted to the
-// positions of U that fall in the tile's rows (aI0 .. aI0 + nI) and columns
-// (aJ0 .. aJ0 + nJ):  C[U[a] - 64 I][U[b] - 64 J] += sum_q w_q Q[a][q] Q[b][q].
+// with sign -1, or a row panel, stored as sqrt(w_r) h_r with sign +1)
+// restricted to the positions of U that fall in the tile's rows
+// (aI0 .. aI0 + nI) and columns (aJ0 .. aJ0 + nJ):
+//   C[U[a] - 64 I][U[b] - 64 J] += sign sum_q Q[a][q] Q[b][q].
 // The tile's incidences are staged in LDS in chunks, with their panel and
 // index offsets resolved, so a wave's work on an incidence starts with no
 // dependent descriptor loads.  Each wave takes one incidence at a time and
 // computes it in 16 x 16 blocks on the FP64 matrix cores; all loads of a
-// block (indices, kAsmKC panel columns of both operands, row weights) are
+// block (indices, kAsmKC panel columns of both operands) are
 // issued together before its MFMAs.  Results are added into the LDS tile
 // (LDS atomics, since waves work on different incidences); the tile is then
 // written once.
 constexpr int kAsmChunk = 128;  // incidences staged per pass
-constexpr int kAsmKC = 32;      // panel columns per batch of loads
+constexpr int kAsmKC = 20;      // panel columns per batch of loads
 
 // A wave-uniform 64-bit value moved to scalar registers.
 __device__ inline int64_t uniform64(int64_t x) {
@@ -194,8 +197,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
     const int64_t* __restrict__ up_Q_off, const int32_t* __restrict__ up_nU,
     const int32_t* __restrict__ up_k, const int32_t* __restrict__ up_w_off,
     const int32_t* __restrict__ U, const double* __restrict__ panel,
-    const double* __restrict__ rpw, double* __restrict__ S, int64_t ld,
-    int64_t n_root) {
+    double* __restrict__ S, int64_t ld, int64_t n_root) {
   __shared__ double C[kET][kET + 1];
   __shared__ int64_t s_qa[kAsmChunk], s_qb[kAsmChunk];
   __shared__ int64_t s_ua[kAsmChunk], s_ub[kAsmChunk];
@@ -261,27 +263,25 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
             rb[v] = (sb + 4 * v + lk < nJ) ? rb[v] - (int)j0 : -1;
           v4d acc = {0.0, 0.0, 0.0, 0.0};
           for (int kc = 0; kc < k; kc += kAsmKC) {
-            double av[kAsmKC / 4], bv[kAsmKC / 4], wv[kAsmKC / 4];
+            double av[kAsmKC / 4], bv[kAsmKC / 4];
 #pragma unroll
             for (int s = 0; s < kAsmKC / 4; ++s) {
               const int qc = min(kc + 4 * s + lk, k - 1);
               av[s] = Qa[ac + qc * nU];
               bv[s] = Qb[bc + qc * nU];
-              wv[s] = woff >= 0 ? rpw[woff + qc] : -1.0;  // uniform branch
             }
 #pragma unroll
             for (int s = 0; s < kAsmKC / 4; ++s) {
               const bool vq = kc + 4 * s + lk < k;
-              av[s] = (vq && va) ? av[s] * wv[s] : 0.0;
+              av[s] = (vq && va) ? (woff < 0 ? -av[s] : av[s]) : 0.0;
               bv[s] = (vq && vb) ? bv[s] : 0.0;
             }
             // lane (lx, lk) item v of the result: row sa + lx, column
             // sb + 4 v + lk (operand order as in the root GEMM)
+            // (steps past k have zero operands: no guard, no branch)
 #pragma unroll
             for (int s = 0; s < kAsmKC / 4; ++s)
-              if (kc + 4 * s < k)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[s], av[s], acc, 0,
-                                                           0, 0);
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[s], av[s], acc, 0, 0, 0);
           }
           if (ra >= 0) {
 #pragma unroll
@@ -306,7 +306,7 @@ hipError_t launch_assemble_root(Handle& h) {
   hipLaunchKernelGGL(k_assemble_root, dim3((unsigned)a.n_tiles), dim3(kAsmThreads), 0,
                      h.stream, h.d.tile_order, h.d.inc_ptr, h.d.inc, h.d.up_U_off,
                      h.d.up_Q_off, h.d.up_nU, h.d.up_k, h.d.up_w_off, h.d.U,
-                     h.panel, h.rpw, h.S, a.n_pad, a.n_root);
+                     h.panel, h.S, a.n_pad, a.n_root);
   return hipGetLastError();
 }
 
@@ -696,34 +696,63 @@ __global__ __launch_bounds__(256) void k_selinv_leaf(
   const int32_t* Ug = U + grp_U_ptr[g];
   const int I0 = I * kET, J0 = J * kET;
   const int na = (int)min<int64_t>(kET, nU - I0), nb = (int)min<int64_t>(kET, nU - J0);
-  // gather Z_UU block (lower storage: Z[max, min])
-  for (int e = t; e < kET * kET; e += 256) {
-    const int a = e % kET, b = e / kET;
-    double v = 0.0;
-    if (a < na && b < nb) {
-      int64_t ua = Ug[I0 + a], ub = Ug[J0 + b];
-      v = ua >= ub ? Z[ua + ub * ld] : Z[ub + ua * ld];
-    }
-    Zt[a][b] = v;
+  // Root indices of the two U ranges first (one round trip), then every
+  // gather of the Z_UU block is issued at once with clamped, always valid
+  // addresses (out-of-range entries are zeroed afterwards).
+  __shared__ int32_t sU[2][kET];
+  if (t < 2 * kET) {
+    const int side = t / kET, a = t % kET;
+    const int len = side ? nb : na, base = side ? J0 : I0;
+    sU[side][a] = Ug[base + min(a, len - 1)];
+  }
+  __syncthreads();
+  constexpr int kPer = kET * kET / 256;
+  double zv[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int e = t + 256 * i, a = e % kET, b = e / kET;
+    const int64_t ua = sU[0][a], ub = sU[1][b];
+    zv[i] = ua >= ub ? Z[ua + ub * ld] : Z[ub + ua * ld];  // lower storage
+  }
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int e = t + 256 * i, a = e % kET, b = e / kET;
+    Zt[a][b] = (a < na && b < nb) ? zv[i] : 0.0;
   }
   const double* Pg = panel + grp_panel_off[g];
   const double fac = (I == J) ? 1.0 : 2.0;
   for (int q0 = 0; q0 < p; q0 += kQC) {
     const int pc = min(kQC, p - q0);
     __syncthreads();
-    for (int e = t; e < kQC * kET; e += 256) {
-      int a = e % kET, q = e / kET;
-      PI[q][a] = (q < pc && a < na) ? Pg[(int64_t)(q0 + q) * nU + I0 + a] : 0.0;
-      PJ[q][a] = (q < pc && a < nb) ? Pg[(int64_t)(q0 + q) * nU + J0 + a] : 0.0;
+    constexpr int kPP = kQC * kET / 256;
+    double pi[kPP], pj[kPP];
+#pragma unroll
+    for (int i = 0; i < kPP; ++i) {  // all panel loads in flight together
+      const int e = t + 256 * i, a = e % kET, q = e / kET;
+      const int64_t col = (int64_t)(q0 + min(q, pc - 1)) * nU;
+      pi[i] = Pg[col + I0 + min(a, na - 1)];
+      pj[i] = Pg[col + J0 + min(a, nb - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < kPP; ++i) {
+      const int e = t + 256 * i, a = e % kET, q = e / kET;
+      PI[q][a] = (q < pc && a < na) ? pi[i] : 0.0;
+      PJ[q][a] = (q < pc && a < nb) ? pj[i] : 0.0;
     }
     __syncthreads();
     // thread (b = lane, q = wave + 4k): y_b = sum_a PI[q][a] Zt[a][b]; s_q += y_b PJ[q][b]
     for (int q = wave; q < kQC; q += 4) {
       double s = 0.0;
       if (q < pc) {
-        double y = 0.0;
-        for (int a = 0; a < kET; ++a) y += PI[q][a] * Zt[a][lane];
-        s = y * PJ[q][lane];
+        double y[4] = {0.0, 0.0, 0.0, 0.0};  // four independent FMA chains
+#pragma unroll 4
+        for (int a = 0; a < kET; a += 4) {
+          y[0] += PI[q][a] * Zt[a][lane];
+          y[1] += PI[q][a + 1] * Zt[a + 1][lane];
+          y[2] += PI[q][a + 2] * Zt[a + 2][lane];
+          y[3] += PI[q][a + 3] * Zt[a + 3][lane];
+        }
+        s = ((y[0] + y[1]) + (y[2] + y[3])) * PJ[q][lane];
       }
       for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
       if (lane == 0) red[wave][q / 4] = s;

@@ -74,7 +74,7 @@ struct Analysis {
   std::vector<int64_t> up_Q_off;       // into the panel buffer (leaf | rows)
   std::vector<int32_t> up_nU;
   std::vector<int32_t> up_k;
-  std::vector<int32_t> up_w_off;       // into the row weights, -1: weight -1
+  std::vector<int32_t> up_w_off;       // -1: leaf panel (sign -1); else row panel
   // incidences of the update panels on the 64 x 64 lower tiles of the root
   int64_t n_tiles = 0;                 // T (T + 1) / 2, T = n_pad / 64
   std::vector<int32_t> tile_order;     // tiles by decreasing work
@@ -176,7 +176,6 @@ struct Handle {
   double* sw = nullptr;      // weight per slot
   double* sleaf = nullptr;   // leaf coefficient per slot
   double* rrval = nullptr;   // root entries in compact slot order
-  double* rpw = nullptr;     // row weights in row-panel order
   // factor
   double* panel = nullptr;   // leaf panels L_UG, dense column-major per front,
                              // followed by the dense row panels
