@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("medium", "batch", "learned"),
+    ap.add_argument("--workload", choices=("medium", "batch", "learned", "copy"),
                     default="medium")
     ap.add_argument("--bands", type=int, default=64,
                     help="batch: number of bands; learned: PCG sample size")
@@ -132,6 +132,8 @@ def main():
         return run_batch(args)
     if args.workload == "learned":
         return run_learned(args)
+    if args.workload == "copy":
+        return run_copy(args)
     import torch
     import spi_synth
     from paper_1305_5683_amd import SpiSolver
@@ -189,8 +191,11 @@ def measure(p, prec, args):
         s.solve(bbuf, out=xbuf)
         s.diag_inv(out=dbuf)
 
-    print(f"# {prec}: analysis {t_an:.2f}s; warmup {args.warmup}", file=sys.stderr,
-          flush=True)
+    # the library's autotuner picks the root POTRF block on this system
+    s.set_values(val, w)
+    blk = s.autotune()
+    print(f"# {prec}: analysis {t_an:.2f}s; POTRF block {blk}; warmup {args.warmup}",
+          file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -243,6 +248,7 @@ def measure(p, prec, args):
         "analysis_s": t_an,
         "phases_ms": {k[2:-3]: round(v, 4) for k, v in ph.items()},
         "refine_steps": refine,
+        "potrf_block": blk,
         "roofline": {"bound": "mfma", "kernel": "k_gemm<128,128,KC,KC> (root W^T W)",
                      "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                      "frac": ach / peak, "traffic": None},
@@ -358,6 +364,22 @@ def run_batch(args):
     bb.close()
     sb.close()
     print(json.dumps(out))
+
+
+def run_copy(args):
+    """A plain streaming kernel of known size (y = 1.0 * x over 2^27 doubles,
+    1 GiB read and 1 GiB written per launch): the reference that scales the
+    HBM counters (FETCH_SIZE, WRITE_SIZE) of the other kernels."""
+    import torch
+    torch.cuda.set_device(0)
+    n = 1 << 27
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.steps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n,
+                      "launches": args.steps}))
 
 
 def run_learned(args):

@@ -464,18 +464,17 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
           }
       }
     }
-    // tiles with the most work first
-    std::vector<double> tw(a.n_tiles, 0.0);
-    for (int64_t t = 0; t < a.n_tiles; ++t)
-      for (int64_t q = a.inc_ptr[t]; q < a.inc_ptr[t + 1]; ++q) {
-        const int32_t* p = a.inc.data() + 4 * q;
-        const int nI = p[3] & 0xffff, nJ = p[3] >> 16;
-        tw[t] += (double)((nI + 15) / 16) * ((nJ + 15) / 16) * (a.up_k[p[0]] + 3) / 4 + 1.0;
-      }
-    a.tile_order.resize(a.n_tiles);
-    std::iota(a.tile_order.begin(), a.tile_order.end(), 0);
-    std::stable_sort(a.tile_order.begin(), a.tile_order.end(),
-                     [&](int32_t x, int32_t y) { return tw[x] > tw[y]; });
+    // launch order: groups of 8 tile rows, column by column inside a group
+    // (with the XCD remap, 64 consecutive tiles = an 8 x 8 block, run
+    // together on one XCD, whose incidences share panel rows in its L2)
+    a.tile_order.clear();
+    a.tile_order.reserve(a.n_tiles);
+    for (int64_t g0 = 0; g0 < T; g0 += 8) {
+      const int64_t g1 = std::min<int64_t>(T, g0 + 8);
+      for (int64_t J = 0; J < g1; ++J)
+        for (int64_t I = std::max(g0, J); I < g1; ++I)
+          a.tile_order.push_back((int32_t)(I * (I + 1) / 2 + J));
+    }
   }
 
   phase("incidences");

@@ -71,8 +71,10 @@ struct GemmArgs {
 };
 
 // Logical tile t -> (I, J).  Tiles are visited in groups of kGroup tile
-// rows, column by column inside a group, so that the tiles running together
-// share kGroup row panels of A and one column panel of B.
+// rows, column by column inside a group; with xcd_remap<8> each XCD takes 8
+// consecutive logical tiles of every 64 (one column of the group, sharing
+// its panel of B), and every XCD gets an equal share of each part of the
+// launch (tiles whose K range depends on the tile index stay balanced).
 __device__ inline void tile_of(const GemmArgs& g, int t, int& I, int& J) {
   const int G = kGroup;
   if (!g.lower) {
@@ -110,18 +112,6 @@ __device__ inline void tile_of(const GemmArgs& g, int t, int& I, int& J) {
   I = J + local;
 }
 
-// Map the hardware workgroup index to a logical tile.  Workgroups are
-// dispatched round-robin over the 8 XCDs (w % 8).  Within every block of 64
-// logical tiles, XCD x takes the chunk of 8 consecutive tiles [8x, 8x + 8):
-// a chunk shares its operand panels in that XCD's L2, and every XCD gets an
-// equal share of every part of the launch (tiles whose K range shrinks with
-// the tile index stay balanced).  The last partial block maps to itself.
-__device__ inline int xcd_remap(int w, int n) {
-  if (w >= (n & ~63)) return w;
-  const int r = w & 63;
-  return (w & ~63) + 8 * (r & 7) + (r >> 3);
-}
-
 template <int BM, int BN, int OPA, int OPB, typename T>
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -133,7 +123,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   __shared__ T Bs[B_SZ];
 
   int I, J;
-  tile_of(g, xcd_remap(blockIdx.x, g.n_tiles), I, J);
+  tile_of(g, xcd_remap<8>(blockIdx.x, g.n_tiles), I, J);
   const int i0 = I * BM, j0 = J * BN;
   if (g.diag_mask && i0 + BM - 1 < j0) return;  // tile above the diagonal
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

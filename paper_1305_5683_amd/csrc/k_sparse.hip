@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
   __shared__ int64_t s_ua[kAsmChunk], s_ub[kAsmChunk];
   __shared__ int32_t s_nU[kAsmChunk], s_k[kAsmChunk], s_w[kAsmChunk],
       s_n[kAsmChunk];
-  const int t = tile_order[blockIdx.x];
+  const int t = tile_order[xcd_remap<64>(blockIdx.x, gridDim.x)];
   int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
   while (I * (I + 1) / 2 > t) --I;
@@ -688,7 +688,7 @@ __global__ __launch_bounds__(256) void k_selinv_leaf(
   __shared__ double PJ[kQC][kET];
   __shared__ double red[4][kQC / 4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int tk = order[blockIdx.x];
+  const int tk = order[xcd_remap<64>(blockIdx.x, gridDim.x)];
   const int g = tasks[3 * tk], I = tasks[3 * tk + 1], J = tasks[3 * tk + 2];
   const int p = (int)(grp_col_ptr[g + 1] - grp_col_ptr[g]);
   if (p == 0) return;

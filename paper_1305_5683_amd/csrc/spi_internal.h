@@ -186,7 +186,8 @@ struct Handle {
   double* invd2 = nullptr;   // inverses of the 256 x 256 diagonal blocks
   double* scratch = nullptr; // n_pad x 256 staging for in-place products
   hipStream_t side = nullptr;       // lookahead stream of the root POTRF
-  hipEvent_t ev_next = nullptr, ev_panel = nullptr;
+  hipStream_t bulk = nullptr;       // its trailing updates (CU-masked)
+  hipEvent_t ev_next = nullptr, ev_panel = nullptr, ev_bulk = nullptr;
   double* Z = nullptr;       // A^-1 restricted to the root (lower triangle)
   double* part = nullptr;    // selected-inversion partial sums
   int64_t* flag = nullptr;   // first failing pivot in elimination order
@@ -251,6 +252,21 @@ int factor_finish(Handle& h, uint64_t flag);
 int solve_enqueue(Handle& h, const double* b, double* x, int steps);
 int diag_enqueue(Handle& h, double* d);
 hipError_t ensure_side_stream(Handle& h);
+
+// Workgroup index -> logical work item, XCD-aware.  Workgroups are
+// dispatched round-robin over the 8 XCDs (w % 8).  xcd_remap<B>: logical
+// items come in chunks of 8 B; chunk item block x (B consecutive items) goes
+// to XCD x, so the items running together on an XCD are consecutive ones,
+// which share data in that XCD's L2.  The last partial chunk maps to itself.
+//   B = 8:  the dense GEMM (8 tiles of one column of a group of 8 rows);
+//   B = 64: the root assembly and selected inversion (an 8 x 8 tile block).
+template <int B>
+__device__ inline int xcd_remap(int w, int n) {
+  constexpr int C = 8 * B;
+  if (w >= (n / C) * C) return w;
+  const int x = w & 7, j = w >> 3;
+  return (j / B) * C + x * B + (j % B);
+}
 
 // kernel launchers (stream-ordered); return hipError_t of the launch
 hipError_t launch_gather_values(Handle& h);
