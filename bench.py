@@ -36,6 +36,11 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# HBM bytes moved by one launch of the reported kernel (the root W^T W GEMM)
+# on the medium workload: rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by
+# what the same counter reads for a copy kernel of known size (fetch x2.0,
+# write x1.0).  Taken on the current GEMM kernel; None for other workloads.
+LAUUM_HBM_BYTES_MEDIUM = 19.306e9 + 0.409e9
 
 
 def parse():
@@ -251,7 +256,8 @@ def measure(p, prec, args):
         "potrf_block": blk,
         "roofline": {"bound": "mfma", "kernel": "k_gemm<128,128,KC,KC> (root W^T W)",
                      "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                     "frac": ach / peak, "traffic": None},
+                     "frac": ach / peak,
+                     "traffic": LAUUM_HBM_BYTES_MEDIUM if args.config == 1 else None},
     }
     s.close()
     return out, xbuf, dbuf
