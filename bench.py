@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--bands", type=int, default=64,
                     help="batch: number of bands; learned: PCG sample size")
     ap.add_argument("--subproblems", type=int, default=32)
+    ap.add_argument("--potrf-block", type=int, default=0, choices=(0, 128, 256, 512),
+                    help="root POTRF outer block; 0 = the library's autotuner")
     ap.add_argument("--precision", choices=("fp64", "mixed", "both"), default="fp64",
                     help="fp64: every stage in binary64; mixed: binary32 "
                          "matrix-core products on the root front, binary64 "
@@ -197,8 +199,13 @@ def measure(p, prec, args):
         s.diag_inv(out=dbuf)
 
     # the library's autotuner picks the root POTRF block on this system
+    # (unless one is given, as in profiling runs)
     s.set_values(val, w)
-    blk = s.autotune()
+    if args.potrf_block:
+        s.potrf_block = args.potrf_block
+        blk = args.potrf_block
+    else:
+        blk = s.autotune()
     print(f"# {prec}: analysis {t_an:.2f}s; POTRF block {blk}; warmup {args.warmup}",
           file=sys.stderr, flush=True)
     for _ in range(args.warmup):

@@ -104,7 +104,7 @@ void free_all(Handle& h) {
                   d.up_w_off, d.tile_order, d.inc_ptr, d.inc,
                   h.val, h.w, h.sw, h.sleaf, h.rrval, h.panel, h.ldiag, h.S,
                   h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
-                  h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2, h.scratch,
+                  h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2,
                   h.colscale, h.vbh, h.vxh, h.diagA, d.root_of_col};
   free_lp_work(h);
   for (void* p : ptrs)
@@ -162,7 +162,7 @@ int setup_device(spi_handle* H) {
   AL(h.flag, 1); AL(h.vleaf, nl); AL(h.vroot, np); AL(h.vres, a.n);
   AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 2);
   AL(h.vroot2, np); AL(h.vpart, root_inv_part_size(np));
-  AL(h.invd2, ((np + 255) / 256) * 256 * 256); AL(h.scratch, np * 256);
+  AL(h.invd2, ((np + 255) / 256) * 256 * 256);
   AL(h.colscale, a.n); AL(h.vbh, a.n); AL(h.vxh, a.n); AL(h.diagA, a.n);
 #undef AL
   if (he == hipSuccess) he = hipStreamSynchronize(h.stream);

@@ -446,11 +446,15 @@ static hipError_t copy2d(hipStream_t s, const double* src, int64_t lds,
 //   S_>k,<k -= T * S_k,<k
 //   S_k,<k   = -X_kk * S_k,<k         (final row block k of L^-1)
 //   S_kk     = X_kk
-// The two in-place products read their input from a scratch copy.  Each
+// The two in-place products read their input from a staged copy in rows
+// [off, off + size) of Z (which holds nothing until the root block of A^-1
+// is formed), so inversions of disjoint blocks may run concurrently.  Each
 // product sums kNBO terms (binary32 in mixed precision, then binary64).
-static hipError_t trtri_sweep(Handle& h, int off, int size, bool f32) {
+static hipError_t trtri_sweep(Handle& h, hipStream_t st, int off, int size,
+                              bool f32) {
   const int64_t ld = h.an.n_pad;
   double* Wb = h.W + off + (int64_t)off * ld;
+  double* scr = h.Z + off;  // staging, leading dimension ld
   hipError_t e;
   for (int K0 = 0; K0 < size; K0 += kNBO) {
     const int KB = std::min(kNBO, size - K0), K1 = K0 + KB;
@@ -461,68 +465,74 @@ static hipError_t trtri_sweep(Handle& h, int off, int size, bool f32) {
     double* W20 = Wb + (int64_t)K1;
     const int bk = (KB % 128 == 0) ? 128 : 64;
     if (rest > 0) {
-      if ((e = copy2d(h.stream, W21, ld, h.scratch, ld, rest, KB)) != hipSuccess)
-        return e;
-      e = gemm(h.stream, pick_bm(rest), bk, kXC, kKC, h.scratch, ld, X11, kNBO,
-               W21, ld, rest, KB, KB, 1.0, 0.0, false, false, false, f32);
+      if ((e = copy2d(st, W21, ld, scr, ld, rest, KB)) != hipSuccess) return e;
+      e = gemm(st, pick_bm(rest), bk, kXC, kKC, scr, ld, X11, kNBO, W21, ld, rest,
+               KB, KB, 1.0, 0.0, false, false, false, f32);
       if (e != hipSuccess) return e;
       if (K0 > 0) {
-        e = gemm(h.stream, pick_bm(rest), 128, kXC, kKC, W21, ld, W10, ld, W20,
-                 ld, rest, K0, KB, -1.0, 1.0, false, false, false, f32);
+        e = gemm(st, pick_bm(rest), 128, kXC, kKC, W21, ld, W10, ld, W20, ld, rest,
+                 K0, KB, -1.0, 1.0, false, false, false, f32);
         if (e != hipSuccess) return e;
       }
     }
     if (K0 > 0) {
-      if ((e = copy2d(h.stream, W10, ld, h.scratch, kNBO, KB, K0)) != hipSuccess)
-        return e;
-      e = gemm(h.stream, bk, 128, kXC, kKC, X11, kNBO, h.scratch, kNBO, W10, ld,
-               KB, K0, KB, -1.0, 0.0, false, false, false, f32);
+      if ((e = copy2d(st, W10, ld, scr, ld, KB, K0)) != hipSuccess) return e;
+      e = gemm(st, bk, 128, kXC, kKC, X11, kNBO, scr, ld, W10, ld, KB, K0, KB, -1.0,
+               0.0, false, false, false, f32);
       if (e != hipSuccess) return e;
     }
-    if ((e = copy2d(h.stream, X11, kNBO, Wb + (int64_t)K0 * (ld + 1), ld, KB,
-                    KB)) != hipSuccess)
+    if ((e = copy2d(st, X11, kNBO, Wb + (int64_t)K0 * (ld + 1), ld, KB, KB)) !=
+        hipSuccess)
       return e;
   }
   return hipSuccess;
 }
 
 // Below this order a diagonal block is inverted by the sweep: its GEMMs
-// span all rows below the step and keep the GPU full, where further halving
+// span all rows below the step and keep the GPU busy, where further halving
 // would launch products of a few tiles each.
 constexpr int kTrtriRecMin = 4096;
 
-// FP64: the top of the inversion by halving.  Split at hh (a multiple of
-// kNBO), invert both diagonal halves, then
+// Inversion by halving (FP64): split at hh (a multiple of kNBO), invert both
+// diagonal halves, then
 //   W21 = -X22 (L21 X11)
 // as two GEMMs with a triangular operand each (the K range of a tile is
 // trimmed to where that operand is non-zero).  These GEMMs have K up to
 // size / 2 and carry most of the flops; the sweep's products have K = kNBO.
-// T = L21 X11 is staged in Z, which holds nothing until the root block of
-// A^-1 is formed.
-static hipError_t trtri_rec(Handle& h, int off, int size) {
-  if (size <= kTrtriRecMin) return trtri_sweep(h, off, size, false);
-  const int64_t ld = h.an.n_pad;
-  hipError_t e;
+// T = L21 X11 is staged in rows [off + hh, off + size) of Z.
+static hipError_t trtri_join(Handle& h, hipStream_t st, int off, int size, int hh);
+
+static hipError_t trtri_rec(Handle& h, hipStream_t st, int off, int size) {
+  if (size <= kTrtriRecMin) return trtri_sweep(h, st, off, size, false);
   const int hh = ((size / 2 + kNBO - 1) / kNBO) * kNBO;
+  hipError_t e;
+  if ((e = trtri_rec(h, st, off, hh)) != hipSuccess) return e;
+  if ((e = trtri_rec(h, st, off + hh, size - hh)) != hipSuccess) return e;
+  return trtri_join(h, st, off, size, hh);
+}
+
+// The products that join two inverted halves (see trtri_rec).
+static hipError_t trtri_join(Handle& h, hipStream_t st, int off, int size, int hh) {
+  const int64_t ld = h.an.n_pad;
   const int r = size - hh;
-  if ((e = trtri_rec(h, off, hh)) != hipSuccess) return e;
-  if ((e = trtri_rec(h, off + hh, r)) != hipSuccess) return e;
   const double* L21 = h.S + (off + hh) + (int64_t)off * ld;
   const double* X11 = h.W + off + (int64_t)off * ld;
   const double* X22 = h.W + (off + hh) + (int64_t)(off + hh) * ld;
   double* W21 = h.W + (off + hh) + (int64_t)off * ld;
-  double* T = h.Z;
-  e = gemm(h.stream, pick_bm(r), 128, kXC, kKC, L21, ld, X11, ld, T, ld, r, hh, hh,
-           1.0, 0.0, false, false, false, false, kGemmKStartCol);
+  double* T = h.Z + (off + hh);
+  hipError_t e = gemm(st, pick_bm(r), 128, kXC, kKC, L21, ld, X11, ld, T, ld, r, hh,
+                      hh, 1.0, 0.0, false, false, false, false, kGemmKStartCol);
   if (e != hipSuccess) return e;
-  return gemm(h.stream, pick_bm(r), 128, kXC, kKC, X22, ld, T, ld, W21, ld, r, hh,
-              r, -1.0, 0.0, false, false, false, false, kGemmKEndRow);
+  return gemm(st, pick_bm(r), 128, kXC, kKC, X22, ld, T, ld, W21, ld, r, hh, r, -1.0,
+              0.0, false, false, false, false, kGemmKEndRow);
 }
 
 // Inverse of the root factor, W = L^-1.  W starts as a copy of L's lower
 // triangle with zeros above (the zeros matter: later products read whole
-// diagonal tiles).  Mixed precision uses the sweep alone, whose products
-// sum at most kNBO terms in binary32 before the binary64 accumulation.
+// diagonal tiles).  FP64: the two halves of the top split are inverted
+// concurrently (main and side streams), then joined.  Mixed precision uses
+// the sweep alone, whose products sum at most kNBO terms in binary32 before
+// the binary64 accumulation.
 hipError_t root_trtri(Handle& h) {
   const bool f32 = h.opts.precision == SPI_MIXED;
   const int np = (int)h.an.n_pad;
@@ -530,7 +540,17 @@ hipError_t root_trtri(Handle& h) {
                      h.stream, h.S, h.W, (int64_t)np);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return f32 ? trtri_sweep(h, 0, np, true) : trtri_rec(h, 0, np);
+  if (f32) return trtri_sweep(h, h.stream, 0, np, true);
+  if (np <= kTrtriRecMin) return trtri_sweep(h, h.stream, 0, np, false);
+  if ((e = ensure_side_stream(h)) != hipSuccess) return e;
+  const int hh = ((np / 2 + kNBO - 1) / kNBO) * kNBO;
+  if ((e = hipEventRecord(h.ev_next, h.stream)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(h.side, h.ev_next, 0)) != hipSuccess) return e;
+  if ((e = trtri_rec(h, h.side, hh, np - hh)) != hipSuccess) return e;
+  if ((e = hipEventRecord(h.ev_panel, h.side)) != hipSuccess) return e;
+  if ((e = trtri_rec(h, h.stream, 0, hh)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(h.stream, h.ev_panel, 0)) != hipSuccess) return e;
+  return trtri_join(h, h.stream, 0, np, hh);
 }
 
 // Z = W^T W (lower tiles); tile (I, J) sums over K >= I since W is lower

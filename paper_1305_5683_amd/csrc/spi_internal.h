@@ -184,7 +184,6 @@ struct Handle {
   double* invd = nullptr;    // inverses of the kNB diagonal blocks of L_RR
   double* W = nullptr;       // L_RR^-1 (selected inversion scratch)
   double* invd2 = nullptr;   // inverses of the 256 x 256 diagonal blocks
-  double* scratch = nullptr; // n_pad x 256 staging for in-place products
   hipStream_t side = nullptr;       // lookahead stream of the root POTRF
   hipStream_t bulk = nullptr;       // its trailing updates (CU-masked)
   hipEvent_t ev_next = nullptr, ev_panel = nullptr, ev_bulk = nullptr;

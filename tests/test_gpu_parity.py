@@ -296,3 +296,55 @@ def test_mixed_medium_config_parity():
     _say(f"case mixed medium config m={p.m} n={p.n}")
     g = run_gpu(p, precision=1)
     _check(p, g, o, idx=idx, tol_x=TOL_X_MIXED, tol_d=TOL_D_MIXED)
+
+
+# ------------------------------------------------------------- edge cases
+def _problem_from_rows(rows, n, seed=0, name="edge"):
+    """CSR problem from a list of (cols, vals) rows; y drawn around H x."""
+    rng = np.random.default_rng(seed)
+    rowptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum([len(c) for c, _ in rows])
+    col = np.concatenate([np.asarray(c, np.int32) for c, _ in rows]) if rows else \
+        np.zeros(0, np.int32)
+    val = np.concatenate([np.asarray(v, np.float64) for _, v in rows]) if rows else \
+        np.zeros(0)
+    m = len(rows)
+    w = 0.5 + rng.random(m)
+    y = rng.random(m) * 10 + 1
+    return synth.Problem(m=m, n=n, n_bg=0, rowptr=rowptr, col=col, val=val, w=w,
+                         y=y, x_true=np.ones(n), name=name)
+
+
+def test_single_unknown():
+    p = _problem_from_rows([([0], [2.0]), ([0], [0.5]), ([0], [1.5])], 1)
+    _say("case edge n=1")
+    g = run_gpu(p)
+    a = np.sum(p.w * p.val ** 2)
+    assert abs(g["x"][0] - np.sum(p.w * p.val * p.y) / a) <= 1e-14 * abs(g["x"][0])
+    assert abs(g["d"][0] - 1.0 / a) <= 1e-14 / a
+
+
+def test_empty_rows_and_single_root_unknown():
+    """Rows with no entries contribute nothing; a root of order 1 is padded
+    to a full tile."""
+    rows = [([], []), ([0, 3], [1.0, 0.3]), ([1, 3], [0.7, 0.2]), ([], []),
+            ([2, 3], [0.4, 0.9]), ([3], [0.6]), ([0], [0.2]), ([1], [0.8]),
+            ([2], [0.5]), ([], [])]
+    p = _problem_from_rows(rows, 4)
+    _say("case edge empty rows, root order 1")
+    g = run_gpu(p)
+    o = oracle_solve(p)
+    _check(p, g, o)
+    assert g["info"]["n_root"] >= 1
+
+
+def test_ragged_root_sizes_across_tile_edges():
+    """Dense roots (no leaves) of order 127, 128, 129 and 257: identity
+    padding and ragged last tiles of the 64/128/256 blocks."""
+    for nr in (127, 128, 129, 257):
+        p = synth.make_random(3 * nr, nr, 12, seed=nr)
+        _say(f"case edge dense root {nr}")
+        g = run_gpu(p, leaf_max_work=0.0)
+        assert g["info"]["n_root"] == nr
+        o = oracle_solve(p)
+        _check(p, g, o)
