@@ -319,15 +319,17 @@ static hipError_t factor_panel(Handle& h, hipStream_t s, int K0, int KB) {
     // panel solve P := P L_kk^-T as a product with the inverse (each tile
     // owns whole rows of the 64-wide panel, so it is safe in place)
     double* Pp = h.S + (int64_t)(k0 + kNB) + (int64_t)k0 * ld;
-    e = gemm(s, pick_bm(rest), 64, kXC, kXC, Pp, ld, inv, kNB, Pp, ld, rest,
-             kNB, kNB, 1.0, 0.0, false, false, false, f32);
+    // (64-row tiles: these products are on the critical path and short,
+    // so more, smaller workgroups finish sooner)
+    e = gemm(s, 64, 64, kXC, kXC, Pp, ld, inv, kNB, Pp, ld, rest, kNB, kNB, 1.0,
+             0.0, false, false, false, f32);
     if (e != hipSuccess) return e;
     const int ncols = K0 + KB - k0 - kNB;  // panel columns still to update
     if (ncols > 0) {
       double* P = h.S + (int64_t)(k0 + kNB) + (int64_t)k0 * ld;
       double* C = h.S + (int64_t)(k0 + kNB) * (ld + 1);
-      e = gemm(s, pick_bm(rest), 64, kXC, kXC, P, ld, P, ld, C, ld, rest, ncols,
-               kNB, -1.0, 1.0, false, false, true, f32);
+      e = gemm(s, 64, 64, kXC, kXC, P, ld, P, ld, C, ld, rest, ncols, kNB, -1.0,
+               1.0, false, false, true, f32);
       if (e != hipSuccess) return e;
     }
   }
