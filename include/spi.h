@@ -381,7 +381,8 @@ void spi_batch_destroy(spi_batch* b);
 int spi_autotune(spi_handle* h, int32_t* chosen);
 /* Current outer block of the root POTRF, or -1 for a NULL handle. */
 int spi_get_potrf_block(const spi_handle* h);
-/* Set the outer block by hand: 128, 256 or 512. */
+/* Set the outer block by hand: 128, 256 or 512 (SPI_MIXED uses at most 256,
+ * the longest binary32 accumulation it allows). */
 int spi_set_potrf_block(spi_handle* h, int32_t block);
 
 #ifdef __cplusplus

@@ -105,7 +105,7 @@ void free_all(Handle& h) {
                   h.val, h.w, h.sw, h.sleaf, h.rrval, h.panel, h.ldiag, h.S,
                   h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
                   h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2,
-                  h.colscale, h.vbh, h.vxh, h.diagA, d.root_of_col};
+                  h.colscale, h.vbh, h.vxh, h.diagA, d.root_of_col, h.vfront};
   free_lp_work(h);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -159,7 +159,7 @@ int setup_device(spi_handle* H) {
   AL(h.ldiag, nl);
   AL(h.S, np * np); AL(h.W, np * np); AL(h.Z, np * np);
   AL(h.invd, np * kNB); AL(h.part, a.task_part_off.back());
-  AL(h.flag, 1); AL(h.vleaf, nl); AL(h.vroot, np); AL(h.vres, a.n);
+  AL(h.flag, 1); AL(h.vleaf, nl); AL(h.vfront, a.grp_U_ptr.back()); AL(h.vroot, np); AL(h.vres, a.n);
   AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 2);
   AL(h.vroot2, np); AL(h.vpart, root_inv_part_size(np));
   AL(h.invd2, ((np + 255) / 256) * 256 * 256);

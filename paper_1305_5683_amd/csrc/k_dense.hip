@@ -380,7 +380,9 @@ hipError_t root_potrf(Handle& h) {
   const int64_t ld = np;
   hipError_t e;
   if ((e = ensure_side_stream(h)) != hipSuccess) return e;
-  const int NBO = h.potrf_block;  // outer block: 128, 256 or 512
+  // outer block: 128, 256 or 512; binary32 accumulation (mixed precision)
+  // runs over at most kNBO terms, so its trailing updates use K <= kNBO
+  const int NBO = f32 ? std::min(h.potrf_block, kNBO) : h.potrf_block;
   if ((e = factor_panel(h, h.stream, 0, std::min(NBO, np))) != hipSuccess)
     return e;
   for (int K0 = 0; K0 < np; K0 += NBO) {

@@ -565,15 +565,37 @@ __global__ void k_fwd_leaf(const double* __restrict__ b,
     vleaf[l] = b[leaf_cols[l]] / ldiag[l];
 }
 
-// z_i = b[root_col_i] - sum over the leaf panels that contain i of
-// (L_Ug y_g)_i : one wave per root unknown, over its incidences.
+// Forward substitution's update of the root, z_R = b_R - sum_g L_Ug y_g, in
+// two deterministic passes.  (1) One wave per leaf front: t_g = L_Ug y_g,
+// reading the column-major panel along U (coalesced).  (2) One wave per root
+// unknown i: z_i = b_i - sum of t_g[u] over the (front, position) pairs
+// that contain i, in a fixed order.
+__global__ __launch_bounds__(256) void k_fwd_front(
+    const int64_t* __restrict__ grp_U_ptr, const int64_t* __restrict__ grp_col_ptr,
+    const int64_t* __restrict__ grp_panel_off, const double* __restrict__ panel,
+    const double* __restrict__ vleaf, double* __restrict__ t, int64_t n_groups) {
+  const int64_t g = blockIdx.x;  // one workgroup per front
+  const int64_t u0 = grp_U_ptr[g], nU = grp_U_ptr[g + 1] - u0;
+  const int64_t c0 = grp_col_ptr[g];
+  const int p = (int)(grp_col_ptr[g + 1] - c0);
+  const double* P = panel + grp_panel_off[g];
+  for (int64_t u = threadIdx.x; u < nU; u += 256) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};  // independent chains, loads in flight
+    int q = 0;
+    for (; q + 4 <= p; q += 4)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s[e] += P[u + (q + e) * nU] * vleaf[c0 + q + e];
+    for (; q < p; ++q) s[0] += P[u + q * nU] * vleaf[c0 + q];
+    t[u0 + u] = (s[0] + s[1]) + (s[2] + s[3]);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_fwd_root_gather(
     const double* __restrict__ b, const int32_t* __restrict__ root_cols,
     const int64_t* __restrict__ rinc_ptr, const int32_t* __restrict__ rinc_grp,
     const int32_t* __restrict__ rinc_u, const int64_t* __restrict__ grp_U_ptr,
-    const int64_t* __restrict__ grp_col_ptr, const int64_t* __restrict__ grp_panel_off,
-    const double* __restrict__ panel, const double* __restrict__ vleaf,
-    double* __restrict__ z, int64_t n_root, int64_t n_pad) {
+    const double* __restrict__ t, double* __restrict__ z, int64_t n_root,
+    int64_t n_pad) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n_pad) return;
@@ -582,14 +604,8 @@ __global__ __launch_bounds__(256) void k_fwd_root_gather(
     return;
   }
   double s = 0.0;
-  for (int64_t k = rinc_ptr[i] + lane; k < rinc_ptr[i + 1]; k += 64) {
-    const int g = rinc_grp[k];
-    const int64_t u = rinc_u[k];
-    const int64_t nU = grp_U_ptr[g + 1] - grp_U_ptr[g];
-    const int64_t c0 = grp_col_ptr[g], p = grp_col_ptr[g + 1] - c0;
-    const double* P = panel + grp_panel_off[g] + u;
-    for (int64_t q = 0; q < p; ++q) s += P[q * nU] * vleaf[c0 + q];
-  }
+  for (int64_t k = rinc_ptr[i] + lane; k < rinc_ptr[i + 1]; k += 64)
+    s += t[grp_U_ptr[rinc_grp[k]] + rinc_u[k]];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) z[i] = b[root_cols[i]] - s;
 }
@@ -632,10 +648,13 @@ hipError_t launch_solve_pass(Handle& h, const double* b, double* x) {
     hipLaunchKernelGGL(k_fwd_leaf, dim3(grid_for(nl, 256)), dim3(256), 0,
                        h.stream, b, h.d.leaf_cols, h.ldiag, h.vleaf, nl);
   if (a.n_pad) {
+    if (a.n_groups)
+      hipLaunchKernelGGL(k_fwd_front, dim3((unsigned)a.n_groups), dim3(256), 0,
+                         h.stream, h.d.grp_U_ptr, h.d.grp_col_ptr, h.d.grp_panel_off,
+                         h.panel, h.vleaf, h.vfront, a.n_groups);
     hipLaunchKernelGGL(k_fwd_root_gather, dim3(wave_grid(a.n_pad)), dim3(256),
                        0, h.stream, b, h.d.root_cols, h.d.rinc_ptr, h.d.rinc_grp,
-                       h.d.rinc_u, h.d.grp_U_ptr, h.d.grp_col_ptr,
-                       h.d.grp_panel_off, h.panel, h.vleaf, h.vroot, a.n_root,
+                       h.d.rinc_u, h.d.grp_U_ptr, h.vfront, h.vroot, a.n_root,
                        a.n_pad);
     if (h.have_inv) {
       if ((e = root_inv_apply(h, h.vroot, h.vroot2)) != hipSuccess) return e;

@@ -192,6 +192,7 @@ struct Handle {
   int64_t* flag = nullptr;   // first failing pivot in elimination order
   // solve scratch
   double* vleaf = nullptr;   // n_leaf
+  double* vfront = nullptr;  // sum of |U| over leaf fronts: L_Ug y_g
   double* vroot = nullptr;   // n_pad
   double* vres = nullptr;    // n (residual / correction)
   double* vx = nullptr;      // n (iterate)
