@@ -703,9 +703,9 @@ __global__ __launch_bounds__(256) void k_selinv_leaf(
     const double* __restrict__ Z, int64_t ld,
     const int64_t* __restrict__ task_part_off, double* __restrict__ part) {
   __shared__ double Zt[kET][kET + 1];
-  __shared__ double PI[kQC][kET];
-  __shared__ double PJ[kQC][kET];
-  __shared__ double red[4][kQC / 4];
+  __shared__ double PI[kQC][kET + 1];  // padded rows: the MFMA operand reads
+  __shared__ double PJ[kQC][kET + 1];  // of 16 different q are conflict-free
+  __shared__ double red[4][kQC];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int tk = order[xcd_remap<64>(blockIdx.x, gridDim.x)];
   const int g = tasks[3 * tk], I = tasks[3 * tk + 1], J = tasks[3 * tk + 2];
@@ -759,25 +759,29 @@ __global__ __launch_bounds__(256) void k_selinv_leaf(
       PJ[q][a] = (q < pc && a < nb) ? pj[i] : 0.0;
     }
     __syncthreads();
-    // thread (b = lane, q = wave + 4k): y_b = sum_a PI[q][a] Zt[a][b]; s_q += y_b PJ[q][b]
-    for (int q = wave; q < kQC; q += 4) {
-      double s = 0.0;
-      if (q < pc) {
-        double y[4] = {0.0, 0.0, 0.0, 0.0};  // four independent FMA chains
-#pragma unroll 4
-        for (int a = 0; a < kET; a += 4) {
-          y[0] += PI[q][a] * Zt[a][lane];
-          y[1] += PI[q][a + 1] * Zt[a + 1][lane];
-          y[2] += PI[q][a + 2] * Zt[a + 2][lane];
-          y[3] += PI[q][a + 3] * Zt[a + 3][lane];
-        }
-        s = ((y[0] + y[1]) + (y[2] + y[3])) * PJ[q][lane];
+    // Y = PI Zt on the FP64 matrix cores: wave w owns columns
+    // b in [16 w, 16 w + 16) of Y (16 q x 64 b), K = 64 in 16 steps.  Result
+    // layout: Y[q][b] in lane (b - 16 w) + 16 (q % 4), item q / 4.  Then
+    // s_q += sum_b Y[q][b] PJ[q][b], reduced over the 16 lanes of each q.
+    {
+      const int lx = lane & 15, lk = lane >> 4, b0 = 16 * wave;
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < kET; ks += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(PI[lx][ks + lk],
+                                                   Zt[ks + lk][b0 + lx], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int q = 4 * v + lk;
+        double y = acc[v] * PJ[q][b0 + lx];
+        for (int off = 8; off > 0; off >>= 1) y += __shfl_xor(y, off, 64);
+        if (lx == 0) red[wave][q] = y;
       }
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-      if (lane == 0) red[wave][q / 4] = s;
     }
     __syncthreads();
-    if (t < pc) part[task_part_off[tk] + q0 + t] = fac * red[t % 4][t / 4];
+    if (t < pc)
+      part[task_part_off[tk] + q0 + t] =
+          fac * ((red[0][t] + red[1][t]) + (red[2][t] + red[3][t]));
   }
 }
 
