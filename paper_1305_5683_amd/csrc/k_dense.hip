@@ -495,7 +495,7 @@ static hipError_t trtri_sweep(Handle& h, hipStream_t st, int off, int size,
 // Below this order a diagonal block is inverted by the sweep: its GEMMs
 // span all rows below the step and keep the GPU busy, where further halving
 // would launch products of a few tiles each.
-constexpr int kTrtriRecMin = 4096;
+constexpr int kTrtriRecMin = 2048;
 
 // Inversion by halving (FP64): split at hh (a multiple of kNBO), invert both
 // diagonal halves, then
