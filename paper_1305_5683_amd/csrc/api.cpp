@@ -90,9 +90,7 @@ void free_all(Handle& h) {
   free_timers(h);
   if (h.ev_next) (void)hipEventDestroy(h.ev_next);
   if (h.ev_panel) (void)hipEventDestroy(h.ev_panel);
-  if (h.ev_bulk) (void)hipEventDestroy(h.ev_bulk);
   if (h.side) (void)hipStreamDestroy(h.side);
-  if (h.bulk) (void)hipStreamDestroy(h.bulk);
   DevAnalysis& d = h.d;
   void* ptrs[] = {d.rowptr, d.col, d.colptr, d.csc_pos, d.csc_row, d.leaf_cols,
                   d.leaf_grp, d.leaf_slot_ptr, d.grp_col_ptr, d.grp_U_ptr, d.U,

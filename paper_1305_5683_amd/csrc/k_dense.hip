@@ -9,7 +9,6 @@
 // 16x16x4 FP64 matrix cores; the kNB x kNB diagonal blocks are factored and
 // inverted by a single-workgroup kernel in LDS.
 #include <hip/hip_runtime.h>
-#include <hip/hip_ext.h>
 
 #include <vector>
 
@@ -336,33 +335,13 @@ static hipError_t factor_panel(Handle& h, hipStream_t s, int K0, int KB) {
   return hipSuccess;
 }
 
-// CUs kept free of the trailing updates, so the panel chain on the side
-// stream (a 64-column diagonal factorisation every few microseconds, on the
-// critical path) finds a CU without waiting for GEMM workgroups to drain.
-constexpr int kPanelCUs = 8;
-
 hipError_t ensure_side_stream(Handle& h) {
   hipError_t e;
   if (!h.side) {
     if ((e = hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking)) != hipSuccess)
       return e;
   }
-  if (!h.bulk) {
-    int n_cu = 0;
-    if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount,
-                                   h.device)) != hipSuccess)
-      return e;
-    std::vector<uint32_t> mask((n_cu + 31) / 32, 0u);
-    for (int c = kPanelCUs; c < n_cu; ++c) mask[c / 32] |= 1u << (c % 32);
-    if (n_cu <= 2 * kPanelCUs ||
-        hipExtStreamCreateWithCUMask(&h.bulk, (uint32_t)mask.size(), mask.data()) !=
-            hipSuccess) {
-      (void)hipGetLastError();  // masks unavailable: an ordinary stream
-      if ((e = hipStreamCreateWithFlags(&h.bulk, hipStreamNonBlocking)) != hipSuccess)
-        return e;
-    }
-  }
-  hipEvent_t* evs[] = {&h.ev_next, &h.ev_panel, &h.ev_bulk};
+  hipEvent_t* evs[] = {&h.ev_next, &h.ev_panel};
   for (hipEvent_t* ev : evs)
     if (!*ev && (e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess)
       return e;
@@ -400,18 +379,14 @@ hipError_t root_potrf(Handle& h) {
     if ((e = hipStreamWaitEvent(h.side, h.ev_next, 0)) != hipSuccess) return e;
     if ((e = factor_panel(h, h.side, K1, KB2)) != hipSuccess) return e;
     if ((e = hipEventRecord(h.ev_panel, h.side)) != hipSuccess) return e;
-    // T2: trailing square beyond the next panel, lower triangle, on the
-    // CU-masked bulk stream
+    // T2: trailing square beyond the next panel, lower triangle
     const int r2 = rest - KB2;
     if (r2 > 0) {
-      if ((e = hipStreamWaitEvent(h.bulk, h.ev_next, 0)) != hipSuccess) return e;
       const int t = (r2 % 128 == 0) ? 128 : 64;
-      e = gemm(h.bulk, t, t, kXC, kXC, P + KB2, ld, P + KB2, ld,
+      e = gemm(h.stream, t, t, kXC, kXC, P + KB2, ld, P + KB2, ld,
                h.S + (int64_t)(K1 + KB2) * (ld + 1), ld, r2, r2, KB, -1.0, 1.0,
                true, false, false, f32);
       if (e != hipSuccess) return e;
-      if ((e = hipEventRecord(h.ev_bulk, h.bulk)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(h.stream, h.ev_bulk, 0)) != hipSuccess) return e;
     }
     if ((e = hipStreamWaitEvent(h.stream, h.ev_panel, 0)) != hipSuccess) return e;
   }

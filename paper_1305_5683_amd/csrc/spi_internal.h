@@ -185,8 +185,7 @@ struct Handle {
   double* W = nullptr;       // L_RR^-1 (selected inversion scratch)
   double* invd2 = nullptr;   // inverses of the 256 x 256 diagonal blocks
   hipStream_t side = nullptr;       // lookahead stream of the root POTRF
-  hipStream_t bulk = nullptr;       // its trailing updates (CU-masked)
-  hipEvent_t ev_next = nullptr, ev_panel = nullptr, ev_bulk = nullptr;
+  hipEvent_t ev_next = nullptr, ev_panel = nullptr;
   double* Z = nullptr;       // A^-1 restricted to the root (lower triangle)
   double* part = nullptr;    // selected-inversion partial sums
   int64_t* flag = nullptr;   // first failing pivot in elimination order
