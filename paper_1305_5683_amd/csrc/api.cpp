@@ -103,7 +103,8 @@ void free_all(Handle& h) {
                   h.val, h.w, h.sw, h.sleaf, h.rrval, h.panel, h.ldiag, h.S,
                   h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
                   h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2,
-                  h.colscale, h.vbh, h.vxh, h.diagA, d.root_of_col, h.vfront};
+                  h.colscale, h.vbh, h.vxh, h.diagA, d.root_of_col, h.vfront,
+                  h.band};
   free_lp_work(h);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -156,6 +157,8 @@ int setup_device(spi_handle* H) {
   AL(h.panel, a.grp_panel_off.back() + a.rp_val_off.back());
   AL(h.ldiag, nl);
   AL(h.S, np * np); AL(h.W, np * np); AL(h.Z, np * np);
+  h.band_nb = (int)std::min<int64_t>(512, np);
+  AL(h.band, 4 * (int64_t)h.band_nb * np + 2 * (int64_t)h.band_nb * h.band_nb);
   AL(h.invd, np * kNB); AL(h.part, a.task_part_off.back());
   AL(h.flag, 1); AL(h.vleaf, nl); AL(h.vfront, a.grp_U_ptr.back()); AL(h.vroot, np); AL(h.vres, a.n);
   AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 2);
@@ -190,10 +193,13 @@ int factor_enqueue(Handle& h) {
     phase_begin(h, kPhExtend);
     SPI_CK(launch_assemble_root(h), "root assembly");
     phase_end(h, kPhExtend);
+    // FP64 with the root inverse wanted: sweeps turn S into A_RR^-1;
+    // otherwise Cholesky (and the inverse of the factor if wanted)
+    h.swept = h.opts.root_inverse && h.opts.precision == SPI_FP64;
     phase_begin(h, kPhPotrf);
-    SPI_CK(root_potrf(h), "root factorisation");
+    SPI_CK(h.swept ? root_sweep(h) : root_potrf(h), "root factorisation");
     phase_end(h, kPhPotrf);
-    if (h.opts.root_inverse) {
+    if (h.opts.root_inverse && !h.swept) {
       phase_begin(h, kPhTrtri);
       SPI_CK(root_trtri(h), "root factor inversion");
       phase_end(h, kPhTrtri);
@@ -245,7 +251,8 @@ int solve_enqueue(Handle& h, const double* bc, double* xc, int steps) {
 }
 
 int diag_enqueue(Handle& h, double* d) {
-  if (h.an.n_pad) {
+  h.Zr = h.swept ? h.S : h.Z;
+  if (h.an.n_pad && !h.swept) {
     if (!h.have_inv) {
       phase_begin(h, kPhTrtri);
       SPI_CK(root_trtri(h), "root factor inversion");

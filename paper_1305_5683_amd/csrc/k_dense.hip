@@ -543,6 +543,350 @@ hipError_t root_lauum(Handle& h) {
               np, 1.0, 0.0, true, true);
 }
 
+// ------------------------------------- root inverse by symmetric sweeps
+// The root block of A^-1 is the inverse of the dense root front, and the
+// factorisation, the inversion of the factor and the product W^T W of the
+// Takahashi route (Sect. 3.3 asks for the diagonal of A^-1) can be traded
+// for one sweep per column block: with M the root front and K a block of
+// kb columns whose pivot block D = M_KK (the Schur complement of the blocks
+// swept before, the same matrix the Cholesky factorisation pivots on):
+//   M_ij -= M_iK D^-1 M_Kj     for i, j outside K
+//   M_iK  = M_iK D^-1          for i outside K
+//   M_KK  = -D^-1
+// After every block has been swept, M = -A_RR^-1 (Schur complement form of
+// the root).  Each step's bulk is one symmetric rank-kb update of the whole
+// lower triangle, n^3 flops in total as for factor + inversion + product,
+// but in uniform launches that fill the GPU instead of shrinking trailing
+// matrices.  The pivot blocks are the ones Cholesky sees, so a pivot that is
+// not positive is reported at the same elimination index.
+//
+// A step gathers the band of K (all np rows of columns K, the rows above K
+// taken from row block K of the lower storage) into a column-major buffer V
+// and its pivot block D into a kb x kb buffer, sweeps D alone in kNB steps
+// (one launch each, ping-pong between two buffers) to get -D^-1, forms
+// B = V D^-1 outside K in one product, and writes B (and -D^-1 on K) back.
+// The bulk is then M_ij -= B_i V_j^T over rows and columns outside K.  With
+// a one-band lookahead the next band is updated and gathered first, and its
+// pivot block (a chain of small launches) is swept on the side stream while
+// the main stream applies the bulk to everything else; the last bulk and the
+// last band are written negated, so S ends holding +A_RR^-1.
+
+// Band [k0, k0 + kb) of the symmetric matrix in lower storage S (leading
+// dimension ld) <-> column-major np x kb buffers; 64 x 64 tiles through LDS.
+// to_band: V receives the full symmetric columns and D (leading dimension
+// kb) its rows in K; otherwise the lower-storage positions of S receive
+// sgn times B, or D on the rows in K.
+__global__ __launch_bounds__(256) void k_band_move(double* __restrict__ S, int64_t ld,
+                                                   const double* __restrict__ B,
+                                                   double* __restrict__ V,
+                                                   double* __restrict__ D,
+                                                   int64_t np, int k0, int kb,
+                                                   int to_band, double sgn) {
+  __shared__ double T[64][65];
+  const int i0 = blockIdx.x * 64, c0 = blockIdx.y * 64, g0 = k0 + c0;
+  const int t = threadIdx.x, a = t & 63, q = t >> 6;
+  // kind: 1 direct (all rows below the columns), -1 transposed (all rows
+  // above), 0 diagonal tile (rows of the tile are the tile's columns)
+  const int kind = (i0 > g0) ? 1 : (i0 < g0 ? -1 : 0);
+  const bool inK = i0 >= k0 && i0 < k0 + kb;
+  if (to_band) {
+    for (int b = q; b < 64; b += 4) {
+      // T[a][b]: element (i0 + a, g0 + b) of the symmetric matrix
+      if (kind >= 0)
+        T[a][b] = S[(int64_t)(i0 + a) + (int64_t)(g0 + b) * ld];
+      else  // S row g0 + a, column i0 + b holds element (i0 + b, g0 + a)
+        T[b][a] = S[(int64_t)(g0 + a) + (int64_t)(i0 + b) * ld];
+    }
+    __syncthreads();
+    for (int b = q; b < 64; b += 4) {
+      const double v = (kind == 0 && a < b) ? T[b][a] : T[a][b];
+      V[i0 + a + (int64_t)(c0 + b) * np] = v;
+      if (inK) D[(i0 - k0 + a) + (int64_t)(c0 + b) * kb] = v;
+    }
+  } else {
+    for (int b = q; b < 64; b += 4)
+      T[a][b] = sgn * (inK ? D[(i0 - k0 + a) + (int64_t)(c0 + b) * kb]
+                           : B[i0 + a + (int64_t)(c0 + b) * np]);
+    __syncthreads();
+    for (int b = q; b < 64; b += 4) {
+      if (kind > 0 || (kind == 0 && a >= b))
+        S[(int64_t)(i0 + a) + (int64_t)(g0 + b) * ld] = T[a][b];
+      else if (kind < 0)
+        S[(int64_t)(g0 + a) + (int64_t)(i0 + b) * ld] = T[b][a];
+    }
+  }
+}
+
+// 1 / d for d > 0: hardware estimate refined by two Newton steps (a
+// shorter dependent chain than a rounded division).
+__device__ inline double rcp_nr(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  y = y * fma(-d, y, 2.0);
+  y = y * fma(-d, y, 2.0);
+  return y;
+}
+
+// One kNB-column step s of the sweep of a kb x kb symmetric block held in
+// full (both triangles, leading dimension kb): Din -> Dout, so the step
+// reads only values from before it.  A workgroup per lower 64 x 64 tile
+// (I, C), I >= C, writing the tile and its transpose.  Every workgroup
+// sweeps the pivot block Ds = Din_ss itself (64 rank-1 steps on a 4 x 4
+// block per thread in registers, one column broadcast through LDS per step)
+// to get M = -Ds^-1, then
+//   (s, s):          M
+//   (I, s), I != s:  Din_Is Ds^-1 = -Din_Is M
+//   (s, C), C != s:  Ds^-1 Din_sC = -M Din_sC
+//   otherwise:       Din_IC + (Din_Is M) Din_sC
+// The workgroup of tile (s, s) records a pivot that is not positive and
+// finite (index base + s * kNB + k) with atomicMin in `fail` and continues
+// with pivot 1.  Two 64 x 64 LDS buffers, so the workgroup fits beside a
+// GEMM workgroup on one CU.
+__global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict__ Din,
+                                                        double* __restrict__ Dout,
+                                                        int kb, int sb, int64_t* fail,
+                                                        int64_t base) {
+  __shared__ double Mv[kNB][kNB + 1];
+  __shared__ double Xa[kNB][kNB + 1];
+  __shared__ double colk[2][kNB];
+  int I = 0, C = blockIdx.x;
+  while (C > I) C -= ++I;  // lower tiles in row order: (0,0), (1,0), (1,1), ...
+  const int t = threadIdx.x, ri = (t & 15) * 4, cj = (t >> 4) * 4;
+  const int64_t s0 = (int64_t)sb * kNB;
+  auto at = [&](int bi, int bc, int r, int c) -> const double& {
+    return Din[(int64_t)bi * kNB + r + ((int64_t)bc * kNB + c) * kb];
+  };
+  double m[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) m[x][y] = at(sb, sb, ri + x, cj + y);
+  const bool reporter = (I == sb && C == sb && t == 0);
+  // pivots k = k4 + y; the column owner's register index y is static
+  for (int k4 = 0; k4 < kNB; k4 += 4) {
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int k = k4 + y, par = y & 1;
+      if (cj == k4) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) colk[par][ri + x] = m[x][y];
+      }
+      __syncthreads();
+      double d = colk[par][k];
+      if (!(d > 0.0) || !isfinite(d)) {
+        if (reporter)
+          atomicMin((unsigned long long*)fail, (unsigned long long)(base + s0 + k));
+        d = 1.0;
+      }
+      const double r = rcp_nr(d);
+      double ci[4], cc[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        ci[x] = colk[par][ri + x];
+        cc[x] = colk[par][cj + x];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const double pr = ci[x] * r;                  // M_ik / d
+        const double colv = (ri + x == k) ? -r : pr;  // new column k
+#pragma unroll
+        for (int y2 = 0; y2 < 4; ++y2) {
+          const double t1 = fma(-pr, cc[y2], m[x][y2]);
+          const double v = (ri + x == k) ? cc[y2] * r : t1;  // new row k
+          m[x][y2] = (cj + y2 == k) ? colv : v;
+        }
+      }
+    }
+  }
+  auto load = [&](double (*X)[kNB + 1], int bi, int bc) {
+    constexpr int kPer = kNB * kNB / 256;
+    double v[kPer];  // every load in flight before the LDS stores
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = t + 256 * q;
+      v[q] = at(bi, bc, e % kNB, e / kNB);
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = t + 256 * q;
+      X[e % kNB][e / kNB] = v[q];
+    }
+  };
+  // acc = X Y for this thread's 4 x 4 block
+  auto mul = [&](double (*X)[kNB + 1], double (*Y)[kNB + 1], double (&acc)[4][4]) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    for (int k = 0; k < kNB; ++k) {
+      double u[4], v[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        u[x] = X[ri + x][k];
+        v[x] = Y[k][cj + x];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(u[x], v[y], acc[x][y]);
+    }
+  };
+  auto put = [&](double (*X)[kNB + 1], const double (&v)[4][4]) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) X[ri + x][cj + y] = v[x][y];
+  };
+  double out[4][4];
+  if (I == sb && C == sb) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) out[x][y] = m[x][y];
+  } else if (C == sb || I == sb) {
+    // (I, s) below the pivot block, or (s, C) left of it
+    put(Mv, m);
+    load(Xa, C == sb ? I : sb, C == sb ? sb : C);
+    __syncthreads();
+    if (C == sb) mul(Xa, Mv, out); else mul(Mv, Xa, out);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) out[x][y] = -out[x][y];
+  } else {
+    put(Mv, m);
+    load(Xa, I, sb);
+    __syncthreads();
+    double tt[4][4];
+    mul(Xa, Mv, tt);   // T = Din_Is M
+    __syncthreads();
+    put(Xa, tt);
+    load(Mv, sb, C);   // Din_sC
+    __syncthreads();
+    mul(Xa, Mv, out);  // T Din_sC
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) out[x][y] += at(I, C, ri + x, cj + y);
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int64_t r = (int64_t)I * kNB + ri + x, c = (int64_t)C * kNB + cj + y;
+      Dout[r + c * kb] = out[x][y];
+      if (I != C) Dout[c + r * kb] = out[x][y];
+    }
+}
+
+static hipError_t band_move(hipStream_t st, Handle& h, const double* B, double* V,
+                            double* D, int k0, int kb, bool to_band, double sgn) {
+  const int64_t np = h.an.n_pad;
+  hipLaunchKernelGGL(k_band_move, dim3((unsigned)(np / 64), (unsigned)(kb / 64)),
+                     dim3(256), 0, st, h.S, np, B, V, D, np, k0, kb,
+                     to_band ? 1 : 0, sgn);
+  return hipGetLastError();
+}
+
+// The band of [k0, k0 + kb) in three parts: gather into V and the pivot
+// block (Dw[0]); sweep the pivot block to -D^-1 (kb / kNB launches, ending
+// in Dw[0] since kb / kNB is even); B = V D^-1 outside K and scatter back
+// (negated for the last band).
+static hipError_t band_gather(Handle& h, hipStream_t st, int k0, int kb, double* V) {
+  return band_move(st, h, nullptr, V, h.band + 4 * (int64_t)h.an.n_pad * h.band_nb,
+                   k0, kb, true, 1.0);
+}
+
+static hipError_t band_pivot_sweep(Handle& h, hipStream_t st, int k0, int kb) {
+  const int64_t np = h.an.n_pad;
+  const int64_t base = (int64_t)h.an.leaf_cols.size() + k0;
+  double* Dw[2] = {h.band + 4 * np * h.band_nb,
+                   h.band + 4 * np * h.band_nb + (int64_t)h.band_nb * h.band_nb};
+  const int nsb = kb / kNB, nt = nsb * (nsb + 1) / 2;
+  for (int sb = 0; sb < nsb; ++sb) {
+    hipLaunchKernelGGL(k_dsweep_step, dim3(nt), dim3(256), 0, st, Dw[sb & 1],
+                       Dw[(sb + 1) & 1], kb, sb, h.flag, base);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static hipError_t band_finish(Handle& h, hipStream_t st, int k0, int kb, double* B,
+                              const double* V, bool last) {
+  const int64_t np = h.an.n_pad;
+  double* Dm = h.band + 4 * np * h.band_nb;  // -D^-1, full
+  GemmSkip rows;
+  rows.r0 = k0;
+  rows.r1 = k0 + kb;
+  hipError_t e = gemm(st, 64, 64, kXC, kXC, V, np, Dm, kb, B, np, (int)np, kb, kb,
+                      -1.0, 0.0, false, false, false, false, 0, rows);
+  if (e != hipSuccess) return e;
+  return band_move(st, h, B, nullptr, Dm, k0, kb, false, last ? -1.0 : 1.0);
+}
+
+hipError_t root_sweep(Handle& h) {
+  const int np = (int)h.an.n_pad;
+  const int64_t ld = np;
+  hipError_t e;
+  if ((e = ensure_side_stream(h)) != hipSuccess) return e;
+  const int NB = std::min(h.potrf_block, h.band_nb);
+  const int nblk = (np + NB - 1) / NB;
+  double* Bb[2] = {h.band, h.band + 2 * (int64_t)np * h.band_nb};
+  double* Vb[2] = {h.band + (int64_t)np * h.band_nb, h.band + 3 * (int64_t)np * h.band_nb};
+  auto width = [&](int k) { return std::min(NB, np - k * NB); };
+  // band 0
+  if ((e = band_gather(h, h.stream, 0, width(0), Vb[0])) != hipSuccess) return e;
+  if ((e = band_pivot_sweep(h, h.stream, 0, width(0))) != hipSuccess) return e;
+  if ((e = band_finish(h, h.stream, 0, width(0), Bb[0], Vb[0], nblk == 1)) != hipSuccess)
+    return e;
+  for (int k = 0; k < nblk; ++k) {
+    const int k0 = k * NB, kb = width(k), k1 = k0 + kb;
+    const double* Bk = Bb[k & 1];
+    const double* Vk = Vb[k & 1];
+    int k2 = k1;
+    if (k + 1 < nblk) {
+      const int kbn = width(k + 1);
+      k2 = k1 + kbn;
+      // the next band first: its column part (rows >= k1) and its row part
+      // (columns < k0); the columns of K are the swept band itself
+      e = gemm(h.stream, 64, 64, kXC, kXC, Bk + k1, np, Vk + k1, np,
+               h.S + (int64_t)k1 * (ld + 1), ld, np - k1, kbn, kb, -1.0, 1.0, false,
+               false, true);
+      if (e != hipSuccess) return e;
+      if (k0 > 0) {
+        e = gemm(h.stream, 64, 64, kXC, kXC, Bk + k1, np, Vk, np, h.S + k1, ld, kbn,
+                 k0, kb, -1.0, 1.0, false, false, false);
+        if (e != hipSuccess) return e;
+      }
+      if ((e = band_gather(h, h.stream, k1, kbn, Vb[(k + 1) & 1])) != hipSuccess)
+        return e;
+      // its pivot block is swept on the side stream during the bulk
+      if ((e = hipEventRecord(h.ev_next, h.stream)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(h.side, h.ev_next, 0)) != hipSuccess) return e;
+      if ((e = band_pivot_sweep(h, h.side, k1, kbn)) != hipSuccess) return e;
+      if ((e = hipEventRecord(h.ev_panel, h.side)) != hipSuccess) return e;
+    }
+    // bulk: everything outside [k0, k2), lower triangle (negated at the end)
+    if (k2 - k0 < np) {
+      GemmSkip band;
+      band.r0 = band.c0 = k0;
+      band.r1 = band.c1 = k2;
+      const bool lastk = k + 1 == nblk;
+      e = gemm(h.stream, 128, 128, kXC, kXC, Bk, np, Vk, np, h.S, ld, np, np, kb,
+               lastk ? 1.0 : -1.0, lastk ? -1.0 : 1.0, true, false, false, false, 0,
+               band);
+      if (e != hipSuccess) return e;
+    }
+    if (k + 1 < nblk) {
+      if ((e = hipStreamWaitEvent(h.stream, h.ev_panel, 0)) != hipSuccess) return e;
+      e = band_finish(h, h.stream, k1, width(k + 1), Bb[(k + 1) & 1], Vb[(k + 1) & 1],
+                      k + 2 == nblk);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
 // ------------------------------------------------ dense triangular solves
 // Forward L z = b on the root, in chunks of kTrsvChunk rows: a single
 // workgroup solves the chunk block by block with the stored inverse
@@ -692,6 +1036,70 @@ hipError_t root_inv_apply(Handle& h, double* z, double* tmp) {
                      h.stream, h.vpart, tmp, np);
   hipLaunchKernelGGL(k_trmv_upper_t, dim3((np + 3) / 4), dim3(256), 0, h.stream,
                      h.W, (int64_t)np, tmp, z, np);
+  return hipGetLastError();
+}
+
+// y = Z v for the symmetric root inverse in lower storage (the upper
+// triangle of S holds nothing meaningful), reading Z twice: partial sums of
+// the lower part (j <= r) by row blocks and column chunks, the strictly
+// upper part as column dot products, then the sum of the two.
+__global__ __launch_bounds__(256) void k_symv_lower_part(const double* __restrict__ Z,
+                                                         int64_t ld,
+                                                         const double* __restrict__ v,
+                                                         double* __restrict__ part,
+                                                         int np) {
+  __shared__ double red[4][kNB];
+  const int I = blockIdx.x, C = blockIdx.y;
+  const int c0 = C * kMvChunk;
+  if (c0 > I * kNB + kNB - 1) return;  // chunk entirely above the diagonal
+  const int t = threadIdx.x, i = t % kNB, g = t / kNB;
+  const int r = I * kNB + i;
+  const int c1 = min(r + 1, min(np, c0 + kMvChunk));
+  double s = 0.0;
+  for (int j = c0 + g; j < c1; j += 4) s += Z[(int64_t)r + (int64_t)j * ld] * v[j];
+  red[g][i] = s;
+  __syncthreads();
+  if (t < kNB)
+    part[(int64_t)C * np + I * kNB + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+}
+
+// u[j] = sum_{i > j} Z[i, j] v[i]: one wave per column.
+__global__ __launch_bounds__(256) void k_symv_upper(const double* __restrict__ Z,
+                                                    int64_t ld,
+                                                    const double* __restrict__ v,
+                                                    double* __restrict__ u, int np) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= np) return;
+  const double* col = Z + (int64_t)j * ld;
+  double s = 0.0;
+  for (int i = j + 1 + lane; i < np; i += 64) s += col[i] * v[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) u[j] = s;
+}
+
+__global__ void k_symv_reduce(const double* __restrict__ part,
+                              const double* __restrict__ u, double* __restrict__ y,
+                              int np) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np;
+       r += gridDim.x * blockDim.x) {
+    const int last = r / kMvChunk;
+    double s = u[r];
+    for (int C = 0; C <= last; ++C) s += part[(int64_t)C * np + r];
+    y[r] = s;
+  }
+}
+
+// z (in/out, length n_pad): z := Z z with the root inverse held in S.
+hipError_t root_sym_apply(Handle& h, double* z, double* tmp) {
+  const int np = (int)h.an.n_pad;
+  const int nch = (np + kMvChunk - 1) / kMvChunk;
+  hipLaunchKernelGGL(k_symv_lower_part, dim3(np / kNB, nch), dim3(256), 0,
+                     h.stream, h.S, (int64_t)np, z, h.vpart, np);
+  hipLaunchKernelGGL(k_symv_upper, dim3((np + 3) / 4), dim3(256), 0, h.stream, h.S,
+                     (int64_t)np, z, tmp, np);
+  hipLaunchKernelGGL(k_symv_reduce, dim3((np + 255) / 256), dim3(256), 0, h.stream,
+                     h.vpart, tmp, z, np);
   return hipGetLastError();
 }
 

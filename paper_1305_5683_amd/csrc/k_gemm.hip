@@ -25,7 +25,9 @@
 // range of tile (I, J) starts at I * BM (products whose left factor is lower
 // triangular with zeros stored above the diagonal).  `diag_mask`: C's
 // origin lies on the matrix diagonal and only its lower part (i >= j) is
-// written; tiles entirely above the diagonal do nothing.
+// written; tiles entirely above the diagonal do nothing.  `skip`: tiles
+// whose rows meet [r0, r1) or whose columns meet [c0, c1) do nothing (the
+// bands that other work owns at the same time).
 #include <hip/hip_runtime.h>
 
 #include "spi_internal.h"
@@ -68,6 +70,7 @@ struct GemmArgs {
   int lower, kstart_diag, diag_mask;
   int kmask;  // kGemmKStartCol / kGemmKEndRow: triangular operands
   int tiles_m, tiles_n, n_tiles;
+  GemmSkip skip;
 };
 
 // Logical tile t -> (I, J).  Tiles are visited in groups of kGroup tile
@@ -126,6 +129,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   tile_of(g, xcd_remap<8>(blockIdx.x, g.n_tiles), I, J);
   const int i0 = I * BM, j0 = J * BN;
   if (g.diag_mask && i0 + BM - 1 < j0) return;  // tile above the diagonal
+  if ((i0 < g.skip.r1 && i0 + BM > g.skip.r0) ||
+      (j0 < g.skip.c1 && j0 + BN > g.skip.c0))
+    return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   // K range of the tile: an upper-triangular A starts at i0 (kstart_diag),
@@ -265,12 +271,12 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* C, int64_t ldc, int M, int N, int K, double alpha,
                 double beta, bool lower, bool kstart_diag, bool diag_mask,
-                bool f32, int kmask) {
+                bool f32, int kmask, GemmSkip skip) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (M % bm || N % bn || K % kKT || (lower && (bm != bn || M != N)))
     return hipErrorInvalidValue;
   GemmArgs a{A, B, C, lda, ldb, ldc, M, N, K, alpha, beta, lower ? 1 : 0,
-             kstart_diag ? 1 : 0, diag_mask ? 1 : 0, kmask, 0, 0, 0};
+             kstart_diag ? 1 : 0, diag_mask ? 1 : 0, kmask, 0, 0, 0, skip};
 #define SPI_GEMM_CASE(BM_, BN_, OA, OB)                                   \
   if (bm == BM_ && bn == BN_ && opA == OA && opB == OB)                  \
     return f32 ? gemm_t<BM_, BN_, OA, OB, float>(s, a)                   \

@@ -656,7 +656,9 @@ hipError_t launch_solve_pass(Handle& h, const double* b, double* x) {
                        0, h.stream, b, h.d.root_cols, h.d.rinc_ptr, h.d.rinc_grp,
                        h.d.rinc_u, h.d.grp_U_ptr, h.vfront, h.vroot, a.n_root,
                        a.n_pad);
-    if (h.have_inv) {
+    if (h.swept) {
+      if ((e = root_sym_apply(h, h.vroot, h.vroot2)) != hipSuccess) return e;
+    } else if (h.have_inv) {
       if ((e = root_inv_apply(h, h.vroot, h.vroot2)) != hipSuccess) return e;
     } else {
       if ((e = root_trsv_fwd(h, h.vroot)) != hipSuccess) return e;
@@ -686,7 +688,7 @@ __global__ void k_diag_root(const double* __restrict__ Z, int64_t ld,
 hipError_t launch_diag_root(Handle& h, double* d) {
   if (!h.an.n_root) return hipSuccess;
   hipLaunchKernelGGL(k_diag_root, dim3(grid_for(h.an.n_root, 256)), dim3(256),
-                     0, h.stream, h.Z, h.an.n_pad, h.d.root_cols, d,
+                     0, h.stream, h.Zr, h.an.n_pad, h.d.root_cols, d,
                      h.an.n_root);
   return hipGetLastError();
 }
@@ -818,7 +820,7 @@ hipError_t launch_selinv_leaves(Handle& h, double* d) {
       hipLaunchKernelGGL(k_selinv_leaf, dim3((unsigned)c), dim3(256), 0,
                          h.stream, h.d.tasks, h.d.sel_order + t0, h.d.grp_U_ptr,
                          h.d.U,
-                         h.d.grp_col_ptr, h.d.grp_panel_off, h.panel, h.Z,
+                         h.d.grp_col_ptr, h.d.grp_panel_off, h.panel, h.Zr,
                          a.n_pad, h.d.task_part_off, h.part);
     }
   }

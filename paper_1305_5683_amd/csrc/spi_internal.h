@@ -187,6 +187,11 @@ struct Handle {
   hipStream_t side = nullptr;       // lookahead stream of the root POTRF
   hipEvent_t ev_next = nullptr, ev_panel = nullptr;
   double* Z = nullptr;       // A^-1 restricted to the root (lower triangle)
+  double* band = nullptr;    // root sweeps: 2 x (band, copy) np x band_nb,
+                             // 2 pivot blocks band_nb x band_nb
+  int band_nb = 0;           // widest band: min(512, n_pad)
+  bool swept = false;        // S holds A_RR^-1 (sweeps) instead of L_RR
+  double* Zr = nullptr;      // where the root block of A^-1 is: S or Z
   double* part = nullptr;    // selected-inversion partial sums
   int64_t* flag = nullptr;   // first failing pivot in elimination order
   // solve scratch
@@ -279,6 +284,8 @@ hipError_t root_trsv_bwd(Handle& h, double* z);
 hipError_t root_inv_apply(Handle& h, double* z, double* tmp);
 int64_t root_inv_part_size(int64_t np);
 hipError_t root_trtri(Handle& h);
+hipError_t root_sweep(Handle& h);
+hipError_t root_sym_apply(Handle& h, double* z, double* tmp);
 hipError_t root_lauum(Handle& h);
 hipError_t launch_solve_pass(Handle& h, const double* b, double* x);
 hipError_t launch_residual_dd(Handle& h, const double* b, const double* x,
@@ -295,12 +302,17 @@ hipError_t fill_f64(hipStream_t s, double* p, double v, int64_t n);
 // dense kernels, exposed for tests of the root-front building blocks
 enum GemmOp { kXC = 0, kKC = 1 };  // operand access, see k_gemm.hip
 enum GemmKMask { kGemmKStartCol = 1, kGemmKEndRow = 2 };
+// Tiles of C whose rows meet [r0, r1) or whose columns meet [c0, c1) are
+// left alone (empty ranges: none).
+struct GemmSkip {
+  int r0 = 0, r1 = 0, c0 = 0, c1 = 0;
+};
 hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* C, int64_t ldc, int M, int N, int K, double alpha,
                 double beta, bool lower, bool kstart_diag,
                 bool diag_mask = false, bool f32 = false,
-                int kmask = 0);
+                int kmask = 0, GemmSkip skip = GemmSkip());
 
 // learned preconditioner and PCG (k_learned.hip)
 int64_t lp_param_count(int hidden);

@@ -348,3 +348,61 @@ def test_ragged_root_sizes_across_tile_edges():
         assert g["info"]["n_root"] == nr
         o = oracle_solve(p)
         _check(p, g, o)
+
+
+def _run_blocks(p, block, **opts):
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver
+    dev = torch.device("cuda")
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col, **opts)
+    s.potrf_block = block
+    s.set_values(torch.from_numpy(p.val).to(dev), torch.from_numpy(p.w).to(dev))
+    s.factor()
+    b = s.rhs(torch.from_numpy(p.y).to(dev))
+    x = s.solve(b)
+    d = s.diag_inv()
+    torch.cuda.synchronize()
+    out = {"b": b.cpu().numpy(), "x": x.cpu().numpy(), "d": d.cpu().numpy(),
+           "info": s.info()}
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("block", [128, 256, 512])
+def test_root_sweeps_over_several_bands(block):
+    """Dense root of order 700 (padded 768): 6, 3 or 2 bands, so the
+    lookahead band update, the bulk outside both bands and the negated last
+    band all run; also the Cholesky route (root_inverse=0) on the same
+    system with the same outer block."""
+    p = synth.make_random(2100, 700, 14, seed=77)
+    o = oracle_solve(p)
+    for ri in (1, 0):
+        _say(f"case sweeps block={block} root_inverse={ri}")
+        g = _run_blocks(p, block, leaf_max_work=0.0, root_inverse=ri)
+        assert g["info"]["n_root"] == 700
+        _check(p, g, o)
+
+
+def test_root_pivot_failure_same_column_both_routes():
+    """A dense root made indefinite by strongly negative weights on a few
+    rows: the sweeps and the Cholesky factorisation pivot on the same Schur
+    complements, so both report the same first failing column."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiError
+    p = synth.make_random(1200, 400, 10, seed=5)
+    w = p.w.copy()
+    w[[300, 301, 302]] = -1e3
+    dev = torch.device("cuda")
+    cols = []
+    for ri in (1, 0):
+        s = SpiSolver(p.m, p.n, p.rowptr, p.col, leaf_max_work=0.0, root_inverse=ri)
+        s.potrf_block = 128
+        s.set_values(torch.from_numpy(p.val).to(dev), torch.from_numpy(w).to(dev))
+        _say(f"case root pivot failure root_inverse={ri}")
+        with pytest.raises(SpiError) as ei:
+            s.factor()
+        assert ei.value.status == 3
+        cols.append(s.info()["failed_col"])
+        s.close()
+    _say(f"  failed columns {cols}")
+    assert cols[0] == cols[1] and cols[0] >= 0
