@@ -36,11 +36,14 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-# HBM bytes moved by one launch of the reported kernel (the root W^T W GEMM)
-# on the medium workload: rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by
+# HBM bytes moved by one launch of the reported mixed-precision kernel (the
+# root W^T W GEMM) on the medium workload: rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by
 # what the same counter reads for a copy kernel of known size (fetch x2.0,
 # write x1.0).  Taken on the current GEMM kernel; None for other workloads.
 LAUUM_HBM_BYTES_MEDIUM = 19.306e9 + 0.409e9
+# The same for the reported FP64 kernel, the bulk update of the root sweeps
+# (average per launch, outer block 512); None until counted on this kernel.
+BULK_HBM_BYTES_MEDIUM = None
 
 
 def parse():
@@ -172,6 +175,18 @@ def main():
     print(json.dumps(out))
 
 
+def sweep_bulk_launches(np_pad, blk):
+    """Bulk updates of one root inversion by sweeps: one per band whose
+    two-band skip leaves rows outside it."""
+    nb = min(blk, np_pad, 512)
+    widths = [min(nb, np_pad - k) for k in range(0, np_pad, nb)]
+    cnt = 0
+    for k, w in enumerate(widths):
+        span = w + (widths[k + 1] if k + 1 < len(widths) else 0)
+        cnt += span < np_pad
+    return cnt
+
+
 def measure(p, prec, args):
     """Time `args.steps` whole systems at one precision; returns the JSON
     object and the last x and diag(A^-1) (device tensors)."""
@@ -228,12 +243,32 @@ def measure(p, prec, args):
     refine = i1["refine_steps_done"]
     flops = (i1["flops_factor"] + i1["flops_selinv"] +
              i1["flops_solve"] * (1 + refine) + i1["flops_assembly"])
-    # reported kernel: the root inverse product Z = W^T W (an FP64 MFMA GEMM
-    # in both precisions; n_R^3 / 3 algorithmic flops)
     peak = PEAK_FP64_TFLOPS
-    lauum_flops = nR ** 3 / 3.0
-    lauum_s = ph["t_lauum_ms"] / 1e3
-    ach = lauum_flops / lauum_s / 1e12 if lauum_s > 0 else 0.0
+    bulk_s = (i1["t_sweep_bulk_ms"] - i0["t_sweep_bulk_ms"]) / 1e3
+    if bulk_s > 0:
+        # FP64: the root inverse by block sweeps; reported kernel = the bulk
+        # update (one FP64 MFMA GEMM per band: lower triangle of the rows
+        # outside two bands, rank = the block; flops timed by the library)
+        bulk_flops = i1["flops_sweep_bulk"] - i0["flops_sweep_bulk"]
+        launches = sweep_bulk_launches(i1["n_root_padded"], blk)
+        roof = {"bound": "mfma",
+                "kernel": "k_gemm<128,128,XC,XC> (root sweep bulk update)",
+                "achieved": bulk_flops / bulk_s / 1e12, "peak": peak,
+                "unit": "TFLOP/s", "frac": bulk_flops / bulk_s / 1e12 / peak,
+                "traffic": (BULK_HBM_BYTES_MEDIUM
+                            if args.config == 1 and blk == 512 else None),
+                "launches_per_system": launches,
+                "flops_per_launch": bulk_flops / (K * launches),
+                "avg_launch_us": bulk_s * 1e6 / (K * launches)}
+    else:
+        # mixed: the root inverse product Z = W^T W (an FP64 MFMA GEMM,
+        # n_R^3 / 3 algorithmic flops, one launch)
+        lauum_s = ph["t_lauum_ms"] / 1e3
+        ach = (nR ** 3 / 3.0) / lauum_s / 1e12 if lauum_s > 0 else 0.0
+        roof = {"bound": "mfma", "kernel": "k_gemm<128,128,KC,KC> (root W^T W)",
+                "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak,
+                "traffic": LAUUM_HBM_BYTES_MEDIUM if args.config == 1 else None}
     out = {
         "metric": "s/system for solve+diag(A^-1)",
         "value": ms / 1e3,
@@ -261,10 +296,7 @@ def measure(p, prec, args):
         "phases_ms": {k[2:-3]: round(v, 4) for k, v in ph.items()},
         "refine_steps": refine,
         "potrf_block": blk,
-        "roofline": {"bound": "mfma", "kernel": "k_gemm<128,128,KC,KC> (root W^T W)",
-                     "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                     "frac": ach / peak,
-                     "traffic": LAUUM_HBM_BYTES_MEDIUM if args.config == 1 else None},
+        "roofline": roof,
     }
     s.close()
     return out, xbuf, dbuf

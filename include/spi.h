@@ -101,7 +101,12 @@ typedef struct spi_opts {
                                do not get there; 0: exactly refine_steps
                                steps.  Default 0; SPI_MIXED uses 1e-14 and at
                                least 10 steps when this is 0 */
-    int32_t reserved[2];    /* must be zero */
+    int32_t keep_root_order;/* 0: the analysis numbers the root unknowns
+                               for locality (columns that share many rows
+                               end up in the same 64-column tiles, so fewer
+                               tiles of the dense root see each row); 1:
+                               original order.  Default 0 */
+    int32_t reserved;       /* must be zero */
 } spi_opts;
 
 typedef struct spi_info_t {
@@ -133,6 +138,12 @@ typedef struct spi_info_t {
     double t_trtri_ms;          /* inverse of the root factor */
     double t_lauum_ms;          /* root block of A^-1 from the inverse factor */
     double t_selinv_ms;         /* leaf selected inversion + diagonal output */
+    /* The root inversion by block sweeps (SPI_FP64 with root_inverse = 1)
+     * is timed in t_potrf_ms; its bulk updates (one symmetric rank-kb
+     * product per column band) also separately: */
+    double t_sweep_bulk_ms;     /* device time of the bulk updates */
+    double flops_sweep_bulk;    /* their algorithmic flops (lower triangles
+                                   only), summed over the timed calls */
 } spi_info_t;
 
 /* Fill `o` with the defaults listed above. */

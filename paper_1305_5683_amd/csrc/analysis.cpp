@@ -11,7 +11,7 @@
 // per-time-bin background unknowns before any sky pixel.  Consecutive
 // leaves with overlapping structure are amalgamated into one front
 // (supernode) while the dense panel stays dense enough; every other unknown
-// goes into one dense root front, in its original order.  The result is a
+// goes into one dense root front, numbered for locality (below).  The result is a
 // two-level assembly tree: independent leaf fronts, all children of the root.
 // It is exact for any SPD matrix (with no leaves it is a dense Cholesky).
 //
@@ -29,6 +29,7 @@
 #include <sstream>
 #include <chrono>
 #include <cstdio>
+#include <functional>
 #include <cstdlib>
 #include <thread>
 
@@ -100,6 +101,134 @@ void tile_runs(const int32_t* U, int64_t nU,
     a = b;
   }
 }
+// Locality numbering of the root unknowns (the dense root front's order is
+// free: any symmetric permutation is factored in the same flops).  Two root
+// columns are neighbours when they appear together in many rows: each
+// column keeps its kNbr most frequent partners, counted over up to
+// kSampleRows of its rows (evenly spaced, so the result is deterministic;
+// ties go to the lower index).  The numbering recursively bisects that
+// graph: a part is ordered by breadth-first distance from a far node (the
+// last one reached by a first search) and split in two, at a multiple of 64
+// when it is larger than 128, down to parts of at most 64 that become
+// consecutive root indices.  A row's root columns then fall in few 64-column
+// tiles, and the tile-by-tile assembly reads each row panel fewer times.
+constexpr int kNbr = 8;
+constexpr int kSampleRows = 128;
+
+std::vector<int32_t> root_locality_order(const Analysis& a, const int64_t* rowptr,
+                                         const int32_t* col,
+                                         const std::vector<int32_t>& roots,
+                                         const std::vector<int32_t>& rof,
+                                         unsigned NT) {
+  const int64_t nr = (int64_t)roots.size();
+  std::vector<int32_t> perm(nr);
+  std::iota(perm.begin(), perm.end(), 0);
+  if (nr <= 64) return perm;
+  // neighbours
+  std::vector<int32_t> nbr((size_t)nr * kNbr, -1);
+  parallel(NT, [&](unsigned t) {
+    std::vector<int32_t> cnt(nr, 0), touched;
+    std::vector<std::pair<int32_t, int32_t>> cand;
+    for (int64_t j = t; j < nr; j += NT) {
+      const int32_t c0 = roots[j];
+      const int64_t r0 = a.colptr[c0], len = a.colptr[c0 + 1] - r0;
+      const int64_t ns = std::min<int64_t>(len, kSampleRows);
+      touched.clear();
+      for (int64_t i = 0; i < ns; ++i) {
+        const int32_t r = a.csc_row[r0 + (i * len) / ns];
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          const int32_t c = rof[col[e]];
+          if (c < 0 || c == j) continue;
+          if (cnt[c]++ == 0) touched.push_back(c);
+        }
+      }
+      cand.clear();
+      for (int32_t c : touched) {
+        cand.emplace_back(-cnt[c], c);
+        cnt[c] = 0;
+      }
+      const size_t k = std::min<size_t>(kNbr, cand.size());
+      std::partial_sort(cand.begin(), cand.begin() + k, cand.end());
+      for (size_t q = 0; q < k; ++q) nbr[(size_t)j * kNbr + q] = cand[q].second;
+    }
+  });
+  // symmetric adjacency (CSR)
+  std::vector<int64_t> ap(nr + 1, 0);
+  for (int64_t j = 0; j < nr; ++j)
+    for (int q = 0; q < kNbr; ++q) {
+      const int32_t c = nbr[(size_t)j * kNbr + q];
+      if (c >= 0) {
+        ++ap[j + 1];
+        ++ap[c + 1];
+      }
+    }
+  for (int64_t j = 0; j < nr; ++j) ap[j + 1] += ap[j];
+  std::vector<int32_t> adj(ap[nr]);
+  {
+    std::vector<int64_t> fill(ap.begin(), ap.end() - 1);
+    for (int64_t j = 0; j < nr; ++j)
+      for (int q = 0; q < kNbr; ++q) {
+        const int32_t c = nbr[(size_t)j * kNbr + q];
+        if (c >= 0) {
+          adj[fill[j]++] = c;
+          adj[fill[c]++] = (int32_t)j;
+        }
+      }
+  }
+  // recursive bisection; label[v] = the part v is in, seen[v] = last search
+  std::vector<int32_t> label(nr, 0), seen(nr, -1);
+  int32_t next_label = 1, search = 0;
+  std::vector<int32_t> out;
+  out.reserve(nr);
+  std::vector<int32_t> queue;
+  // breadth-first order of `part` from `src` within label L; unreached
+  // vertices follow in their given order
+  auto bfs = [&](const std::vector<int32_t>& part, int32_t src, int32_t L,
+                 std::vector<int32_t>& order) {
+    const int32_t sid = search++;
+    order.clear();
+    order.push_back(src);
+    seen[src] = sid;
+    for (size_t h = 0; h < order.size(); ++h) {
+      const int32_t v = order[h];
+      for (int64_t e = ap[v]; e < ap[v + 1]; ++e) {
+        const int32_t u = adj[e];
+        if (label[u] == L && seen[u] != sid) {
+          seen[u] = sid;
+          order.push_back(u);
+        }
+      }
+    }
+    for (int32_t v : part)
+      if (seen[v] != sid) order.push_back(v);
+  };
+  std::function<void(std::vector<int32_t>&, int32_t)> bisect =
+      [&](std::vector<int32_t>& part, int32_t L) {
+        if (part.size() <= 64) {
+          out.insert(out.end(), part.begin(), part.end());
+          return;
+        }
+        std::vector<int32_t> o1, o2;
+        bfs(part, part[0], L, o1);
+        bfs(part, o1.back(), L, o2);
+        size_t h = part.size() / 2;
+        if (part.size() > 128) h = std::max<size_t>(64, h / 64 * 64);
+        std::vector<int32_t> left(o2.begin(), o2.begin() + h),
+            right(o2.begin() + h, o2.end());
+        const int32_t La = next_label++, Lb = next_label++;
+        for (int32_t v : left) label[v] = La;
+        for (int32_t v : right) label[v] = Lb;
+        part.clear();
+        part.shrink_to_fit();
+        bisect(left, La);
+        bisect(right, Lb);
+      };
+  std::vector<int32_t> all(nr);
+  std::iota(all.begin(), all.end(), 0);
+  bisect(all, 0);
+  return out;
+}
+
 }  // namespace
 
 std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
@@ -202,13 +331,22 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   }
 
   phase("leaf selection");
-  // ---- root numbering (original order)
+  // ---- root numbering: locality order (or the original order)
   a.root_of_col.assign(n, -1);
   for (int64_t j = 0; j < n; ++j)
     if (!is_leaf[j]) {
       a.root_of_col[j] = (int32_t)a.root_cols.size();
       a.root_cols.push_back((int32_t)j);
     }
+  if (!o.keep_root_order) {
+    const std::vector<int32_t> perm =
+        root_locality_order(a, rowptr, col, a.root_cols, a.root_of_col, NT);
+    std::vector<int32_t> orig = a.root_cols;
+    for (size_t i = 0; i < perm.size(); ++i) {
+      a.root_cols[i] = orig[perm[i]];
+      a.root_of_col[orig[perm[i]]] = (int32_t)i;
+    }
+  }
   a.n_root = (int64_t)a.root_cols.size();
   a.n_pad = a.n_root ? round_up(a.n_root, kRootPad) : 0;
 

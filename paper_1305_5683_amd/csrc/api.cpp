@@ -59,6 +59,9 @@ void collect(PhaseTimer& t) {
   t.pending.clear();
 }
 
+}  // namespace
+
+namespace spi {
 void phase_begin(Handle& h, Phase p) {
   if (!h.opts.timing) return;
   PhaseTimer& t = h.timer[p];
@@ -77,6 +80,10 @@ void phase_end(Handle& h, Phase p) {
   t.pending.emplace_back(t.open, e);
   t.open = nullptr;
 }
+
+}  // namespace spi
+
+namespace {
 
 void free_timers(Handle& h) {
   for (auto& t : h.timer) {
@@ -117,7 +124,8 @@ bool check_opts(spi_opts& o) {
     return false;
   }
   if (o.max_group < 1 || o.refine_steps < 0 || !(o.amalg_density >= 0.0) ||
-      !(o.refine_tol >= 0.0)) {
+      !(o.refine_tol >= 0.0) || (o.keep_root_order != 0 && o.keep_root_order != 1) ||
+      o.reserved != 0) {
     g_analyze_err = "invalid options";
     return false;
   }
@@ -338,7 +346,8 @@ int spi_analyze_like(spi_handle** out, const spi_handle* src, const spi_opts* op
   if (!check_opts(o)) return SPI_E_ARG;
   if (o.max_group != src->h.opts.max_group ||
       o.leaf_max_work != src->h.opts.leaf_max_work ||
-      o.amalg_density != src->h.opts.amalg_density) {
+      o.amalg_density != src->h.opts.amalg_density ||
+      o.keep_root_order != src->h.opts.keep_root_order) {
     g_analyze_err = "analysis options must match the source handle";
     return SPI_E_ARG;
   }
@@ -565,6 +574,8 @@ int spi_info(const spi_handle* Hc, spi_info_t* info) {
   info->t_trtri_ms = h.timer[kPhTrtri].total_ms;
   info->t_lauum_ms = h.timer[kPhLauum].total_ms;
   info->t_selinv_ms = h.timer[kPhSelinv].total_ms;
+  info->t_sweep_bulk_ms = h.timer[kPhBulk].total_ms;
+  info->flops_sweep_bulk = h.bulk_flops;
   return SPI_OK;
 }
 

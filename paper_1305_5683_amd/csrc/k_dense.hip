@@ -648,6 +648,9 @@ __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict
   __shared__ double Mv[kNB][kNB + 1];
   __shared__ double Xa[kNB][kNB + 1];
   __shared__ double colk[2][kNB];
+  // these steps are the critical path while bulk updates share the CUs:
+  // issue ahead of their waves
+  __builtin_amdgcn_s_setprio(3);
   int I = 0, C = blockIdx.x;
   while (C > I) C -= ++I;  // lower tiles in row order: (0,0), (1,0), (1,1), ...
   const int t = threadIdx.x, ri = (t & 15) * 4, cj = (t >> 4) * 4;
@@ -872,10 +875,16 @@ hipError_t root_sweep(Handle& h) {
       band.r0 = band.c0 = k0;
       band.r1 = band.c1 = k2;
       const bool lastk = k + 1 == nblk;
+      phase_begin(h, kPhBulk);
       e = gemm(h.stream, 128, 128, kXC, kXC, Bk, np, Vk, np, h.S, ld, np, np, kb,
                lastk ? 1.0 : -1.0, lastk ? -1.0 : 1.0, true, false, false, false, 0,
                band);
       if (e != hipSuccess) return e;
+      phase_end(h, kPhBulk);
+      if (h.opts.timing) {  // lower triangle of the rows outside [k0, k2)
+        const double R = (double)(np - (k2 - k0));
+        h.bulk_flops += 2.0 * kb * R * (R + 1) / 2;
+      }
     }
     if (k + 1 < nblk) {
       if ((e = hipStreamWaitEvent(h.stream, h.ev_panel, 0)) != hipSuccess) return e;

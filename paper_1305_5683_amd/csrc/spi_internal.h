@@ -154,7 +154,7 @@ struct DevAnalysis {
 };
 
 enum Phase { kPhLeaf = 0, kPhExtend, kPhPotrf, kPhSolve, kPhTrtri, kPhLauum,
-             kPhSelinv, kNumPhases };
+             kPhSelinv, kPhBulk, kNumPhases };
 
 struct PhaseTimer {
   std::vector<hipEvent_t> free_ev;
@@ -220,6 +220,7 @@ struct Handle {
   } lp;
   bool val32_ok = false;
   int potrf_block = 256;     // outer block of the root POTRF (autotuned)
+  double bulk_flops = 0;     // algorithmic flops of the timed sweep bulk updates
   bool have_inv = false;     // W = L_RR^-1 is valid
   // phase timing (opts.timing): HIP event pairs recorded on the stream,
   // accumulated lazily (spi_info synchronises and sums them)
@@ -285,6 +286,9 @@ hipError_t root_inv_apply(Handle& h, double* z, double* tmp);
 int64_t root_inv_part_size(int64_t np);
 hipError_t root_trtri(Handle& h);
 hipError_t root_sweep(Handle& h);
+// phase timing (opts.timing): event pairs on the handle's stream
+void phase_begin(Handle& h, Phase p);
+void phase_end(Handle& h, Phase p);
 hipError_t root_sym_apply(Handle& h, double* z, double* tmp);
 hipError_t root_lauum(Handle& h);
 hipError_t launch_solve_pass(Handle& h, const double* b, double* x);

@@ -406,3 +406,15 @@ def test_root_pivot_failure_same_column_both_routes():
         s.close()
     _say(f"  failed columns {cols}")
     assert cols[0] == cols[1] and cols[0] >= 0
+
+
+def test_root_order_original_and_locality_agree():
+    """The locality numbering of the root (default) and the original order
+    give the same solution and variances (an internal permutation of the
+    dense root)."""
+    p = synth.make_problem(synth.SkyConfig("order-s24", 24, 300, 9, 4), seed=3)
+    o = oracle_solve(p)
+    for keep in (0, 1):
+        _say(f"case root order keep_root_order={keep}")
+        g = run_gpu(p, keep_root_order=keep)
+        _check(p, g, o)
