@@ -246,17 +246,24 @@ def measure(p, prec, args):
     peak = PEAK_FP64_TFLOPS
     bulk_s = (i1["t_sweep_bulk_ms"] - i0["t_sweep_bulk_ms"]) / 1e3
     if bulk_s > 0:
-        # FP64: the root inverse by block sweeps; reported kernel = the bulk
-        # update (one FP64 MFMA GEMM per band: lower triangle of the rows
-        # outside two bands, rank = the block; flops timed by the library)
+        # the root inverse by block sweeps; reported kernel = the bulk update
+        # (one MFMA GEMM per band, FP64, or FP32 in launches of K <= 256 for
+        # mixed precision: lower triangle of the rows outside two bands,
+        # rank = the block; time and flops from the library's timers)
         bulk_flops = i1["flops_sweep_bulk"] - i0["flops_sweep_bulk"]
         launches = sweep_bulk_launches(i1["n_root_padded"], blk)
+        if mixed:
+            peak = PEAK_FP32_TFLOPS
+            launches *= max(1, min(blk, 512) // 256)
         roof = {"bound": "mfma",
-                "kernel": "k_gemm<128,128,XC,XC> (root sweep bulk update)",
+                "kernel": ("k_gemm<128,128,XC,XC,float> (root sweep bulk update)"
+                           if mixed else
+                           "k_gemm<128,128,XC,XC> (root sweep bulk update)"),
                 "achieved": bulk_flops / bulk_s / 1e12, "peak": peak,
                 "unit": "TFLOP/s", "frac": bulk_flops / bulk_s / 1e12 / peak,
                 "traffic": (BULK_HBM_BYTES_MEDIUM
-                            if args.config == 1 and blk == 512 else None),
+                            if args.config == 1 and blk == 512 and not mixed
+                            else None),
                 "launches_per_system": launches,
                 "flops_per_launch": bulk_flops / (K * launches),
                 "avg_launch_us": bulk_s * 1e6 / (K * launches)}

@@ -62,13 +62,15 @@ enum spi_status {
 
 enum spi_precision {
     SPI_FP64 = 0,       /* every stage in binary64 */
-    SPI_MIXED = 1       /* root front factorisation and factor inversion
-                           with binary32 matrix-core products (each launch
-                           sums at most 256 terms in binary32, partial
-                           results are combined in binary64); binary64
-                           storage, diagonal 64-blocks, leaf fronts,
-                           refinement residuals, and the selected-inversion
-                           sums (root block of A^-1 and leaf terms) */
+    SPI_MIXED = 1       /* the rank-k updates of the root front (the bulk
+                           and lookahead updates of the block sweeps, or
+                           with root_inverse = 0 the Cholesky and factor
+                           inversion products) on the binary32 matrix
+                           cores: each launch sums at most 256 terms in
+                           binary32 and launches add up in binary64;
+                           binary64 storage, pivot blocks, band products,
+                           leaf fronts, refinement residuals and the leaf
+                           selected-inversion sums */
 };
 
 typedef struct spi_opts {
@@ -83,11 +85,15 @@ typedef struct spi_opts {
                                double-double residual; default 2 */
     int32_t timing;         /* 1: time the phases with HIP events on the
                                handle's stream (see spi_info); default 0 */
-    int32_t root_inverse;   /* 1: spi_factor also forms the inverse of the
-                               root factor, L_RR^-1, which spi_solve then
-                               applies as two products and spi_diag_inv
-                               reuses; 0: it is formed by spi_diag_inv and
-                               spi_solve substitutes.  Default 1 */
+    int32_t root_inverse;   /* 1: spi_factor inverts the dense root front
+                               by block sweeps (Gauss-Jordan on the
+                               symmetric Schur complement, the Cholesky
+                               pivot blocks), so the root block of A^-1 is
+                               ready for spi_diag_inv and spi_solve applies
+                               it as a symmetric product; 0: spi_factor
+                               computes the Cholesky factor, spi_solve
+                               substitutes, and spi_diag_inv inverts the
+                               factor and forms W^T W.  Default 1 */
     int32_t equilibrate;    /* 1: factor S A S with S = diag(s), s_c the power
                                of two 2^-floor(log2(A_cc)/2) (scaled diagonal
                                in [1, 4)); exact, so FP64 results do not
@@ -133,14 +139,14 @@ typedef struct spi_info_t {
      * events on the handle's stream when opts.timing = 1 (else 0): */
     double t_leaf_ms;           /* leaf fronts: assembly, pivots, panels */
     double t_extend_ms;         /* root assembly + extend-add of the leaves */
-    double t_potrf_ms;          /* root Cholesky */
+    double t_potrf_ms;          /* root Cholesky, or the root inversion by
+                                   block sweeps (root_inverse = 1) */
     double t_solve_ms;          /* whole spi_solve incl. refinement */
     double t_trtri_ms;          /* inverse of the root factor */
     double t_lauum_ms;          /* root block of A^-1 from the inverse factor */
     double t_selinv_ms;         /* leaf selected inversion + diagonal output */
-    /* The root inversion by block sweeps (SPI_FP64 with root_inverse = 1)
-     * is timed in t_potrf_ms; its bulk updates (one symmetric rank-kb
-     * product per column band) also separately: */
+    /* The bulk updates of the root inversion by block sweeps
+     * (root_inverse = 1; one symmetric rank-kb product per column band): */
     double t_sweep_bulk_ms;     /* device time of the bulk updates */
     double flops_sweep_bulk;    /* their algorithmic flops (lower triangles
                                    only), summed over the timed calls */
@@ -383,17 +389,19 @@ int spi_batch_run(spi_batch* b, const double* const* y, double* const* rhs,
 void spi_batch_destroy(spi_batch* b);
 
 /*
- * Autotuner of the root POTRF's outer block (128, 256 or 512 columns per
- * trailing update with one-panel lookahead).  It times spi_factor on the
- * handle's current values with each candidate, keeps the fastest, and
- * leaves a factor computed with it.
+ * Autotuner of the root front's outer block: the band width of the block
+ * sweeps, or of the Cholesky's trailing updates (128, 256 or 512 columns,
+ * one band or panel of lookahead).  It times spi_factor on the handle's
+ * current values with each candidate, keeps the fastest, and leaves a
+ * factor computed with it.
  *  chosen  host, may be NULL
  */
 int spi_autotune(spi_handle* h, int32_t* chosen);
-/* Current outer block of the root POTRF, or -1 for a NULL handle. */
+/* Current outer block of the root front, or -1 for a NULL handle. */
 int spi_get_potrf_block(const spi_handle* h);
-/* Set the outer block by hand: 128, 256 or 512 (SPI_MIXED uses at most 256,
- * the longest binary32 accumulation it allows). */
+/* Set the outer block by hand: 128, 256 or 512 (SPI_MIXED with
+ * root_inverse = 0 uses at most 256, the longest binary32 accumulation it
+ * allows; the sweeps split longer products into launches of 256). */
 int spi_set_potrf_block(spi_handle* h, int32_t block);
 
 #ifdef __cplusplus

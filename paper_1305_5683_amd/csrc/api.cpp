@@ -201,9 +201,8 @@ int factor_enqueue(Handle& h) {
     phase_begin(h, kPhExtend);
     SPI_CK(launch_assemble_root(h), "root assembly");
     phase_end(h, kPhExtend);
-    // FP64 with the root inverse wanted: sweeps turn S into A_RR^-1;
-    // otherwise Cholesky (and the inverse of the factor if wanted)
-    h.swept = h.opts.root_inverse && h.opts.precision == SPI_FP64;
+    // root inverse wanted: sweeps turn S into A_RR^-1; otherwise Cholesky
+    h.swept = h.opts.root_inverse != 0;
     phase_begin(h, kPhPotrf);
     SPI_CK(h.swept ? root_sweep(h) : root_potrf(h), "root factorisation");
     phase_end(h, kPhPotrf);

@@ -173,7 +173,8 @@ int spi_autotune(spi_handle* H, int32_t* chosen) {
   h.opts.timing = 0;
   for (int c : cand) {
     if (h.an.n_pad > 0 && c > h.an.n_pad) continue;
-    if (h.opts.precision == SPI_MIXED && c > 256) continue;  // binary32 sums <= 256
+    // the Cholesky route caps binary32 sums by its outer block
+    if (h.opts.precision == SPI_MIXED && !h.opts.root_inverse && c > 256) continue;
     h.potrf_block = c;
     double t_min = 1e300;
     for (int rep = 0; rep < 2; ++rep) {

@@ -827,6 +827,27 @@ static hipError_t band_finish(Handle& h, hipStream_t st, int k0, int kb, double*
   return band_move(st, h, B, nullptr, Dm, k0, kb, false, last ? -1.0 : 1.0);
 }
 
+// C = beta C + alpha A B^T for the sweep updates (A, B: kXC, column-major
+// band buffers).  Mixed precision: binary32 matrix-core products, K split
+// into launches of at most kNBO terms, so every binary32 accumulation sums
+// at most kNBO products and the launches add up in binary64.
+static hipError_t sweep_update(Handle& h, hipStream_t st, int bm, const double* A,
+                               int64_t lda, const double* B, int64_t ldb, double* C,
+                               int64_t ldc, int M, int N, int K, double alpha,
+                               double beta, bool lower, bool diag_mask,
+                               GemmSkip skip = GemmSkip()) {
+  const bool f32 = h.opts.precision == SPI_MIXED;
+  const int kc = f32 ? kNBO : K;
+  for (int k0 = 0; k0 < K; k0 += kc) {
+    const int kk = std::min(kc, K - k0);
+    hipError_t e = gemm(st, bm, bm, kXC, kXC, A + (int64_t)k0 * lda, lda,
+                        B + (int64_t)k0 * ldb, ldb, C, ldc, M, N, kk, alpha,
+                        k0 == 0 ? beta : 1.0, lower, false, diag_mask, f32, 0, skip);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t root_sweep(Handle& h) {
   const int np = (int)h.an.n_pad;
   const int64_t ld = np;
@@ -852,13 +873,13 @@ hipError_t root_sweep(Handle& h) {
       k2 = k1 + kbn;
       // the next band first: its column part (rows >= k1) and its row part
       // (columns < k0); the columns of K are the swept band itself
-      e = gemm(h.stream, 64, 64, kXC, kXC, Bk + k1, np, Vk + k1, np,
-               h.S + (int64_t)k1 * (ld + 1), ld, np - k1, kbn, kb, -1.0, 1.0, false,
-               false, true);
+      e = sweep_update(h, h.stream, 64, Bk + k1, np, Vk + k1, np,
+                       h.S + (int64_t)k1 * (ld + 1), ld, np - k1, kbn, kb, -1.0, 1.0,
+                       false, true);
       if (e != hipSuccess) return e;
       if (k0 > 0) {
-        e = gemm(h.stream, 64, 64, kXC, kXC, Bk + k1, np, Vk, np, h.S + k1, ld, kbn,
-                 k0, kb, -1.0, 1.0, false, false, false);
+        e = sweep_update(h, h.stream, 64, Bk + k1, np, Vk, np, h.S + k1, ld, kbn, k0,
+                         kb, -1.0, 1.0, false, false);
         if (e != hipSuccess) return e;
       }
       if ((e = band_gather(h, h.stream, k1, kbn, Vb[(k + 1) & 1])) != hipSuccess)
@@ -876,9 +897,8 @@ hipError_t root_sweep(Handle& h) {
       band.r1 = band.c1 = k2;
       const bool lastk = k + 1 == nblk;
       phase_begin(h, kPhBulk);
-      e = gemm(h.stream, 128, 128, kXC, kXC, Bk, np, Vk, np, h.S, ld, np, np, kb,
-               lastk ? 1.0 : -1.0, lastk ? -1.0 : 1.0, true, false, false, false, 0,
-               band);
+      e = sweep_update(h, h.stream, 128, Bk, np, Vk, np, h.S, ld, np, np, kb,
+                       lastk ? 1.0 : -1.0, lastk ? -1.0 : 1.0, true, false, band);
       if (e != hipSuccess) return e;
       phase_end(h, kPhBulk);
       if (h.opts.timing) {  // lower triangle of the rows outside [k0, k2)
