@@ -238,21 +238,35 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
     }
   }
 
+  // Epilogue, one row block of 16 at a time: all of its C loads are issued
+  // before any store (a load after a store to the same array would wait for
+  // the store), then the stores, predicated on the triangle mask.
+  const bool mask_tile = (g.lower && I == J) || g.diag_mask;
 #pragma unroll
-  for (int a = 0; a < MI; ++a)
+  for (int a = 0; a < MI; ++a) {
+    const int i = i0 + wm * WM + a * 16 + lx;
+    double cv[NI][4];
+    if (g.beta != 0.0) {
+#pragma unroll
+      for (int b = 0; b < NI; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = j0 + wn * WN + b * 16 +
+                        (sizeof(T) == 8 ? v * 4 + lk : lk * 4 + v);
+          cv[b][v] = g.C[(int64_t)i + (int64_t)j * g.ldc];
+        }
+    }
 #pragma unroll
     for (int b = 0; b < NI; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wm * WM + a * 16 + lx;
         const int j = j0 + wn * WN + b * 16 +
                       (sizeof(T) == 8 ? v * 4 + lk : lk * 4 + v);
-        if (((g.lower && I == J) || g.diag_mask) && i < j) continue;
-        double* c = g.C + (int64_t)i + (int64_t)j * g.ldc;
         double r = g.alpha * (double)acc[a][b][v];
-        if (g.beta != 0.0) r += g.beta * (*c);
-        *c = r;
+        if (g.beta != 0.0) r = fma(g.beta, cv[b][v], r);
+        if (!(mask_tile && i < j)) g.C[(int64_t)i + (int64_t)j * g.ldc] = r;
       }
+  }
 }
 
 template <int BM, int BN, int OPA, int OPB, typename T>
