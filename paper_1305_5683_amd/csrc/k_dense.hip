@@ -630,9 +630,9 @@ __device__ inline double rcp_nr(double d) {
 // full (both triangles, leading dimension kb): Din -> Dout, so the step
 // reads only values from before it.  A workgroup per lower 64 x 64 tile
 // (I, C), I >= C, writing the tile and its transpose.  Every workgroup
-// sweeps the pivot block Ds = Din_ss itself (64 rank-1 steps on a 4 x 4
-// block per thread in registers, one column broadcast through LDS per step)
-// to get M = -Ds^-1, then
+// sweeps the pivot block Ds = Din_ss itself (64 rank-1 steps on 16 entries
+// per thread in registers, one column broadcast through LDS per step) to
+// get M = -Ds^-1, then
 //   (s, s):          M
 //   (I, s), I != s:  Din_Is Ds^-1 = -Din_Is M
 //   (s, C), C != s:  Ds^-1 Din_sC = -M Din_sC
@@ -653,26 +653,29 @@ __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict
   __builtin_amdgcn_s_setprio(3);
   int I = 0, C = blockIdx.x;
   while (C > I) C -= ++I;  // lower tiles in row order: (0,0), (1,0), (1,1), ...
-  const int t = threadIdx.x, ri = (t & 15) * 4, cj = (t >> 4) * 4;
+  const int t = threadIdx.x;
   const int64_t s0 = (int64_t)sb * kNB;
   auto at = [&](int bi, int bc, int r, int c) -> const double& {
     return Din[(int64_t)bi * kNB + r + ((int64_t)bc * kNB + c) * kb];
   };
-  double m[4][4];
+  // Pivot block in registers: wave w holds rows [16 w, 16 w + 16) and lane l
+  // column l (read through the symmetric twin, so the loads are contiguous
+  // over lanes).
+  const int lane = t & 63, wave = t >> 6;
+  double m[16];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) m[x][y] = at(sb, sb, ri + x, cj + y);
+  for (int q = 0; q < 16; ++q) m[q] = at(sb, sb, lane, 16 * wave + q);
   const bool reporter = (I == sb && C == sb && t == 0);
-  // pivots k = k4 + y; the column owner's register index y is static
-  for (int k4 = 0; k4 < kNB; k4 += 4) {
+  // Step k: the wave holding row k publishes it (= column k) in LDS; then
+  // element (i, l) becomes M_il - M_ik M_kl / d, column k (lane k) M_ik / d,
+  // row k M_kl / d and the pivot -1 / d.  Column k is written as
+  // fma(M_ik, r, 0 * m) and the others as fma(-M_ik, M_kl r, 1 * m), so all
+  // lanes run the same instructions.
+  for (int kw = 0; kw < 4; ++kw) {
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int k = k4 + y, par = y & 1;
-      if (cj == k4) {
-#pragma unroll
-        for (int x = 0; x < 4; ++x) colk[par][ri + x] = m[x][y];
-      }
+    for (int q = 0; q < 16; ++q) {
+      const int k = 16 * kw + q, par = q & 1;
+      if (wave == kw) colk[par][lane] = m[q];
       __syncthreads();
       double d = colk[par][k];
       if (!(d > 0.0) || !isfinite(d)) {
@@ -681,23 +684,14 @@ __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict
         d = 1.0;
       }
       const double r = rcp_nr(d);
-      double ci[4], cc[4];
+      const bool piv = lane == k;
+      const double tl = colk[par][lane] * r;  // M_kl / d
+      const double a = piv ? r : -tl;
+      const double keep = piv ? 0.0 : 1.0;
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        ci[x] = colk[par][ri + x];
-        cc[x] = colk[par][cj + x];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const double pr = ci[x] * r;                  // M_ik / d
-        const double colv = (ri + x == k) ? -r : pr;  // new column k
-#pragma unroll
-        for (int y2 = 0; y2 < 4; ++y2) {
-          const double t1 = fma(-pr, cc[y2], m[x][y2]);
-          const double v = (ri + x == k) ? cc[y2] * r : t1;  // new row k
-          m[x][y2] = (cj + y2 == k) ? colv : v;
-        }
-      }
+      for (int q2 = 0; q2 < 16; ++q2)
+        m[q2] = fma(colk[par][16 * wave + q2], a, keep * m[q2]);
+      if (wave == kw) m[q] = piv ? -r : tl;
     }
   }
   auto load = [&](double (*X)[kNB + 1], int bi, int bc) {
@@ -714,71 +708,94 @@ __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict
       X[e % kNB][e / kNB] = v[q];
     }
   };
-  // acc = X Y for this thread's 4 x 4 block
-  auto mul = [&](double (*X)[kNB + 1], double (*Y)[kNB + 1], double (&acc)[4][4]) {
+  // 64 x 64 products on the FP64 matrix cores: wave w owns the 32 x 32
+  // quadrant (32 (w & 1), 32 (w >> 1)) as 2 x 2 blocks of 16 x 16; element
+  // (bi, bj, v) of a lane is row 32 wr + 16 bi + lx, column 32 wc + 16 bj +
+  // 4 v + lk (the 16x16x4 FP64 result layout with the B fragment first)
+  const int lx = lane & 15, lk = lane >> 4;
+  const int r0 = 32 * (wave & 1), c0 = 32 * (wave >> 1);
+  auto mul = [&](double (*X)[kNB + 1], double (*Y)[kNB + 1], v4d (&acc)[2][2]) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-    for (int k = 0; k < kNB; ++k) {
-      double u[4], v[4];
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = 0; k < kNB; k += 4) {
+      double fa[2], fb[2];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        u[x] = X[ri + x][k];
-        v[x] = Y[k][cj + x];
+      for (int q = 0; q < 2; ++q) {
+        fa[q] = X[r0 + 16 * q + lx][k + lk];
+        fb[q] = Y[k + lk][c0 + 16 * q + lx];
       }
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(u[x], v[y], acc[x][y]);
+        for (int bj = 0; bj < 2; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[bj], fa[bi], acc[bi][bj],
+                                                            0, 0, 0);
     }
   };
-  auto put = [&](double (*X)[kNB + 1], const double (&v)[4][4]) {
+  auto row_of = [&](int bi) { return r0 + 16 * bi + lx; };
+  auto col_of = [&](int bj, int v) { return c0 + 16 * bj + 4 * v + lk; };
+  auto store = [&](const v4d (&o)[2][2]) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) X[ri + x][cj + y] = v[x][y];
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t r = (int64_t)I * kNB + row_of(bi);
+          const int64_t c = (int64_t)C * kNB + col_of(bj, v);
+          Dout[r + c * kb] = o[bi][bj][v];
+          if (I != C) Dout[c + r * kb] = o[bi][bj][v];
+        }
   };
-  double out[4][4];
-  if (I == sb && C == sb) {
+  if (I == sb && C == sb) {  // M itself (written through the symmetric twin)
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) out[x][y] = m[x][y];
-  } else if (C == sb || I == sb) {
-    // (I, s) below the pivot block, or (s, C) left of it
-    put(Mv, m);
-    load(Xa, C == sb ? I : sb, C == sb ? sb : C);
-    __syncthreads();
-    if (C == sb) mul(Xa, Mv, out); else mul(Mv, Xa, out);
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) out[x][y] = -out[x][y];
-  } else {
-    put(Mv, m);
-    load(Xa, I, sb);
-    __syncthreads();
-    double tt[4][4];
-    mul(Xa, Mv, tt);   // T = Din_Is M
-    __syncthreads();
-    put(Xa, tt);
-    load(Mv, sb, C);   // Din_sC
-    __syncthreads();
-    mul(Xa, Mv, out);  // T Din_sC
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) out[x][y] += at(I, C, ri + x, cj + y);
+    for (int q = 0; q < 16; ++q) Dout[(s0 + lane) + (s0 + 16 * wave + q) * kb] = m[q];
+    return;
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int q = 0; q < 16; ++q) Mv[16 * wave + q][lane] = m[q];
+  v4d acc[2][2];
+  if (C == sb || I == sb) {
+    // (I, s) below the pivot block: -Din_Is M; (s, C) left of it: -M Din_sC
+    load(Xa, C == sb ? I : sb, C == sb ? sb : C);
+    __syncthreads();
+    if (C == sb) mul(Xa, Mv, acc); else mul(Mv, Xa, acc);
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int64_t r = (int64_t)I * kNB + ri + x, c = (int64_t)C * kNB + cj + y;
-      Dout[r + c * kb] = out[x][y];
-      if (I != C) Dout[c + r * kb] = out[x][y];
-    }
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = -acc[bi][bj];
+  } else {
+    load(Xa, I, sb);
+    __syncthreads();
+    mul(Xa, Mv, acc);   // T = Din_Is M
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Xa[row_of(bi)][col_of(bj, v)] = acc[bi][bj][v];
+    load(Mv, sb, C);    // Din_sC
+    __syncthreads();
+    double cin[2][2][4];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cin[bi][bj][v] = at(I, C, row_of(bi), col_of(bj, v));
+    mul(Xa, Mv, acc);   // T Din_sC
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[bi][bj][v] += cin[bi][bj][v];
+  }
+  store(acc);
 }
 
 static hipError_t band_move(hipStream_t st, Handle& h, const double* B, double* V,
@@ -814,6 +831,11 @@ static hipError_t band_pivot_sweep(Handle& h, hipStream_t st, int k0, int kb) {
   return hipSuccess;
 }
 
+// Tile edges of the band product and of the lookahead update (the bulk
+// uses 128).
+constexpr int kBandTile = 64;
+constexpr int kLookTile = 64;
+
 static hipError_t band_finish(Handle& h, hipStream_t st, int k0, int kb, double* B,
                               const double* V, bool last) {
   const int64_t np = h.an.n_pad;
@@ -821,8 +843,8 @@ static hipError_t band_finish(Handle& h, hipStream_t st, int k0, int kb, double*
   GemmSkip rows;
   rows.r0 = k0;
   rows.r1 = k0 + kb;
-  hipError_t e = gemm(st, 64, 64, kXC, kXC, V, np, Dm, kb, B, np, (int)np, kb, kb,
-                      -1.0, 0.0, false, false, false, false, 0, rows);
+  hipError_t e = gemm(st, kBandTile, kBandTile, kXC, kXC, V, np, Dm, kb, B, np,
+                      (int)np, kb, kb, -1.0, 0.0, false, false, false, false, 0, rows);
   if (e != hipSuccess) return e;
   return band_move(st, h, B, nullptr, Dm, k0, kb, false, last ? -1.0 : 1.0);
 }
@@ -873,12 +895,12 @@ hipError_t root_sweep(Handle& h) {
       k2 = k1 + kbn;
       // the next band first: its column part (rows >= k1) and its row part
       // (columns < k0); the columns of K are the swept band itself
-      e = sweep_update(h, h.stream, 64, Bk + k1, np, Vk + k1, np,
+      e = sweep_update(h, h.stream, kLookTile, Bk + k1, np, Vk + k1, np,
                        h.S + (int64_t)k1 * (ld + 1), ld, np - k1, kbn, kb, -1.0, 1.0,
                        false, true);
       if (e != hipSuccess) return e;
       if (k0 > 0) {
-        e = sweep_update(h, h.stream, 64, Bk + k1, np, Vk, np, h.S + k1, ld, kbn, k0,
+        e = sweep_update(h, h.stream, kLookTile, Bk + k1, np, Vk, np, h.S + k1, ld, kbn, k0,
                          kb, -1.0, 1.0, false, false);
         if (e != hipSuccess) return e;
       }
