@@ -836,16 +836,20 @@ static hipError_t band_pivot_sweep(Handle& h, hipStream_t st, int k0, int kb) {
 constexpr int kBandTile = 64;
 constexpr int kLookTile = 64;
 
-static hipError_t band_finish(Handle& h, hipStream_t st, int k0, int kb, double* B,
-                              const double* V, bool last) {
+static hipError_t band_product(Handle& h, hipStream_t st, int k0, int kb, double* B,
+                               const double* V) {
   const int64_t np = h.an.n_pad;
-  double* Dm = h.band + 4 * np * h.band_nb;  // -D^-1, full
+  const double* Dm = h.band + 4 * np * h.band_nb;  // -D^-1, full
   GemmSkip rows;
   rows.r0 = k0;
   rows.r1 = k0 + kb;
-  hipError_t e = gemm(st, kBandTile, kBandTile, kXC, kXC, V, np, Dm, kb, B, np,
-                      (int)np, kb, kb, -1.0, 0.0, false, false, false, false, 0, rows);
-  if (e != hipSuccess) return e;
+  return gemm(st, kBandTile, kBandTile, kXC, kXC, V, np, Dm, kb, B, np, (int)np, kb,
+              kb, -1.0, 0.0, false, false, false, false, 0, rows);
+}
+
+static hipError_t band_scatter(Handle& h, hipStream_t st, int k0, int kb,
+                               const double* B, bool last) {
+  double* Dm = h.band + 4 * (int64_t)h.an.n_pad * h.band_nb;
   return band_move(st, h, B, nullptr, Dm, k0, kb, false, last ? -1.0 : 1.0);
 }
 
@@ -880,10 +884,20 @@ hipError_t root_sweep(Handle& h) {
   double* Bb[2] = {h.band, h.band + 2 * (int64_t)np * h.band_nb};
   double* Vb[2] = {h.band + (int64_t)np * h.band_nb, h.band + 3 * (int64_t)np * h.band_nb};
   auto width = [&](int k) { return std::min(NB, np - k * NB); };
+  // main -> side -> main handoffs
+  auto fork = [&]() -> hipError_t {
+    hipError_t x = hipEventRecord(h.ev_next, h.stream);
+    return x != hipSuccess ? x : hipStreamWaitEvent(h.side, h.ev_next, 0);
+  };
+  auto join = [&]() -> hipError_t {
+    hipError_t x = hipEventRecord(h.ev_panel, h.side);
+    return x != hipSuccess ? x : hipStreamWaitEvent(h.stream, h.ev_panel, 0);
+  };
   // band 0
   if ((e = band_gather(h, h.stream, 0, width(0), Vb[0])) != hipSuccess) return e;
   if ((e = band_pivot_sweep(h, h.stream, 0, width(0))) != hipSuccess) return e;
-  if ((e = band_finish(h, h.stream, 0, width(0), Bb[0], Vb[0], nblk == 1)) != hipSuccess)
+  if ((e = band_product(h, h.stream, 0, width(0), Bb[0], Vb[0])) != hipSuccess) return e;
+  if ((e = band_scatter(h, h.stream, 0, width(0), Bb[0], nblk == 1)) != hipSuccess)
     return e;
   for (int k = 0; k < nblk; ++k) {
     const int k0 = k * NB, kb = width(k), k1 = k0 + kb;
@@ -893,22 +907,26 @@ hipError_t root_sweep(Handle& h) {
     if (k + 1 < nblk) {
       const int kbn = width(k + 1);
       k2 = k1 + kbn;
-      // the next band first: its column part (rows >= k1) and its row part
-      // (columns < k0); the columns of K are the swept band itself
+      // the next band first: its column part (rows >= k1) on the main
+      // stream; band k's scatter (deferred from the previous step) and the
+      // next band's row part (columns < k0) on the side stream; the columns
+      // of K are the swept band itself.  The three touch disjoint entries.
+      if (k > 0) {
+        if ((e = fork()) != hipSuccess) return e;
+        if ((e = band_scatter(h, h.side, k0, kb, Bk, false)) != hipSuccess) return e;
+        e = sweep_update(h, h.side, kLookTile, Bk + k1, np, Vk, np, h.S + k1, ld, kbn,
+                         k0, kb, -1.0, 1.0, false, false);
+        if (e != hipSuccess) return e;
+      }
       e = sweep_update(h, h.stream, kLookTile, Bk + k1, np, Vk + k1, np,
                        h.S + (int64_t)k1 * (ld + 1), ld, np - k1, kbn, kb, -1.0, 1.0,
                        false, true);
       if (e != hipSuccess) return e;
-      if (k0 > 0) {
-        e = sweep_update(h, h.stream, kLookTile, Bk + k1, np, Vk, np, h.S + k1, ld, kbn, k0,
-                         kb, -1.0, 1.0, false, false);
-        if (e != hipSuccess) return e;
-      }
+      if (k > 0 && (e = join()) != hipSuccess) return e;
       if ((e = band_gather(h, h.stream, k1, kbn, Vb[(k + 1) & 1])) != hipSuccess)
         return e;
       // its pivot block is swept on the side stream during the bulk
-      if ((e = hipEventRecord(h.ev_next, h.stream)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(h.side, h.ev_next, 0)) != hipSuccess) return e;
+      if ((e = fork()) != hipSuccess) return e;
       if ((e = band_pivot_sweep(h, h.side, k1, kbn)) != hipSuccess) return e;
       if ((e = hipEventRecord(h.ev_panel, h.side)) != hipSuccess) return e;
     }
@@ -930,9 +948,12 @@ hipError_t root_sweep(Handle& h) {
     }
     if (k + 1 < nblk) {
       if ((e = hipStreamWaitEvent(h.stream, h.ev_panel, 0)) != hipSuccess) return e;
-      e = band_finish(h, h.stream, k1, width(k + 1), Bb[(k + 1) & 1], Vb[(k + 1) & 1],
-                      k + 2 == nblk);
+      const int kbn = width(k + 1);
+      e = band_product(h, h.stream, k1, kbn, Bb[(k + 1) & 1], Vb[(k + 1) & 1]);
       if (e != hipSuccess) return e;
+      if (k + 2 == nblk &&  // the last band: nothing follows to defer to
+          (e = band_scatter(h, h.stream, k1, kbn, Bb[(k + 1) & 1], true)) != hipSuccess)
+        return e;
     }
   }
   return hipSuccess;

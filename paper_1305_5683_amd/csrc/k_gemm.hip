@@ -147,24 +147,27 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   // kXC: a k-row of the slab is X contiguous doubles; X / 2 threads read it
   // as double2 (a wave covers whole rows), so both the global read and the
   // LDS write of one instruction are contiguous.  kKC: every x has kKT
-  // contiguous k; kKT / E threads share one x.
-  auto load = [&](const double* base, int64_t ld, int x0, int k0, int op,
-                  int X, int E, double* r) {
+  // contiguous k; kKT / E threads share one x.  Each thread's addresses are
+  // formed once (slab kbeg) and advanced by one slab per iteration.
+  auto first = [&](const double* base, int64_t ld, int x0, int op, int X,
+                   int E) -> const double* {
     if (op == kXC) {
-      const int tpr = X / 2, rows = 256 / tpr;
-      const int r0 = tid / tpr, x = (tid % tpr) * 2;
+      const int tpr = X / 2, r0 = tid / tpr, x = (tid % tpr) * 2;
+      return base + (int64_t)(x0 + x) + (int64_t)(kbeg + r0) * ld;
+    }
+    const int tpx = kKT / E, x = tid / tpx, kk = (tid % tpx) * E;
+    return base + (int64_t)(kbeg + kk) + (int64_t)(x0 + x) * ld;
+  };
+  auto load = [&](const double* p, int64_t ld, int op, int X, int E, double* r) {
+    if (op == kXC) {
+      const int64_t st = (int64_t)(256 / (X / 2)) * ld;  // rows per pass
 #pragma unroll
       for (int i = 0; i < E / 2; ++i) {
-        const int kk = r0 + i * rows;
-        double2 v = *reinterpret_cast<const double2*>(
-            base + (int64_t)(x0 + x) + (int64_t)(k0 + kk) * ld);
+        double2 v = *reinterpret_cast<const double2*>(p + i * st);
         r[2 * i] = v.x;
         r[2 * i + 1] = v.y;
       }
     } else {
-      const int tpx = kKT / E;
-      const int x = tid / tpx, kk = (tid % tpx) * E;
-      const double* p = base + (int64_t)(k0 + kk) + (int64_t)(x0 + x) * ld;
 #pragma unroll
       for (int e = 0; e < E; e += 2) {
         double2 v = *reinterpret_cast<const double2*>(p + e);
@@ -198,9 +201,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
 #pragma unroll
     for (int b = 0; b < NI; ++b) acc[a][b] = VA{0, 0, 0, 0};
 
+  const double* pa = first(g.A, g.lda, i0, OPA, BM, EA);
+  const double* pb = first(g.B, g.ldb, j0, OPB, BN, EB);
+  const int64_t stepA = (OPA == kXC) ? kKT * g.lda : kKT;
+  const int64_t stepB = (OPB == kXC) ? kKT * g.ldb : kKT;
   if (kbeg < kend) {
-    load(g.A, g.lda, i0, kbeg, OPA, BM, EA, ra);
-    load(g.B, g.ldb, j0, kbeg, OPB, BN, EB, rb);
+    load(pa, g.lda, OPA, BM, EA, ra);
+    load(pb, g.ldb, OPB, BN, EB, rb);
   }
   const int lx = lane & 15, lk = lane >> 4;
   for (int k0 = kbeg; k0 < kend; k0 += kKT) {
@@ -209,8 +216,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
     store(Bs, OPB, BN, EB, rb);
     __syncthreads();
     if (k0 + kKT < kend) {
-      load(g.A, g.lda, i0, k0 + kKT, OPA, BM, EA, ra);
-      load(g.B, g.ldb, j0, k0 + kKT, OPB, BN, EB, rb);
+      pa += stepA;
+      pb += stepB;
+      load(pa, g.lda, OPA, BM, EA, ra);
+      load(pb, g.ldb, OPB, BN, EB, rb);
     }
 #pragma unroll
     for (int ks = 0; ks < kKT; ks += 4) {
