@@ -500,6 +500,7 @@ int spi_symbolic(int64_t m, int64_t n, const int64_t* rowptr,
   spi_opts o;
   spi_default_opts(&o);
   if (opts) o = *opts;
+  if (!check_opts(o)) return SPI_E_ARG;
   Analysis a;
   auto t0 = std::chrono::steady_clock::now();
   std::string e = analyze(m, n, rowptr, col, o, a);

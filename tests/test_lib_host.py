@@ -134,3 +134,48 @@ def test_symbolic_max_group_and_density_options():
     assert i1["n_groups"] == i1["n_leaf"]
     i2, _, _, f2 = _symbolic(p, leaf_max_work=0.0)
     assert i2["n_leaf"] == 0 and i2["n_root"] == p.n
+
+
+def _root_tiles_per_row(p, order, n_leaf):
+    """Mean number of lower 64 x 64 tiles of the dense root that a row's
+    root columns touch, for the root numbering in `order`."""
+    pos = np.full(p.n, -1, dtype=np.int64)
+    pos[order[n_leaf:]] = np.arange(p.n - n_leaf)
+    tot = 0.0
+    for cols in _rows_of(p):
+        r = pos[cols]
+        b = np.unique(r[r >= 0] // 64)
+        tot += len(b) * (len(b) + 1) / 2
+    return tot / p.m
+
+
+def test_root_numbering_original_order_option():
+    p = synth.make_config(0)
+    info, order, _, _ = _symbolic(p, keep_root_order=1)
+    nl = info["n_leaf"]
+    assert np.all(np.diff(order[nl:]) > 0)   # root columns in original order
+
+
+def test_root_locality_numbering_is_deterministic_and_local():
+    """The default root numbering is a permutation of the same root set,
+    the same on every call, and puts a row's root columns into fewer
+    64-column tiles than the original (row-major sky) order."""
+    p = synth.make_problem(synth.SkyConfig("order-s40", 40, 800, 17, 4), seed=1)
+    i0, o0, _, _ = _symbolic(p, keep_root_order=1)
+    i1, o1, _, _ = _symbolic(p)
+    _, o2, _, _ = _symbolic(p)
+    nl = i0["n_leaf"]
+    assert i1["n_leaf"] == nl and np.array_equal(o0[:nl], o1[:nl])
+    assert sorted(o1[nl:].tolist()) == sorted(o0[nl:].tolist())
+    assert np.array_equal(o1, o2)
+    t_orig = _root_tiles_per_row(p, o0, nl)
+    t_loc = _root_tiles_per_row(p, o1, nl)
+    print(f"lower root tiles per row: original {t_orig:.1f}, locality {t_loc:.1f}")
+    assert t_loc <= 0.75 * t_orig
+
+
+def test_root_order_option_is_validated():
+    from paper_1305_5683_amd import SpiError
+    p = synth.make_config(0)
+    with pytest.raises(SpiError, match="invalid options"):
+        _symbolic(p, keep_root_order=2)
