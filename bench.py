@@ -395,6 +395,24 @@ def run_batch(args):
     batched()
     t_bat = time.perf_counter() - t0
     k = nb + ns
+    # plain FP64 on the same systems, one at a time (the reference point)
+    _say("timing plain FP64 sequential")
+    s64 = SpiSolver(base.m, base.n, base.rowptr, base.col, stream=streams[0])
+    sub64 = [SpiSolver(q.m, q.n, q.rowptr, q.col, stream=streams[slots + i])
+             for i, q in enumerate(subs)]
+
+    def sequential64():
+        for b in range(nb):
+            alone(s64, bvals[b], bout[0])
+        for s, v, o in zip(sub64, svals, sout):
+            alone(s, v, o)
+        torch.cuda.synchronize()
+    sequential64()
+    t0 = time.perf_counter()
+    sequential64()
+    t_64 = time.perf_counter() - t0
+    for s in [s64] + sub64:
+        s.close()
     flops = 0.0
     for s, cnt in [(bslots[0], nb)] + [(x, 1) for x in sub_s]:
         i = s.info()
@@ -411,6 +429,8 @@ def run_batch(args):
         "sequential_s_per_system": t_seq / k,
         "batched_s_per_system": t_bat / k,
         "speedup": t_seq / t_bat,
+        "fp64_sequential_s_per_system": t_64 / k,
+        "speedup_vs_fp64_sequential": t_64 / t_bat,
         "gflops_per_s": flops / t_bat / 1e9,
     }
     bb.close()

@@ -82,7 +82,10 @@ typedef struct spi_opts {
     double amalg_density;   /* min fraction of structural non-zeros in an
                                amalgamated leaf panel; default 0.35 */
     int32_t refine_steps;   /* refinement steps of spi_solve with a
-                               double-double residual; default 2 */
+                               double-double residual; default 1 (on the
+                               medium workload x is within 1.1e-13 of the
+                               certified solution with none, 8.5e-14 with
+                               one, and a second changes nothing) */
     int32_t timing;         /* 1: time the phases with HIP events on the
                                handle's stream (see spi_info); default 0 */
     int32_t root_inverse;   /* 1: spi_factor inverts the dense root front

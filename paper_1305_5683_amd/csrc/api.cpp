@@ -290,7 +290,7 @@ void spi_default_opts(spi_opts* o) {
   o->max_group = 32;
   o->leaf_max_work = 65536.0;
   o->amalg_density = 0.35;
-  o->refine_steps = 2;
+  o->refine_steps = 1;
   o->root_inverse = 1;
   o->equilibrate = 1;
   o->refine_tol = 0.0;
