@@ -192,9 +192,13 @@ int spi_set_values(spi_handle* h, const double* val, const double* w);
 /*
  * Numerical factorisation (Sect. 3.2.2): assembles A = H^T W H directly into
  * the leaf fronts and the root front (extend-add of the leaf contribution
- * blocks), then factors the root.  Synchronises the handle's stream.
- * Returns SPI_E_NOT_SPD if a pivot is not positive; spi_info().failed_col
- * then names the original column.  SPI_E_STATE before spi_set_values.
+ * blocks), factors the leaf fronts, then treats the dense root: with
+ * opts.root_inverse = 1 (default) it is inverted in place by block sweeps,
+ * whose pivot blocks are those of its Cholesky factorisation; with 0 it is
+ * Cholesky-factored.  Synchronises the handle's stream.  Returns
+ * SPI_E_NOT_SPD if a pivot is not positive (the same pivot on either
+ * route); spi_info().failed_col then names the original column.
+ * SPI_E_STATE before spi_set_values.
  */
 int spi_factor(spi_handle* h);
 
@@ -206,9 +210,10 @@ int spi_rhs(spi_handle* h, const double* y, double* b);
 
 /*
  * Solve A x = b by forward and backward substitution over the assembly tree
- * (Sect. 3.2.3), followed by opts.refine_steps steps of iterative
- * refinement whose residual b - H^T W (H x) is accumulated in double-double
- * arithmetic from H itself.
+ * (Sect. 3.2.3; at the root, one product with the root block of A^-1, or
+ * substitution with its Cholesky factor when root_inverse = 0), followed by
+ * opts.refine_steps steps of iterative refinement whose residual
+ * b - H^T W (H x) is accumulated in double-double arithmetic from H itself.
  *  b     device, float64, column-major n x nrhs with leading dimension ldb
  *  x     device, float64, same layout (written); may not alias b
  *  nrhs  >= 1;  ldb >= n
@@ -221,7 +226,9 @@ int spi_solve(spi_handle* h, const double* b, double* x, int32_t nrhs,
  * Variances: d_i = (A^-1)_ii for every unknown, original order, unscaled
  * (Sect. 2.4.1 variance relation; Sect. 3.3 partial computation of the
  * inverse).  Computed by selected inversion on the pattern of L: the full
- * inverse of the root front, then for every leaf front the entries it needs.
+ * inverse of the root front (already formed by spi_factor's sweeps, or by
+ * inverting its Cholesky factor when root_inverse = 0), then for every leaf
+ * front the entries it needs.
  *  d  device, float64[n] (written)
  * SPI_E_STATE if no valid factor.
  */

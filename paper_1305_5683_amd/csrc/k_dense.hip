@@ -3,11 +3,13 @@
 // The root front of the multifrontal factorisation (Sect. 3.2.2 of Bouchet
 // et al.: a partial factorisation of a dense matrix at every node, here the
 // complete factorisation at the root) is a dense SPD matrix stored
-// column-major, n_pad x n_pad, padded with identity.  Its Cholesky factor,
-// the inverse of that factor and the product giving the root block of A^-1
-// are blocked algorithms whose bulk is one tiled GEMM kernel on the
-// 16x16x4 FP64 matrix cores; the kNB x kNB diagonal blocks are factored and
-// inverted by a single-workgroup kernel in LDS.
+// column-major (lower triangle), n_pad x n_pad, padded with identity.  By
+// default it is inverted in place by symmetric block sweeps (the root block
+// of A^-1 is what the variances need); otherwise its Cholesky factor, the
+// inverse of that factor and the product W^T W are formed.  Either way the
+// bulk is one tiled GEMM kernel on the 16x16x4 FP64 (or 16x16x4 FP32)
+// matrix cores; 64 x 64 diagonal blocks are factored, inverted or swept by
+// small kernels in registers and LDS.  Also here: the dense root solves.
 #include <hip/hip_runtime.h>
 
 #include <vector>
