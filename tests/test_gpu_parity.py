@@ -368,6 +368,33 @@ def _run_blocks(p, block, **opts):
     return out
 
 
+def test_sweep_bulk_timers_count_the_bulk_flops():
+    """With timing on, the library times the sweeps' bulk updates and sums
+    their algorithmic flops: 2 kb R(R+1)/2 per band, R the rows outside the
+    band and the next one (the roofline figure of the benchmark)."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver
+    p = synth.make_random(2100, 700, 14, seed=77)
+    dev = torch.device("cuda")
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col, leaf_max_work=0.0, timing=1)
+    s.potrf_block = 128
+    s.set_values(torch.from_numpy(p.val).to(dev), torch.from_numpy(p.w).to(dev))
+    s.factor()
+    i = s.info()
+    npad, nb = i["n_root_padded"], 128
+    widths = [min(nb, npad - k) for k in range(0, npad, nb)]
+    want = 0.0
+    for k, w in enumerate(widths):
+        span = w + (widths[k + 1] if k + 1 < len(widths) else 0)
+        R = npad - span
+        if R > 0:
+            want += 2.0 * w * R * (R + 1) / 2
+    _say(f"case bulk timers: {i['flops_sweep_bulk']:.4e} flops in {i['t_sweep_bulk_ms']:.3f} ms")
+    assert i["flops_sweep_bulk"] == want
+    assert i["t_sweep_bulk_ms"] > 0.0
+    s.close()
+
+
 @pytest.mark.parametrize("block", [128, 256, 512])
 def test_root_sweeps_over_several_bands(block):
     """Dense root of order 700 (padded 768): 6, 3 or 2 bands, so the
