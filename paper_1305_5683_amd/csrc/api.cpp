@@ -111,7 +111,7 @@ void free_all(Handle& h) {
                   h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
                   h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2,
                   h.colscale, h.vbh, h.vxh, h.diagA, d.root_of_col, h.vfront,
-                  h.band};
+                  h.band, h.valc};
   free_lp_work(h);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -159,7 +159,7 @@ int setup_device(spi_handle* H) {
   const int64_t np = a.n_pad;
 #define AL(ptr, cnt) \
   if (he == hipSuccess) he = dev_alloc(ptr, cnt)
-  AL(h.val, a.nnz); AL(h.w, a.m); AL(h.sw, a.n_slots);
+  AL(h.val, a.nnz); AL(h.valc, a.nnz); AL(h.w, a.m); AL(h.sw, a.n_slots);
   AL(h.sleaf, a.n_slots);
   AL(h.rrval, (int64_t)a.rr_src.size());
   AL(h.panel, a.grp_panel_off.back() + a.rp_val_off.back());

@@ -320,29 +320,42 @@ hipError_t launch_assemble_root(Handle& h) {
 // intermediates of the mixed-precision path stay finite whatever the
 // column scales of H).  Columns with a zero or non-finite diagonal keep
 // s_c = 1 and fail at their pivot as before.
+// valc[k] = val[csc_pos[k]]: H's values in column order, so that the
+// column-wise kernels (diagonal, right-hand side, residual) read them
+// contiguously instead of gathering them from the row-ordered copy.
+__global__ void k_gather_csc(const double* __restrict__ val,
+                             const int64_t* __restrict__ csc_pos,
+                             double* __restrict__ valc, int64_t nnz) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x)
+    valc[k] = val[csc_pos[k]];
+}
+
 __global__ __launch_bounds__(256) void k_col_scale(
-    const int64_t* __restrict__ colptr, const int64_t* __restrict__ csc_pos,
-    const int32_t* __restrict__ csc_row, const double* __restrict__ val,
-    const double* __restrict__ w, double* __restrict__ diag,
-    double* __restrict__ scale, int64_t n) {
+    const int64_t* __restrict__ colptr, const int32_t* __restrict__ csc_row,
+    double* __restrict__ valc, const double* __restrict__ w,
+    double* __restrict__ diag, double* __restrict__ scale, int64_t n) {
   const int lane = threadIdx.x & 63;
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= n) return;
   double d = 0.0;
   for (int64_t k = colptr[c] + lane; k < colptr[c + 1]; k += 64) {
-    const double v = val[csc_pos[k]];
+    const double v = valc[k];
     d += w[csc_row[k]] * v * v;
   }
   for (int off = 32; off > 0; off >>= 1) d += __shfl_down(d, off, 64);
+  d = __shfl(d, 0, 64);
+  double s = 1.0;
+  if (d > 0.0 && d <= 1.7976931348623157e308) {
+    const int e = ilogb(d);     // d = m 2^e, 1 <= m < 2
+    s = ldexp(1.0, -(e >> 1));  // arithmetic shift: floor(e / 2)
+  }
   if (lane == 0) {
     diag[c] = d;
-    double s = 1.0;
-    if (d > 0.0 && d <= 1.7976931348623157e308) {
-      const int e = ilogb(d);     // d = m 2^e, 1 <= m < 2
-      s = ldexp(1.0, -(e >> 1));  // arithmetic shift: floor(e / 2)
-    }
     if (scale) scale[c] = s;
   }
+  if (scale)  // the column-ordered copy takes the scale here (exact)
+    for (int64_t k = colptr[c] + lane; k < colptr[c + 1]; k += 64) valc[k] *= s;
 }
 
 __global__ void k_scale_vals(double* __restrict__ val, const int32_t* __restrict__ col,
@@ -362,13 +375,18 @@ __global__ void k_scale_vec(const double* x, const double* __restrict__ s, doubl
   }
 }
 
-// diag(A) into h.diagA, and with opts.equilibrate the column scales and
-// the scaled values of H.
+// diag(A) into h.diagA, the column-ordered copy of H's values, and with
+// opts.equilibrate the column scales and the scaled values of H (both
+// copies).
 hipError_t launch_equilibrate(Handle& h) {
   const Analysis& a = h.an;
   const bool eq = h.opts.equilibrate != 0;
+  if (a.nnz)
+    hipLaunchKernelGGL(k_gather_csc, dim3((unsigned)std::min<int64_t>(
+                                         (a.nnz + 255) / 256, 16384)),
+                       dim3(256), 0, h.stream, h.val, h.d.csc_pos, h.valc, a.nnz);
   hipLaunchKernelGGL(k_col_scale, dim3(wave_grid(a.n)), dim3(256), 0, h.stream,
-                     h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.w, h.diagA,
+                     h.d.colptr, h.d.csc_row, h.valc, h.w, h.diagA,
                      eq ? h.colscale : nullptr, a.n);
   if (eq && a.nnz)
     hipLaunchKernelGGL(k_scale_vals, dim3((unsigned)std::min<int64_t>(
@@ -413,9 +431,8 @@ hipError_t fill_f64(hipStream_t s, double* p, double v, int64_t n) {
 // ------------------------------------------------------------------ rhs
 // b_c = sum_{r} h_rc w_r y_r over the column's entries (one wave per column).
 __global__ __launch_bounds__(256) void k_rhs(const int64_t* __restrict__ colptr,
-                                             const int64_t* __restrict__ csc_pos,
                                              const int32_t* __restrict__ csc_row,
-                                             const double* __restrict__ val,
+                                             const double* __restrict__ valc,
                                              const double* __restrict__ w,
                                              const double* __restrict__ y,
                                              const double* __restrict__ scale,
@@ -426,7 +443,7 @@ __global__ __launch_bounds__(256) void k_rhs(const int64_t* __restrict__ colptr,
   double s = 0.0;
   for (int64_t k = colptr[c] + lane; k < colptr[c + 1]; k += 64) {
     int32_t r = csc_row[k];
-    s += val[csc_pos[k]] * (w[r] * y[r]);
+    s += valc[k] * (w[r] * y[r]);
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   // val holds H S: undo the (power-of-two, exact) column scale
@@ -435,7 +452,7 @@ __global__ __launch_bounds__(256) void k_rhs(const int64_t* __restrict__ colptr,
 
 hipError_t launch_rhs(Handle& h, const double* y, double* b) {
   hipLaunchKernelGGL(k_rhs, dim3(wave_grid(h.an.n)), dim3(256), 0, h.stream,
-                     h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.w, y,
+                     h.d.colptr, h.d.csc_row, h.valc, h.w, y,
                      h.opts.equilibrate ? h.colscale : nullptr, b, h.an.n);
   return hipGetLastError();
 }
@@ -491,9 +508,8 @@ __global__ __launch_bounds__(256) void k_hx_dd(const int64_t* __restrict__ rowpt
 
 // r_c = b_c - sum_r h_rc t_r in double-double (one wave per column).
 __global__ __launch_bounds__(256) void k_htt_dd(const int64_t* __restrict__ colptr,
-                                                const int64_t* __restrict__ csc_pos,
                                                 const int32_t* __restrict__ csc_row,
-                                                const double* __restrict__ val,
+                                                const double* __restrict__ valc,
                                                 const double* __restrict__ t,
                                                 const double* __restrict__ b,
                                                 double* __restrict__ r, int64_t n) {
@@ -503,7 +519,7 @@ __global__ __launch_bounds__(256) void k_htt_dd(const int64_t* __restrict__ colp
   dd s{0.0, 0.0};
   for (int64_t k = colptr[c] + lane; k < colptr[c + 1]; k += 64) {
     const int32_t row = csc_row[k];
-    const double h = val[csc_pos[k]];
+    const double h = valc[k];
     dd tr{t[2 * row], t[2 * row + 1]};
     s = dd_add(s, dd_mul_d(tr, h));
   }
@@ -520,8 +536,7 @@ hipError_t launch_residual_dd(Handle& h, const double* b, const double* x,
   hipLaunchKernelGGL(k_hx_dd, dim3(wave_grid(a.m)), dim3(256), 0, h.stream,
                      h.d.rowptr, h.d.col, h.val, h.w, x, h.vdd, a.m);
   hipLaunchKernelGGL(k_htt_dd, dim3(wave_grid(a.n)), dim3(256), 0, h.stream,
-                     h.d.colptr, h.d.csc_pos, h.d.csc_row, h.val, h.vdd, b, r,
-                     a.n);
+                     h.d.colptr, h.d.csc_row, h.valc, h.vdd, b, r, a.n);
   return hipGetLastError();
 }
 

@@ -172,6 +172,7 @@ struct Handle {
   DevAnalysis d;
   // values in front (slot) order
   double* val = nullptr;     // H values, CSR order (copy)
+  double* valc = nullptr;    // H values, CSC order (same scaling)
   double* w = nullptr;       // weights, original row order (copy)
   double* sw = nullptr;      // weight per slot
   double* sleaf = nullptr;   // leaf coefficient per slot
