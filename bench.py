@@ -42,8 +42,9 @@ PEAK_HBM_GBS = 8000.0
 # write x1.0).  Taken on the current GEMM kernel; None for other workloads.
 LAUUM_HBM_BYTES_MEDIUM = 19.306e9 + 0.409e9
 # The same for the reported FP64 kernel, the bulk update of the root sweeps
-# (average per launch, outer block 512).
-BULK_HBM_BYTES_MEDIUM = 1.0028e9 + 0.3334e9
+# (average per launch, outer block 512); None until taken on the current
+# launch shape.
+BULK_HBM_BYTES_MEDIUM = None
 
 
 def parse():
@@ -176,14 +177,16 @@ def main():
 
 
 def sweep_bulk_launches(np_pad, blk):
-    """Bulk updates of one root inversion by sweeps: one per band whose
-    two-band skip leaves rows outside it."""
+    """Bulk updates of one root inversion by sweeps: one per band that
+    leaves lower-triangle entries outside its rows and columns and outside
+    the next band's pivot block."""
     nb = min(blk, np_pad, 512)
     widths = [min(nb, np_pad - k) for k in range(0, np_pad, nb)]
     cnt = 0
     for k, w in enumerate(widths):
-        span = w + (widths[k + 1] if k + 1 < len(widths) else 0)
-        cnt += span < np_pad
+        kn = widths[k + 1] if k + 1 < len(widths) else 0
+        R = np_pad - w
+        cnt += R * (R + 1) // 2 - kn * (kn + 1) // 2 > 0
     return cnt
 
 
@@ -263,7 +266,7 @@ def measure(p, prec, args):
                 "unit": "TFLOP/s", "frac": bulk_flops / bulk_s / 1e12 / peak,
                 "traffic": (BULK_HBM_BYTES_MEDIUM
                             if args.config == 1 and blk == 512 and not mixed
-                            else None),
+                            and BULK_HBM_BYTES_MEDIUM is not None else None),
                 "launches_per_system": launches,
                 "flops_per_launch": bulk_flops / (K * launches),
                 "avg_launch_us": bulk_s * 1e6 / (K * launches)}

@@ -343,7 +343,7 @@ hipError_t ensure_side_stream(Handle& h) {
     if ((e = hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking)) != hipSuccess)
       return e;
   }
-  hipEvent_t* evs[] = {&h.ev_next, &h.ev_panel};
+  hipEvent_t* evs[] = {&h.ev_next, &h.ev_panel, &h.ev_diag};
   for (hipEvent_t* ev : evs)
     if (!*ev && (e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess)
       return e;
@@ -568,24 +568,27 @@ hipError_t root_lauum(Handle& h) {
 // (one launch each, ping-pong between two buffers) to get -D^-1, forms
 // B = V D^-1 outside K in one product, and writes B (and -D^-1 on K) back.
 // The bulk is then M_ij -= B_i V_j^T over rows and columns outside K.  With
-// a one-band lookahead the next band is updated and gathered first, and its
-// pivot block (a chain of small launches) is swept on the side stream while
-// the main stream applies the bulk to everything else; the last bulk and the
-// last band are written negated, so S ends holding +A_RR^-1.
+// a one-band lookahead only the next band's pivot block is brought up to
+// date first: on the side stream it is updated, gathered and swept (a chain
+// of small launches) while the main stream's bulk updates everything else,
+// the rest of the next band included; the next band's columns are gathered
+// after the bulk.  The last bulk and the last band are written negated, so
+// S ends holding +A_RR^-1.
 
 // Band [k0, k0 + kb) of the symmetric matrix in lower storage S (leading
-// dimension ld) <-> column-major np x kb buffers; 64 x 64 tiles through LDS.
-// to_band: V receives the full symmetric columns and D (leading dimension
-// kb) its rows in K; otherwise the lower-storage positions of S receive
-// sgn times B, or D on the rows in K.
+// dimension ld) <-> column-major np x kb buffers; 64 x 64 tiles through LDS,
+// over the rows from row0 (one tile row per blockIdx.x).
+// to_band: V (if given) receives the full symmetric columns and D (if
+// given; leading dimension kb) its rows in K; otherwise the lower-storage
+// positions of S receive sgn times B, or D on the rows in K.
 __global__ __launch_bounds__(256) void k_band_move(double* __restrict__ S, int64_t ld,
                                                    const double* __restrict__ B,
                                                    double* __restrict__ V,
                                                    double* __restrict__ D,
                                                    int64_t np, int k0, int kb,
-                                                   int to_band, double sgn) {
+                                                   int to_band, double sgn, int row0) {
   __shared__ double T[64][65];
-  const int i0 = blockIdx.x * 64, c0 = blockIdx.y * 64, g0 = k0 + c0;
+  const int i0 = row0 + blockIdx.x * 64, c0 = blockIdx.y * 64, g0 = k0 + c0;
   const int t = threadIdx.x, a = t & 63, q = t >> 6;
   // kind: 1 direct (all rows below the columns), -1 transposed (all rows
   // above), 0 diagonal tile (rows of the tile are the tile's columns)
@@ -602,8 +605,8 @@ __global__ __launch_bounds__(256) void k_band_move(double* __restrict__ S, int64
     __syncthreads();
     for (int b = q; b < 64; b += 4) {
       const double v = (kind == 0 && a < b) ? T[b][a] : T[a][b];
-      V[i0 + a + (int64_t)(c0 + b) * np] = v;
-      if (inK) D[(i0 - k0 + a) + (int64_t)(c0 + b) * kb] = v;
+      if (V) V[i0 + a + (int64_t)(c0 + b) * np] = v;
+      if (inK && D) D[(i0 - k0 + a) + (int64_t)(c0 + b) * kb] = v;
     }
   } else {
     for (int b = q; b < 64; b += 4)
@@ -801,11 +804,13 @@ __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict
 }
 
 static hipError_t band_move(hipStream_t st, Handle& h, const double* B, double* V,
-                            double* D, int k0, int kb, bool to_band, double sgn) {
+                            double* D, int k0, int kb, bool to_band, double sgn,
+                            int row0 = 0, int rows = -1) {
   const int64_t np = h.an.n_pad;
-  hipLaunchKernelGGL(k_band_move, dim3((unsigned)(np / 64), (unsigned)(kb / 64)),
+  if (rows < 0) rows = (int)np;
+  hipLaunchKernelGGL(k_band_move, dim3((unsigned)(rows / 64), (unsigned)(kb / 64)),
                      dim3(256), 0, st, h.S, np, B, V, D, np, k0, kb,
-                     to_band ? 1 : 0, sgn);
+                     to_band ? 1 : 0, sgn, row0);
   return hipGetLastError();
 }
 
@@ -816,6 +821,17 @@ static hipError_t band_move(hipStream_t st, Handle& h, const double* B, double* 
 static hipError_t band_gather(Handle& h, hipStream_t st, int k0, int kb, double* V) {
   return band_move(st, h, nullptr, V, h.band + 4 * (int64_t)h.an.n_pad * h.band_nb,
                    k0, kb, true, 1.0);
+}
+
+// The columns alone (into V) or the pivot block alone (into Dw[0]).
+static hipError_t band_gather_cols(Handle& h, hipStream_t st, int k0, int kb, double* V) {
+  return band_move(st, h, nullptr, V, nullptr, k0, kb, true, 1.0);
+}
+
+static hipError_t band_gather_pivot(Handle& h, hipStream_t st, int k0, int kb) {
+  return band_move(st, h, nullptr, nullptr,
+                   h.band + 4 * (int64_t)h.an.n_pad * h.band_nb, k0, kb, true, 1.0,
+                   k0, kb);
 }
 
 static hipError_t band_pivot_sweep(Handle& h, hipStream_t st, int k0, int kb) {
@@ -886,16 +902,7 @@ hipError_t root_sweep(Handle& h) {
   double* Bb[2] = {h.band, h.band + 2 * (int64_t)np * h.band_nb};
   double* Vb[2] = {h.band + (int64_t)np * h.band_nb, h.band + 3 * (int64_t)np * h.band_nb};
   auto width = [&](int k) { return std::min(NB, np - k * NB); };
-  // main -> side -> main handoffs
-  auto fork = [&]() -> hipError_t {
-    hipError_t x = hipEventRecord(h.ev_next, h.stream);
-    return x != hipSuccess ? x : hipStreamWaitEvent(h.side, h.ev_next, 0);
-  };
-  auto join = [&]() -> hipError_t {
-    hipError_t x = hipEventRecord(h.ev_panel, h.side);
-    return x != hipSuccess ? x : hipStreamWaitEvent(h.stream, h.ev_panel, 0);
-  };
-  // band 0
+  // band 0: gathered, swept, multiplied and scattered on the main stream
   if ((e = band_gather(h, h.stream, 0, width(0), Vb[0])) != hipSuccess) return e;
   if ((e = band_pivot_sweep(h, h.stream, 0, width(0))) != hipSuccess) return e;
   if ((e = band_product(h, h.stream, 0, width(0), Bb[0], Vb[0])) != hipSuccess) return e;
@@ -905,57 +912,54 @@ hipError_t root_sweep(Handle& h) {
     const int k0 = k * NB, kb = width(k), k1 = k0 + kb;
     const double* Bk = Bb[k & 1];
     const double* Vk = Vb[k & 1];
-    int k2 = k1;
-    if (k + 1 < nblk) {
-      const int kbn = width(k + 1);
-      k2 = k1 + kbn;
-      // the next band first: its column part (rows >= k1) on the main
-      // stream; band k's scatter (deferred from the previous step) and the
-      // next band's row part (columns < k0) on the side stream; the columns
-      // of K are the swept band itself.  The three touch disjoint entries.
-      if (k > 0) {
-        if ((e = fork()) != hipSuccess) return e;
-        if ((e = band_scatter(h, h.side, k0, kb, Bk, false)) != hipSuccess) return e;
-        e = sweep_update(h, h.side, kLookTile, Bk + k1, np, Vk, np, h.S + k1, ld, kbn,
-                         k0, kb, -1.0, 1.0, false, false);
-        if (e != hipSuccess) return e;
-      }
-      e = sweep_update(h, h.stream, kLookTile, Bk + k1, np, Vk + k1, np,
-                       h.S + (int64_t)k1 * (ld + 1), ld, np - k1, kbn, kb, -1.0, 1.0,
+    const bool next = k + 1 < nblk;
+    const int kbn = next ? width(k + 1) : 0, k2 = k1 + kbn;
+    if (next) {
+      // Lookahead on the side stream: band k's update of the next pivot
+      // block alone (lower storage), its gather, and its sweeps, which run
+      // during the bulk.  Band k is already scattered, so the pivot buffers
+      // are free.
+      if ((e = hipEventRecord(h.ev_next, h.stream)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(h.side, h.ev_next, 0)) != hipSuccess) return e;
+      e = sweep_update(h, h.side, kLookTile, Bk + k1, np, Vk + k1, np,
+                       h.S + (int64_t)k1 * (ld + 1), ld, kbn, kbn, kb, -1.0, 1.0,
                        false, true);
       if (e != hipSuccess) return e;
-      if (k > 0 && (e = join()) != hipSuccess) return e;
-      if ((e = band_gather(h, h.stream, k1, kbn, Vb[(k + 1) & 1])) != hipSuccess)
-        return e;
-      // its pivot block is swept on the side stream during the bulk
-      if ((e = fork()) != hipSuccess) return e;
+      if ((e = band_gather_pivot(h, h.side, k1, kbn)) != hipSuccess) return e;
+      if ((e = hipEventRecord(h.ev_diag, h.side)) != hipSuccess) return e;
       if ((e = band_pivot_sweep(h, h.side, k1, kbn)) != hipSuccess) return e;
       if ((e = hipEventRecord(h.ev_panel, h.side)) != hipSuccess) return e;
     }
-    // bulk: everything outside [k0, k2), lower triangle (negated at the end)
-    if (k2 - k0 < np) {
+    // bulk: the lower triangle outside band k's rows and columns and outside
+    // the next pivot block (negated at the end for the last band); it also
+    // brings the rest of the next band up to date
+    const double R = (double)(np - kb);
+    const double cells = R * (R + 1) / 2 - (double)kbn * (kbn + 1) / 2;
+    if (cells > 0) {
       GemmSkip band;
       band.r0 = band.c0 = k0;
-      band.r1 = band.c1 = k2;
-      const bool lastk = k + 1 == nblk;
+      band.r1 = band.c1 = k1;
+      band.s0 = k1;
+      band.s1 = k2;
       phase_begin(h, kPhBulk);
       e = sweep_update(h, h.stream, 128, Bk, np, Vk, np, h.S, ld, np, np, kb,
-                       lastk ? 1.0 : -1.0, lastk ? -1.0 : 1.0, true, false, band);
+                       next ? -1.0 : 1.0, next ? 1.0 : -1.0, true, false, band);
       if (e != hipSuccess) return e;
       phase_end(h, kPhBulk);
-      if (h.opts.timing) {  // lower triangle of the rows outside [k0, k2)
-        const double R = (double)(np - (k2 - k0));
-        h.bulk_flops += 2.0 * kb * R * (R + 1) / 2;
-      }
+      if (h.opts.timing) h.bulk_flops += 2.0 * kb * cells;
     }
-    if (k + 1 < nblk) {
+    if (next) {
+      // the next band's columns (after the bulk and band k's scatter; its
+      // pivot rows are the side stream's, hence the wait), its product once
+      // the sweeps are done, and its scatter before the next lookahead
+      if ((e = hipStreamWaitEvent(h.stream, h.ev_diag, 0)) != hipSuccess) return e;
+      if ((e = band_gather_cols(h, h.stream, k1, kbn, Vb[(k + 1) & 1])) != hipSuccess)
+        return e;
       if ((e = hipStreamWaitEvent(h.stream, h.ev_panel, 0)) != hipSuccess) return e;
-      const int kbn = width(k + 1);
       e = band_product(h, h.stream, k1, kbn, Bb[(k + 1) & 1], Vb[(k + 1) & 1]);
       if (e != hipSuccess) return e;
-      if (k + 2 == nblk &&  // the last band: nothing follows to defer to
-          (e = band_scatter(h, h.stream, k1, kbn, Bb[(k + 1) & 1], true)) != hipSuccess)
-        return e;
+      e = band_scatter(h, h.stream, k1, kbn, Bb[(k + 1) & 1], k + 2 == nblk);
+      if (e != hipSuccess) return e;
     }
   }
   return hipSuccess;

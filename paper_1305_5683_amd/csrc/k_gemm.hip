@@ -130,7 +130,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   const int i0 = I * BM, j0 = J * BN;
   if (g.diag_mask && i0 + BM - 1 < j0) return;  // tile above the diagonal
   if ((i0 < g.skip.r1 && i0 + BM > g.skip.r0) ||
-      (j0 < g.skip.c1 && j0 + BN > g.skip.c0))
+      (j0 < g.skip.c1 && j0 + BN > g.skip.c0) ||
+      (i0 < g.skip.s1 && i0 + BM > g.skip.s0 && j0 < g.skip.s1 && j0 + BN > g.skip.s0))
     return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;

@@ -186,7 +186,7 @@ struct Handle {
   double* W = nullptr;       // L_RR^-1 (selected inversion scratch)
   double* invd2 = nullptr;   // inverses of the 256 x 256 diagonal blocks
   hipStream_t side = nullptr;       // lookahead stream of the root POTRF
-  hipEvent_t ev_next = nullptr, ev_panel = nullptr;
+  hipEvent_t ev_next = nullptr, ev_panel = nullptr, ev_diag = nullptr;
   double* Z = nullptr;       // A^-1 restricted to the root (lower triangle)
   double* band = nullptr;    // root sweeps: 2 x (band, copy) np x band_nb,
                              // 2 pivot blocks band_nb x band_nb
@@ -310,7 +310,8 @@ enum GemmKMask { kGemmKStartCol = 1, kGemmKEndRow = 2 };
 // Tiles of C whose rows meet [r0, r1) or whose columns meet [c0, c1) are
 // left alone (empty ranges: none).
 struct GemmSkip {
-  int r0 = 0, r1 = 0, c0 = 0, c1 = 0;
+  int r0 = 0, r1 = 0, c0 = 0, c1 = 0;  // rows [r0, r1), columns [c0, c1)
+  int s0 = 0, s1 = 0;                  // the square [s0, s1) x [s0, s1)
 };
 hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 const double* A, int64_t lda, const double* B, int64_t ldb,

@@ -370,8 +370,10 @@ def _run_blocks(p, block, **opts):
 
 def test_sweep_bulk_timers_count_the_bulk_flops():
     """With timing on, the library times the sweeps' bulk updates and sums
-    their algorithmic flops: 2 kb R(R+1)/2 per band, R the rows outside the
-    band and the next one (the roofline figure of the benchmark)."""
+    their algorithmic flops: 2 kb per lower-triangle entry outside the band's
+    rows and columns and outside the next band's pivot block, i.e.
+    2 kb (R(R+1)/2 - kn(kn+1)/2) with R = n - kb rows outside the band and kn
+    the next band's width (the roofline figure of the benchmark)."""
     torch = _torch()
     from paper_1305_5683_amd import SpiSolver
     p = synth.make_random(2100, 700, 14, seed=77)
@@ -385,10 +387,11 @@ def test_sweep_bulk_timers_count_the_bulk_flops():
     widths = [min(nb, npad - k) for k in range(0, npad, nb)]
     want = 0.0
     for k, w in enumerate(widths):
-        span = w + (widths[k + 1] if k + 1 < len(widths) else 0)
-        R = npad - span
-        if R > 0:
-            want += 2.0 * w * R * (R + 1) / 2
+        kn = widths[k + 1] if k + 1 < len(widths) else 0
+        R = npad - w
+        cells = R * (R + 1) / 2 - kn * (kn + 1) / 2
+        if cells > 0:
+            want += 2.0 * w * cells
     _say(f"case bulk timers: {i['flops_sweep_bulk']:.4e} flops in {i['t_sweep_bulk_ms']:.3f} ms")
     assert i["flops_sweep_bulk"] == want
     assert i["t_sweep_bulk_ms"] > 0.0
