@@ -97,7 +97,6 @@ void free_all(Handle& h) {
   free_timers(h);
   if (h.ev_next) (void)hipEventDestroy(h.ev_next);
   if (h.ev_panel) (void)hipEventDestroy(h.ev_panel);
-  if (h.ev_diag) (void)hipEventDestroy(h.ev_diag);
   if (h.side) (void)hipStreamDestroy(h.side);
   DevAnalysis& d = h.d;
   void* ptrs[] = {d.rowptr, d.col, d.colptr, d.csc_pos, d.csc_row, d.leaf_cols,

@@ -343,7 +343,7 @@ hipError_t ensure_side_stream(Handle& h) {
     if ((e = hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking)) != hipSuccess)
       return e;
   }
-  hipEvent_t* evs[] = {&h.ev_next, &h.ev_panel, &h.ev_diag};
+  hipEvent_t* evs[] = {&h.ev_next, &h.ev_panel};
   for (hipEvent_t* ev : evs)
     if (!*ev && (e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess)
       return e;
@@ -647,6 +647,7 @@ __device__ inline double rcp_nr(double d) {
 // with pivot 1.  Two 64 x 64 LDS buffers, so the workgroup fits beside a
 // GEMM workgroup on one CU.
 __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict__ Din,
+                                                        int64_t ldin, int sym_lower,
                                                         double* __restrict__ Dout,
                                                         int kb, int sb, int64_t* fail,
                                                         int64_t base) {
@@ -660,8 +661,16 @@ __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict
   while (C > I) C -= ++I;  // lower tiles in row order: (0,0), (1,0), (1,1), ...
   const int t = threadIdx.x;
   const int64_t s0 = (int64_t)sb * kNB;
-  auto at = [&](int bi, int bc, int r, int c) -> const double& {
-    return Din[(int64_t)bi * kNB + r + ((int64_t)bc * kNB + c) * kb];
+  // Din: the full kb x kb block (leading dimension ldin), or with sym_lower
+  // its lower triangle only (element (r, c), r < c, read at (c, r))
+  auto at = [&](int bi, int bc, int r, int c) -> double {
+    int64_t gr = (int64_t)bi * kNB + r, gc = (int64_t)bc * kNB + c;
+    if (sym_lower && gr < gc) {
+      const int64_t x = gr;
+      gr = gc;
+      gc = x;
+    }
+    return Din[gr + gc * ldin];
   };
   // Pivot block in registers: wave w holds rows [16 w, 16 w + 16) and lane l
   // column l (read through the symmetric twin, so the loads are contiguous
@@ -814,26 +823,15 @@ static hipError_t band_move(hipStream_t st, Handle& h, const double* B, double* 
   return hipGetLastError();
 }
 
-// The band of [k0, k0 + kb) in three parts: gather into V and the pivot
-// block (Dw[0]); sweep the pivot block to -D^-1 (kb / kNB launches, ending
-// in Dw[0] since kb / kNB is even); B = V D^-1 outside K and scatter back
-// (negated for the last band).
+// The band of [k0, k0 + kb) in three parts: gather its columns into V;
+// sweep the pivot block to -D^-1 (kb / kNB launches, the first reading S,
+// ending in Dw[0] since kb / kNB is even); B = V D^-1 outside K and scatter
+// back (negated for the last band).
 static hipError_t band_gather(Handle& h, hipStream_t st, int k0, int kb, double* V) {
-  return band_move(st, h, nullptr, V, h.band + 4 * (int64_t)h.an.n_pad * h.band_nb,
-                   k0, kb, true, 1.0);
-}
-
-// The columns alone (into V) or the pivot block alone (into Dw[0]).
-static hipError_t band_gather_cols(Handle& h, hipStream_t st, int k0, int kb, double* V) {
   return band_move(st, h, nullptr, V, nullptr, k0, kb, true, 1.0);
 }
 
-static hipError_t band_gather_pivot(Handle& h, hipStream_t st, int k0, int kb) {
-  return band_move(st, h, nullptr, nullptr,
-                   h.band + 4 * (int64_t)h.an.n_pad * h.band_nb, k0, kb, true, 1.0,
-                   k0, kb);
-}
-
+// The first step reads the pivot block from the lower storage of S.
 static hipError_t band_pivot_sweep(Handle& h, hipStream_t st, int k0, int kb) {
   const int64_t np = h.an.n_pad;
   const int64_t base = (int64_t)h.an.leaf_cols.size() + k0;
@@ -841,7 +839,10 @@ static hipError_t band_pivot_sweep(Handle& h, hipStream_t st, int k0, int kb) {
                    h.band + 4 * np * h.band_nb + (int64_t)h.band_nb * h.band_nb};
   const int nsb = kb / kNB, nt = nsb * (nsb + 1) / 2;
   for (int sb = 0; sb < nsb; ++sb) {
-    hipLaunchKernelGGL(k_dsweep_step, dim3(nt), dim3(256), 0, st, Dw[sb & 1],
+    const bool first = sb == 0;
+    hipLaunchKernelGGL(k_dsweep_step, dim3(nt), dim3(256), 0, st,
+                       first ? h.S + (int64_t)k0 * (np + 1) : Dw[sb & 1],
+                       first ? np : (int64_t)kb, first ? 1 : 0,
                        Dw[(sb + 1) & 1], kb, sb, h.flag, base);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -915,18 +916,16 @@ hipError_t root_sweep(Handle& h) {
     const bool next = k + 1 < nblk;
     const int kbn = next ? width(k + 1) : 0, k2 = k1 + kbn;
     if (next) {
-      // Lookahead on the side stream: band k's update of the next pivot
-      // block alone (lower storage), its gather, and its sweeps, which run
-      // during the bulk.  Band k is already scattered, so the pivot buffers
-      // are free.
-      if ((e = hipEventRecord(h.ev_next, h.stream)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(h.side, h.ev_next, 0)) != hipSuccess) return e;
-      e = sweep_update(h, h.side, kLookTile, Bk + k1, np, Vk + k1, np,
+      // Lookahead: band k's update of the next pivot block alone (lower
+      // storage, a small launch ahead of the bulk), then its sweeps on the
+      // side stream during the bulk.  Band k is already scattered, so the
+      // pivot buffers are free.
+      e = sweep_update(h, h.stream, kLookTile, Bk + k1, np, Vk + k1, np,
                        h.S + (int64_t)k1 * (ld + 1), ld, kbn, kbn, kb, -1.0, 1.0,
                        false, true);
       if (e != hipSuccess) return e;
-      if ((e = band_gather_pivot(h, h.side, k1, kbn)) != hipSuccess) return e;
-      if ((e = hipEventRecord(h.ev_diag, h.side)) != hipSuccess) return e;
+      if ((e = hipEventRecord(h.ev_next, h.stream)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(h.side, h.ev_next, 0)) != hipSuccess) return e;
       if ((e = band_pivot_sweep(h, h.side, k1, kbn)) != hipSuccess) return e;
       if ((e = hipEventRecord(h.ev_panel, h.side)) != hipSuccess) return e;
     }
@@ -949,11 +948,10 @@ hipError_t root_sweep(Handle& h) {
       if (h.opts.timing) h.bulk_flops += 2.0 * kb * cells;
     }
     if (next) {
-      // the next band's columns (after the bulk and band k's scatter; its
-      // pivot rows are the side stream's, hence the wait), its product once
-      // the sweeps are done, and its scatter before the next lookahead
-      if ((e = hipStreamWaitEvent(h.stream, h.ev_diag, 0)) != hipSuccess) return e;
-      if ((e = band_gather_cols(h, h.stream, k1, kbn, Vb[(k + 1) & 1])) != hipSuccess)
+      // the next band's columns (after the bulk and band k's scatter), its
+      // product once the sweeps are done, and its scatter before the next
+      // lookahead
+      if ((e = band_gather(h, h.stream, k1, kbn, Vb[(k + 1) & 1])) != hipSuccess)
         return e;
       if ((e = hipStreamWaitEvent(h.stream, h.ev_panel, 0)) != hipSuccess) return e;
       e = band_product(h, h.stream, k1, kbn, Bb[(k + 1) & 1], Vb[(k + 1) & 1]);

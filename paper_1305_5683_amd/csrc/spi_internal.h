@@ -186,7 +186,7 @@ struct Handle {
   double* W = nullptr;       // L_RR^-1 (selected inversion scratch)
   double* invd2 = nullptr;   // inverses of the 256 x 256 diagonal blocks
   hipStream_t side = nullptr;       // lookahead stream of the root POTRF
-  hipEvent_t ev_next = nullptr, ev_panel = nullptr, ev_diag = nullptr;
+  hipEvent_t ev_next = nullptr, ev_panel = nullptr;
   double* Z = nullptr;       // A^-1 restricted to the root (lower triangle)
   double* band = nullptr;    // root sweeps: 2 x (band, copy) np x band_nb,
                              // 2 pivot blocks band_nb x band_nb
