@@ -17,7 +17,7 @@
 //   B, kKC: B(k, j) = B[k + j * ldb]   (k contiguous)
 // Tiles are BM x BN, 256 threads = 4 waves in a 2 x 2 grid; each wave owns
 // a (BM/2) x (BN/2) block of 16 x 16 accumulators.  K advances in slabs of
-// kKT = 32, staged through LDS with a register prefetch of the next slab.
+// kKT = 16, staged through two LDS buffers with a register prefetch.
 // `kmask`: kGemmKStartCol (B lower triangular: k >= j only) and
 // kGemmKEndRow (A lower triangular: k <= i only) trim the K range per tile.
 // `lower`: only tiles with I >= J are enumerated (square tiles) and the
@@ -48,7 +48,7 @@ __device__ inline v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int kKT = 32;
+constexpr int kKT = 16;
 constexpr int kGroup = 8;      // tile rows per group of the launch order
 // LDS layouts.  kXC slabs are [k][x] with the row padded so that a row's
 // stride is 64 bytes mod 256: the four 16-lane groups of a fragment read
@@ -122,8 +122,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   constexpr int kPadXC = PadXC<T>::v;
   constexpr int A_SZ = (OPA == kXC) ? kKT * (BM + kPadXC) : BM * kStrKC;
   constexpr int B_SZ = (OPB == kXC) ? kKT * (BN + kPadXC) : BN * kStrKC;
-  __shared__ T As[A_SZ];
-  __shared__ T Bs[B_SZ];
+  __shared__ T As[2][A_SZ];
+  __shared__ T Bs[2][B_SZ];
 
   int I, J;
   tile_of(g, xcd_remap<8>(blockIdx.x, g.n_tiles), I, J);
@@ -206,34 +206,40 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   const double* pb = first(g.B, g.ldb, j0, OPB, BN, EB);
   const int64_t stepA = (OPA == kXC) ? kKT * g.lda : kKT;
   const int64_t stepB = (OPB == kXC) ? kKT * g.ldb : kKT;
+  // Two LDS buffers: slab s is read from buffer s & 1 while slab s + 1 is
+  // stored into the other one (after the slab's products, so they are not
+  // held up by the global loads), and the loads of slab s + 2 are issued;
+  // one barrier per slab.
   if (kbeg < kend) {
     load(pa, g.lda, OPA, BM, EA, ra);
     load(pb, g.ldb, OPB, BN, EB, rb);
-  }
-  const int lx = lane & 15, lk = lane >> 4;
-  for (int k0 = kbeg; k0 < kend; k0 += kKT) {
-    __syncthreads();
-    store(As, OPA, BM, EA, ra);
-    store(Bs, OPB, BN, EB, rb);
-    __syncthreads();
-    if (k0 + kKT < kend) {
+    store(As[0], OPA, BM, EA, ra);
+    store(Bs[0], OPB, BN, EB, rb);
+    if (kbeg + kKT < kend) {
       pa += stepA;
       pb += stepB;
       load(pa, g.lda, OPA, BM, EA, ra);
       load(pb, g.ldb, OPB, BN, EB, rb);
     }
+  }
+  const int lx = lane & 15, lk = lane >> 4;
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += kKT) {
+    __syncthreads();  // slab k0 complete in buf; buf ^ 1 no longer read
+    const T* Ab = As[buf];
+    const T* Bb = Bs[buf];
 #pragma unroll
     for (int ks = 0; ks < kKT; ks += 4) {
       T fa[MI], fb[NI];
 #pragma unroll
       for (int a = 0; a < MI; ++a) {
         const int x = wm * WM + a * 16 + lx, kk = ks + lk;
-        fa[a] = (OPA == kXC) ? As[kk * (BM + kPadXC) + x] : As[x * kStrKC + kk];
+        fa[a] = (OPA == kXC) ? Ab[kk * (BM + kPadXC) + x] : Ab[x * kStrKC + kk];
       }
 #pragma unroll
       for (int b = 0; b < NI; ++b) {
         const int x = wn * WN + b * 16 + lx, kk = ks + lk;
-        fb[b] = (OPB == kXC) ? Bs[kk * (BN + kPadXC) + x] : Bs[x * kStrKC + kk];
+        fb[b] = (OPB == kXC) ? Bb[kk * (BN + kPadXC) + x] : Bb[x * kStrKC + kk];
       }
       // D = Bfrag^T * Afrag, so lane (lx, lk) holds output row i = lx of
       // the 16 x 16 block (column-major stores of C stay contiguous over 16
@@ -246,6 +252,17 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < NI; ++b) acc[a][b] = mfma16(fb[b], fa[a], acc[a][b]);
     }
+    if (k0 + kKT < kend) {
+      store(As[buf ^ 1], OPA, BM, EA, ra);
+      store(Bs[buf ^ 1], OPB, BN, EB, rb);
+      if (k0 + 2 * kKT < kend) {
+        pa += stepA;
+        pb += stepB;
+        load(pa, g.lda, OPA, BM, EA, ra);
+        load(pb, g.ldb, OPB, BN, EB, rb);
+      }
+    }
+    buf ^= 1;
   }
 
   // Epilogue, one row block of 16 at a time: all of its C loads are issued
