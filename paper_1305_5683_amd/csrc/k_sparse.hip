@@ -712,14 +712,13 @@ hipError_t launch_diag_root(Handle& h, double* d) {
 // c = L_Ul, Z_Ul = -Z_UU c / L_ll and Z_ll = (1 + c^T Z_UU c) / L_ll^2.
 // Task (g, I, J) adds its block of the quadratic forms c^T Z_UU c for all
 // pivots of g: the full square block for I == J, twice the block for I > J.
-__global__ __launch_bounds__(256) void k_selinv_leaf(
+__global__ __launch_bounds__(256, 6) void k_selinv_leaf(
     const int32_t* __restrict__ tasks, const int32_t* __restrict__ order,
     const int64_t* __restrict__ grp_U_ptr,
     const int32_t* __restrict__ U, const int64_t* __restrict__ grp_col_ptr,
     const int64_t* __restrict__ grp_panel_off, const double* __restrict__ panel,
     const double* __restrict__ Z, int64_t ld,
     const int64_t* __restrict__ task_part_off, double* __restrict__ part) {
-  __shared__ double Zt[kET][kET + 1];
   __shared__ double PI[kQC][kET + 1];  // padded rows: the MFMA operand reads
   __shared__ double PJ[kQC][kET + 1];  // of 16 different q are conflict-free
   __shared__ double red[4][kQC];
@@ -742,19 +741,20 @@ __global__ __launch_bounds__(256) void k_selinv_leaf(
     sU[side][a] = Ug[base + min(a, len - 1)];
   }
   __syncthreads();
-  constexpr int kPer = kET * kET / 256;
-  double zv[kPer];
+  // The block Z_IJ stays in registers as the first operand of the FP64
+  // matrix-core products: wave w holds rows a = 16 w + lx, lane (lx, lk)
+  // the columns b = 4 s + lk for the 16 steps s over b.
+  const int lx = lane & 15, lk = lane >> 4, a = 16 * wave + lx;
+  const int64_t ua = sU[0][a];
+  double zf[kET / 4];
 #pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    const int e = t + 256 * i, a = e % kET, b = e / kET;
-    const int64_t ua = sU[0][a], ub = sU[1][b];
-    zv[i] = ua >= ub ? Z[ua + ub * ld] : Z[ub + ua * ld];  // lower storage
+  for (int st = 0; st < kET / 4; ++st) {
+    const int64_t ub = sU[1][4 * st + lk];
+    zf[st] = ua >= ub ? Z[ua + ub * ld] : Z[ub + ua * ld];  // lower storage
   }
 #pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    const int e = t + 256 * i, a = e % kET, b = e / kET;
-    Zt[a][b] = (a < na && b < nb) ? zv[i] : 0.0;
-  }
+  for (int st = 0; st < kET / 4; ++st)
+    if (!(a < na && 4 * st + lk < nb)) zf[st] = 0.0;
   const double* Pg = panel + grp_panel_off[g];
   const double fac = (I == J) ? 1.0 : 2.0;
   for (int q0 = 0; q0 < p; q0 += kQC) {
@@ -764,37 +764,33 @@ __global__ __launch_bounds__(256) void k_selinv_leaf(
     double pi[kPP], pj[kPP];
 #pragma unroll
     for (int i = 0; i < kPP; ++i) {  // all panel loads in flight together
-      const int e = t + 256 * i, a = e % kET, q = e / kET;
+      const int e = t + 256 * i, r = e % kET, q = e / kET;
       const int64_t col = (int64_t)(q0 + min(q, pc - 1)) * nU;
-      pi[i] = Pg[col + I0 + min(a, na - 1)];
-      pj[i] = Pg[col + J0 + min(a, nb - 1)];
+      pi[i] = Pg[col + I0 + min(r, na - 1)];
+      pj[i] = Pg[col + J0 + min(r, nb - 1)];
     }
 #pragma unroll
     for (int i = 0; i < kPP; ++i) {
-      const int e = t + 256 * i, a = e % kET, q = e / kET;
-      PI[q][a] = (q < pc && a < na) ? pi[i] : 0.0;
-      PJ[q][a] = (q < pc && a < nb) ? pj[i] : 0.0;
+      const int e = t + 256 * i, r = e % kET, q = e / kET;
+      PI[q][r] = (q < pc && r < na) ? pi[i] : 0.0;
+      PJ[q][r] = (q < pc && r < nb) ? pj[i] : 0.0;
     }
     __syncthreads();
-    // Y = PI Zt on the FP64 matrix cores: wave w owns columns
-    // b in [16 w, 16 w + 16) of Y (16 q x 64 b), K = 64 in 16 steps.  Result
-    // layout: Y[q][b] in lane (b - 16 w) + 16 (q % 4), item q / 4.  Then
-    // s_q += sum_b Y[q][b] PJ[q][b], reduced over the 16 lanes of each q.
-    {
-      const int lx = lane & 15, lk = lane >> 4, b0 = 16 * wave;
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
+    // Y = Z_IJ PJ^T (rows a of the wave, 16 q), K = 64 over b.  Result
+    // layout: Y[a][q] in lane q + 16 (a % 4), item a / 4 (a local to the
+    // wave).  Then s_q += sum_a PI[q][a] Y[a][q]: over the items, then over
+    // the four lane groups, then over the waves.
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int ks = 0; ks < kET; ks += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(PI[lx][ks + lk],
-                                                   Zt[ks + lk][b0 + lx], acc, 0, 0, 0);
+    for (int st = 0; st < kET / 4; ++st)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(zf[st], PJ[lx][4 * st + lk], acc, 0, 0,
+                                                 0);
+    double y = 0.0;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int q = 4 * v + lk;
-        double y = acc[v] * PJ[q][b0 + lx];
-        for (int off = 8; off > 0; off >>= 1) y += __shfl_xor(y, off, 64);
-        if (lx == 0) red[wave][q] = y;
-      }
-    }
+    for (int v = 0; v < 4; ++v) y += acc[v] * PI[lx][16 * wave + 4 * v + lk];
+    y += __shfl_xor(y, 16, 64);
+    y += __shfl_xor(y, 32, 64);
+    if (lk == 0) red[wave][lx] = y;
     __syncthreads();
     if (t < pc)
       part[task_part_off[tk] + q0 + t] =
