@@ -42,9 +42,8 @@ PEAK_HBM_GBS = 8000.0
 # write x1.0).  Taken on the current GEMM kernel; None for other workloads.
 LAUUM_HBM_BYTES_MEDIUM = 19.306e9 + 0.409e9
 # The same for the reported FP64 kernel, the bulk update of the root sweeps
-# (average per launch, outer block 512); None until taken on the current
-# launch shape.
-BULK_HBM_BYTES_MEDIUM = None
+# (average per launch, outer block 512).
+BULK_HBM_BYTES_MEDIUM = 1.2562e9 + 0.3683e9
 
 
 def parse():
@@ -251,8 +250,9 @@ def measure(p, prec, args):
     if bulk_s > 0:
         # the root inverse by block sweeps; reported kernel = the bulk update
         # (one MFMA GEMM per band, FP64, or FP32 in launches of K <= 256 for
-        # mixed precision: lower triangle of the rows outside two bands,
-        # rank = the block; time and flops from the library's timers)
+        # mixed precision: the lower triangle outside the band's rows and
+        # columns and outside the next band's pivot block, rank = the block;
+        # time and flops from the library's timers)
         bulk_flops = i1["flops_sweep_bulk"] - i0["flops_sweep_bulk"]
         launches = sweep_bulk_launches(i1["n_root_padded"], blk)
         if mixed:
@@ -266,7 +266,7 @@ def measure(p, prec, args):
                 "unit": "TFLOP/s", "frac": bulk_flops / bulk_s / 1e12 / peak,
                 "traffic": (BULK_HBM_BYTES_MEDIUM
                             if args.config == 1 and blk == 512 and not mixed
-                            and BULK_HBM_BYTES_MEDIUM is not None else None),
+                            else None),
                 "launches_per_system": launches,
                 "flops_per_launch": bulk_flops / (K * launches),
                 "avg_launch_us": bulk_s * 1e6 / (K * launches)}
