@@ -850,10 +850,11 @@ static hipError_t band_pivot_sweep(Handle& h, hipStream_t st, int k0, int kb) {
   return hipSuccess;
 }
 
-// Tile edges of the band product and of the lookahead update (the bulk
+// Tile edges of the band product and of the next pivot block's update (a
+// 512 x 512 lower triangle: small tiles give it more workgroups; the bulk
 // uses 128).
 constexpr int kBandTile = 64;
-constexpr int kLookTile = 64;
+constexpr int kPivotTile = 32;
 
 static hipError_t band_product(Handle& h, hipStream_t st, int k0, int kb, double* B,
                                const double* V) {
@@ -920,7 +921,7 @@ hipError_t root_sweep(Handle& h) {
       // storage, a small launch ahead of the bulk), then its sweeps on the
       // side stream during the bulk.  Band k is already scattered, so the
       // pivot buffers are free.
-      e = sweep_update(h, h.stream, kLookTile, Bk + k1, np, Vk + k1, np,
+      e = sweep_update(h, h.stream, kPivotTile, Bk + k1, np, Vk + k1, np,
                        h.S + (int64_t)k1 * (ld + 1), ld, kbn, kbn, kb, -1.0, 1.0,
                        false, true);
       if (e != hipSuccess) return e;
@@ -1115,72 +1116,109 @@ hipError_t root_inv_apply(Handle& h, double* z, double* tmp) {
   return hipGetLastError();
 }
 
-// y = Z v for the symmetric root inverse in lower storage (the upper
-// triangle of S holds nothing meaningful), reading Z twice: partial sums of
-// the lower part (j <= r) by row blocks and column chunks, the strictly
-// upper part as column dot products, then the sum of the two.
-__global__ __launch_bounds__(256) void k_symv_lower_part(const double* __restrict__ Z,
-                                                         int64_t ld,
-                                                         const double* __restrict__ v,
-                                                         double* __restrict__ part,
-                                                         int np) {
+// y = Z v with Z symmetric in lower storage, in one pass over the lower
+// triangle.  Workgroup (I, C) stages the 64 x 64 tiles (I, J), J <= I, of
+// column chunk C through LDS one after the other (the next tile's loads in
+// flight during the current one's sums) and forms both products of each
+// tile: the row sums Z_IJ v_J, added up over the chunk into rowpart[C][r],
+// and the column sums Z_IJ^T v_I (strictly below the diagonal) into
+// colpart[I][c].  k_symv_reduce adds the partial sums of each entry in a
+// fixed order.
+constexpr int kSymChunk = 128;  // columns per workgroup of the symmetric product
+
+__global__ __launch_bounds__(256) void k_symv_part(const double* __restrict__ Z,
+                                                   int64_t ld,
+                                                   const double* __restrict__ v,
+                                                   double* __restrict__ rowpart,
+                                                   double* __restrict__ colpart,
+                                                   int np) {
+  __shared__ double T[kNB][kNB + 1];
+  __shared__ double vI[kNB], vJ[kNB];
   __shared__ double red[4][kNB];
   const int I = blockIdx.x, C = blockIdx.y;
-  const int c0 = C * kMvChunk;
-  if (c0 > I * kNB + kNB - 1) return;  // chunk entirely above the diagonal
+  const int J0 = C * (kSymChunk / kNB), J1 = min(I + 1, J0 + kSymChunk / kNB);
+  if (J0 > I) return;  // chunk entirely above the diagonal
   const int t = threadIdx.x, i = t % kNB, g = t / kNB;
-  const int r = I * kNB + i;
-  const int c1 = min(r + 1, min(np, c0 + kMvChunk));
-  double s = 0.0;
-  for (int j = c0 + g; j < c1; j += 4) s += Z[(int64_t)r + (int64_t)j * ld] * v[j];
-  red[g][i] = s;
+  const int64_t r0 = (int64_t)I * kNB;
+  if (t < kNB) vI[t] = v[r0 + t];
+  constexpr int kPer = kNB * kNB / 256;
+  double zr[kPer];
+  auto load = [&](int J) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      zr[q] = Z[(r0 + i) + ((int64_t)J * kNB + g + 4 * q) * ld];
+  };
+  load(J0);
+  double rs = 0.0;
+  for (int J = J0; J < J1; ++J) {
+    __syncthreads();  // the previous tile's sums are done
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) T[i][g + 4 * q] = zr[q];
+    if (t < kNB) vJ[t] = v[(int64_t)J * kNB + t];
+    __syncthreads();
+    if (J + 1 < J1) load(J + 1);
+    const bool diag = J == I;
+    // row i: columns b = g, g + 4, ... (b <= i on the diagonal tile)
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int b = g + 4 * q;
+      if (!diag || b <= i) rs += T[i][b] * vJ[b];
+    }
+    // column j = i: rows a = g, g + 4, ... (a > j on the diagonal tile)
+    double cs = 0.0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int a = g + 4 * q;
+      if (!diag || a > i) cs += T[a][i] * vI[a];
+    }
+    red[g][i] = cs;
+    __syncthreads();
+    if (t < kNB)
+      colpart[(int64_t)I * np + (int64_t)J * kNB + t] =
+          (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+  }
+  __syncthreads();
+  red[g][i] = rs;
   __syncthreads();
   if (t < kNB)
-    part[(int64_t)C * np + I * kNB + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    rowpart[(int64_t)C * np + r0 + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
 
-// u[j] = sum_{i > j} Z[i, j] v[i]: one wave per column.
-__global__ __launch_bounds__(256) void k_symv_upper(const double* __restrict__ Z,
-                                                    int64_t ld,
-                                                    const double* __restrict__ v,
-                                                    double* __restrict__ u, int np) {
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= np) return;
-  const double* col = Z + (int64_t)j * ld;
-  double s = 0.0;
-  for (int i = j + 1 + lane; i < np; i += 64) s += col[i] * v[i];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) u[j] = s;
-}
-
-__global__ void k_symv_reduce(const double* __restrict__ part,
-                              const double* __restrict__ u, double* __restrict__ y,
-                              int np) {
+// y[r] = sum of the row partial sums of r's chunks, then of the column
+// partial sums of the tile rows at or below r's.
+__global__ void k_symv_reduce(const double* __restrict__ rowpart,
+                              const double* __restrict__ colpart,
+                              double* __restrict__ y, int np) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np;
        r += gridDim.x * blockDim.x) {
-    const int last = r / kMvChunk;
-    double s = u[r];
-    for (int C = 0; C <= last; ++C) s += part[(int64_t)C * np + r];
+    const int last = r / kSymChunk, Ir = r / kNB;
+    double s = 0.0;
+    for (int C = 0; C <= last; ++C) s += rowpart[(int64_t)C * np + r];
+    for (int I = Ir; I < np / kNB; ++I) s += colpart[(int64_t)I * np + r];
     y[r] = s;
   }
 }
 
 // z (in/out, length n_pad): z := Z z with the root inverse held in S.
 hipError_t root_sym_apply(Handle& h, double* z, double* tmp) {
+  (void)tmp;
   const int np = (int)h.an.n_pad;
-  const int nch = (np + kMvChunk - 1) / kMvChunk;
-  hipLaunchKernelGGL(k_symv_lower_part, dim3(np / kNB, nch), dim3(256), 0,
-                     h.stream, h.S, (int64_t)np, z, h.vpart, np);
-  hipLaunchKernelGGL(k_symv_upper, dim3((np + 3) / 4), dim3(256), 0, h.stream, h.S,
-                     (int64_t)np, z, tmp, np);
+  const int nch = (np + kSymChunk - 1) / kSymChunk;
+  double* rowpart = h.vpart;
+  double* colpart = h.vpart + (int64_t)nch * np;
+  hipLaunchKernelGGL(k_symv_part, dim3(np / kNB, nch), dim3(256), 0, h.stream, h.S,
+                     (int64_t)np, z, rowpart, colpart, np);
   hipLaunchKernelGGL(k_symv_reduce, dim3((np + 255) / 256), dim3(256), 0, h.stream,
-                     h.vpart, tmp, z, np);
+                     rowpart, colpart, z, np);
   return hipGetLastError();
 }
 
+// the symmetric product's row partial sums (chunks x n_pad) and column
+// partial sums (tile rows x n_pad); the triangular products use fewer
+// (kMvChunk >= kSymChunk)
 int64_t root_inv_part_size(int64_t np) {
-  return ((np + kMvChunk - 1) / kMvChunk) * np;
+  static_assert(kMvChunk >= kSymChunk, "partial-sum buffer sized for the symmetric product");
+  return ((np + kSymChunk - 1) / kSymChunk) * np + (np / kNB) * np;
 }
 
 hipError_t root_trsv_fwd(Handle& h, double* z) {

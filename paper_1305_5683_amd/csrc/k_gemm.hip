@@ -330,6 +330,7 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
   SPI_GEMM_OPS(128, 64)
   SPI_GEMM_OPS(64, 128)
   SPI_GEMM_OPS(64, 64)
+  SPI_GEMM_CASE(32, 32, kXC, kXC)
 #undef SPI_GEMM_OPS
 #undef SPI_GEMM_CASE
   return hipErrorInvalidValue;
