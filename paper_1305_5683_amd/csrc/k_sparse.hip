@@ -175,9 +175,10 @@ hipError_t launch_fill_rowpanels(Handle& h) {
 // The tile's incidences are staged in LDS in chunks, with their panel and
 // index offsets resolved, so a wave's work on an incidence starts with no
 // dependent descriptor loads.  Each wave takes one incidence at a time and
-// computes it in 16 x 16 blocks on the FP64 matrix cores; all loads of a
-// block (indices, kAsmKC panel columns of both operands) are
-// issued together before its MFMAs.  Results are added into the LDS tile
+// computes it in 32 x 32 super-blocks of up to 2 x 2 blocks of 16 x 16 on
+// the FP64 matrix cores; all loads of a super-block (indices, kAsmKC panel
+// columns of both row blocks and both column blocks) are issued together
+// before its MFMAs, and each loaded panel row serves two products.  Results are added into the LDS tile
 // (LDS atomics, since waves work on different incidences); the tile is then
 // written once.
 constexpr int kAsmChunk = 128;  // incidences staged per pass
@@ -245,50 +246,89 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
       const int woff = __builtin_amdgcn_readfirstlane(s_w[q]);
       const int nn = __builtin_amdgcn_readfirstlane(s_n[q]);
       const int nI = nn & 0xffff, nJ = nn >> 16;
-      for (int sa = 0; sa < nI; sa += 16)
-        for (int sb = 0; sb < nJ; sb += 16) {
+      // 32 x 32 super-blocks of up to 2 x 2 blocks of 16 x 16: the panel
+      // rows of both row blocks and both column blocks are loaded once and
+      // shared by the (up to) four products.
+      for (int sa = 0; sa < nI; sa += 32)
+        for (int sb = 0; sb < nJ; sb += 32) {
+          const bool a2 = sa + 16 < nI, b2 = sb + 16 < nJ;  // wave-uniform
           // Addresses are clamped into the incidence (and the panel) and the
           // out-of-range values replaced afterwards, so every load is issued
           // unconditionally and the whole batch is in flight at once.
-          const int a = sa + lx, b = sb + lx;
-          const bool va = a < nI, vb = b < nJ;
-          const int ac = va ? a : nI - 1, bc = vb ? b : nJ - 1;
-          int ra = Ua[ac];
-          int rb[4];
+          int ac[2], bc[2], ra[2], rb[2][4];
+          bool va[2], vb[2];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) rb[v] = Ub[min(sb + 4 * v + lk, nJ - 1)];
-          ra = va ? ra - (int)i0 : -1;
+          for (int x = 0; x < 2; ++x) {
+            const int a = sa + 16 * x + lx, b = sb + 16 * x + lx;
+            va[x] = a < nI;
+            vb[x] = b < nJ;
+            ac[x] = va[x] ? a : nI - 1;
+            bc[x] = vb[x] ? b : nJ - 1;
+          }
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            rb[v] = (sb + 4 * v + lk < nJ) ? rb[v] - (int)j0 : -1;
-          v4d acc = {0.0, 0.0, 0.0, 0.0};
+          for (int x = 0; x < 2; ++x) {
+            const bool use_a = x == 0 || a2, use_b = x == 0 || b2;  // wave-uniform
+            ra[x] = use_a ? Ua[ac[x]] : 0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              rb[x][v] = use_b ? Ub[min(sb + 16 * x + 4 * v + lk, nJ - 1)] : 0;
+          }
+#pragma unroll
+          for (int x = 0; x < 2; ++x) {
+            ra[x] = va[x] ? ra[x] - (int)i0 : -1;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              rb[x][v] = (sb + 16 * x + 4 * v + lk < nJ) ? rb[x][v] - (int)j0 : -1;
+          }
+          v4d acc[2][2];
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
           for (int kc = 0; kc < k; kc += kAsmKC) {
-            double av[kAsmKC / 4], bv[kAsmKC / 4];
+            double av[2][kAsmKC / 4], bv[2][kAsmKC / 4];
 #pragma unroll
             for (int s = 0; s < kAsmKC / 4; ++s) {
               const int qc = min(kc + 4 * s + lk, k - 1);
-              av[s] = Qa[ac + qc * nU];
-              bv[s] = Qb[bc + qc * nU];
+              av[0][s] = Qa[ac[0] + qc * nU];
+              bv[0][s] = Qb[bc[0] + qc * nU];
+              av[1][s] = a2 ? Qa[ac[1] + qc * nU] : 0.0;
+              bv[1][s] = b2 ? Qb[bc[1] + qc * nU] : 0.0;
             }
 #pragma unroll
             for (int s = 0; s < kAsmKC / 4; ++s) {
               const bool vq = kc + 4 * s + lk < k;
-              av[s] = (vq && va) ? (woff < 0 ? -av[s] : av[s]) : 0.0;
-              bv[s] = (vq && vb) ? bv[s] : 0.0;
+#pragma unroll
+              for (int x = 0; x < 2; ++x) {
+                av[x][s] = (vq && va[x]) ? (woff < 0 ? -av[x][s] : av[x][s]) : 0.0;
+                bv[x][s] = (vq && vb[x]) ? bv[x][s] : 0.0;
+              }
             }
-            // lane (lx, lk) item v of the result: row sa + lx, column
-            // sb + 4 v + lk (operand order as in the root GEMM)
-            // (steps past k have zero operands: no guard, no branch)
+            // lane (lx, lk) item v of block (x, y): row sa + 16 x + lx,
+            // column sb + 16 y + 4 v + lk (operand order as in the root
+            // GEMM); steps past k have zero operands
 #pragma unroll
-            for (int s = 0; s < kAsmKC / 4; ++s)
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[s], av[s], acc, 0, 0, 0);
+            for (int s = 0; s < kAsmKC / 4; ++s) {
+              acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[0][s], av[0][s], acc[0][0], 0, 0, 0);
+              if (b2)
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[1][s], av[0][s], acc[0][1], 0, 0, 0);
+              if (a2) {
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[0][s], av[1][s], acc[1][0], 0, 0, 0);
+                if (b2)
+                  acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[1][s], av[1][s], acc[1][1], 0, 0, 0);
+              }
+            }
           }
-          if (ra >= 0) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-              if (rb[v] >= 0 && (I != J || ra >= rb[v]))
-                atomicAdd(&C[ra][rb[v]], acc[v]);
-          }
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+              if ((x == 1 && !a2) || (y == 1 && !b2) || ra[x] < 0) continue;
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                if (rb[y][v] >= 0 && (I != J || ra[x] >= rb[y][v]))
+                  atomicAdd(&C[ra[x]][rb[y][v]], acc[x][y][v]);
+            }
         }
     }
   }
