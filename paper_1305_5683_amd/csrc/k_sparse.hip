@@ -265,13 +265,17 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
             ac[x] = va[x] ? a : nI - 1;
             bc[x] = vb[x] ? b : nJ - 1;
           }
+          {
+            // the 32 root rows and 32 root columns of the super-block: one
+            // load per lane, handed to the lanes that need them by shuffles
+            const int la = min(sa + (lane & 31), nI - 1), lb = min(sb + (lane & 31), nJ - 1);
+            const int ua_l = Ua[la], ub_l = Ub[lb];
 #pragma unroll
-          for (int x = 0; x < 2; ++x) {
-            const bool use_a = x == 0 || a2, use_b = x == 0 || b2;  // wave-uniform
-            ra[x] = use_a ? Ua[ac[x]] : 0;
+            for (int x = 0; x < 2; ++x) {
+              ra[x] = __shfl(ua_l, 16 * x + lx, 64);
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-              rb[x][v] = use_b ? Ub[min(sb + 16 * x + 4 * v + lk, nJ - 1)] : 0;
+              for (int v = 0; v < 4; ++v) rb[x][v] = __shfl(ub_l, 16 * x + 4 * v + lk, 64);
+            }
           }
 #pragma unroll
           for (int x = 0; x < 2; ++x) {
