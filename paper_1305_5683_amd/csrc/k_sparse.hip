@@ -761,7 +761,7 @@ __global__ __launch_bounds__(256, 6) void k_selinv_leaf(
     const int64_t* __restrict__ grp_U_ptr,
     const int32_t* __restrict__ U, const int64_t* __restrict__ grp_col_ptr,
     const int64_t* __restrict__ grp_panel_off, const double* __restrict__ panel,
-    const double* __restrict__ Z, int64_t ld,
+    const double* __restrict__ Z, int64_t ld, const int64_t* __restrict__ grp_task_ptr,
     const int64_t* __restrict__ task_part_off, double* __restrict__ part) {
   __shared__ double PI[kQC][kET + 1];  // padded rows: the MFMA operand reads
   __shared__ double PJ[kQC][kET + 1];  // of 16 different q are conflict-free
@@ -801,6 +801,9 @@ __global__ __launch_bounds__(256, 6) void k_selinv_leaf(
     if (!(a < na && 4 * st + lk < nb)) zf[st] = 0.0;
   const double* Pg = panel + grp_panel_off[g];
   const double fac = (I == J) ? 1.0 : 2.0;
+  // the front's partial sums, pivot-major: [q][task of the front]
+  const int64_t t0g = grp_task_ptr[g], ntg = grp_task_ptr[g + 1] - t0g;
+  double* pg = part + task_part_off[t0g] + (tk - t0g);
   for (int q0 = 0; q0 < p; q0 += kQC) {
     const int pc = min(kQC, p - q0);
     __syncthreads();
@@ -837,27 +840,29 @@ __global__ __launch_bounds__(256, 6) void k_selinv_leaf(
     if (lk == 0) red[wave][lx] = y;
     __syncthreads();
     if (t < pc)
-      part[task_part_off[tk] + q0 + t] =
-          fac * ((red[0][t] + red[1][t]) + (red[2][t] + red[3][t]));
+      pg[(q0 + t) * ntg] = fac * ((red[0][t] + red[1][t]) + (red[2][t] + red[3][t]));
   }
 }
 
-// d[leaf_col_l] = (1 + sum over the front's tasks of the partial sums) / L_ll^2
-__global__ void k_selinv_reduce(const int32_t* __restrict__ leaf_grp,
-                                const int64_t* __restrict__ grp_col_ptr,
-                                const int64_t* __restrict__ grp_task_ptr,
-                                const int64_t* __restrict__ task_part_off,
-                                const double* __restrict__ part,
-                                const double* __restrict__ ldiag,
-                                const int32_t* __restrict__ leaf_cols,
-                                double* __restrict__ d, int64_t n_leaf) {
-  for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < n_leaf;
-       l += (int64_t)gridDim.x * blockDim.x) {
-    const int g = leaf_grp[l];
-    const int64_t q = l - grp_col_ptr[g];
-    double s = 0.0;
-    for (int64_t tk = grp_task_ptr[g]; tk < grp_task_ptr[g + 1]; ++tk)
-      s += part[task_part_off[tk] + q];
+// d[leaf_col_l] = (1 + sum over the front's tasks of the partial sums) / L_ll^2:
+// one wave per pivot, lanes over the front's tasks (contiguous in the
+// pivot-major layout), then a fixed reduction tree.
+__global__ __launch_bounds__(256) void k_selinv_reduce(
+    const int32_t* __restrict__ leaf_grp, const int64_t* __restrict__ grp_col_ptr,
+    const int64_t* __restrict__ grp_task_ptr, const int64_t* __restrict__ task_part_off,
+    const double* __restrict__ part, const double* __restrict__ ldiag,
+    const int32_t* __restrict__ leaf_cols, double* __restrict__ d, int64_t n_leaf) {
+  const int lane = threadIdx.x & 63;
+  const int64_t l = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (l >= n_leaf) return;
+  const int g = leaf_grp[l];
+  const int64_t q = l - grp_col_ptr[g];
+  const int64_t t0g = grp_task_ptr[g], ntg = grp_task_ptr[g + 1] - t0g;
+  const double* pq = part + task_part_off[t0g] + q * ntg;
+  double s = 0.0;
+  for (int64_t t = lane; t < ntg; t += 64) s += pq[t];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) {
     const double L = ldiag[l];
     d[leaf_cols[l]] = (1.0 + s) / (L * L);
   }
@@ -876,10 +881,10 @@ hipError_t launch_selinv_leaves(Handle& h, double* d) {
                          h.stream, h.d.tasks, h.d.sel_order + t0, h.d.grp_U_ptr,
                          h.d.U,
                          h.d.grp_col_ptr, h.d.grp_panel_off, h.panel, h.Zr,
-                         a.n_pad, h.d.task_part_off, h.part);
+                         a.n_pad, h.d.grp_task_ptr, h.d.task_part_off, h.part);
     }
   }
-  hipLaunchKernelGGL(k_selinv_reduce, dim3(grid_for(nl, 256)), dim3(256), 0,
+  hipLaunchKernelGGL(k_selinv_reduce, dim3(wave_grid(nl)), dim3(256), 0,
                      h.stream, h.d.leaf_grp, h.d.grp_col_ptr, h.d.grp_task_ptr,
                      h.d.task_part_off, h.part, h.ldiag, h.d.leaf_cols, d, nl);
   return hipGetLastError();
