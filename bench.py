@@ -249,15 +249,15 @@ def measure(p, prec, args):
     bulk_s = (i1["t_sweep_bulk_ms"] - i0["t_sweep_bulk_ms"]) / 1e3
     if bulk_s > 0:
         # the root inverse by block sweeps; reported kernel = the bulk update
-        # (one MFMA GEMM per band, FP64, or FP32 in launches of K <= 256 for
-        # mixed precision: the lower triangle outside the band's rows and
-        # columns and outside the next band's pivot block, rank = the block;
-        # time and flops from the library's timers)
+        # (one MFMA GEMM per band, FP64, or FP32 for mixed precision with
+        # binary32 sums of at most 256 terms added in FP64: the lower
+        # triangle outside the band's rows and columns and outside the next
+        # band's pivot block, rank = the block; time and flops from the
+        # library's timers)
         bulk_flops = i1["flops_sweep_bulk"] - i0["flops_sweep_bulk"]
         launches = sweep_bulk_launches(i1["n_root_padded"], blk)
         if mixed:
             peak = PEAK_FP32_TFLOPS
-            launches *= max(1, min(blk, 512) // 256)
         roof = {"bound": "mfma",
                 "kernel": ("k_gemm<128,128,XC,XC,float> (root sweep bulk update)"
                            if mixed else

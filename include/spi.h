@@ -66,8 +66,8 @@ enum spi_precision {
                            and lookahead updates of the block sweeps, or
                            with root_inverse = 0 the Cholesky and factor
                            inversion products) on the binary32 matrix
-                           cores: each launch sums at most 256 terms in
-                           binary32 and launches add up in binary64;
+                           cores: every binary32 sum runs over at most 256
+                           terms and such sums add up in binary64;
                            binary64 storage, pivot blocks, band products,
                            leaf fronts, refinement residuals and the leaf
                            selected-inversion sums */

@@ -563,17 +563,17 @@ hipError_t root_lauum(Handle& h) {
 // not positive is reported at the same elimination index.
 //
 // A step gathers the band of K (all np rows of columns K, the rows above K
-// taken from row block K of the lower storage) into a column-major buffer V
-// and its pivot block D into a kb x kb buffer, sweeps D alone in kNB steps
-// (one launch each, ping-pong between two buffers) to get -D^-1, forms
-// B = V D^-1 outside K in one product, and writes B (and -D^-1 on K) back.
-// The bulk is then M_ij -= B_i V_j^T over rows and columns outside K.  With
-// a one-band lookahead only the next band's pivot block is brought up to
-// date first: on the side stream it is updated, gathered and swept (a chain
-// of small launches) while the main stream's bulk updates everything else,
-// the rest of the next band included; the next band's columns are gathered
-// after the bulk.  The last bulk and the last band are written negated, so
-// S ends holding +A_RR^-1.
+// taken from row block K of the lower storage) into a column-major buffer V,
+// sweeps its pivot block D alone in kNB steps (one launch each; the first
+// reads D from the lower storage, then they ping-pong between two kb x kb
+// buffers) to get -D^-1, forms B = V D^-1 outside K in one product, and
+// writes B (and -D^-1 on K) back.  The bulk is then M_ij -= B_i V_j^T over
+// rows and columns outside K.  With a one-band lookahead only the next
+// band's pivot block is brought up to date first (a small launch); its
+// sweep steps then run on the side stream while the main stream's bulk
+// updates everything else, the rest of the next band included, and the
+// next band's columns are gathered after the bulk.  The last bulk and the
+// last band are written negated, so S ends holding +A_RR^-1.
 
 // Band [k0, k0 + kb) of the symmetric matrix in lower storage S (leading
 // dimension ld) <-> column-major np x kb buffers; 64 x 64 tiles through LDS,
@@ -874,15 +874,19 @@ static hipError_t band_scatter(Handle& h, hipStream_t st, int k0, int kb,
 }
 
 // C = beta C + alpha A B^T for the sweep updates (A, B: kXC, column-major
-// band buffers).  Mixed precision: binary32 matrix-core products, K split
-// into launches of at most kNBO terms, so every binary32 accumulation sums
-// at most kNBO products and the launches add up in binary64.
+// band buffers).  Mixed precision: binary32 matrix-core products in sums of
+// at most kNBO terms that add up in binary64: a band of up to 2 kNBO in one
+// launch (two binary32 sums per tile, added in the epilogue), wider ones in
+// launches of kNBO.
 static hipError_t sweep_update(Handle& h, hipStream_t st, int bm, const double* A,
                                int64_t lda, const double* B, int64_t ldb, double* C,
                                int64_t ldc, int M, int N, int K, double alpha,
                                double beta, bool lower, bool diag_mask,
                                GemmSkip skip = GemmSkip()) {
   const bool f32 = h.opts.precision == SPI_MIXED;
+  if (f32 && K <= 2 * kNBO)
+    return gemm(st, bm, bm, kXC, kXC, A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, lower,
+                false, diag_mask, true, 0, skip, K > kNBO ? kNBO : 0);
   const int kc = f32 ? kNBO : K;
   for (int k0 = 0; k0 < K; k0 += kc) {
     const int kk = std::min(kc, K - k0);
@@ -1200,8 +1204,7 @@ __global__ void k_symv_reduce(const double* __restrict__ rowpart,
 }
 
 // z (in/out, length n_pad): z := Z z with the root inverse held in S.
-hipError_t root_sym_apply(Handle& h, double* z, double* tmp) {
-  (void)tmp;
+hipError_t root_sym_apply(Handle& h, double* z) {
   const int np = (int)h.an.n_pad;
   const int nch = (np + kSymChunk - 1) / kSymChunk;
   double* rowpart = h.vpart;

@@ -71,6 +71,8 @@ struct GemmArgs {
   int kmask;  // kGemmKStartCol / kGemmKEndRow: triangular operands
   int tiles_m, tiles_n, n_tiles;
   GemmSkip skip;
+  int ksplit;  // binary32: the products of k < ksplit and of k >= ksplit are
+               // summed apart and added in binary64 (K <= 2 ksplit)
 };
 
 // Logical tile t -> (I, J).  Tiles are visited in groups of kGroup tile
@@ -196,11 +198,19 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   };
 
   typedef typename Acc<T>::type VA;
+  constexpr bool kF32 = sizeof(T) == 4;
   VA acc[MI][NI];
+  VA acc0[kF32 ? MI : 1][kF32 ? NI : 1];  // binary32: sums of k < ksplit
 #pragma unroll
   for (int a = 0; a < MI; ++a)
 #pragma unroll
     for (int b = 0; b < NI; ++b) acc[a][b] = VA{0, 0, 0, 0};
+  if constexpr (kF32) {
+#pragma unroll
+    for (int a = 0; a < MI; ++a)
+#pragma unroll
+      for (int b = 0; b < NI; ++b) acc0[a][b] = VA{0, 0, 0, 0};
+  }
 
   const double* pa = first(g.A, g.lda, i0, OPA, BM, EA);
   const double* pb = first(g.B, g.ldb, j0, OPB, BN, EB);
@@ -225,6 +235,17 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   const int lx = lane & 15, lk = lane >> 4;
   int buf = 0;
   for (int k0 = kbeg; k0 < kend; k0 += kKT) {
+    if constexpr (kF32) {
+      if (k0 == g.ksplit && k0 != 0) {  // start of the second binary32 sum
+#pragma unroll
+        for (int a = 0; a < MI; ++a)
+#pragma unroll
+          for (int b = 0; b < NI; ++b) {
+            acc0[a][b] = acc[a][b];
+            acc[a][b] = VA{0, 0, 0, 0};
+          }
+      }
+    }
     __syncthreads();  // slab k0 complete in buf; buf ^ 1 no longer read
     const T* Ab = As[buf];
     const T* Bb = Bs[buf];
@@ -289,7 +310,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
       for (int v = 0; v < 4; ++v) {
         const int j = j0 + wn * WN + b * 16 +
                       (sizeof(T) == 8 ? v * 4 + lk : lk * 4 + v);
-        double r = g.alpha * (double)acc[a][b][v];
+        double r;
+        if constexpr (kF32)
+          r = g.alpha * ((double)acc0[a][b][v] + (double)acc[a][b][v]);
+        else
+          r = g.alpha * (double)acc[a][b][v];
         if (g.beta != 0.0) r = fma(g.beta, cv[b][v], r);
         if (!(mask_tile && i < j)) g.C[(int64_t)i + (int64_t)j * g.ldc] = r;
       }
@@ -312,12 +337,14 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 const double* A, int64_t lda, const double* B, int64_t ldb,
                 double* C, int64_t ldc, int M, int N, int K, double alpha,
                 double beta, bool lower, bool kstart_diag, bool diag_mask,
-                bool f32, int kmask, GemmSkip skip) {
+                bool f32, int kmask, GemmSkip skip, int ksplit) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (M % bm || N % bn || K % kKT || (lower && (bm != bn || M != N)))
     return hipErrorInvalidValue;
+  if (ksplit < 0 || ksplit % kKT || (ksplit && (!f32 || K > 2 * ksplit)))
+    return hipErrorInvalidValue;
   GemmArgs a{A, B, C, lda, ldb, ldc, M, N, K, alpha, beta, lower ? 1 : 0,
-             kstart_diag ? 1 : 0, diag_mask ? 1 : 0, kmask, 0, 0, 0, skip};
+             kstart_diag ? 1 : 0, diag_mask ? 1 : 0, kmask, 0, 0, 0, skip, ksplit};
 #define SPI_GEMM_CASE(BM_, BN_, OA, OB)                                   \
   if (bm == BM_ && bn == BN_ && opA == OA && opB == OB)                  \
     return f32 ? gemm_t<BM_, BN_, OA, OB, float>(s, a)                   \

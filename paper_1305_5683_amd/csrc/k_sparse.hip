@@ -716,7 +716,7 @@ hipError_t launch_solve_pass(Handle& h, const double* b, double* x) {
                        h.d.rinc_u, h.d.grp_U_ptr, h.vfront, h.vroot, a.n_root,
                        a.n_pad);
     if (h.swept) {
-      if ((e = root_sym_apply(h, h.vroot, h.vroot2)) != hipSuccess) return e;
+      if ((e = root_sym_apply(h, h.vroot)) != hipSuccess) return e;
     } else if (h.have_inv) {
       if ((e = root_inv_apply(h, h.vroot, h.vroot2)) != hipSuccess) return e;
     } else {

@@ -290,7 +290,7 @@ hipError_t root_sweep(Handle& h);
 // phase timing (opts.timing): event pairs on the handle's stream
 void phase_begin(Handle& h, Phase p);
 void phase_end(Handle& h, Phase p);
-hipError_t root_sym_apply(Handle& h, double* z, double* tmp);
+hipError_t root_sym_apply(Handle& h, double* z);
 hipError_t root_lauum(Handle& h);
 hipError_t launch_solve_pass(Handle& h, const double* b, double* x);
 hipError_t launch_residual_dd(Handle& h, const double* b, const double* x,
@@ -318,7 +318,7 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 double* C, int64_t ldc, int M, int N, int K, double alpha,
                 double beta, bool lower, bool kstart_diag,
                 bool diag_mask = false, bool f32 = false,
-                int kmask = 0, GemmSkip skip = GemmSkip());
+                int kmask = 0, GemmSkip skip = GemmSkip(), int ksplit = 0);
 
 // learned preconditioner and PCG (k_learned.hip)
 int64_t lp_param_count(int hidden);
