@@ -117,7 +117,7 @@ __device__ inline void tile_of(const GemmArgs& g, int t, int& I, int& J) {
   I = J + local;
 }
 
-template <int BM, int BN, int OPA, int OPB, typename T>
+template <int BM, int BN, int OPA, int OPB, typename T, bool SPLIT>
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int MI = WM / 16, NI = WN / 16;
@@ -198,7 +198,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   };
 
   typedef typename Acc<T>::type VA;
-  constexpr bool kF32 = sizeof(T) == 4;
+  // SPLIT (binary32 only): the sums of k < ksplit and k >= ksplit are kept
+  // apart and added in binary64 (an instantiation of its own, since the
+  // second accumulator set costs registers)
+  constexpr bool kF32 = SPLIT && sizeof(T) == 4;
   VA acc[MI][NI];
   VA acc0[kF32 ? MI : 1][kF32 ? NI : 1];  // binary32: sums of k < ksplit
 #pragma unroll
@@ -321,14 +324,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   }
 }
 
-template <int BM, int BN, int OPA, int OPB, typename T>
+template <int BM, int BN, int OPA, int OPB, typename T, bool SPLIT = false>
 static hipError_t gemm_t(hipStream_t s, const GemmArgs& a0) {
   GemmArgs a = a0;
   a.tiles_m = a.M / BM;
   a.tiles_n = a.N / BN;
   a.n_tiles = a.lower ? a.tiles_m * (a.tiles_m + 1) / 2 : a.tiles_m * a.tiles_n;
   if (a.n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm<BM, BN, OPA, OPB, T>), dim3(a.n_tiles), dim3(256), 0,
+  hipLaunchKernelGGL((k_gemm<BM, BN, OPA, OPB, T, SPLIT>), dim3(a.n_tiles), dim3(256), 0,
                      s, a);
   return hipGetLastError();
 }
@@ -345,6 +348,13 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
     return hipErrorInvalidValue;
   GemmArgs a{A, B, C, lda, ldb, ldc, M, N, K, alpha, beta, lower ? 1 : 0,
              kstart_diag ? 1 : 0, diag_mask ? 1 : 0, kmask, 0, 0, 0, skip, ksplit};
+  if (ksplit) {  // the shapes of the sweep updates
+    if (bm == 128 && bn == 128 && opA == kXC && opB == kXC)
+      return gemm_t<128, 128, kXC, kXC, float, true>(s, a);
+    if (bm == 32 && bn == 32 && opA == kXC && opB == kXC)
+      return gemm_t<32, 32, kXC, kXC, float, true>(s, a);
+    return hipErrorInvalidValue;
+  }
 #define SPI_GEMM_CASE(BM_, BN_, OA, OB)                                   \
   if (bm == BM_ && bn == BN_ && opA == OA && opB == OB)                  \
     return f32 ? gemm_t<BM_, BN_, OA, OB, float>(s, a)                   \
