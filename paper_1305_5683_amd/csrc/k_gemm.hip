@@ -26,8 +26,11 @@
 // triangular with zeros stored above the diagonal).  `diag_mask`: C's
 // origin lies on the matrix diagonal and only its lower part (i >= j) is
 // written; tiles entirely above the diagonal do nothing.  `skip`: tiles
-// whose rows meet [r0, r1) or whose columns meet [c0, c1) do nothing (the
-// bands that other work owns at the same time).
+// whose rows meet [r0, r1), whose columns meet [c0, c1), or whose rows and
+// columns both meet [s0, s1) do nothing (the parts that other work owns at
+// the same time).  `ksplit` (binary32 only, a kernel instantiation of its
+// own): the products of k < ksplit and of k >= ksplit are summed apart in
+// binary32 and added in binary64 in the epilogue.
 #include <hip/hip_runtime.h>
 
 #include "spi_internal.h"
