@@ -625,7 +625,7 @@ __global__ void k_fwd_leaf(const double* __restrict__ b,
 }
 
 // Forward substitution's update of the root, z_R = b_R - sum_g L_Ug y_g, in
-// two deterministic passes.  (1) One wave per leaf front: t_g = L_Ug y_g,
+// two deterministic passes.  (1) One workgroup per leaf front: t_g = L_Ug y_g,
 // reading the column-major panel along U (coalesced).  (2) One wave per root
 // unknown i: z_i = b_i - sum of t_g[u] over the (front, position) pairs
 // that contain i, in a fixed order.
@@ -634,6 +634,7 @@ __global__ __launch_bounds__(256) void k_fwd_front(
     const int64_t* __restrict__ grp_panel_off, const double* __restrict__ panel,
     const double* __restrict__ vleaf, double* __restrict__ t, int64_t n_groups) {
   const int64_t g = blockIdx.x;  // one workgroup per front
+  if (g >= n_groups) return;
   const int64_t u0 = grp_U_ptr[g], nU = grp_U_ptr[g + 1] - u0;
   const int64_t c0 = grp_col_ptr[g];
   const int p = (int)(grp_col_ptr[g + 1] - c0);
