@@ -399,6 +399,20 @@ def test_sweep_bulk_timers_count_the_bulk_flops():
 
 
 @pytest.mark.parametrize("block", [128, 256, 512])
+def test_mixed_sweeps_over_several_bands(block):
+    """Mixed precision on a dense root of order 700 (padded 768) with 6, 3 or
+    2 bands: bands of 128 and 256 take one binary32 sum per launch, bands of
+    512 two sums of 256 terms added in binary64 (the split kernel), for the
+    bulk and for the next pivot block's update alike."""
+    p = synth.make_random(2100, 700, 14, seed=77)
+    o = oracle_solve(p)
+    _say(f"case mixed sweeps block={block}")
+    g = _run_blocks(p, block, leaf_max_work=0.0, precision=1)
+    assert g["info"]["n_root"] == 700 and g["info"]["precision"] == 1
+    _check(p, g, o, tol_x=TOL_X_MIXED, tol_d=TOL_D_MIXED)
+
+
+@pytest.mark.parametrize("block", [128, 256, 512])
 def test_root_sweeps_over_several_bands(block):
     """Dense root of order 700 (padded 768): 6, 3 or 2 bands, so the
     lookahead band update, the bulk outside both bands and the negated last
