@@ -77,14 +77,19 @@ hipError_t launch_gather_values(Handle& h) {
 // One wave per leaf unknown l (front g, position q): accumulate
 // A_ll = sum_r w_r h_rl^2 and the panel column A_Ug,l = sum_r w_r h_rl h_rU
 // over the rows of l (sequentially, lanes over a row's entries, which have
-// distinct positions), then L_ll = sqrt(A_ll) and the column / L_ll.
+// distinct positions), then L_ll = sqrt(A_ll) and the column / L_ll.  With
+// kLds the column is accumulated in a wave-private LDS buffer of `cap`
+// entries (dynamic LDS, cap >= |U| of every front) and written once;
+// otherwise in place in the panel.
+template <bool kLds>
 __global__ __launch_bounds__(256) void k_leaf_assemble(
     const int32_t* __restrict__ leaf_grp, const int64_t* __restrict__ leaf_slot_ptr,
     const int64_t* __restrict__ grp_col_ptr, const int64_t* __restrict__ grp_U_ptr,
     const int64_t* __restrict__ grp_panel_off, const int64_t* __restrict__ slot_rr_ptr,
     const int32_t* __restrict__ rr_lpos, const double* __restrict__ rrval,
     const double* __restrict__ sw, const double* __restrict__ sleaf,
-    double* panel, double* __restrict__ ldiag, int64_t* fail, int64_t n_leaf) {
+    double* panel, double* __restrict__ ldiag, int64_t* fail, int64_t n_leaf, int cap) {
+  extern __shared__ double lbuf[];
   const int lane = threadIdx.x & 63;
   const int64_t l = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (l >= n_leaf) return;
@@ -92,14 +97,15 @@ __global__ __launch_bounds__(256) void k_leaf_assemble(
   const int64_t q = l - grp_col_ptr[g];
   const int64_t nU = grp_U_ptr[g + 1] - grp_U_ptr[g];
   double* P = panel + grp_panel_off[g] + q * nU;
-  for (int64_t u = lane; u < nU; u += 64) P[u] = 0.0;
+  double* acc = kLds ? lbuf + (int64_t)(threadIdx.x >> 6) * cap : P;
+  for (int64_t u = lane; u < nU; u += 64) acc[u] = 0.0;
   __threadfence_block();
   double d = 0.0;
   for (int64_t s = leaf_slot_ptr[l]; s < leaf_slot_ptr[l + 1]; ++s) {
     const double t = sw[s] * sleaf[s];
     d += t * sleaf[s];
     for (int64_t k = slot_rr_ptr[s] + lane; k < slot_rr_ptr[s + 1]; k += 64)
-      P[rr_lpos[k]] += t * rrval[k];
+      acc[rr_lpos[k]] += t * rrval[k];
     __threadfence_block();
   }
   bool bad = !(d > 0.0) || !isfinite(d);
@@ -109,18 +115,33 @@ __global__ __launch_bounds__(256) void k_leaf_assemble(
     if (bad) atomicMin((unsigned long long*)fail, (unsigned long long)l);
   }
   const double inv = 1.0 / lll;
-  for (int64_t u = lane; u < nU; u += 64) P[u] *= inv;
+  for (int64_t u = lane; u < nU; u += 64) P[u] = acc[u] * inv;
 }
+
+// LDS per wave of the accumulating variant, at most (4 waves per workgroup)
+constexpr int kLeafLdsCap = 2048;
 
 hipError_t launch_leaf_assemble(Handle& h) {
   const Analysis& a = h.an;
   const int64_t nl = (int64_t)a.leaf_cols.size();
   if (!nl) return hipSuccess;
-  hipLaunchKernelGGL(k_leaf_assemble, dim3(wave_grid(nl)), dim3(256), 0,
-                     h.stream, h.d.leaf_grp, h.d.leaf_slot_ptr, h.d.grp_col_ptr,
-                     h.d.grp_U_ptr, h.d.grp_panel_off, h.d.slot_rr_ptr,
-                     h.d.rr_lpos, h.rrval, h.sw, h.sleaf, h.panel, h.ldiag,
-                     h.flag, nl);
+  int64_t max_u = 1;
+  for (int64_t g = 0; g < a.n_groups; ++g)
+    max_u = std::max<int64_t>(max_u, a.grp_U_ptr[g + 1] - a.grp_U_ptr[g]);
+  if (max_u <= kLeafLdsCap) {
+    const int cap = (int)max_u;
+    hipLaunchKernelGGL(k_leaf_assemble<true>, dim3(wave_grid(nl)), dim3(256),
+                       4 * (size_t)cap * sizeof(double), h.stream, h.d.leaf_grp,
+                       h.d.leaf_slot_ptr, h.d.grp_col_ptr, h.d.grp_U_ptr,
+                       h.d.grp_panel_off, h.d.slot_rr_ptr, h.d.rr_lpos, h.rrval, h.sw,
+                       h.sleaf, h.panel, h.ldiag, h.flag, nl, cap);
+  } else {
+    hipLaunchKernelGGL(k_leaf_assemble<false>, dim3(wave_grid(nl)), dim3(256), 0,
+                       h.stream, h.d.leaf_grp, h.d.leaf_slot_ptr, h.d.grp_col_ptr,
+                       h.d.grp_U_ptr, h.d.grp_panel_off, h.d.slot_rr_ptr,
+                       h.d.rr_lpos, h.rrval, h.sw, h.sleaf, h.panel, h.ldiag,
+                       h.flag, nl, 0);
+  }
   return hipGetLastError();
 }
 
