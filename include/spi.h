@@ -104,12 +104,15 @@ typedef struct spi_opts {
                                SPI_MIXED in range; 0: no scaling.  Default 1 */
     double refine_tol;      /* > 0: spi_solve stops refining once the
                                max-norm of the correction is <= refine_tol
-                               times the max-norm of x (reading the norms
-                               back synchronises the stream after each step)
-                               and returns SPI_E_NOCONV if refine_steps steps
-                               do not get there; 0: exactly refine_steps
-                               steps.  Default 0; SPI_MIXED uses 1e-14 and at
-                               least 10 steps when this is 0 */
+                               times the max-norm of x, or once the last two
+                               corrections contract (by at least half) at a
+                               rate that puts the next one below that
+                               (reading the norms back synchronises the
+                               stream after each step), and returns
+                               SPI_E_NOCONV if refine_steps steps do not get
+                               there; 0: exactly refine_steps steps.
+                               Default 0; SPI_MIXED uses 1e-14 and at least
+                               10 steps when this is 0 */
     int32_t keep_root_order;/* 0: the analysis numbers the root unknowns
                                for locality (columns that share many rows
                                end up in the same 64-column tiles, so fewer

@@ -439,6 +439,7 @@ int spi_solve(spi_handle* H, const double* b, double* x, int32_t nrhs,
     SPI_CK(launch_solve_pass(h, src, dst), "solve");
     bool converged = tol <= 0.0;
     int done = 0;
+    double prev = 0.0;  // relative size of the previous correction
     for (int s = 0; s < h.opts.refine_steps; ++s) {
       SPI_CK(launch_residual_dd(h, src, dst, h.vres), "residual");
       SPI_CK(launch_solve_pass(h, h.vres, h.vx), "correction");
@@ -450,10 +451,16 @@ int spi_solve(spi_handle* H, const double* b, double* x, int32_t nrhs,
         SPI_CK(hipMemcpyAsync(nv, h.vnorm, sizeof(nv), hipMemcpyDeviceToHost,
                               h.stream), "norm readback");
         SPI_CK(hipStreamSynchronize(h.stream), "refinement");
-        if (nv[0] <= tol * nv[1]) {
+        // Converged once the correction is below tol, or once two
+        // corrections contract (by at least half) at a rate that puts the
+        // next one, i.e. the error left in x, below tol.
+        const double cur = nv[1] > 0.0 ? nv[0] / nv[1] : 0.0;
+        const bool contracting = prev > 0.0 && cur <= 0.5 * prev;
+        if (cur <= tol || (contracting && cur * (cur / prev) <= tol)) {
           converged = true;
           break;
         }
+        prev = cur;
       }
     }
     if (eq) SPI_CK(launch_scale_vec(h, h.vxh, xc, 0), "scale solution");
