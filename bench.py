@@ -43,7 +43,7 @@ PEAK_HBM_GBS = 8000.0
 LAUUM_HBM_BYTES_MEDIUM = 19.306e9 + 0.409e9
 # The same for the reported FP64 kernel, the bulk update of the root sweeps
 # (average per launch, outer block 512).
-BULK_HBM_BYTES_MEDIUM = 1.2549e9 + 0.3683e9
+BULK_HBM_BYTES_MEDIUM = 1.2546e9 + 0.3683e9
 
 
 def parse():
