@@ -100,7 +100,3 @@ class BlockCholesky:
             del E
         return out
 
-    def nnz_L(self):
-        ns = self.n - self.n_b
-        lbb = self.n_b if self.bb_diagonal else np.count_nonzero(np.tril(self.Lbb))
-        return int(lbb + self.Lsb.nnz + ns * (ns + 1) // 2)

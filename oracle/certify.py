@@ -48,12 +48,15 @@ def apply_normal_ld(rowptr, col, val, w, z):
     return r
 
 
-def refine_solution(prob, solve, x0, steps: int = 3):
-    """Refine ``x`` for ``H^T W H x = H^T W y``; ``solve`` is a float64 solver."""
+def refine_solution(prob, solve, x0, steps: int = 3, residual=None):
+    """Refine ``x`` for ``H^T W H x = H^T W y``; ``solve`` is a float64 solver.
+
+    ``residual`` (default :func:`normal_residual_ld`) takes the arguments of
+    that function; the pins substitute deliberately wrong variants of it."""
+    res = normal_residual_ld if residual is None else residual
     x = np.asarray(x0).astype(LD)
     for _ in range(steps):
-        r = normal_residual_ld(prob.rowptr, prob.col, prob.val, prob.w,
-                               prob.y, x)
+        r = res(prob.rowptr, prob.col, prob.val, prob.w, prob.y, x)
         x = x + np.asarray(solve(r.astype(np.float64))).astype(LD)
     return x
 

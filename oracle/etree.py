@@ -115,13 +115,3 @@ def is_postorder(order, parent):
             return False
     return True
 
-
-def pruned_paths(parent, i, j):
-    """Nodes visited to compute (A^-1)_ij with pruning (Sect. 3.3.1).
-
-    Returns (forward, backward): the forward solve L z = e_j touches j and its
-    ancestors (bottom-up); the backward solve touches the root down to i.
-    """
-    fwd = [j] + ancestors(parent, j)
-    bwd = list(reversed([i] + ancestors(parent, i)))
-    return fwd, bwd

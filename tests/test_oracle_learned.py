@@ -137,3 +137,21 @@ def test_pcg_reference():
     Ari = np.linalg.inv(Ar)
     xs, it = L.pcg(A, rhs, lambda r: Ari @ r, 1e-12, 200)
     assert it > 1 and np.linalg.norm(xs - x) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_features_hand_worked_fixture():
+    """Features against a hand-worked fixture; a mean over all unknowns in
+    place of the per-kind mean f2 fails it."""
+    import os
+    fx = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "lp_features_6.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, *v = line.split()
+                fx[k] = np.array([float(x) for x in v])
+    phi = L.features(fx["diag_band"], fx["diag_ref"], fx["is_root"])
+    assert phi.shape == (6, 3)
+    for c, key in enumerate(("f0", "f1", "f2")):
+        assert np.allclose(phi[:, c], fx[key], rtol=1e-15, atol=1e-15), key
+    assert not np.allclose(np.full(6, phi[:, 0].mean()), fx["f2"], rtol=1e-6)

@@ -18,7 +18,8 @@ from oracle import (normal_equations, normal_equations_bruteforce, cholesky,
                     inverse_from_cholesky, diag_inv_colnorms,
                     selected_entry_pruned, BlockCholesky, oracle_solve)
 from oracle import etree as et
-from oracle.certify import normal_residual_ld, refine_inverse_column
+from oracle.certify import (normal_residual_ld, refine_inverse_column,
+                            refine_solution, LD)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -318,6 +319,63 @@ def test_certified_solution_and_inverse_column(tiny):
     for j, dj in zip(out["diag_idx"], out["diag"]):
         zc = refine_inverse_column(p, f.solve, int(j))
         assert abs(float(zc[j]) - dj) <= 1e-13 * dj
+
+
+def _exact_lsq(p):
+    """Exact rational solution of H^T W H x = H^T W y for integer H, W, y."""
+    H = p.scipy_csr().toarray()
+    A = H.T @ (p.w[:, None] * H)            # integers: exact in binary64
+    b = H.T @ (p.w * p.y)
+    assert np.array_equal(A, np.round(A)) and np.array_equal(b, np.round(b))
+    Zx = _exact_inverse(A)
+    bx = [Fraction(int(v)) for v in b]
+    n = len(bx)
+    return A, b, [sum(Zx[i][k] * bx[k] for k in range(n)) for i in range(n)]
+
+
+def _rel_err_exact(x, xe):
+    """max_i |x_i - xe_i| / max_i |xe_i| in exact arithmetic."""
+    num = max(abs(Fraction(*LD(v).as_integer_ratio()) - e) for v, e in zip(x, xe))
+    return float(num / max(abs(e) for e in xe))
+
+
+def _residual_sign_flip(rowptr, col, val, w, y, x):
+    """Planted mistake: H^T W (y + H x) instead of H^T W (y - H x)."""
+    return normal_residual_ld(rowptr, col, val, w, y, -np.asarray(x, dtype=LD))
+
+
+def _residual_wrong_row(rowptr, col, val, w, y, x):
+    """Planted mistake: the weights and data of the next row (shifted index)."""
+    return normal_residual_ld(rowptr, col, val, np.roll(w, 1), np.roll(y, 1), x)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_refined_solution_matches_exact_rational(seed):
+    """The long-double refinement that certifies every reference x reaches
+    the exact rational solution of an integer problem far below binary64
+    resolution; a residual with a sign error or a shifted row index, fed to
+    the same refinement, misses it."""
+    p = synth.make_random(30, 10, 4, seed=seed, integer=True)
+    A, b, xe = _exact_lsq(p)
+    solve = lambda r: np.linalg.solve(A, r)        # binary64 LAPACK solve
+    x0 = solve(b)
+    assert _rel_err_exact(x0, xe) > 1e-17          # binary64 alone is not exact
+    x = refine_solution(p, solve, x0, steps=3)
+    assert x.dtype == LD
+    assert _rel_err_exact(x, xe) <= 1e-18
+    for bad in (_residual_sign_flip, _residual_wrong_row):
+        xb = refine_solution(p, solve, x0, steps=3, residual=bad)
+        assert _rel_err_exact(xb, xe) > 1e-6, bad.__name__
+
+
+def test_refined_solution_agrees_with_block_solve(tiny):
+    """On the tiny workload the certified x equals the block factor's plain
+    binary64 solution to within that solution's own rounding."""
+    p, A, b = tiny
+    f = BlockCholesky(A, p.n_bg)
+    xb = f.solve(b)
+    xr = refine_solution(p, f.solve, xb, steps=2).astype(np.float64)
+    assert np.linalg.norm(xr - xb) / np.linalg.norm(xr) <= 1e-13
 
 
 def test_pulls_have_unit_scale():
