@@ -15,6 +15,10 @@ Cholesky factor of the Schur complement ``S = A_ss - L_sb L_sb^T``.
 
 Solution (Sect. 3.2.3): forward ``z = L^-1 b`` then backward ``x = L^-T z``.
 
+The product ``L_sb L_sb^T`` is taken with a sparse product, or with a dense
+BLAS product of the same formula when ``L_sb`` is more than 10% dense (wide
+fields of view: the sparse product is then about 100 times slower).
+
 Variances (Sect. 2.4.1) ``(A^-1)_ii = ||L^-1 e_i||^2`` (the left-looking
 formula of Sect. 4.3 with D = I).  Column i of ``L^-1`` is
 ``[u; -L_ss^-1 L_sb u]`` with ``u = L_bb^-1 e_i`` for a background unknown
@@ -29,6 +33,9 @@ import scipy.sparse as sp
 
 
 class BlockCholesky:
+    # L_sb is kept dense above this fraction of structural non-zeros
+    DENSE_FRACTION = 0.1
+
     def __init__(self, A, n_b: int):
         A = sp.csr_matrix(A)
         n = A.shape[0]
@@ -47,13 +54,17 @@ class BlockCholesky:
                 raise ValueError("background block not positive definite")
             self.Lbb = np.sqrt(d)                       # diagonal factor
             self.Lsb = (Asb @ sp.diags(1.0 / self.Lbb)).tocsr()
+            if self.Lsb.nnz > self.DENSE_FRACTION * max(
+                    1, self.Lsb.shape[0] * self.Lsb.shape[1]):
+                self.Lsb = self.Lsb.toarray()           # dense products below
         else:
             self.Lbb = np.linalg.cholesky(Abb.toarray())
             self.Lsb = sp.csr_matrix(
                 sla.solve_triangular(self.Lbb, Asb.toarray().T, lower=True).T)
         S = Ass.toarray()
         if n_b:
-            S -= (self.Lsb @ self.Lsb.T).toarray()
+            LLt = self.Lsb @ self.Lsb.T
+            S -= LLt.toarray() if sp.issparse(LLt) else LLt
         self.Lss = np.linalg.cholesky(S)
 
     # -- triangular solves with the block factor ------------------------------
@@ -94,7 +105,11 @@ class BlockCholesky:
             E = np.zeros((self.n, len(sel)))
             E[sel, np.arange(len(sel))] = 1.0
             U = self._lbb_solve(E[:nb])                    # L_bb^-1 part
-            V = sla.solve_triangular(self.Lss, E[nb:] - self.Lsb @ U,
+            # L_sb U with U taken as sparse when L_sb is (U has at most one
+            # non-zero per column on the diagonal branch)
+            LU = self.Lsb @ (sp.csc_matrix(U) if sp.issparse(self.Lsb) else U)
+            LU = LU.toarray() if sp.issparse(LU) else LU
+            V = sla.solve_triangular(self.Lss, E[nb:] - LU,
                                      lower=True)          # L_ss^-1 part
             out[k0:k0 + block] = (U * U).sum(axis=0) + (V * V).sum(axis=0)
             del E

@@ -299,6 +299,23 @@ def test_block_factor_matches_dense_and_invariants(tiny):
     assert np.max(np.abs(d_b - np.diag(Z)) / np.diag(Z)) < 1e-10
 
 
+def test_block_factor_sparse_and_dense_products_agree(tiny, monkeypatch):
+    """The coupling block is dense on the tiny workload (dense products);
+    forced sparse, the same factor gives the same x and variances, and both
+    match the dense oracle's own loop."""
+    p, A, b = tiny
+    fd = BlockCholesky(A, p.n_bg)
+    assert not sp.issparse(fd.Lsb)
+    monkeypatch.setattr(BlockCholesky, "DENSE_FRACTION", 2.0)
+    fs = BlockCholesky(A, p.n_bg)
+    assert sp.issparse(fs.Lsb)
+    x_d, L = solve_dense(A.toarray(), b)
+    d_d = diag_inv_colnorms(L)
+    for f in (fd, fs):
+        assert np.linalg.norm(f.solve(b) - x_d) / np.linalg.norm(x_d) < 1e-12
+        assert np.max(np.abs(f.diag_inv() - d_d) / d_d) < 1e-12
+
+
 def test_block_factor_general_pivot_block():
     """Leading block that is not diagonal goes through the general branch."""
     p = synth.make_random(60, 12, 4, seed=4)
