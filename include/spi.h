@@ -118,7 +118,18 @@ typedef struct spi_opts {
                                end up in the same 64-column tiles, so fewer
                                tiles of the dense root see each row); 1:
                                original order.  Default 0 */
-    int32_t reserved;       /* must be zero */
+    int32_t leaf_lds_cap;   /* widest leaf front (root positions) whose
+                               panel columns are accumulated in on-chip
+                               memory (LDS) before one write; wider fronts
+                               accumulate in place in device memory.  0:
+                               2048 (the most LDS allows); 1..2048 a
+                               smaller cap (tests use it to run the in-place
+                               path on small problems) */
+    int32_t selinv_chunk;   /* tasks (64 x 64 blocks of a front's row
+                               structure) per launch of the leaf selected
+                               inversion.  0: 4194304 (a launch must stay
+                               below 2^24 workgroups); >= 1 a smaller chunk
+                               (tests use it to run several launches) */
 } spi_opts;
 
 typedef struct spi_info_t {
@@ -156,6 +167,18 @@ typedef struct spi_info_t {
     double t_sweep_bulk_ms;     /* device time of the bulk updates */
     double flops_sweep_bulk;    /* their algorithmic flops (lower triangles
                                    only), summed over the timed calls */
+    /* Flops the kernels execute, zeros of the dense panels included (the
+     * algorithmic counts above take the exact column counts of L): */
+    double flops_exec_assembly; /* root assembly: sum over the panels'
+                                   incidences on the 64 x 64 root tiles of
+                                   2 nI nJ k */
+    double flops_exec_selinv;   /* leaf selected inversion: sum over its
+                                   tasks of 2 na nb p */
+    double flops_root_assembly; /* algorithmic flops of the root front's
+                                   assembly: the lower triangles of the row
+                                   products w_r h_rR h_rR^T and of the leaf
+                                   updates L_Ul L_Ul^T on the exact
+                                   structure, len (len + 1) per row or leaf */
 } spi_info_t;
 
 /* Fill `o` with the defaults listed above. */
@@ -188,7 +211,16 @@ int spi_analyze(spi_handle** h, int64_t m, int64_t n, const int64_t* rowptr,
  * CSR order and the row weights W = Sigma^-2 (Sect. 2.4.1).  Stream-ordered
  * device-to-device copy into handle-owned buffers; invalidates any factor.
  *
- *  val  device, float64[nnz(H)]       w  device, float64[m], every w_r > 0
+ *  val  device, float64[nnz(H)], finite
+ *  w    device, float64[m], finite.  The paper's weights are positive
+ *       (inverse variances).  Zero and negative weights are accepted: a zero
+ *       weight drops a row (the Hessian of the likelihood fit has weight
+ *       d_r / e_r^2, zero where no count was recorded), a negative one
+ *       removes a row's contribution; A may then be singular or indefinite,
+ *       which spi_factor reports as SPI_E_NOT_SPD.
+ * The values are checked on the device, without a synchronisation here: a
+ * NaN or infinite value or weight makes the next spi_factor (or batch run)
+ * return SPI_E_ARG.
  */
 int spi_set_values(spi_handle* h, const double* val, const double* w);
 
@@ -201,7 +233,8 @@ int spi_set_values(spi_handle* h, const double* val, const double* w);
  * Cholesky-factored.  Synchronises the handle's stream.  Returns
  * SPI_E_NOT_SPD if a pivot is not positive (the same pivot on either
  * route); spi_info().failed_col then names the original column.
- * SPI_E_STATE before spi_set_values.
+ * SPI_E_STATE before spi_set_values; SPI_E_ARG if the values or weights of
+ * the last spi_set_values hold a NaN or an infinity (no factor is left).
  */
 int spi_factor(spi_handle* h);
 
@@ -356,7 +389,9 @@ typedef struct spi_pcg_info {
  * binary64 solves.  Then x += e.
  * Stops when ||b - A_b x|| <= tol ||b|| (binary64).
  * If `maxit` inner iterations do not get there, the band is factored and
- * solved directly (its own multifrontal factor) and `fell_back` is set.
+ * solved directly (its own multifrontal factor) and `fell_back` is set;
+ * if even that x misses `tol`, the call returns SPI_E_NOCONV (x and `info`
+ * are still written).
  *  b, x  device, float64[n];  tol > 0;  maxit >= 1
  *  info  host, may be NULL
  * Synchronises the stream (the scalars of CG are read back every iteration).
@@ -368,7 +403,8 @@ int spi_pcg_solve(spi_handle* band, spi_handle* ref, const spi_lp* lp,
 /* ------------------------------------------------------------------------
  * Batches: many systems in flight together
  * ------------------------------------------------------------------------
- * The paper solves its energy bands one after the other (Sect. 4.2).  A
+ * The paper analyses its energy bands one after the other, as many
+ * sequential computations (Sect. 5: 24 consecutive bands; Sect. 6).  A
  * batch takes k handles of any patterns, each on its own stream (bands
  * from spi_analyze_like, independent sub-problems from spi_analyze).  It
  * enqueues each system's whole pipeline and synchronises once per stream
@@ -389,12 +425,16 @@ int spi_batch_create(spi_batch** b, spi_handle* const* hs, int32_t k,
  *  - spi_factor;
  *  - rhs[i] = H^T W y[i];
  *  - x[i] = A^-1 rhs[i], with exactly opts.refine_steps refinement steps
- *    (no refine_tol read-back inside a batch);
+ *    (no read-back between steps inside a batch);
  *  - d[i] = diag(A^-1).
  * y, rhs, x, d: host arrays of k device pointers.  d may be NULL, as may
  * any d[i], to skip the variances.  status: host int32[k] or NULL, each
- * system's status (SPI_E_NOT_SPD etc.).  Returns SPI_OK, or the first
- * failing status.  All systems are finished on return.
+ * system's status (SPI_E_NOT_SPD etc.).  With opts.refine_tol > 0 (always
+ * so in SPI_MIXED) the sizes of the last two corrections are read back at
+ * the final synchronisation, and a system whose refinement did not reach
+ * refine_tol by the rule of spi_solve gets SPI_E_NOCONV (x is still
+ * written).  Returns SPI_OK, or the first failing status.  All systems are
+ * finished on return.
  */
 int spi_batch_run(spi_batch* b, const double* const* y, double* const* rhs,
                   double* const* x, double* const* d, int32_t* status);

@@ -363,6 +363,7 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   int64_t front = 0;
   std::vector<int32_t> curU, curCols;
   int64_t cur_sum = 0;
+  double leaf_work = 0.0, leaf_update = 0.0;
   auto close_front = [&]() {
     std::sort(curU.begin(), curU.end());
     for (int32_t j : curCols) {
@@ -413,6 +414,11 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
       }
     curCols.push_back(j);
     cur_sum += (int64_t)rj.size();
+    // algorithmic work of leaf j as its own front (p = 1, c = the root
+    // unknowns of its rows, its exact column count in L)
+    const double c = (double)rj.size();
+    leaf_work += 1.0 / 3.0 + c + c * c;
+    leaf_update += c * (c + 1.0);
   }
   if (!curCols.empty()) close_front();
   a.n_groups = front;
@@ -713,15 +719,40 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
     for (auto& x : th) x.join();
     a.nnz_a = std::accumulate(c.begin(), c.end(), (int64_t)0);
   }
+  // Algorithmic flops: per front p^3/3 + c p^2 + c^2 p for the factor and
+  // twice that for the selected inversion, with the exact structure of L:
+  // every leaf is a front of its own (leaves share no row, so the pivot
+  // block of an amalgamated front is diagonal) and c is the number of root
+  // unknowns in its rows; the root is a dense front of its unpadded order.
   double nR = (double)a.n_root;
   a.nnz_l = n_leaf + a.grp_panel_off[a.n_groups] + a.n_root * (a.n_root + 1) / 2;
-  a.flops_factor = nR * nR * nR / 3.0;
-  a.flops_selinv = 2.0 * nR * nR * nR / 3.0;
-  for (int64_t g = 0; g < a.n_groups; ++g) {
-    double p = (double)(a.grp_col_ptr[g + 1] - a.grp_col_ptr[g]);
-    double c = (double)(a.grp_U_ptr[g + 1] - a.grp_U_ptr[g]);
-    a.flops_factor += p * p * p / 3.0 + c * p * p + c * c * p;
-    a.flops_selinv += 2.0 * (p * p * p / 3.0 + c * p * p + c * c * p);
+  a.flops_factor = nR * nR * nR / 3.0 + leaf_work;
+  a.flops_selinv = 2.0 * (nR * nR * nR / 3.0 + leaf_work);
+  // Executed flops, zeros of the dense panels included: the root
+  // assembly's matrix-core products per incidence, and the leaf selected
+  // inversion's per task.
+  // Root front assembly, algorithmic: the lower triangles of the row
+  // products w_r h_rR h_rR^T and of the leaf updates l_U l_U^T, each a
+  // multiply-add per entry on the exact structure.
+  a.flops_root_asm = leaf_update;
+  for (int64_t r = 0; r < m; ++r) {
+    const double len = (double)root_cnt[r];
+    a.flops_root_asm += len * (len + 1.0);
+  }
+  a.flops_exec_asm = 0.0;
+  for (int64_t q = 0; q < (int64_t)a.inc.size() / 4; ++q) {
+    const int32_t* p = a.inc.data() + 4 * q;
+    const double nI = p[3] & 0xffff, nJ = p[3] >> 16;
+    a.flops_exec_asm += 2.0 * nI * nJ * (double)a.up_k[p[0]];
+  }
+  a.flops_exec_selinv = 0.0;
+  for (int64_t t = 0; t < (int64_t)a.tasks.size() / 3; ++t) {
+    const int64_t f = a.tasks[3 * t], I = a.tasks[3 * t + 1], J = a.tasks[3 * t + 2];
+    const int64_t nU = a.grp_U_ptr[f + 1] - a.grp_U_ptr[f];
+    const double na = (double)std::min<int64_t>(kET, nU - I * kET);
+    const double nb = (double)std::min<int64_t>(kET, nU - J * kET);
+    a.flops_exec_selinv +=
+        2.0 * na * nb * (double)(a.grp_col_ptr[f + 1] - a.grp_col_ptr[f]);
   }
   a.flops_solve = 4.0 * (double)a.nnz_l;
   a.flops_asm = 0;

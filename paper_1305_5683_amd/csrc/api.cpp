@@ -125,7 +125,7 @@ bool check_opts(spi_opts& o) {
   }
   if (o.max_group < 1 || o.refine_steps < 0 || !(o.amalg_density >= 0.0) ||
       !(o.refine_tol >= 0.0) || (o.keep_root_order != 0 && o.keep_root_order != 1) ||
-      o.reserved != 0) {
+      o.leaf_lds_cap < 0 || o.leaf_lds_cap > kLeafLdsCapMax || o.selinv_chunk < 0) {
     g_analyze_err = "invalid options";
     return false;
   }
@@ -164,14 +164,19 @@ int setup_device(spi_handle* H) {
   AL(h.rrval, (int64_t)a.rr_src.size());
   AL(h.panel, a.grp_panel_off.back() + a.rp_val_off.back());
   AL(h.ldiag, nl);
-  AL(h.S, np * np); AL(h.W, np * np); AL(h.Z, np * np);
+  AL(h.S, np * np);
+  // the Cholesky route's buffers: the inverse factor, the root block of A^-1
+  // and the inverses of the diagonal blocks (the sweeps need none of them)
+  if (!h.opts.root_inverse) {
+    AL(h.W, np * np); AL(h.Z, np * np);
+    AL(h.invd, np * kNB); AL(h.invd2, ((np + 255) / 256) * 256 * 256);
+  }
   h.band_nb = (int)std::min<int64_t>(512, np);
   AL(h.band, 4 * (int64_t)h.band_nb * np + 2 * (int64_t)h.band_nb * h.band_nb);
-  AL(h.invd, np * kNB); AL(h.part, a.task_part_off.back());
-  AL(h.flag, 1); AL(h.vleaf, nl); AL(h.vfront, a.grp_U_ptr.back()); AL(h.vroot, np); AL(h.vres, a.n);
-  AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 2);
+  AL(h.part, a.task_part_off.back());
+  AL(h.flag, 2); AL(h.vleaf, nl); AL(h.vfront, a.grp_U_ptr.back()); AL(h.vroot, np); AL(h.vres, a.n);
+  AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 4);
   AL(h.vroot2, np); AL(h.vpart, root_inv_part_size(np));
-  AL(h.invd2, ((np + 255) / 256) * 256 * 256);
   AL(h.colscale, a.n); AL(h.vbh, a.n); AL(h.vxh, a.n); AL(h.diagA, a.n);
 #undef AL
   if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
@@ -188,6 +193,16 @@ int setup_device(spi_handle* H) {
 
 // ---- stream-ordered pieces of the entry points (also used by batches)
 namespace spi {
+
+// Converged once the last correction (relative max-norm `cur`) is below
+// tol, or once two corrections contract (by at least half) at a rate that
+// puts the next one, i.e. the error left in x, below tol.  prev <= 0: no
+// earlier correction.
+bool refine_converged(double cur, double prev, double tol) {
+  if (cur <= tol) return true;
+  return prev > 0.0 && cur <= 0.5 * prev && cur * (cur / prev) <= tol;
+}
+
 
 int factor_enqueue(Handle& h) {
   h.have_factor = false;
@@ -219,10 +234,15 @@ int factor_enqueue(Handle& h) {
 }
 
 // Interpret the pivot flag read back after factor_enqueue's work completed.
-int factor_finish(Handle& h, uint64_t f) {
-  if (f != std::numeric_limits<uint64_t>::max()) {
+int factor_finish(Handle& h, const uint64_t* f) {
+  if (f[1] != 0) {
+    h.have_inv = false;
+    return fail(h, SPI_E_ARG, hipSuccess,
+                "a value or weight given to spi_set_values is NaN or infinite");
+  }
+  if (f[0] != std::numeric_limits<uint64_t>::max()) {
     const int64_t nl = (int64_t)h.an.leaf_cols.size();
-    int64_t k = (int64_t)f;
+    int64_t k = (int64_t)f[0];
     if (k < nl) h.failed_col = h.an.leaf_cols[k];
     else if (k - nl < h.an.n_root) h.failed_col = h.an.root_cols[k - nl];
     std::ostringstream os;
@@ -247,11 +267,14 @@ int solve_enqueue(Handle& h, const double* bc, double* xc, int steps) {
     dst = h.vxh;
   }
   SPI_CK(launch_solve_pass(h, src, dst), "solve");
+  // step s leaves (max |dx|, max |x|) in vnorm[2 (s & 1) ..], so the sizes
+  // of the last two corrections can be read back after the work completes
   for (int s = 0; s < steps; ++s) {
     SPI_CK(launch_residual_dd(h, src, dst, h.vres), "residual");
     SPI_CK(launch_solve_pass(h, h.vres, h.vx), "correction");
-    SPI_CK(fill_f64(h.stream, h.vnorm, 0.0, 2), "norms");
-    SPI_CK(launch_axpy_norms(h, dst, h.vx), "update");
+    double* nv = h.vnorm + 2 * (s & 1);
+    SPI_CK(fill_f64(h.stream, nv, 0.0, 2), "norms");
+    SPI_CK(launch_axpy_norms(h, dst, h.vx, nv), "update");
   }
   if (eq) SPI_CK(launch_scale_vec(h, h.vxh, xc, 0), "scale solution");
   return SPI_OK;
@@ -377,6 +400,10 @@ int spi_set_values(spi_handle* H, const double* val, const double* w) {
                         hipMemcpyDeviceToDevice, h.stream), "copy values");
   SPI_CK(hipMemcpyAsync(h.w, w, h.an.m * sizeof(double),
                         hipMemcpyDeviceToDevice, h.stream), "copy weights");
+  // flag[1] collects non-finite inputs (values: while gathered into column
+  // order; weights: here); spi_factor reports it
+  SPI_CK(fill_i64(h.stream, h.flag + 1, 0, 1), "input flag");
+  SPI_CK(launch_check_finite(h, h.w, h.an.m), "weights");
   SPI_CK(launch_equilibrate(h), "diagonal / equilibration");
   h.val32_ok = false;
   SPI_CK(launch_gather_values(h), "gather values");
@@ -394,8 +421,8 @@ int spi_factor(spi_handle* H) {
     return fail(h, SPI_E_STATE, hipSuccess, "spi_factor before spi_set_values");
   int st = factor_enqueue(h);
   if (st != SPI_OK) return st;
-  uint64_t f = 0;
-  SPI_CK(hipMemcpyAsync(&f, h.flag, sizeof(f), hipMemcpyDeviceToHost, h.stream),
+  uint64_t f[2] = {0, 0};
+  SPI_CK(hipMemcpyAsync(f, h.flag, sizeof(f), hipMemcpyDeviceToHost, h.stream),
          "flag readback");
   SPI_CK(hipStreamSynchronize(h.stream), "factor");
   return factor_finish(h, f);
@@ -444,19 +471,15 @@ int spi_solve(spi_handle* H, const double* b, double* x, int32_t nrhs,
       SPI_CK(launch_residual_dd(h, src, dst, h.vres), "residual");
       SPI_CK(launch_solve_pass(h, h.vres, h.vx), "correction");
       SPI_CK(fill_f64(h.stream, h.vnorm, 0.0, 2), "norms");
-      SPI_CK(launch_axpy_norms(h, dst, h.vx), "update");
+      SPI_CK(launch_axpy_norms(h, dst, h.vx, h.vnorm), "update");
       ++done;
       if (tol > 0.0) {
         double nv[2];
         SPI_CK(hipMemcpyAsync(nv, h.vnorm, sizeof(nv), hipMemcpyDeviceToHost,
                               h.stream), "norm readback");
         SPI_CK(hipStreamSynchronize(h.stream), "refinement");
-        // Converged once the correction is below tol, or once two
-        // corrections contract (by at least half) at a rate that puts the
-        // next one, i.e. the error left in x, below tol.
         const double cur = nv[1] > 0.0 ? nv[0] / nv[1] : 0.0;
-        const bool contracting = prev > 0.0 && cur <= 0.5 * prev;
-        if (cur <= tol || (contracting && cur * (cur / prev) <= tol)) {
+        if (refine_converged(cur, prev, tol)) {
           converged = true;
           break;
         }
@@ -469,6 +492,7 @@ int spi_solve(spi_handle* H, const double* b, double* x, int32_t nrhs,
   }
   phase_end(h, kPhSolve);
   h.refine_done = done_max;
+  h.last_norm_pair = 0;
   if (status != SPI_OK)
     return fail(h, status, hipSuccess,
                 "iterative refinement did not reach refine_tol");
@@ -498,6 +522,9 @@ static void fill_analysis_info(const Analysis& a, spi_info_t* info) {
   info->flops_selinv = a.flops_selinv;
   info->flops_solve = a.flops_solve;
   info->flops_assembly = a.flops_asm;
+  info->flops_exec_assembly = a.flops_exec_asm;
+  info->flops_exec_selinv = a.flops_exec_selinv;
+  info->flops_root_assembly = a.flops_root_asm;
 }
 
 int spi_symbolic(int64_t m, int64_t n, const int64_t* rowptr,
@@ -569,7 +596,8 @@ int spi_info(const spi_handle* Hc, spi_info_t* info) {
   info->refine_steps_done = h.refine_done;
   if (h.refine_done > 0 && h.vnorm) {
     double nv[2] = {0, 0};
-    if (hipMemcpyAsync(nv, h.vnorm, sizeof(nv), hipMemcpyDeviceToHost,
+    if (hipMemcpyAsync(nv, h.vnorm + 2 * h.last_norm_pair, sizeof(nv),
+                       hipMemcpyDeviceToHost,
                        h.stream) == hipSuccess &&
         hipStreamSynchronize(h.stream) == hipSuccess && nv[1] > 0)
       info->last_refine_norm = nv[0] / nv[1];

@@ -2,7 +2,7 @@
 // (declared in include/spi.h).
 //
 // Energy bands share the pattern of H and differ in W and y (Sect. 2.2.3);
-// the paper solves them one after the other (Sect. 4.2).  A batch enqueues
+// the paper analyses them one after the other (Sect. 5, Sect. 6).  A batch enqueues
 // the whole pipeline of every system (factorisation, right-hand side, solve,
 // variances) on each handle's own stream before synchronising once, so
 // systems run concurrently and fill the gaps of each other's dependency
@@ -137,20 +137,39 @@ int spi_batch_run(spi_batch* B, const double* const* y, double* const* rhs,
     }
     launched[i] = true;
   }
-  // one synchronisation per stream; pivot flags decide each status
+  // one synchronisation per stream; the input and pivot flags, then the
+  // sizes of the last two refinement corrections, decide each status
   for (int i = 0; i < k; ++i) {
     if (!launched[i]) continue;
     Handle& h = B->hs[i]->h;
-    uint64_t f = 0;
-    hipError_t he = hipMemcpyAsync(&f, h.flag, sizeof(f), hipMemcpyDeviceToHost,
+    uint64_t f[2] = {0, 0};
+    double nv[4] = {0, 0, 0, 0};
+    hipError_t he = hipMemcpyAsync(f, h.flag, sizeof(f), hipMemcpyDeviceToHost,
                                    h.stream);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(nv, h.vnorm, sizeof(nv), hipMemcpyDeviceToHost, h.stream);
     if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
     if (he != hipSuccess) {
       note(i, fail(h, SPI_E_HIP, he, "batch"));
       continue;
     }
-    note(i, factor_finish(h, f));
-    h.refine_done = h.opts.refine_steps;
+    int st = factor_finish(h, f);
+    const int steps = h.opts.refine_steps;
+    h.refine_done = steps;
+    h.last_norm_pair = steps > 0 ? (steps - 1) & 1 : 0;
+    if (st == SPI_OK && h.opts.refine_tol > 0.0) {
+      // step s wrote pair s & 1: the last step's pair, then the one before
+      auto rel = [&](int s) {
+        const double* p = nv + 2 * (s & 1);
+        return p[1] > 0.0 ? p[0] / p[1] : 0.0;
+      };
+      const double cur = steps > 0 ? rel(steps - 1) : 1.0;
+      const double prev = steps > 1 ? rel(steps - 2) : 0.0;
+      if (!refine_converged(cur, prev, h.opts.refine_tol))
+        st = fail(h, SPI_E_NOCONV, hipSuccess,
+                  "iterative refinement did not reach refine_tol in the batch");
+    }
+    note(i, st);
   }
   return first_bad;
 }

@@ -359,6 +359,11 @@ int spi_pcg_solve(spi_handle* band, spi_handle* ref, const spi_lp* lp,
     double r2 = 0.0;
     SPI_CK(dot64(h, w.r64, w.r64, &r2), "||r||");
     out.rel_residual = nb > 0.0 ? std::sqrt(r2) / nb : 0.0;
+    if (out.rel_residual > tol) {
+      if (info) *info = out;
+      return fail(h, SPI_E_NOCONV, hipSuccess,
+                  "PCG and its direct fallback both missed the tolerance");
+    }
   }
   if (info) *info = out;
   return SPI_OK;

@@ -118,9 +118,6 @@ __global__ __launch_bounds__(256) void k_leaf_assemble(
   for (int64_t u = lane; u < nU; u += 64) P[u] = acc[u] * inv;
 }
 
-// LDS per wave of the accumulating variant, at most (4 waves per workgroup)
-constexpr int kLeafLdsCap = 2048;
-
 hipError_t launch_leaf_assemble(Handle& h) {
   const Analysis& a = h.an;
   const int64_t nl = (int64_t)a.leaf_cols.size();
@@ -128,7 +125,9 @@ hipError_t launch_leaf_assemble(Handle& h) {
   int64_t max_u = 1;
   for (int64_t g = 0; g < a.n_groups; ++g)
     max_u = std::max<int64_t>(max_u, a.grp_U_ptr[g + 1] - a.grp_U_ptr[g]);
-  if (max_u <= kLeafLdsCap) {
+  // LDS per wave of the accumulating variant, at most (4 waves per workgroup)
+  const int64_t lds_cap = h.opts.leaf_lds_cap > 0 ? h.opts.leaf_lds_cap : kLeafLdsCapMax;
+  if (max_u <= lds_cap) {
     const int cap = (int)max_u;
     hipLaunchKernelGGL(k_leaf_assemble<true>, dim3(wave_grid(nl)), dim3(256),
                        4 * (size_t)cap * sizeof(double), h.stream, h.d.leaf_grp,
@@ -388,12 +387,37 @@ hipError_t launch_assemble_root(Handle& h) {
 // valc[k] = val[csc_pos[k]]: H's values in column order, so that the
 // column-wise kernels (diagonal, right-hand side, residual) read them
 // contiguously instead of gathering them from the row-ordered copy.
+// A NaN or infinity among the values sets *bad (one atomic per wave that
+// saw one): the factorisation reports it.
 __global__ void k_gather_csc(const double* __restrict__ val,
                              const int64_t* __restrict__ csc_pos,
-                             double* __restrict__ valc, int64_t nnz) {
+                             double* __restrict__ valc, int64_t nnz,
+                             int64_t* bad) {
+  bool nonfinite = false;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const double v = val[csc_pos[k]];
+    nonfinite |= !isfinite(v);
+    valc[k] = v;
+  }
+  if (__any(nonfinite) && (threadIdx.x & 63) == 0)
+    atomicOr((unsigned long long*)bad, 1ull);
+}
+
+__global__ void k_check_finite(const double* __restrict__ v, int64_t n, int64_t* bad) {
+  bool nonfinite = false;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x)
-    valc[k] = val[csc_pos[k]];
+    nonfinite |= !isfinite(v[k]);
+  if (__any(nonfinite) && (threadIdx.x & 63) == 0)
+    atomicOr((unsigned long long*)bad, 1ull);
+}
+
+hipError_t launch_check_finite(Handle& h, const double* v, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, 256 * 8)), dim3(256), 0,
+                     h.stream, v, n, h.flag + 1);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_col_scale(
@@ -449,7 +473,8 @@ hipError_t launch_equilibrate(Handle& h) {
   if (a.nnz)
     hipLaunchKernelGGL(k_gather_csc, dim3((unsigned)std::min<int64_t>(
                                          (a.nnz + 255) / 256, 16384)),
-                       dim3(256), 0, h.stream, h.val, h.d.csc_pos, h.valc, a.nnz);
+                       dim3(256), 0, h.stream, h.val, h.d.csc_pos, h.valc, a.nnz,
+                       h.flag + 1);
   hipLaunchKernelGGL(k_col_scale, dim3(wave_grid(a.n)), dim3(256), 0, h.stream,
                      h.d.colptr, h.d.csc_row, h.valc, h.w, h.diagA,
                      eq ? h.colscale : nullptr, a.n);
@@ -627,9 +652,10 @@ __global__ void k_axpy_norms(double* __restrict__ x, const double* __restrict__ 
   }
 }
 
-hipError_t launch_axpy_norms(Handle& h, double* x, const double* dx) {
+hipError_t launch_axpy_norms(Handle& h, double* x, const double* dx,
+                             double* norms) {
   hipLaunchKernelGGL(k_axpy_norms, dim3(grid_for(h.an.n, 256)), dim3(256), 0,
-                     h.stream, x, dx, (unsigned long long*)h.vnorm, h.an.n);
+                     h.stream, x, dx, (unsigned long long*)norms, h.an.n);
   return hipGetLastError();
 }
 
@@ -896,7 +922,7 @@ hipError_t launch_selinv_leaves(Handle& h, double* d) {
   if (!nl) return hipSuccess;
   const int64_t n_lt = a.grp_task_ptr[a.n_groups];  // tasks of leaf fronts
   if (n_lt && a.n_pad) {
-    const int64_t chunk = 1 << 20;
+    const int64_t chunk = h.opts.selinv_chunk > 0 ? h.opts.selinv_chunk : kSelinvChunk;
     for (int64_t t0 = 0; t0 < n_lt; t0 += chunk) {
       int64_t c = std::min(chunk, n_lt - t0);
       hipLaunchKernelGGL(k_selinv_leaf, dim3((unsigned)c), dim3(256), 0,

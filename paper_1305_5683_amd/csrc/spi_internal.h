@@ -23,6 +23,12 @@ constexpr int kNB = 64;
 constexpr int kET = 64;
 // Rows of the dense root triangular-solve chunks.
 constexpr int kTrsvChunk = 512;
+// Widest leaf front (root positions) accumulated in LDS by the leaf
+// assembly: 4 waves x 2048 x 8 B = 64 KB per workgroup.
+constexpr int kLeafLdsCapMax = 2048;
+// Default tasks per launch of the leaf selected inversion (a launch stays
+// below 2^24 workgroups of 256 threads).
+constexpr int64_t kSelinvChunk = int64_t(1) << 22;
 
 // ---------------------------------------------------------------- analysis
 // Host result of the symbolic analysis.  "slot" = a measurement row in
@@ -100,6 +106,7 @@ struct Analysis {
   // counters
   int64_t nnz_a = 0, nnz_l = 0;
   double flops_factor = 0, flops_selinv = 0, flops_solve = 0, flops_asm = 0;
+  double flops_exec_asm = 0, flops_exec_selinv = 0, flops_root_asm = 0;
 };
 
 // Returns an empty string on success, else the error text.
@@ -194,7 +201,8 @@ struct Handle {
   bool swept = false;        // S holds A_RR^-1 (sweeps) instead of L_RR
   double* Zr = nullptr;      // where the root block of A^-1 is: S or Z
   double* part = nullptr;    // selected-inversion partial sums
-  int64_t* flag = nullptr;   // first failing pivot in elimination order
+  int64_t* flag = nullptr;   // [0] first failing pivot in elimination
+                             // order, [1] non-finite input seen
   // solve scratch
   double* vleaf = nullptr;   // n_leaf
   double* vfront = nullptr;  // sum of |U| over leaf fronts: L_Ug y_g
@@ -202,7 +210,8 @@ struct Handle {
   double* vres = nullptr;    // n (residual / correction)
   double* vx = nullptr;      // n (iterate)
   double* vdd = nullptr;     // 2 m (double-double row values)
-  double* vnorm = nullptr;   // 2 (norm reductions)
+  double* vnorm = nullptr;   // 4: (max |dx|, max |x|) of the last two
+                             // refinement steps (step s at 2 (s & 1))
   double* vroot2 = nullptr;  // n_pad
   double* vpart = nullptr;   // partial products of the root GEMV
   double* colscale = nullptr;  // equilibration: power-of-two column scales s
@@ -230,6 +239,7 @@ struct Handle {
   int64_t failed_col = -1;
   double t_analyze_ms = 0;
   int refine_done = 0;
+  int last_norm_pair = 0;    // vnorm pair of the last refinement step
   double last_refine_norm = 0;
   std::string err;
 };
@@ -254,7 +264,8 @@ void free_lp_work(Handle& h);
 // with no host synchronisation; factor_finish interprets the pivot flag
 // once the factorisation has completed.
 int factor_enqueue(Handle& h);
-int factor_finish(Handle& h, uint64_t flag);
+int factor_finish(Handle& h, const uint64_t* flag);
+bool refine_converged(double cur, double prev, double tol);
 int solve_enqueue(Handle& h, const double* b, double* x, int steps);
 int diag_enqueue(Handle& h, double* d);
 hipError_t ensure_side_stream(Handle& h);
@@ -295,7 +306,9 @@ hipError_t root_lauum(Handle& h);
 hipError_t launch_solve_pass(Handle& h, const double* b, double* x);
 hipError_t launch_residual_dd(Handle& h, const double* b, const double* x,
                               double* r);
-hipError_t launch_axpy_norms(Handle& h, double* x, const double* dx);
+hipError_t launch_axpy_norms(Handle& h, double* x, const double* dx,
+                             double* norms);
+hipError_t launch_check_finite(Handle& h, const double* v, int64_t n);
 hipError_t launch_selinv_leaves(Handle& h, double* d);
 hipError_t launch_diag_root(Handle& h, double* d);
 hipError_t launch_equilibrate(Handle& h);

@@ -35,7 +35,7 @@ class spi_opts(C.Structure):
                 ("refine_steps", C.c_int32), ("timing", C.c_int32),
                 ("root_inverse", C.c_int32), ("equilibrate", C.c_int32),
                 ("refine_tol", C.c_double), ("keep_root_order", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("leaf_lds_cap", C.c_int32), ("selinv_chunk", C.c_int32)]
 
 
 class spi_info_t(C.Structure):
@@ -51,7 +51,9 @@ class spi_info_t(C.Structure):
                 ("t_extend_ms", C.c_double), ("t_potrf_ms", C.c_double),
                 ("t_solve_ms", C.c_double), ("t_trtri_ms", C.c_double),
                 ("t_lauum_ms", C.c_double), ("t_selinv_ms", C.c_double),
-                ("t_sweep_bulk_ms", C.c_double), ("flops_sweep_bulk", C.c_double)]
+                ("t_sweep_bulk_ms", C.c_double), ("flops_sweep_bulk", C.c_double),
+                ("flops_exec_assembly", C.c_double), ("flops_exec_selinv", C.c_double),
+                ("flops_root_assembly", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -195,3 +195,92 @@ def test_batch_graphs_with_multiband_sweeps():
     batch.close()
     for s in solvers:
         s.close()
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_mixed_batch_matches_oracle(graphs):
+    """Mixed precision in a batch (binary32 root products, three fixed
+    refinement steps, no read-back between them): x within 1e-10 and the
+    variances within 1e-6 of the FP64 oracle, and the convergence check at
+    the batch's synchronisation passes."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiBatch
+    base, bands, subs = _systems()
+    _say(f"case mixed batch graphs={graphs}: 3 bands + 3 sub-problems")
+    opts = dict(precision=1, refine_tol=1e-14, refine_steps=3)
+    first = SpiSolver(base.m, base.n, base.rowptr, base.col,
+                      stream=torch.cuda.Stream(), **opts)
+    solvers = [first] + [SpiSolver.like(first, stream=torch.cuda.Stream())
+                         for _ in bands[1:]]
+    solvers += [SpiSolver(q.m, q.n, q.rowptr, q.col, stream=torch.cuda.Stream(), **opts)
+                for q in subs]
+    probs = bands + subs
+    batch = SpiBatch(solvers, use_graphs=bool(graphs))
+    y = [torch.from_numpy(q.y).cuda() for q in probs]
+    rhs = [torch.empty(q.n, dtype=torch.float64, device="cuda") for q in probs]
+    x = [torch.empty_like(r) for r in rhs]
+    d = [torch.empty_like(r) for r in rhs]
+    for rnd in range(2):
+        for s, q in zip(solvers, probs):
+            _set(s, q)
+        torch.cuda.synchronize()
+        assert batch.run(y, rhs, x, d) == [0] * len(probs)
+        for i, q in enumerate(probs):
+            o = oracle_solve(q)
+            ex = _rel(x[i].cpu().numpy(), o["x"])
+            ed = np.max(np.abs(d[i].cpu().numpy() - o["diag"]) / o["diag"])
+            info = solvers[i].info()
+            _say(f"  round {rnd} system {i} n={q.n}: err_x={ex:.2e} err_d={ed:.2e} "
+                 f"last correction {info['last_refine_norm']:.1e}")
+            assert ex <= 1e-10 and ed <= 1e-6
+            assert info["refine_steps_done"] == 3
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_reports_unconverged_refinement():
+    """One refinement step cannot meet a refine_tol of 1e-300: the batch
+    reports SPI_E_NOCONV for that system (x is still written) and SPI_OK
+    for the others."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiBatch
+    base, bands, subs = _systems()
+    _say("case batch with an unreachable refine_tol")
+    s0 = SpiSolver(base.m, base.n, base.rowptr, base.col, stream=torch.cuda.Stream())
+    s1 = SpiSolver(base.m, base.n, base.rowptr, base.col, stream=torch.cuda.Stream(),
+                   refine_tol=1e-300, refine_steps=1)
+    for s in (s0, s1):
+        _set(s, bands[0])
+    batch = SpiBatch([s0, s1], use_graphs=False)
+    y = [torch.from_numpy(bands[0].y).cuda()] * 2
+    rhs = [torch.empty(base.n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    x = [torch.empty_like(r) for r in rhs]
+    assert batch.run(y, rhs, x) == [0, 6]
+    o = oracle_solve(bands[0], want_diag=False)
+    for xi in x:
+        assert _rel(xi.cpu().numpy(), o["x"]) <= TOL
+    batch.close()
+    s0.close()
+    s1.close()
+
+
+def test_batch_reports_nonfinite_input():
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiBatch
+    base, bands, subs = _systems()
+    _say("case batch with a NaN weight")
+    s0 = SpiSolver(base.m, base.n, base.rowptr, base.col, stream=torch.cuda.Stream())
+    s1 = SpiSolver.like(s0, stream=torch.cuda.Stream())
+    _set(s0, bands[0])
+    w = bands[1].w.copy()
+    w[5] = np.nan
+    s1.set_values(torch.from_numpy(bands[1].val).cuda(), torch.from_numpy(w).cuda())
+    batch = SpiBatch([s0, s1], use_graphs=True)
+    y = [torch.from_numpy(q.y).cuda() for q in bands[:2]]
+    rhs = [torch.empty(base.n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    x = [torch.empty_like(r) for r in rhs]
+    assert batch.run(y, rhs, x) == [0, 1]
+    batch.close()
+    s0.close()
+    s1.close()

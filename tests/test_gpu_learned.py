@@ -65,7 +65,10 @@ def _dense(p):
 def test_loss_and_gradient_match_oracle(eq):
     torch = _torch()
     from paper_1305_5683_amd import SpiLearnedPrecond, symbolic
-    base = synth.make_random_leafy(8, 4, 60, 3, 10, 20, seed=11)
+    # a small coded-mask system: its background unknowns (the first n_bg
+    # columns) are the leaves of both the oracle's own ordering and the
+    # library's analysis, the sky pixels the root
+    base = synth.make_problem(synth.SkyConfig("lp-grad", 10, 60, 5, 4), seed=11)
     ref_p, band_p = _band(base, 0), _band(base, 96)
     _say(f"case lp-grad eq={eq} n={base.n}")
     ref = _solver(ref_p, equilibrate=eq)
@@ -78,14 +81,15 @@ def test_loss_and_gradient_match_oracle(eq):
     params[-3:] = [-0.3, 0.05, 0.1]
     lp = SpiLearnedPrecond(HID, params)
     loss, grad = lp.loss_grad(band, ref, rhs, x)
-    # oracle
+    # oracle, from its own normal equations, right-hand side and kinds
     Ar, _ = _dense(ref_p)
-    Ab, _ = _dense(band_p)
+    Ab, rhs_o = _dense(band_p)
+    is_root = (np.arange(base.n) >= base.n_bg).astype(np.float64)
     _, _, _, front = symbolic(base.m, base.n, base.rowptr, base.col)
-    is_root = (front < 0).astype(np.float64)
+    assert np.array_equal(front < 0, is_root > 0)    # the library's split agrees
+    assert np.max(np.abs(rhs.cpu().numpy() - rhs_o)) <= 1e-14 * np.max(np.abs(rhs_o))
     phi = L.features(np.diag(Ab), np.diag(Ar), is_root)
     Ari = np.linalg.inv(Ar)
-    rhs_o = rhs.cpu().numpy()
     x_o = np.linalg.solve(Ab, rhs_o)
     loss_o, grad_o = L.loss_grad(params.astype(np.float64), phi, rhs_o, x_o,
                                  lambda v: Ari @ v, lambda v: Ab @ v, HID)
@@ -137,6 +141,12 @@ def test_pcg_fallback_is_direct_and_exact():
     _say(f"  {info} err_x={ex:.2e}")
     assert info["fell_back"] == 1
     assert ex <= 1e-12 and info["rel_residual"] <= 1e-13
+    # a tolerance even the direct fallback cannot meet: SPI_E_NOCONV
+    from paper_1305_5683_amd import SpiError
+    _say("case pcg fallback misses tol=1e-30")
+    with pytest.raises(SpiError) as ei:
+        pcg_solve(band, ref, rhs, tol=1e-30, maxit=1)
+    assert ei.value.status == 6
     ref.close()
     band.close()
 

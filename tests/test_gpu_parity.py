@@ -81,13 +81,39 @@ def _check(p, g, o, idx=None, tol_x=TOL_X, tol_d=TOL_D):
 
 @functools.lru_cache(maxsize=1)
 def _medium():
-    """The medium workload and its oracle on a sample of diag(A^-1)."""
+    """The medium workload and its oracle, x and every variance."""
     p = synth.make_config(1)
-    rng = np.random.default_rng(1)
-    idx = np.sort(np.concatenate([rng.choice(p.n_bg, 96, replace=False),
-                                  p.n_bg + rng.choice(p.n - p.n_bg, 96,
-                                                      replace=False)]))
-    return p, idx, oracle_solve(p, diag_idx=idx)
+    return p, None, oracle_solve(p)
+
+
+# A large-workload shape at a size the oracle finishes in seconds: the
+# large configuration's 31x31 field of view and random time-bin lengths
+# U{1..10} on a 60x60 sky with 1500 pointings (28,500 rows, 8,711 unknowns).
+# Its leaf fronts see up to the whole 3,600-pixel root, wider than the 2,048
+# positions the leaf assembly accumulates on chip, so the in-place leaf
+# assembly runs.
+LARGE_SHAPE = synth.SkyConfig("large-shape-s60", 60, 1500, 31, 0)
+
+
+@functools.lru_cache(maxsize=1)
+def _large_shape():
+    p = synth.make_problem(LARGE_SHAPE, seed=22)
+    return p, oracle_solve(p)
+
+
+def _front_widths(p):
+    """Root positions of every leaf front, from the analysis' column-to-front
+    map and the pattern of H (host-side counting, no arithmetic of the
+    method)."""
+    from paper_1305_5683_amd import symbolic
+    import scipy.sparse as sp
+    info, _, _, front = symbolic(p.m, p.n, p.rowptr, p.col)
+    Hb = sp.csr_matrix((np.ones(p.nnz), p.col, p.rowptr), shape=(p.m, p.n))
+    leaf = front >= 0
+    G = sp.csr_matrix((np.ones(int(leaf.sum())), (front[leaf], np.nonzero(leaf)[0])),
+                      shape=(info["n_groups"], p.n))
+    FU = (G @ Hb.T) @ Hb[:, ~leaf]
+    return np.diff(FU.tocsr().indptr), info
 
 
 def test_tiny_config_parity():
@@ -213,17 +239,96 @@ def test_state_errors():
 
 @pytest.mark.timeout(900)
 def test_medium_config_parity():
-    """The benchmark workload (100x100 sky, 5000 pointings, 33,750 unknowns):
-    full x against the certified oracle, diag(A^-1) on a sample checked both
-    against the oracle's block factor and against certified inverse columns."""
-    p, idx, o = _medium()
+    """The medium workload (100x100 sky, 5000 pointings, 33,750 unknowns):
+    all of x against the certified oracle, and every variance against the
+    oracle's block factor; a few variances also against certified inverse
+    columns."""
+    p, _, o = _medium()
     _say(f"case medium config m={p.m} n={p.n}")
     g = run_gpu(p)
-    _check(p, g, o, idx=idx)
+    _check(p, g, o)
     f = o["factor"]
-    for j in idx[::24]:
+    rng = np.random.default_rng(1)
+    for j in np.concatenate([rng.choice(p.n_bg, 4, replace=False),
+                             p.n_bg + rng.choice(p.n - p.n_bg, 4, replace=False)]):
         zc = refine_inverse_column(p, f.solve, int(j))
         assert abs(g["d"][j] - float(zc[j])) <= TOL_D * float(zc[j])
+
+
+@pytest.mark.timeout(900)
+def test_large_shape_parity_fp64():
+    """The large workload's field of view (31x31) and random bin lengths:
+    all of x and every variance at 1e-12.  Its fronts are wider than the
+    on-chip accumulation cap (in-place leaf assembly), and a chunk of 50,000
+    tasks splits the leaf selected inversion into several launches."""
+    p, o = _large_shape()
+    widths, info = _front_widths(p)
+    nt = -(-widths // 64)
+    n_tasks = int(np.sum(nt * (nt + 1) // 2))
+    _say(f"case large-shape fp64 m={p.m} n={p.n} root={info['n_root']} "
+         f"widest front {widths.max()}, {n_tasks} selected-inversion tasks")
+    assert widths.max() > 2048 and n_tasks > 3 * 50000
+    g = run_gpu(p, selinv_chunk=50000)
+    _check(p, g, o)
+
+
+@pytest.mark.timeout(900)
+def test_large_shape_parity_mixed():
+    p, o = _large_shape()
+    _say(f"case large-shape mixed m={p.m} n={p.n}")
+    g = run_gpu(p, precision=1)
+    _check(p, g, o, tol_x=TOL_X_MIXED, tol_d=TOL_D_MIXED)
+
+
+FORCED = [
+    # (case, opts): leaf panels accumulated in place (cap below every front
+    # width) and the selected inversion in launches of a few tasks
+    ((30, 3, 200, 4, 30, 0, 2), {"leaf_lds_cap": 16, "selinv_chunk": 7}),
+    ((4, 23, 150, 2, 20, 40, 1), {"leaf_lds_cap": 1, "selinv_chunk": 1}),
+    ((12, 7, 600, 3, 25, 50, 5), {"leaf_lds_cap": 64, "selinv_chunk": 100,
+                                  "precision": 1}),
+]
+
+
+@pytest.mark.parametrize("case", FORCED, ids=[f"forced{i}" for i in range(len(FORCED))])
+def test_inplace_leaf_assembly_and_chunked_selinv(case):
+    shape, opts = case
+    p = synth.make_random_leafy(*shape)
+    _say(f"case forced paths m={p.m} n={p.n} opts={opts}")
+    g = run_gpu(p, **opts)
+    o = oracle_solve(p)
+    mixed = opts.get("precision", 0) == 1
+    _check(p, g, o, tol_x=TOL_X_MIXED if mixed else TOL_X,
+           tol_d=TOL_D_MIXED if mixed else TOL_D)
+
+
+def test_nonfinite_values_are_rejected():
+    """A NaN value or an infinite weight is caught on the device and
+    reported by the factorisation as SPI_E_ARG; good values afterwards
+    factor normally."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiError
+    p = synth.make_config(0)
+    dev = torch.device("cuda")
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col)
+    val, w = p.val.copy(), p.w.copy()
+    val[1234] = np.nan
+    w[77] = np.inf
+    for v, ww, what in ((val, p.w, "nan value"), (p.val, w, "inf weight")):
+        _say(f"case non-finite input: {what}")
+        s.set_values(torch.from_numpy(v).to(dev), torch.from_numpy(ww).to(dev))
+        with pytest.raises(SpiError) as ei:
+            s.factor()
+        assert ei.value.status == 1
+        with pytest.raises(SpiError) as ei:
+            s.diag_inv()
+        assert ei.value.status == 2
+    s.set_values(torch.from_numpy(p.val).to(dev), torch.from_numpy(p.w).to(dev))
+    s.factor()
+    d = s.diag_inv().cpu().numpy()
+    o = oracle_solve(p)
+    assert rel_d(d, o["diag"]) <= TOL_D
+    s.close()
 
 
 # ------------------------------------------------------------ equilibration
@@ -292,10 +397,10 @@ def test_mixed_badly_scaled_columns():
 
 @pytest.mark.timeout(900)
 def test_mixed_medium_config_parity():
-    p, idx, o = _medium()
+    p, _, o = _medium()
     _say(f"case mixed medium config m={p.m} n={p.n}")
     g = run_gpu(p, precision=1)
-    _check(p, g, o, idx=idx, tol_x=TOL_X_MIXED, tol_d=TOL_D_MIXED)
+    _check(p, g, o, tol_x=TOL_X_MIXED, tol_d=TOL_D_MIXED)
 
 
 # ------------------------------------------------------------- edge cases
