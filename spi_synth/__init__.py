@@ -37,6 +37,7 @@ import numpy as np
 __all__ = [
     "SkyConfig", "Problem", "CONFIGS", "make_problem", "make_config",
     "make_band", "band_scales_drift", "make_random", "make_random_leafy",
+    "make_empty_field", "empty_field_groups",
 ]
 
 _CHUNK = 256  # pointings per generation chunk (part of the draw order)
@@ -356,3 +357,67 @@ def subproblem_configs(k: int, seed: int = 0, side_lo: int = 30,
         n_p = 4 * int(np.ceil(0.1 * s * s))
         out.append(SkyConfig(f"sub{i}-s{s}", s, n_p, 17, 4))
     return out
+
+
+def make_empty_field(cfg: SkyConfig, seed: int = 0, u_spread: float = 0.25,
+                     t_lo: float = 0.8, t_hi: float = 1.2) -> Problem:
+    """A coded-mask instance with the paper's background model, for the
+    empty-field loop: one background unknown per time bin (its intensity,
+    shared by the detectors) whose coefficient in row (pointing p, detector
+    d) is ``U^d t_dp``, with the detector pattern ``U`` unknown.
+
+    The same sky draw as :func:`make_problem` (patches, masks, responses),
+    then, in this order: the true pattern ``U_true[d] ~ 1 + u_spread
+    U(-1, 1)``, effective times ``t_dp ~ U(t_lo, t_hi)`` per row, ``x_true``
+    (sky pixels and bin intensities ~ U(1, 50)) and Poisson counts from the
+    true model.  The returned values ``val`` hold the background entries for
+    ``U = 1`` (the starting pattern, entries ``t_dp``); ``meta`` holds
+    ``U_true``, ``t`` (per row), ``bg_pos`` (CSR position of each row's
+    background entry: the first of the row) and ``val_true``.
+    """
+    base = make_problem(cfg, seed)
+    nd = cfg.n_det
+    rng = np.random.default_rng(seed + 7919)
+    m = base.m
+    rows = np.repeat(np.arange(m), np.diff(base.rowptr))
+    det = np.arange(m) % nd
+    old_nbg = base.n_bg
+    n_bins = old_nbg // nd
+    col = base.col.astype(np.int64)
+    is_bg = col < old_nbg
+    # background columns: (bin, detector) -> bin; sky columns shift down
+    col = np.where(is_bg, col // nd, col - old_nbg + n_bins).astype(np.int32)
+    n = base.n - old_nbg + n_bins
+    U_true = 1.0 + u_spread * (2.0 * rng.random(nd) - 1.0)
+    t = t_lo + (t_hi - t_lo) * rng.random(m)
+    x_true = cfg.x_lo + (cfg.x_hi - cfg.x_lo) * rng.random(n)
+    val_true = base.val.copy()
+    val_true[is_bg] = (U_true[det] * t)[rows[is_bg]]
+    d, w = _draw_counts(base.rowptr, col, val_true, x_true, rng)
+    val0 = base.val.copy()
+    val0[is_bg] = t[rows[is_bg]]
+    bg_pos = base.rowptr[:-1].copy()
+    return Problem(m=m, n=n, n_bg=n_bins, rowptr=base.rowptr, col=col, val=val0,
+                   w=w, y=d, x_true=x_true, seed=seed, name=cfg.name + "-ef",
+                   meta=dict(base.meta, U_true=U_true, t=t, bg_pos=bg_pos,
+                             val_true=val_true, n_det=nd))
+
+
+def empty_field_groups(p: Problem, interval: int = 0):
+    """Rows grouped by detector pattern unit: by detector (``interval = 0``,
+    one unit per detector) or by (detector, interval of ``interval``
+    consecutive pointings).  Returns (grp_ptr int64[n_u + 1], grp_rows
+    int32, unit_of_row int32[m]): index bookkeeping only."""
+    nd = p.meta["n_det"]
+    r = np.arange(p.m)
+    det = r % nd
+    if interval > 0:
+        k = (r // nd) // interval
+        unit = k * nd + det
+    else:
+        unit = det
+    order = np.argsort(unit, kind="stable")
+    n_u = int(unit.max()) + 1
+    ptr = np.zeros(n_u + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum(np.bincount(unit, minlength=n_u))
+    return ptr, order.astype(np.int32), unit.astype(np.int32)
