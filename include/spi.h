@@ -271,6 +271,24 @@ int spi_solve(spi_handle* h, const double* b, double* x, int32_t nrhs,
 int spi_diag_inv(spi_handle* h, double* d);
 
 /*
+ * spi_diag_inv for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result as spi_diag_inv, with the selected
+ * inversion's partial sums in a fixed array of device memory inside the
+ * library instead of the handle's buffer.  The call allocates and creates
+ * nothing (no phase timing even with opts.timing; it needs a factor from a
+ * successful spi_factor, which has created everything else it uses).
+ *  d  device, float64[n] (written)
+ * The array holds 2^23 doubles (64 MiB) on each GPU the library runs on,
+ * kept until the process ends; a handle whose selected inversion needs more
+ * (about 38 MiB for the medium workload, far more for the large one) gets
+ * SPI_E_ARG.  All calls on one GPU share that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads) race and must not be
+ * issued.  SPI_E_STATE without a valid factor.
+ */
+int spi_diag_inv_noalloc(spi_handle* h, double* d);
+
+/*
  * The analysis phase alone, on the host, with no device work (Sect. 3.2.1):
  * useful to size a problem before allocating it, and to inspect the
  * elimination order and tree.  Same pattern arguments and errors as

@@ -17,7 +17,8 @@ LIB = os.path.join(PKG, "libspi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["k_gemm.hip", "k_dense.hip", "k_sparse.hip", "k_learned.hip"]
+HIP_SOURCES = ["k_gemm.hip", "k_dense.hip", "k_sparse.hip", "k_learned.hip",
+               "api_noalloc.hip"]
 CPP_SOURCES = ["analysis.cpp", "api.cpp", "api_learned.cpp", "api_batch.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

@@ -280,7 +280,7 @@ int solve_enqueue(Handle& h, const double* bc, double* xc, int steps) {
   return SPI_OK;
 }
 
-int diag_enqueue(Handle& h, double* d) {
+int diag_enqueue(Handle& h, double* d, double* part) {
   h.Zr = h.swept ? h.S : h.Z;
   if (h.an.n_pad && !h.swept) {
     if (!h.have_inv) {
@@ -295,7 +295,7 @@ int diag_enqueue(Handle& h, double* d) {
   }
   phase_begin(h, kPhSelinv);
   if (h.an.n_pad) SPI_CK(launch_diag_root(h, d), "root diagonal");
-  SPI_CK(launch_selinv_leaves(h, d), "leaf selected inversion");
+  SPI_CK(launch_selinv_leaves(h, d, part ? part : h.part), "leaf selected inversion");
   // (S A S)^-1 = S^-1 A^-1 S^-1: undo the scaling, d_i = s_i^2 d'_i
   if (h.opts.equilibrate) SPI_CK(launch_scale_vec(h, d, d, 2), "scale variances");
   phase_end(h, kPhSelinv);

@@ -916,7 +916,7 @@ __global__ __launch_bounds__(256) void k_selinv_reduce(
   }
 }
 
-hipError_t launch_selinv_leaves(Handle& h, double* d) {
+hipError_t launch_selinv_leaves(Handle& h, double* d, double* part) {
   const Analysis& a = h.an;
   const int64_t nl = (int64_t)a.leaf_cols.size();
   if (!nl) return hipSuccess;
@@ -929,12 +929,12 @@ hipError_t launch_selinv_leaves(Handle& h, double* d) {
                          h.stream, h.d.tasks, h.d.sel_order + t0, h.d.grp_U_ptr,
                          h.d.U,
                          h.d.grp_col_ptr, h.d.grp_panel_off, h.panel, h.Zr,
-                         a.n_pad, h.d.grp_task_ptr, h.d.task_part_off, h.part);
+                         a.n_pad, h.d.grp_task_ptr, h.d.task_part_off, part);
     }
   }
   hipLaunchKernelGGL(k_selinv_reduce, dim3(wave_grid(nl)), dim3(256), 0,
                      h.stream, h.d.leaf_grp, h.d.grp_col_ptr, h.d.grp_task_ptr,
-                     h.d.task_part_off, h.part, h.ldiag, h.d.leaf_cols, d, nl);
+                     h.d.task_part_off, part, h.ldiag, h.d.leaf_cols, d, nl);
   return hipGetLastError();
 }
 

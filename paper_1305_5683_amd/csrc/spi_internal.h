@@ -267,7 +267,9 @@ int factor_enqueue(Handle& h);
 int factor_finish(Handle& h, const uint64_t* flag);
 bool refine_converged(double cur, double prev, double tol);
 int solve_enqueue(Handle& h, const double* b, double* x, int steps);
-int diag_enqueue(Handle& h, double* d);
+// part: the selected inversion's partial sums (nullptr: the handle's own
+// buffer, h.part; task_part_off.back() doubles)
+int diag_enqueue(Handle& h, double* d, double* part = nullptr);
 hipError_t ensure_side_stream(Handle& h);
 
 // Workgroup index -> logical work item, XCD-aware.  Workgroups are
@@ -309,7 +311,7 @@ hipError_t launch_residual_dd(Handle& h, const double* b, const double* x,
 hipError_t launch_axpy_norms(Handle& h, double* x, const double* dx,
                              double* norms);
 hipError_t launch_check_finite(Handle& h, const double* v, int64_t n);
-hipError_t launch_selinv_leaves(Handle& h, double* d);
+hipError_t launch_selinv_leaves(Handle& h, double* d, double* part);
 hipError_t launch_diag_root(Handle& h, double* d);
 hipError_t launch_equilibrate(Handle& h);
 // y = s x (mode 0), x / s (mode 1), s^2 x (mode 2) with the column scales

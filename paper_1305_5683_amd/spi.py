@@ -26,7 +26,7 @@ EXPORTED = ["spi_default_opts", "spi_analyze", "spi_set_values", "spi_factor",
             "spi_lp_train_step", "spi_lp_destroy", "spi_pcg_solve",
             "spi_analyze_like", "spi_batch_create", "spi_batch_run",
             "spi_batch_destroy", "spi_autotune", "spi_get_potrf_block",
-            "spi_set_potrf_block"]
+            "spi_set_potrf_block", "spi_diag_inv_noalloc"]
 
 
 class spi_opts(C.Structure):
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
     lib.spi_rhs.argtypes = [P, P, P]
     lib.spi_solve.argtypes = [P, P, P, I32, I64]
     lib.spi_diag_inv.argtypes = [P, P]
+    lib.spi_diag_inv_noalloc.argtypes = [P, P]
     lib.spi_symbolic.argtypes = [I64, I64, P, P, C.POINTER(spi_opts),
                                  C.POINTER(spi_info_t), P, P, P]
     lib.spi_info.argtypes = [P, C.POINTER(spi_info_t)]
@@ -266,6 +267,14 @@ class SpiSolver:
             self.n, dtype=torch.float64, device=torch.device("cuda"))
         self._check(self.lib.spi_diag_inv(self.h, _ptr(d, self.n, torch.float64)))
         return d
+
+    def diag_inv_noalloc(self, out):
+        """diag(A^-1) into ``out`` with the library's fixed scratch array
+        (no device allocation; see spi_diag_inv_noalloc)."""
+        import torch
+        self._check(self.lib.spi_diag_inv_noalloc(
+            self.h, _ptr(out, self.n, torch.float64)))
+        return out
 
     def info(self) -> dict:
         i = spi_info_t()
