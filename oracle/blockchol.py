@@ -115,3 +115,22 @@ class BlockCholesky:
             del E
         return out
 
+    # -- general entries of A^-1 (covariances) -------------------------------
+    def inverse_entries(self, rows, cols, block: int = 128):
+        """``(A^-1)_ij`` for the pairs (rows[k], cols[k]): column j of A^-1
+        solves A z = e_j (forward then backward substitution with the block
+        factor, Sect. 3.3.1), taken for up to ``block`` distinct columns at a
+        time (blocked right-hand sides, Sect. 4.3)."""
+        rows = np.asarray(rows)
+        cols = np.asarray(cols)
+        out = np.empty(len(rows))
+        uniq = np.unique(cols)
+        for k0 in range(0, len(uniq), block):
+            sel = uniq[k0:k0 + block]
+            E = np.zeros((self.n, len(sel)))
+            E[sel, np.arange(len(sel))] = 1.0
+            Z = self.solve(E)
+            where = {int(c): q for q, c in enumerate(sel)}
+            for k in np.nonzero(np.isin(cols, sel))[0]:
+                out[k] = Z[rows[k], where[int(cols[k])]]
+        return out

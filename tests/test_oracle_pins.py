@@ -395,6 +395,36 @@ def test_refined_solution_agrees_with_block_solve(tiny):
     assert np.linalg.norm(xr - xb) / np.linalg.norm(xr) <= 1e-13
 
 
+def test_inverse_entries_match_exact_and_pruned(tiny):
+    """General entries of A^-1 (covariances) by blocked solves with the
+    block factor: the exact rational inverse of an integer problem (both
+    branches of the factor), the paper's pruned traversal on the tiny
+    workload (Sect. 3.3.1), and symmetry."""
+    A, _ = _integer_spd(11, 7)
+    Zx = _exact_inverse(A)
+    for nb in (4, 0):
+        f = BlockCholesky(sp.csr_matrix(A), nb)
+        r, c = np.meshgrid(np.arange(11), np.arange(11), indexing="ij")
+        v = f.inverse_entries(r.ravel(), c.ravel(), block=5)
+        ref = np.array([float(Zx[i][j]) for i, j in zip(r.ravel(), c.ravel())])
+        assert np.max(np.abs(v - ref)) <= 1e-13 * np.max(np.abs(ref))
+    p, A, b = tiny
+    f = BlockCholesky(A, p.n_bg)
+    L = cholesky(A.toarray())
+    pairs = [(i, j) for i in range(L.shape[0]) for j in range(i + 1)
+             if A[i, j] != 0 or i == j]
+    parent = et.etree_from_struct(et.symbolic_cholesky(L.shape[0], pairs))
+    rng = np.random.default_rng(4)
+    rr = rng.integers(0, p.n, 40)
+    cc = rng.integers(0, p.n, 40)
+    v = f.inverse_entries(rr, cc)
+    vt = f.inverse_entries(cc, rr)
+    assert np.max(np.abs(v - vt)) <= 1e-13 * np.max(np.abs(v))
+    for k in range(0, 40, 4):
+        ref, _, _ = selected_entry_pruned(L, parent, int(rr[k]), int(cc[k]))
+        assert abs(v[k] - ref) <= 1e-12 * max(abs(ref), 1e-3)
+
+
 def test_pulls_have_unit_scale():
     """Unscaled diag(A^-1) is the variance: pulls (x - x_true)/sd ~ N(0, 1).
 
