@@ -130,6 +130,12 @@ typedef struct spi_opts {
                                inversion.  0: 4194304 (a launch must stay
                                below 2^24 workgroups); >= 1 a smaller chunk
                                (tests use it to run several launches) */
+    int32_t keep_root_sum;  /* 1: the handle keeps A_RR, the root block of
+                               H^T W H (one more n_pad^2 buffer), so that a
+                               factorisation after spi_set_leaf_values
+                               re-assembles only the leaf fronts' updates
+                               (Sect. 4.1, modified columns of H; App. A.5,
+                               the empty-field loop).  Default 0 */
 } spi_opts;
 
 typedef struct spi_info_t {
@@ -179,6 +185,12 @@ typedef struct spi_info_t {
                                    products w_r h_rR h_rR^T and of the leaf
                                    updates L_Ul L_Ul^T on the exact
                                    structure, len (len + 1) per row or leaf */
+    int32_t root_assembly_mode; /* last spi_factor's root assembly: 0 all
+                                   panels, 1 all panels keeping A_RR
+                                   (opts.keep_root_sum), 2 the kept A_RR
+                                   plus the leaf fronts (after
+                                   spi_set_leaf_values) */
+    int32_t reserved;
 } spi_info_t;
 
 /* Fill `o` with the defaults listed above. */
@@ -225,6 +237,21 @@ int spi_analyze(spi_handle** h, int64_t m, int64_t n, const int64_t* rowptr,
 int spi_set_values(spi_handle* h, const double* val, const double* w);
 
 /*
+ * New values of H in the leaf-front columns only (in the coded-mask model,
+ * the background columns, the first K0 columns of H: App. A.5 updates them
+ * at each pass of the empty-field loop; Sect. 4.1 times such updates of
+ * A = H^T H).  `val` is a full device array like spi_set_values' (float64
+ * [nnz(H)], finite); the weights are kept.  The root block of A does not
+ * depend on leaf columns, so with opts.keep_root_sum = 1 the next
+ * spi_factor starts from the kept A_RR and assembles only the leaf fronts'
+ * updates.  The call compares the root entries of `val` with the values in
+ * use; if any differs, the next spi_factor assembles everything again (the
+ * result is right either way).  SPI_E_STATE before spi_set_values.
+ * Stream-ordered; invalidates any factor.
+ */
+int spi_set_leaf_values(spi_handle* h, const double* val);
+
+/*
  * Numerical factorisation (Sect. 3.2.2): assembles A = H^T W H directly into
  * the leaf fronts and the root front (extend-add of the leaf contribution
  * blocks), factors the leaf fronts, then treats the dense root: with
@@ -269,6 +296,25 @@ int spi_solve(spi_handle* h, const double* b, double* x, int32_t nrhs,
  * SPI_E_STATE if no valid factor.
  */
 int spi_diag_inv(spi_handle* h, double* d);
+
+/*
+ * General entries of A^-1, e.g. covariances between unknowns (Sect. 3.3.1:
+ * the entries a^-1_ij of the inverse that are requested; the diagonal gives
+ * the variances).  out[q] = (A^-1)_{rows[q], cols[q]}, original unknown
+ * order, unscaled.  Every entry is computed from the root block of A^-1
+ * (formed by spi_factor's sweeps, or from the Cholesky factor on the first
+ * call when root_inverse = 0) and the leaf panels, by the same relations as
+ * the selected inversion, one workgroup per entry: an entry between two
+ * leaf unknowns costs |U_g| |U_h| products (the root positions of their
+ * fronts), one with a root unknown |U_g|.
+ *  k           number of entries (>= 0)
+ *  rows, cols  device int32[k], each in [0, n) (copied to the host and
+ *              checked: SPI_E_ARG otherwise; this synchronises the stream)
+ *  out         device float64[k] (written)
+ * SPI_E_STATE without a valid factor.
+ */
+int spi_inv_entries(spi_handle* h, int64_t k, const int32_t* rows,
+                    const int32_t* cols, double* out);
 
 /*
  * spi_diag_inv for callers that cannot allocate device memory (code under
@@ -417,6 +463,99 @@ typedef struct spi_pcg_info {
 int spi_pcg_solve(spi_handle* band, spi_handle* ref, const spi_lp* lp,
                   const double* b, double* x, double tol, int32_t maxit,
                   spi_pcg_info* info);
+
+/* ------------------------------------------------------------------------
+ * Empty-field loop: the detector pattern computed with the solution
+ * ------------------------------------------------------------------------
+ * App. A.4-A.5.  In the paper's background model (Sect. 2.2.3) the
+ * background column of row i = (pointing p, detector d) holds U_u t_i: t_i
+ * the effective time, U_u the detector pattern of the row's unit u (its
+ * detector, or (detector, interval of pointings) for the per-interval
+ * variant), and x at that column the background intensity of the time bin.
+ * With x fixed, the pattern that minimises chi^2 for each unit is
+ *     LSQ: U_u = sum (y_i - D^S_i) g_i w_i / sum g_i^2 w_i,
+ *     MLE: U_u = sum (y_i - D^S_i) / sum g_i,
+ * sums over the unit's rows, g_i = x_bg(i) t_i, D^S_i the source part of
+ * (H x)_i and w_i the handle's weights (sigma_i^-2).  Arguments shared by
+ * both calls (all device memory unless stated):
+ *  val       float64[nnz(H)], H's values as given to spi_set_values (not
+ *            equilibrated); its background entries are rewritten
+ *  y         float64[m], the data
+ *  bg_pos    int64[m], CSR position of row i's background entry, -1 if none
+ *  t         float64[m], t_i
+ *  grp_ptr   int64[n_u + 1], grp_rows int32[grp_ptr[n_u]]: the rows of each
+ *            unit (CSR)
+ *  stat      0: LSQ, 1: MLE update
+ *  U         float64[n_u], the pattern (a unit whose rows give a zero
+ *            denominator keeps its value)
+ * Every sum runs in a fixed order, so results repeat bit for bit.
+ */
+
+/* One pattern update: chi2 (host, may be NULL) receives
+ * sum_i w_i (y_i - (H x)_i)^2 with `val` as given; then U is updated and the
+ * background entries of val set to U_u t_i.  Synchronises (chi2 read back).
+ *  x  float64[n], the current solution */
+int spi_empty_field_update(spi_handle* h, double* val, const double* y,
+                           const double* x, const int64_t* bg_pos, const double* t,
+                           const int64_t* grp_ptr, const int32_t* grp_rows,
+                           int32_t n_u, int32_t stat, double* U, double* chi2);
+
+/* Algorithm 1 (App. A.5).  The handle has had spi_set_values (the weights
+ * and the sky columns' values are taken from there).  Each pass sets the
+ * background entries to U_u t_i (spi_set_leaf_values: with
+ * opts.keep_root_sum = 1 the root front is re-assembled from the kept
+ * A_RR), factors, solves the LSQ problem for x (b = H^T W y), and takes
+ * chi^2 of that x; passes stop once chi^2 decreases by no more than rtol
+ * times its previous value, or after itermax passes; between passes U gets
+ * the closed-form update from x.  On return x, U and val are those of the
+ * last pass, d its variances diag(A^-1) (d may be NULL).
+ *  itermax >= 1, rtol >= 0
+ *  x          float64[n] (written)       d  float64[n] (written) or NULL
+ *  chi2_hist  host float64[itermax] or NULL: chi^2 of every pass
+ *  passes     host, may be NULL: passes run
+ */
+int spi_empty_field_loop(spi_handle* h, double* val, const double* y,
+                         const int64_t* bg_pos, const double* t,
+                         const int64_t* grp_ptr, const int32_t* grp_rows, int32_t n_u,
+                         int32_t stat, int32_t itermax, double rtol, double* U,
+                         double* x, double* d, double* chi2_hist, int32_t* passes);
+
+/* ------------------------------------------------------------------------
+ * Poisson likelihood fit (low counts): Newton's method on the solver
+ * ------------------------------------------------------------------------
+ * App. A.1-A.2.  With the model e = H x and counts y, the fit minimises
+ * C = 2 sum_i (e_i - y_i ln e_i) (the likelihood of App. A.1 with its sign
+ * turned; a row with y_i = 0 adds 2 e_i).  Its gradient is
+ * G = 2 H^T (1 - y/e) and half its Hessian H^T [y/e^2] H, the normal matrix
+ * of the same pattern with weights y_i / e_i^2, so every Newton step is a
+ * factorisation and a solve of this library.
+ *  val  device float64[nnz(H)], H's values (as given to spi_set_values)
+ *  y    device float64[m], the counts (>= 0)
+ */
+
+/* Terms at x (device float64[n]): cash (host, may be NULL) = C; w (device
+ * float64[m]) = y / e^2; g (device float64[n]) = H^T (y/e - 1) = -G/2, the
+ * Newton right-hand side (computed with the handle's values, which must be
+ * `val`).  SPI_E_ARG (cash = +inf) if some e_i <= 0.  Synchronises. */
+int spi_mle_terms(spi_handle* h, const double* val, const double* y, const double* x,
+                  double* w, double* g, double* cash);
+
+/* Newton's method from x (device float64[n], in: the start, e.g. the LSQ
+ * solution, App. A.2; out: the fit).  Each step sets the weights y/e^2
+ * (spi_set_values), factors, solves for the step dx from H^T (y/e - 1), and
+ * takes x + a dx: a = 1, halved while some e_i <= 0 or while C does not fall
+ * by at least 1e-4 a |G . dx| (taken whole once the predicted decrease
+ * |G . dx| is below 1e-12 |C|, which C cannot resolve).  Stops after a
+ * step with max|a dx| <= tol max|x|, or after itermax steps.  d (device
+ * float64[n] or NULL): diag of the inverse Hessian at the fit (App. A.2),
+ * after which the handle holds the Hessian's weights.
+ *  cash_hist  host float64[itermax + 1] or NULL: C at the start and after
+ *             every step;   steps  host, may be NULL: steps taken
+ * SPI_E_ARG if the start's model is not positive; SPI_E_NOCONV if the line
+ * search halves the step below 1e-10.  Synchronises. */
+int spi_mle_newton(spi_handle* h, const double* val, const double* y, double* x,
+                   int32_t itermax, double tol, double* d, double* cash_hist,
+                   int32_t* steps);
 
 /* ------------------------------------------------------------------------
  * Batches: many systems in flight together

@@ -18,8 +18,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["k_gemm.hip", "k_dense.hip", "k_sparse.hip", "k_learned.hip",
-               "api_noalloc.hip"]
-CPP_SOURCES = ["analysis.cpp", "api.cpp", "api_learned.cpp", "api_batch.cpp"]
+               "k_model.hip", "api_noalloc.hip"]
+CPP_SOURCES = ["analysis.cpp", "api.cpp", "api_learned.cpp", "api_batch.cpp",
+               "api_model.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           f"-I{os.path.join(PKG, '..', 'include')}"]

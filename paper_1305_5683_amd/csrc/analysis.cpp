@@ -38,7 +38,7 @@
 namespace spi {
 
 namespace {
-constexpr int kTile = 64;  // root assembly tile
+constexpr int kTile = kAsmTile;  // root assembly tile
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -423,6 +423,9 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   if (!curCols.empty()) close_front();
   a.n_groups = front;
 
+  a.leaf_of_col.assign(n, -1);
+  for (size_t l = 0; l < a.leaf_cols.size(); ++l) a.leaf_of_col[a.leaf_cols[l]] = (int32_t)l;
+
   phase("amalgamation");
   // ---- slots (rows of the leaf fronts, by leaf unknown) and their compact
   // root entries with U-local positions.  Sizes first, then every front
@@ -607,6 +610,14 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
             }
           }
       }
+    }
+    // the first row-panel incidence of each tile (leaf fronts, u < n_groups,
+    // come first: incidences are listed by increasing u)
+    a.inc_split.assign(a.n_tiles, 0);
+    for (int64_t t = 0; t < a.n_tiles; ++t) {
+      int64_t q = a.inc_ptr[t];
+      while (q < a.inc_ptr[t + 1] && a.inc[4 * q] < a.n_groups) ++q;
+      a.inc_split[t] = q;
     }
     // launch order: groups of 8 tile rows, column by column inside a group
     // (with the XCD remap, 64 consecutive tiles = an 8 x 8 block, run

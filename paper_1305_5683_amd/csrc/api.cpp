@@ -6,6 +6,7 @@
 #include <limits>
 #include <new>
 #include <sstream>
+#include <vector>
 
 #include "spi_internal.h"
 
@@ -106,12 +107,14 @@ void free_all(Handle& h) {
                   d.rinc_grp, d.rinc_u, d.tasks, d.grp_task_ptr, d.task_part_off,
                   d.sel_order, d.rp_rows, d.rp_rowbase, d.rpe_ptr, d.rpe_pos,
                   d.rpe_src, d.up_U_off, d.up_Q_off, d.up_nU, d.up_k,
-                  d.up_w_off, d.tile_order, d.inc_ptr, d.inc,
+                  d.up_w_off, d.tile_order, d.inc_ptr, d.inc, d.inc_split,
                   h.val, h.w, h.sw, h.sleaf, h.rrval, h.panel, h.ldiag, h.S,
                   h.invd, h.W, h.Z, h.part, h.flag, h.vleaf, h.vroot, h.vres,
                   h.vx, h.vdd, h.vnorm, h.vroot2, h.vpart, h.invd2,
-                  h.colscale, h.vbh, h.vxh, h.diagA, d.root_of_col, h.vfront,
-                  h.band, h.valc};
+                  h.colscale, h.vbh, h.vxh, h.diagA, d.root_of_col, d.leaf_of_col,
+                  h.vfront,
+                  h.band, h.valc, h.Akeep, h.vrow, h.vsum, h.vb2, h.vm1, h.vm2,
+                  h.vw, h.vr};
   free_lp_work(h);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -125,7 +128,8 @@ bool check_opts(spi_opts& o) {
   }
   if (o.max_group < 1 || o.refine_steps < 0 || !(o.amalg_density >= 0.0) ||
       !(o.refine_tol >= 0.0) || (o.keep_root_order != 0 && o.keep_root_order != 1) ||
-      o.leaf_lds_cap < 0 || o.leaf_lds_cap > kLeafLdsCapMax || o.selinv_chunk < 0) {
+      o.leaf_lds_cap < 0 || o.leaf_lds_cap > kLeafLdsCapMax || o.selinv_chunk < 0 ||
+      (o.keep_root_sum != 0 && o.keep_root_sum != 1)) {
     g_analyze_err = "invalid options";
     return false;
   }
@@ -153,7 +157,8 @@ int setup_device(spi_handle* H) {
   UP(rinc_grp); UP(rinc_u); UP(tasks); UP(grp_task_ptr); UP(task_part_off);
   UP(sel_order); UP(rp_rows); UP(rp_rowbase); UP(rpe_ptr); UP(rpe_pos);
   UP(rpe_src); UP(up_U_off); UP(up_Q_off); UP(up_nU); UP(up_k); UP(up_w_off);
-  UP(tile_order); UP(inc_ptr); UP(inc); UP(root_of_col);
+  UP(tile_order); UP(inc_ptr); UP(inc); UP(inc_split); UP(root_of_col);
+  UP(leaf_of_col);
 #undef UP
   const int64_t nl = (int64_t)a.leaf_cols.size();
   const int64_t np = a.n_pad;
@@ -165,6 +170,7 @@ int setup_device(spi_handle* H) {
   AL(h.panel, a.grp_panel_off.back() + a.rp_val_off.back());
   AL(h.ldiag, nl);
   AL(h.S, np * np);
+  if (h.opts.keep_root_sum) AL(h.Akeep, np * np);
   // the Cholesky route's buffers: the inverse factor, the root block of A^-1
   // and the inverses of the diagonal blocks (the sweeps need none of them)
   if (!h.opts.root_inverse) {
@@ -174,10 +180,12 @@ int setup_device(spi_handle* H) {
   h.band_nb = (int)std::min<int64_t>(512, np);
   AL(h.band, 4 * (int64_t)h.band_nb * np + 2 * (int64_t)h.band_nb * h.band_nb);
   AL(h.part, a.task_part_off.back());
-  AL(h.flag, 2); AL(h.vleaf, nl); AL(h.vfront, a.grp_U_ptr.back()); AL(h.vroot, np); AL(h.vres, a.n);
+  AL(h.flag, 4); AL(h.vleaf, nl); AL(h.vfront, a.grp_U_ptr.back()); AL(h.vroot, np); AL(h.vres, a.n);
   AL(h.vx, a.n); AL(h.vdd, 2 * a.m); AL(h.vnorm, 4);
   AL(h.vroot2, np); AL(h.vpart, root_inv_part_size(np));
   AL(h.colscale, a.n); AL(h.vbh, a.n); AL(h.vxh, a.n); AL(h.diagA, a.n);
+  AL(h.vrow, a.m); AL(h.vsum, sum_scratch_size()); AL(h.vb2, a.n);
+  AL(h.vm1, a.n); AL(h.vm2, a.n); AL(h.vw, a.m); AL(h.vr, a.m);
 #undef AL
   if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
   if (he != hipSuccess) {
@@ -204,18 +212,36 @@ bool refine_converged(double cur, double prev, double tol) {
 }
 
 
-int factor_enqueue(Handle& h) {
+int factor_enqueue(Handle& h, bool may_sync) {
   h.have_factor = false;
   h.have_inv = false;
+  h.z_valid = false;
   h.failed_col = -1;
+  // root assembly: everything (mode 0), everything keeping A_RR (1), or the
+  // kept A_RR plus the leaf fronts (2) after a leaf-only value change whose
+  // root entries were found unchanged
+  int mode = 0;
+  if (h.Akeep) {
+    mode = 1;
+    if (may_sync && h.akeep_valid && h.leaf_update) {
+      uint64_t changed = 1;
+      SPI_CK(hipMemcpyAsync(&changed, h.flag + 2, sizeof(changed),
+                            hipMemcpyDeviceToHost, h.stream), "update flag");
+      SPI_CK(hipStreamSynchronize(h.stream), "update flag");
+      if (!changed) mode = 2;
+    }
+  }
   SPI_CK(fill_i64(h.stream, h.flag, -1, 1), "flag");
   phase_begin(h, kPhLeaf);
   SPI_CK(launch_leaf_assemble(h), "leaf assembly");
   phase_end(h, kPhLeaf);
   if (h.an.n_pad) {
     phase_begin(h, kPhExtend);
-    SPI_CK(launch_assemble_root(h), "root assembly");
+    SPI_CK(launch_assemble_root(h, mode), "root assembly");
     phase_end(h, kPhExtend);
+    if (mode == 1) h.akeep_valid = true;
+    h.leaf_update = false;
+    h.last_asm_mode = mode;
     // root inverse wanted: sweeps turn S into A_RR^-1; otherwise Cholesky
     h.swept = h.opts.root_inverse != 0;
     phase_begin(h, kPhPotrf);
@@ -292,6 +318,7 @@ int diag_enqueue(Handle& h, double* d, double* part) {
     phase_begin(h, kPhLauum);
     SPI_CK(root_lauum(h), "root inverse product");
     phase_end(h, kPhLauum);
+    h.z_valid = true;
   }
   phase_begin(h, kPhSelinv);
   if (h.an.n_pad) SPI_CK(launch_diag_root(h, d), "root diagonal");
@@ -411,6 +438,29 @@ int spi_set_values(spi_handle* H, const double* val, const double* w) {
   h.have_values = true;
   h.have_factor = false;
   h.have_inv = false;
+  h.akeep_valid = false;
+  h.leaf_update = false;
+  return SPI_OK;
+}
+
+int spi_set_leaf_values(spi_handle* H, const double* val) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = H->h;
+  if (!val) return fail(h, SPI_E_ARG, hipSuccess, "null value pointer");
+  if (!h.have_values)
+    return fail(h, SPI_E_STATE, hipSuccess, "spi_set_leaf_values before spi_set_values");
+  SPI_CK(hipMemcpyAsync(h.val, val, h.an.nnz * sizeof(double),
+                        hipMemcpyDeviceToDevice, h.stream), "copy values");
+  // the weights are those of the last spi_set_values (already checked)
+  SPI_CK(fill_i64(h.stream, h.flag + 1, 0, 2), "input flags");
+  SPI_CK(launch_equilibrate(h), "diagonal / equilibration");
+  h.val32_ok = false;
+  SPI_CK(launch_gather_values(h), "gather values");
+  // rewrite the row panels comparing with the root entries in use
+  SPI_CK(launch_fill_rowpanels(h, true), "row panels");
+  h.have_factor = false;
+  h.have_inv = false;
+  h.leaf_update = true;
   return SPI_OK;
 }
 
@@ -419,7 +469,7 @@ int spi_factor(spi_handle* H) {
   Handle& h = H->h;
   if (!h.have_values)
     return fail(h, SPI_E_STATE, hipSuccess, "spi_factor before spi_set_values");
-  int st = factor_enqueue(h);
+  int st = factor_enqueue(h, true);
   if (st != SPI_OK) return st;
   uint64_t f[2] = {0, 0};
   SPI_CK(hipMemcpyAsync(f, h.flag, sizeof(f), hipMemcpyDeviceToHost, h.stream),
@@ -506,6 +556,39 @@ int spi_diag_inv(spi_handle* H, double* d) {
   if (!h.have_factor)
     return fail(h, SPI_E_STATE, hipSuccess, "spi_diag_inv without a valid factor");
   return diag_enqueue(h, d);
+}
+
+int spi_inv_entries(spi_handle* H, int64_t k, const int32_t* rows,
+                    const int32_t* cols, double* out) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = H->h;
+  if (k < 0 || (k > 0 && (!rows || !cols || !out)))
+    return fail(h, SPI_E_ARG, hipSuccess, "invalid inverse-entry arguments");
+  if (!h.have_factor)
+    return fail(h, SPI_E_STATE, hipSuccess, "spi_inv_entries without a valid factor");
+  if (k == 0) return SPI_OK;
+  // the requested columns, checked on the host
+  std::vector<int32_t> rc(2 * (size_t)k);
+  SPI_CK(hipMemcpyAsync(rc.data(), rows, k * sizeof(int32_t), hipMemcpyDeviceToHost,
+                        h.stream), "index readback");
+  SPI_CK(hipMemcpyAsync(rc.data() + k, cols, k * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, h.stream), "index readback");
+  SPI_CK(hipStreamSynchronize(h.stream), "index readback");
+  for (int32_t v : rc)
+    if (v < 0 || v >= h.an.n)
+      return fail(h, SPI_E_ARG, hipSuccess, "inverse-entry index out of range");
+  // the root block of A^-1: from the sweeps, or formed from the factor
+  h.Zr = h.swept ? h.S : h.Z;
+  if (h.an.n_pad && !h.swept && !h.z_valid) {
+    if (!h.have_inv) {
+      SPI_CK(root_trtri(h), "root factor inversion");
+      h.have_inv = true;
+    }
+    SPI_CK(root_lauum(h), "root inverse product");
+    h.z_valid = true;
+  }
+  SPI_CK(launch_inv_entries(h, rows, cols, out, k), "inverse entries");
+  return SPI_OK;
 }
 
 static void fill_analysis_info(const Analysis& a, spi_info_t* info) {
@@ -611,6 +694,7 @@ int spi_info(const spi_handle* Hc, spi_info_t* info) {
   info->t_selinv_ms = h.timer[kPhSelinv].total_ms;
   info->t_sweep_bulk_ms = h.timer[kPhBulk].total_ms;
   info->flops_sweep_bulk = h.bulk_flops;
+  info->root_assembly_mode = h.last_asm_mode;
   return SPI_OK;
 }
 

@@ -20,9 +20,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 // panel columns staged in LDS at a time by the selected-inversion tasks
 constexpr int kQC = 16;
-// threads of a root-assembly workgroup (8 waves share one LDS tile, so that
-// up to 8 waves per SIMD hide the latency of the small panel loads)
-constexpr int kAsmThreads = 512;
 
 // Grid of a grid-stride kernel (capped: the kernel loops).
 static int grid_for(int64_t items, int per_block) {
@@ -154,12 +151,14 @@ __global__ void k_zero(double* __restrict__ p, int64_t n) {
     p[i] = 0.0;
 }
 
+// With `changed`, the panel already holds the values in use: any new value
+// that differs sets *changed (one atomic per wave that saw one).
 __global__ __launch_bounds__(256) void k_fill_rowpanels(
     const double* __restrict__ val, const double* __restrict__ w,
     const int32_t* __restrict__ rp_rows, const int64_t* __restrict__ rp_rowbase,
     const int64_t* __restrict__ rpe_ptr, const int32_t* __restrict__ rpe_pos,
     const int64_t* __restrict__ rpe_src, double* __restrict__ rpbuf,
-    int64_t nrows) {
+    int64_t nrows, int64_t* changed) {
   const int lane = threadIdx.x & 63;
   const int64_t pr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (pr >= nrows) return;
@@ -167,42 +166,61 @@ __global__ __launch_bounds__(256) void k_fill_rowpanels(
   // rows are stored scaled by sqrt(w_r): the panel product is then
   // Q Q^T = sum_r w_r h_r h_r^T with no weights to load in the assembly
   const double sw = sqrt(w[rp_rows[pr]]);
-  for (int64_t e = rpe_ptr[pr] + lane; e < rpe_ptr[pr + 1]; e += 64)
-    col[rpe_pos[e]] = sw * val[rpe_src[e]];
+  bool diff = false;
+  for (int64_t e = rpe_ptr[pr] + lane; e < rpe_ptr[pr + 1]; e += 64) {
+    const double v = sw * val[rpe_src[e]];
+    if (changed) diff |= col[rpe_pos[e]] != v;
+    col[rpe_pos[e]] = v;
+  }
+  if (changed && __any(diff) && lane == 0) atomicOr((unsigned long long*)changed, 1ull);
 }
 
-hipError_t launch_fill_rowpanels(Handle& h) {
+hipError_t launch_fill_rowpanels(Handle& h, bool compare) {
   const Analysis& a = h.an;
   const int64_t nrows = (int64_t)a.rp_rows.size();
   if (!nrows) return hipSuccess;
   double* rpbuf = h.panel + a.grp_panel_off[a.n_groups];
   const int64_t total = a.rp_val_off[a.n_rp];
-  hipLaunchKernelGGL(k_zero, dim3(grid_for(total, 256 * 8)), dim3(256), 0,
-                     h.stream, rpbuf, total);
+  // (the positions of a panel that no row entry fills stay zero)
+  if (!compare)
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(total, 256 * 8)), dim3(256), 0,
+                       h.stream, rpbuf, total);
   hipLaunchKernelGGL(k_fill_rowpanels, dim3(wave_grid(nrows)), dim3(256), 0,
                      h.stream, h.val, h.w, h.d.rp_rows, h.d.rp_rowbase,
-                     h.d.rpe_ptr, h.d.rpe_pos, h.d.rpe_src, rpbuf, nrows);
+                     h.d.rpe_ptr, h.d.rpe_pos, h.d.rpe_src, rpbuf, nrows,
+                     compare ? h.flag + 2 : nullptr);
   return hipGetLastError();
 }
 
 // --------------------------------------------------------- root assembly
-// One workgroup per 64 x 64 lower tile (I, J) of the root front.  The tile
-// is the sum of its incidences: update panel u (a leaf front's panel L_Ug
-// with sign -1, or a row panel, stored as sqrt(w_r) h_r with sign +1)
-// restricted to the positions of U that fall in the tile's rows
+// One workgroup per kAsmTile x kAsmTile lower tile (I, J) of the root front.
+// The tile is the sum of its incidences: update panel u (a leaf front's
+// panel L_Ug with sign -1, or a row panel, stored as sqrt(w_r) h_r with sign
+// +1) restricted to the positions of U that fall in the tile's rows
 // (aI0 .. aI0 + nI) and columns (aJ0 .. aJ0 + nJ):
-//   C[U[a] - 64 I][U[b] - 64 J] += sign sum_q Q[a][q] Q[b][q].
+//   C[U[a] - TS I][U[b] - TS J] += sign sum_q Q[a][q] Q[b][q].
 // The tile's incidences are staged in LDS in chunks, with their panel and
 // index offsets resolved, so a wave's work on an incidence starts with no
 // dependent descriptor loads.  Each wave takes one incidence at a time and
 // computes it in 32 x 32 super-blocks of up to 2 x 2 blocks of 16 x 16 on
 // the FP64 matrix cores; all loads of a super-block (indices, kAsmKC panel
 // columns of both row blocks and both column blocks) are issued together
-// before its MFMAs, and each loaded panel row serves two products.  Results are added into the LDS tile
-// (LDS atomics, since waves work on different incidences); the tile is then
-// written once.
+// before its MFMAs, and each loaded panel row serves two products.  Results
+// are added into the LDS tile (LDS atomics, since waves work on different
+// incidences); the tile is then written once.  A panel row is read once per
+// tile pair it meets, so the larger the tile the fewer the reads: a 128-wide
+// tile (128 KB of LDS, one workgroup of 16 waves per CU) reads each row half
+// as often as a 64-wide one.
+//
+// Within a tile the leaf fronts' incidences come first ([beg, split)), the
+// row panels' after ([split, end)).  Modes:
+//   0  S = row panels + leaf fronts;
+//   1  the same, and the row panels' sum alone (A_RR, the root block of
+//      H^T W H) is also written to Akeep;
+//   2  S = Akeep + leaf fronts (only the leaf fronts' values changed).
 constexpr int kAsmChunk = 128;  // incidences staged per pass
 constexpr int kAsmKC = 20;      // panel columns per batch of loads
+constexpr int kAsmThreads = kAsmTile >= 128 ? 1024 : 512;
 
 // A wave-uniform 64-bit value moved to scalar registers.
 __device__ inline int64_t uniform64(int64_t x) {
@@ -212,14 +230,17 @@ __device__ inline int64_t uniform64(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+template <int TS>
 __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
     const int32_t* __restrict__ tile_order, const int64_t* __restrict__ inc_ptr,
+    const int64_t* __restrict__ inc_split,
     const int32_t* __restrict__ inc, const int64_t* __restrict__ up_U_off,
     const int64_t* __restrict__ up_Q_off, const int32_t* __restrict__ up_nU,
     const int32_t* __restrict__ up_k, const int32_t* __restrict__ up_w_off,
     const int32_t* __restrict__ U, const double* __restrict__ panel,
-    double* __restrict__ S, int64_t ld, int64_t n_root) {
-  __shared__ double C[kET][kET + 1];
+    double* __restrict__ S, double* __restrict__ Akeep, int64_t ld, int64_t n_root,
+    int mode) {
+  __shared__ double C[TS][TS + 1];
   __shared__ int64_t s_qa[kAsmChunk], s_qb[kAsmChunk];
   __shared__ int64_t s_ua[kAsmChunk], s_ub[kAsmChunk];
   __shared__ int32_t s_nU[kAsmChunk], s_k[kAsmChunk], s_w[kAsmChunk],
@@ -229,148 +250,172 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
   while (I * (I + 1) / 2 > t) --I;
   const int J = t - I * (I + 1) / 2;
-  const int64_t i0 = (int64_t)I * kET, j0 = (int64_t)J * kET;
+  const int64_t i0 = (int64_t)I * TS, j0 = (int64_t)J * TS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = kAsmThreads / 64;
-  for (int e = tid; e < kET * kET; e += kAsmThreads) {
-    const int a = e % kET, b = e / kET;
-    C[a][b] = (I == J && a == b && i0 + a >= n_root) ? 1.0 : 0.0;
+  if (mode == 2) {  // start from the kept A_RR tile
+    for (int e = tid; e < TS * TS; e += kAsmThreads) {
+      const int a = e % TS, b = e / TS;
+      C[a][b] = (I == J && a < b) ? 0.0 : Akeep[(i0 + a) + (j0 + b) * ld];
+    }
+  } else {
+    for (int e = tid; e < TS * TS; e += kAsmThreads) {
+      const int a = e % TS, b = e / TS;
+      C[a][b] = (I == J && a == b && i0 + a >= n_root) ? 1.0 : 0.0;
+    }
   }
   const int lx = lane & 15, lk = lane >> 4;
-  const int64_t q_beg = inc_ptr[t], q_end = inc_ptr[t + 1];
-  for (int64_t c0 = q_beg; c0 < q_end; c0 += kAsmChunk) {
-    const int nc = (int)min((int64_t)kAsmChunk, q_end - c0);
-    __syncthreads();  // previous chunk consumed (and C initialised)
-    if (tid < nc) {
-      const int32_t* p = inc + 4 * (c0 + tid);
-      const int u = p[0];
-      const int64_t qo = up_Q_off[u], uo = up_U_off[u];
-      s_qa[tid] = qo + p[1];
-      s_qb[tid] = qo + p[2];
-      s_ua[tid] = uo + p[1];
-      s_ub[tid] = uo + p[2];
-      s_nU[tid] = up_nU[u];
-      s_k[tid] = up_k[u];
-      s_w[tid] = up_w_off[u];
-      s_n[tid] = p[3];
-    }
-    __syncthreads();
-    for (int q = wave; q < nc; q += NW) {
-      // per-incidence values are wave-uniform: keep them in scalar registers
-      const double* Qa = panel + uniform64(s_qa[q]);
-      const double* Qb = panel + uniform64(s_qb[q]);
-      const int32_t* Ua = U + uniform64(s_ua[q]);
-      const int32_t* Ub = U + uniform64(s_ub[q]);
-      const int nU = __builtin_amdgcn_readfirstlane(s_nU[q]);
-      const int k = __builtin_amdgcn_readfirstlane(s_k[q]);
-      const int woff = __builtin_amdgcn_readfirstlane(s_w[q]);
-      const int nn = __builtin_amdgcn_readfirstlane(s_n[q]);
-      const int nI = nn & 0xffff, nJ = nn >> 16;
-      // 32 x 32 super-blocks of up to 2 x 2 blocks of 16 x 16: the panel
-      // rows of both row blocks and both column blocks are loaded once and
-      // shared by the (up to) four products.
-      for (int sa = 0; sa < nI; sa += 32)
-        for (int sb = 0; sb < nJ; sb += 32) {
-          const bool a2 = sa + 16 < nI, b2 = sb + 16 < nJ;  // wave-uniform
-          // Addresses are clamped into the incidence (and the panel) and the
-          // out-of-range values replaced afterwards, so every load is issued
-          // unconditionally and the whole batch is in flight at once.
-          int ac[2], bc[2], ra[2], rb[2][4];
-          bool va[2], vb[2];
-#pragma unroll
-          for (int x = 0; x < 2; ++x) {
-            const int a = sa + 16 * x + lx, b = sb + 16 * x + lx;
-            va[x] = a < nI;
-            vb[x] = b < nJ;
-            ac[x] = va[x] ? a : nI - 1;
-            bc[x] = vb[x] ? b : nJ - 1;
-          }
-          {
-            // the 32 root rows and 32 root columns of the super-block: one
-            // load per lane, handed to the lanes that need them by shuffles
-            const int la = min(sa + (lane & 31), nI - 1), lb = min(sb + (lane & 31), nJ - 1);
-            const int ua_l = Ua[la], ub_l = Ub[lb];
+  // Sum the incidences [q_beg, q_end) into C.
+  auto accumulate = [&](int64_t q_beg, int64_t q_end) {
+    for (int64_t c0 = q_beg; c0 < q_end; c0 += kAsmChunk) {
+      const int nc = (int)min((int64_t)kAsmChunk, q_end - c0);
+      __syncthreads();  // previous chunk consumed (and C initialised)
+      if (tid < nc) {
+        const int32_t* p = inc + 4 * (c0 + tid);
+        const int u = p[0];
+        const int64_t qo = up_Q_off[u], uo = up_U_off[u];
+        s_qa[tid] = qo + p[1];
+        s_qb[tid] = qo + p[2];
+        s_ua[tid] = uo + p[1];
+        s_ub[tid] = uo + p[2];
+        s_nU[tid] = up_nU[u];
+        s_k[tid] = up_k[u];
+        s_w[tid] = up_w_off[u];
+        s_n[tid] = p[3];
+      }
+      __syncthreads();
+      for (int q = wave; q < nc; q += NW) {
+        // per-incidence values are wave-uniform: keep them in scalar registers
+        const double* Qa = panel + uniform64(s_qa[q]);
+        const double* Qb = panel + uniform64(s_qb[q]);
+        const int32_t* Ua = U + uniform64(s_ua[q]);
+        const int32_t* Ub = U + uniform64(s_ub[q]);
+        const int nU = __builtin_amdgcn_readfirstlane(s_nU[q]);
+        const int k = __builtin_amdgcn_readfirstlane(s_k[q]);
+        const int woff = __builtin_amdgcn_readfirstlane(s_w[q]);
+        const int nn = __builtin_amdgcn_readfirstlane(s_n[q]);
+        const int nI = nn & 0xffff, nJ = nn >> 16;
+        // 32 x 32 super-blocks of up to 2 x 2 blocks of 16 x 16: the panel
+        // rows of both row blocks and both column blocks are loaded once and
+        // shared by the (up to) four products.
+        for (int sa = 0; sa < nI; sa += 32)
+          for (int sb = 0; sb < nJ; sb += 32) {
+            const bool a2 = sa + 16 < nI, b2 = sb + 16 < nJ;  // wave-uniform
+            // Addresses are clamped into the incidence (and the panel) and
+            // the out-of-range values replaced afterwards, so every load is
+            // issued unconditionally and the whole batch is in flight at once.
+            int ac[2], bc[2], ra[2], rb[2][4];
+            bool va[2], vb[2];
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-              ra[x] = __shfl(ua_l, 16 * x + lx, 64);
-#pragma unroll
-              for (int v = 0; v < 4; ++v) rb[x][v] = __shfl(ub_l, 16 * x + 4 * v + lk, 64);
+              const int a = sa + 16 * x + lx, b = sb + 16 * x + lx;
+              va[x] = a < nI;
+              vb[x] = b < nJ;
+              ac[x] = va[x] ? a : nI - 1;
+              bc[x] = vb[x] ? b : nJ - 1;
             }
-          }
-#pragma unroll
-          for (int x = 0; x < 2; ++x) {
-            ra[x] = va[x] ? ra[x] - (int)i0 : -1;
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-              rb[x][v] = (sb + 16 * x + 4 * v + lk < nJ) ? rb[x][v] - (int)j0 : -1;
-          }
-          v4d acc[2][2];
-#pragma unroll
-          for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-          for (int kc = 0; kc < k; kc += kAsmKC) {
-            double av[2][kAsmKC / 4], bv[2][kAsmKC / 4];
-#pragma unroll
-            for (int s = 0; s < kAsmKC / 4; ++s) {
-              const int qc = min(kc + 4 * s + lk, k - 1);
-              av[0][s] = Qa[ac[0] + qc * nU];
-              bv[0][s] = Qb[bc[0] + qc * nU];
-              av[1][s] = a2 ? Qa[ac[1] + qc * nU] : 0.0;
-              bv[1][s] = b2 ? Qb[bc[1] + qc * nU] : 0.0;
-            }
-#pragma unroll
-            for (int s = 0; s < kAsmKC / 4; ++s) {
-              const bool vq = kc + 4 * s + lk < k;
+            {
+              // the 32 root rows and 32 root columns of the super-block: one
+              // load per lane, handed to the lanes that need them by shuffles
+              const int la = min(sa + (lane & 31), nI - 1),
+                        lb = min(sb + (lane & 31), nJ - 1);
+              const int ua_l = Ua[la], ub_l = Ub[lb];
 #pragma unroll
               for (int x = 0; x < 2; ++x) {
-                av[x][s] = (vq && va[x]) ? (woff < 0 ? -av[x][s] : av[x][s]) : 0.0;
-                bv[x][s] = (vq && vb[x]) ? bv[x][s] : 0.0;
+                ra[x] = __shfl(ua_l, 16 * x + lx, 64);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) rb[x][v] = __shfl(ub_l, 16 * x + 4 * v + lk, 64);
               }
             }
-            // lane (lx, lk) item v of block (x, y): row sa + 16 x + lx,
-            // column sb + 16 y + 4 v + lk (operand order as in the root
-            // GEMM); steps past k have zero operands
 #pragma unroll
-            for (int s = 0; s < kAsmKC / 4; ++s) {
-              acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[0][s], av[0][s], acc[0][0], 0, 0, 0);
-              if (b2)
-                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[1][s], av[0][s], acc[0][1], 0, 0, 0);
-              if (a2) {
-                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[0][s], av[1][s], acc[1][0], 0, 0, 0);
-                if (b2)
-                  acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[1][s], av[1][s], acc[1][1], 0, 0, 0);
-              }
-            }
-          }
-#pragma unroll
-          for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < 2; ++y) {
-              if ((x == 1 && !a2) || (y == 1 && !b2) || ra[x] < 0) continue;
+            for (int x = 0; x < 2; ++x) {
+              ra[x] = va[x] ? ra[x] - (int)i0 : -1;
 #pragma unroll
               for (int v = 0; v < 4; ++v)
-                if (rb[y][v] >= 0 && (I != J || ra[x] >= rb[y][v]))
-                  atomicAdd(&C[ra[x]][rb[y][v]], acc[x][y][v]);
+                rb[x][v] = (sb + 16 * x + 4 * v + lk < nJ) ? rb[x][v] - (int)j0 : -1;
             }
-        }
+            v4d acc[2][2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+              for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int kc = 0; kc < k; kc += kAsmKC) {
+              double av[2][kAsmKC / 4], bv[2][kAsmKC / 4];
+#pragma unroll
+              for (int s = 0; s < kAsmKC / 4; ++s) {
+                const int qc = min(kc + 4 * s + lk, k - 1);
+                av[0][s] = Qa[ac[0] + qc * nU];
+                bv[0][s] = Qb[bc[0] + qc * nU];
+                av[1][s] = a2 ? Qa[ac[1] + qc * nU] : 0.0;
+                bv[1][s] = b2 ? Qb[bc[1] + qc * nU] : 0.0;
+              }
+#pragma unroll
+              for (int s = 0; s < kAsmKC / 4; ++s) {
+                const bool vq = kc + 4 * s + lk < k;
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+                  av[x][s] = (vq && va[x]) ? (woff < 0 ? -av[x][s] : av[x][s]) : 0.0;
+                  bv[x][s] = (vq && vb[x]) ? bv[x][s] : 0.0;
+                }
+              }
+              // lane (lx, lk) item v of block (x, y): row sa + 16 x + lx,
+              // column sb + 16 y + 4 v + lk (operand order as in the root
+              // GEMM); steps past k have zero operands
+#pragma unroll
+              for (int s = 0; s < kAsmKC / 4; ++s) {
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[0][s], av[0][s], acc[0][0], 0, 0, 0);
+                if (b2)
+                  acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[1][s], av[0][s], acc[0][1], 0, 0, 0);
+                if (a2) {
+                  acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[0][s], av[1][s], acc[1][0], 0, 0, 0);
+                  if (b2)
+                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[1][s], av[1][s], acc[1][1], 0, 0, 0);
+                }
+              }
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+              for (int y = 0; y < 2; ++y) {
+                if ((x == 1 && !a2) || (y == 1 && !b2) || ra[x] < 0) continue;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                  if (rb[y][v] >= 0 && (I != J || ra[x] >= rb[y][v]))
+                    atomicAdd(&C[ra[x]][rb[y][v]], acc[x][y][v]);
+              }
+          }
+      }
     }
+  };
+  auto write_tile = [&](double* out) {
+    __syncthreads();
+    for (int e = tid; e < TS * TS; e += kAsmThreads) {
+      const int a = e % TS, b = e / TS;
+      if (I == J && a < b) continue;
+      out[(i0 + a) + (j0 + b) * ld] = C[a][b];
+    }
+  };
+  const int64_t q_beg = inc_ptr[t], q_split = inc_split[t], q_end = inc_ptr[t + 1];
+  if (mode == 1) {
+    accumulate(q_split, q_end);  // row panels: A_RR
+    write_tile(Akeep);
+    accumulate(q_beg, q_split);  // leaf fronts
+  } else if (mode == 2) {
+    accumulate(q_beg, q_split);
+  } else {
+    accumulate(q_beg, q_end);
   }
-  __syncthreads();
-  for (int e = tid; e < kET * kET; e += kAsmThreads) {
-    const int a = e % kET, b = e / kET;
-    if (I == J && a < b) continue;
-    S[(i0 + a) + (j0 + b) * ld] = C[a][b];
-  }
+  write_tile(S);
 }
 
-hipError_t launch_assemble_root(Handle& h) {
+hipError_t launch_assemble_root(Handle& h, int mode) {
   const Analysis& a = h.an;
   if (!a.n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_assemble_root, dim3((unsigned)a.n_tiles), dim3(kAsmThreads), 0,
-                     h.stream, h.d.tile_order, h.d.inc_ptr, h.d.inc, h.d.up_U_off,
-                     h.d.up_Q_off, h.d.up_nU, h.d.up_k, h.d.up_w_off, h.d.U,
-                     h.panel, h.S, a.n_pad, a.n_root);
+  hipLaunchKernelGGL(k_assemble_root<kAsmTile>, dim3((unsigned)a.n_tiles),
+                     dim3(kAsmThreads), 0, h.stream, h.d.tile_order, h.d.inc_ptr,
+                     h.d.inc_split, h.d.inc, h.d.up_U_off, h.d.up_Q_off, h.d.up_nU,
+                     h.d.up_k, h.d.up_w_off, h.d.U, h.panel, h.S, h.Akeep, a.n_pad,
+                     a.n_root, mode);
   return hipGetLastError();
 }
 
@@ -797,6 +842,95 @@ hipError_t launch_diag_root(Handle& h, double* d) {
   hipLaunchKernelGGL(k_diag_root, dim3(grid_for(h.an.n_root, 256)), dim3(256),
                      0, h.stream, h.Zr, h.an.n_pad, h.d.root_cols, d,
                      h.an.n_root);
+  return hipGetLastError();
+}
+
+// General entries of A^-1 (covariances), one workgroup per requested entry
+// (i, j), from the root block Z' = (S A S)^-1 restricted to the root and
+// the leaf panels (the same relations as the leaf selected inversion: for a
+// leaf l of front g with panel column c_l over U_g and pivot L_ll,
+//   Z'_{r,l} = -(Z'_{r,U_g} c_l) / L_ll              (r a root unknown),
+//   Z'_{l,k} = [l = k] / L_ll^2 + c_l^T Z'_{U_g,U_h} c_k / (L_ll L_kk)
+// for leaves l, k of fronts g, h), then (A^-1)_ij = s_i s_j Z'_ij with the
+// equilibration scales.  Z' is read from its lower storage.
+__device__ inline double zlow(const double* Z, int64_t ld, int64_t a, int64_t b) {
+  return a >= b ? Z[a + b * ld] : Z[b + a * ld];
+}
+
+__global__ __launch_bounds__(256) void k_inv_entries(
+    const int32_t* __restrict__ rows, const int32_t* __restrict__ cols,
+    const int32_t* __restrict__ root_of_col, const int32_t* __restrict__ leaf_of_col,
+    const int32_t* __restrict__ leaf_grp, const int64_t* __restrict__ grp_col_ptr,
+    const int64_t* __restrict__ grp_U_ptr, const int32_t* __restrict__ U,
+    const int64_t* __restrict__ grp_panel_off, const double* __restrict__ panel,
+    const double* __restrict__ ldiag, const double* __restrict__ Z, int64_t ld,
+    const double* __restrict__ scale, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int64_t k = blockIdx.x;
+  const int tid = threadIdx.x;
+  int32_t i = rows[k], j = cols[k];
+  int32_t ri = root_of_col[i], rj = root_of_col[j];
+  if (ri >= 0 && rj < 0) {  // leaf first
+    const int32_t x = i; i = j; j = x;
+    ri = root_of_col[i];
+    rj = root_of_col[j];
+  }
+  const double sij = scale ? scale[i] * scale[j] : 1.0;
+  double v = 0.0;
+  if (ri >= 0) {  // both root
+    if (tid == 0) out[k] = sij * zlow(Z, ld, ri, rj);
+    return;
+  }
+  // i is a leaf: front g, panel column c_l over U_g
+  const int32_t l = leaf_of_col[i];
+  const int32_t g = leaf_grp[l];
+  const int64_t ug = grp_U_ptr[g], nUg = grp_U_ptr[g + 1] - ug;
+  const double* cl = panel + grp_panel_off[g] + (l - grp_col_ptr[g]) * nUg;
+  const double Lll = ldiag[l];
+  if (rj >= 0) {  // leaf-root
+    for (int64_t a = tid; a < nUg; a += 256) v += zlow(Z, ld, U[ug + a], rj) * cl[a];
+  } else {        // leaf-leaf
+    const int32_t q = leaf_of_col[j];
+    const int32_t gh = leaf_grp[q];
+    const int64_t uh = grp_U_ptr[gh], nUh = grp_U_ptr[gh + 1] - uh;
+    const double* ck = panel + grp_panel_off[gh] + (q - grp_col_ptr[gh]) * nUh;
+    for (int64_t b = tid; b < nUh; b += 256) {
+      const int64_t rb = U[uh + b];
+      const double cb = ck[b];
+      double t = 0.0;
+      for (int64_t a = 0; a < nUg; ++a) t += cl[a] * zlow(Z, ld, U[ug + a], rb);
+      v += t * cb;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    const double s = (red[0] + red[1]) + (red[2] + red[3]);
+    double r;
+    if (rj >= 0) {
+      r = -s / Lll;
+    } else {
+      const int32_t q = leaf_of_col[j];
+      const double Lkk = ldiag[q];
+      r = s / (Lll * Lkk) + (q == l ? 1.0 / (Lll * Lll) : 0.0);
+    }
+    out[k] = sij * r;
+  }
+}
+
+hipError_t launch_inv_entries(Handle& h, const int32_t* rows, const int32_t* cols,
+                              double* out, int64_t k) {
+  if (k <= 0) return hipSuccess;
+  const int64_t chunk = int64_t(1) << 24;
+  for (int64_t k0 = 0; k0 < k; k0 += chunk) {
+    const int64_t c = std::min(chunk, k - k0);
+    hipLaunchKernelGGL(k_inv_entries, dim3((unsigned)c), dim3(256), 0, h.stream,
+                       rows + k0, cols + k0, h.d.root_of_col, h.d.leaf_of_col,
+                       h.d.leaf_grp, h.d.grp_col_ptr, h.d.grp_U_ptr, h.d.U,
+                       h.d.grp_panel_off, h.panel, h.ldiag, h.Zr, h.an.n_pad,
+                       h.opts.equilibrate ? h.colscale : nullptr, out + k0);
+  }
   return hipGetLastError();
 }
 

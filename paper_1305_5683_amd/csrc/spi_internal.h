@@ -23,6 +23,13 @@ constexpr int kNB = 64;
 constexpr int kET = 64;
 // Rows of the dense root triangular-solve chunks.
 constexpr int kTrsvChunk = 512;
+// Edge of the root tiles the output-stationary assembly sums in LDS (a
+// 128 x 128 FP64 tile is 128 KB of the CU's 160 KB).  Every panel row is
+// read once per tile pair it meets, so larger tiles read less.
+#ifndef SPI_ASM_TILE
+#define SPI_ASM_TILE 128
+#endif
+constexpr int kAsmTile = SPI_ASM_TILE;
 // Widest leaf front (root positions) accumulated in LDS by the leaf
 // assembly: 4 waves x 2048 x 8 B = 64 KB per workgroup.
 constexpr int kLeafLdsCapMax = 2048;
@@ -81,15 +88,18 @@ struct Analysis {
   std::vector<int32_t> up_nU;
   std::vector<int32_t> up_k;
   std::vector<int32_t> up_w_off;       // -1: leaf panel (sign -1); else row panel
-  // incidences of the update panels on the 64 x 64 lower tiles of the root
-  int64_t n_tiles = 0;                 // T (T + 1) / 2, T = n_pad / 64
-  std::vector<int32_t> tile_order;     // tiles by decreasing work
+  // incidences of the update panels on the kAsmTile x kAsmTile lower tiles
+  // of the root; within a tile the leaf fronts' incidences come first
+  int64_t n_tiles = 0;                 // T (T + 1) / 2, T = n_pad / kAsmTile
+  std::vector<int32_t> tile_order;     // launch order of the tiles
   std::vector<int64_t> inc_ptr;        // n_tiles + 1
+  std::vector<int64_t> inc_split;      // n_tiles: first row-panel incidence
   std::vector<int32_t> inc;            // 4 per incidence: up, aI0, aJ0, nI|nJ<<16
   // root
   int64_t n_root = 0, n_pad = 0;
   std::vector<int32_t> root_cols;      // original column of root index i
   std::vector<int32_t> root_of_col;    // n, root index or -1
+  std::vector<int32_t> leaf_of_col;    // n, leaf index or -1
   // root incidences (transpose of the U lists): for root index i the
   // (front, U-local position) pairs, as global panel row offsets
   std::vector<int64_t> rinc_ptr;       // n_root + 1
@@ -156,8 +166,10 @@ struct DevAnalysis {
   int32_t* up_w_off = nullptr;
   int32_t* tile_order = nullptr;
   int64_t* inc_ptr = nullptr;
+  int64_t* inc_split = nullptr;
   int32_t* inc = nullptr;
   int32_t* root_of_col = nullptr;  // n: root index of a column, -1 for leaves
+  int32_t* leaf_of_col = nullptr;  // n: leaf index of a column, -1 for the root
 };
 
 enum Phase { kPhLeaf = 0, kPhExtend, kPhPotrf, kPhSolve, kPhTrtri, kPhLauum,
@@ -189,6 +201,10 @@ struct Handle {
                              // followed by the dense row panels
   double* ldiag = nullptr;   // leaf pivots L_ll
   double* S = nullptr;       // root front n_pad x n_pad, column-major; L after factor
+  double* Akeep = nullptr;   // opts.keep_root_sum: A_RR (row panels only), lower tiles
+  bool akeep_valid = false;  // Akeep holds A_RR of the current root values
+  bool leaf_update = false;  // values last set by spi_set_leaf_values
+  int last_asm_mode = 0;     // root assembly mode of the last factorisation
   double* invd = nullptr;    // inverses of the kNB diagonal blocks of L_RR
   double* W = nullptr;       // L_RR^-1 (selected inversion scratch)
   double* invd2 = nullptr;   // inverses of the 256 x 256 diagonal blocks
@@ -199,10 +215,13 @@ struct Handle {
                              // 2 pivot blocks band_nb x band_nb
   int band_nb = 0;           // widest band: min(512, n_pad)
   bool swept = false;        // S holds A_RR^-1 (sweeps) instead of L_RR
+  bool z_valid = false;      // Cholesky route: Z holds A_RR^-1 of the factor
   double* Zr = nullptr;      // where the root block of A^-1 is: S or Z
   double* part = nullptr;    // selected-inversion partial sums
   int64_t* flag = nullptr;   // [0] first failing pivot in elimination
-                             // order, [1] non-finite input seen
+                             // order, [1] non-finite input seen, [2] root
+                             // entries changed by spi_set_leaf_values,
+                             // [3] a non-positive model value (likelihood)
   // solve scratch
   double* vleaf = nullptr;   // n_leaf
   double* vfront = nullptr;  // sum of |U| over leaf fronts: L_Ug y_g
@@ -218,6 +237,13 @@ struct Handle {
   double* vbh = nullptr;     // n: scaled right-hand side S b
   double* vxh = nullptr;     // n: solution of the scaled system
   double* diagA = nullptr;   // n: diagonal of A = H^T W H (unscaled)
+  double* vrow = nullptr;    // m: per-row terms of the model loops
+  double* vsum = nullptr;    // fixed-order sum partials (sum_scratch_size())
+  double* vb2 = nullptr;     // n: right-hand side inside the model loops
+  double* vm1 = nullptr;     // n: Newton step
+  double* vm2 = nullptr;     // n: trial point
+  double* vw = nullptr;      // m: Newton weights
+  double* vr = nullptr;      // m: d/e - 1
   // scratch of the learned preconditioner and of PCG, allocated on first use
   struct LpWork {
     float* v32 = nullptr;                   // nnz: H in binary32
@@ -263,7 +289,9 @@ void free_lp_work(Handle& h);
 // Stream-ordered pieces of the entry points (api.cpp): enqueue the work
 // with no host synchronisation; factor_finish interprets the pivot flag
 // once the factorisation has completed.
-int factor_enqueue(Handle& h);
+// may_sync: the root assembly may read a flag back to decide whether the
+// kept A_RR still holds (not under graph capture)
+int factor_enqueue(Handle& h, bool may_sync = false);
 int factor_finish(Handle& h, const uint64_t* flag);
 bool refine_converged(double cur, double prev, double tol);
 int solve_enqueue(Handle& h, const double* b, double* x, int steps);
@@ -290,8 +318,12 @@ __device__ inline int xcd_remap(int w, int n) {
 // kernel launchers (stream-ordered); return hipError_t of the launch
 hipError_t launch_gather_values(Handle& h);
 hipError_t launch_leaf_assemble(Handle& h);
-hipError_t launch_fill_rowpanels(Handle& h);
-hipError_t launch_assemble_root(Handle& h);
+// compare: the panels already hold the root entries in use; flag[2] is set
+// if a new value differs (no zeroing first)
+hipError_t launch_fill_rowpanels(Handle& h, bool compare = false);
+// mode 0: S from all panels; 1: also keep A_RR in h.Akeep; 2: S from the
+// kept A_RR and the leaf fronts only
+hipError_t launch_assemble_root(Handle& h, int mode);
 hipError_t launch_rhs(Handle& h, const double* y, double* b);
 hipError_t root_potrf(Handle& h);
 hipError_t root_trsv_fwd(Handle& h, double* z);
@@ -313,6 +345,10 @@ hipError_t launch_axpy_norms(Handle& h, double* x, const double* dx,
 hipError_t launch_check_finite(Handle& h, const double* v, int64_t n);
 hipError_t launch_selinv_leaves(Handle& h, double* d, double* part);
 hipError_t launch_diag_root(Handle& h, double* d);
+// out[k] = (A^-1)_{rows[k], cols[k]} from the root block of A^-1 (h.Zr) and
+// the leaf panels (columns validated by the caller)
+hipError_t launch_inv_entries(Handle& h, const int32_t* rows, const int32_t* cols,
+                              double* out, int64_t k);
 hipError_t launch_equilibrate(Handle& h);
 // y = s x (mode 0), x / s (mode 1), s^2 x (mode 2) with the column scales
 hipError_t launch_scale_vec(Handle& h, const double* x, double* y, int mode);
@@ -334,6 +370,29 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
                 double beta, bool lower, bool kstart_diag,
                 bool diag_mask = false, bool f32 = false,
                 int kmask = 0, GemmSkip skip = GemmSkip(), int ksplit = 0);
+
+// model-level loops (k_model.hip): empty-field pattern, fixed-order sums
+int64_t sum_scratch_size();
+hipError_t launch_sum(hipStream_t s, const double* v, int64_t n, double* part);
+hipError_t launch_ef_rows(Handle& h, const double* val, const double* y,
+                          const double* x, const int64_t* bg_pos, const double* t,
+                          int stat);
+hipError_t launch_ef_units(Handle& h, const int64_t* grp_ptr, const int32_t* grp_rows,
+                           int n_u, const int64_t* bg_pos, const double* t, double* U,
+                           double* val, bool update);
+
+// Poisson likelihood (k_model.hip): per-row terms into h.vrow (c), w, r;
+// flag[3] set if some e_i <= 0
+hipError_t launch_cash_rows(Handle& h, const double* val, const double* x,
+                            const double* y, double* w, double* r);
+hipError_t launch_htr(Handle& h, const double* r, double* g);
+// sum of a_i b_i into h.vsum[sum_scratch_size() - 1] (tmp: n doubles)
+hipError_t launch_dot(Handle& h, const double* a, const double* b, double* tmp,
+                      int64_t n);
+hipError_t launch_axpy_to(Handle& h, const double* x, double a, const double* dx,
+                          double* xt);
+hipError_t launch_maxabs2(Handle& h, const double* dx, double a, const double* x,
+                          double* nm);
 
 // learned preconditioner and PCG (k_learned.hip)
 int64_t lp_param_count(int hidden);

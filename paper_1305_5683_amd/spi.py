@@ -26,7 +26,9 @@ EXPORTED = ["spi_default_opts", "spi_analyze", "spi_set_values", "spi_factor",
             "spi_lp_train_step", "spi_lp_destroy", "spi_pcg_solve",
             "spi_analyze_like", "spi_batch_create", "spi_batch_run",
             "spi_batch_destroy", "spi_autotune", "spi_get_potrf_block",
-            "spi_set_potrf_block", "spi_diag_inv_noalloc"]
+            "spi_set_potrf_block", "spi_diag_inv_noalloc", "spi_set_leaf_values",
+            "spi_empty_field_update", "spi_empty_field_loop", "spi_mle_terms",
+            "spi_mle_newton", "spi_inv_entries"]
 
 
 class spi_opts(C.Structure):
@@ -35,7 +37,8 @@ class spi_opts(C.Structure):
                 ("refine_steps", C.c_int32), ("timing", C.c_int32),
                 ("root_inverse", C.c_int32), ("equilibrate", C.c_int32),
                 ("refine_tol", C.c_double), ("keep_root_order", C.c_int32),
-                ("leaf_lds_cap", C.c_int32), ("selinv_chunk", C.c_int32)]
+                ("leaf_lds_cap", C.c_int32), ("selinv_chunk", C.c_int32),
+                ("keep_root_sum", C.c_int32)]
 
 
 class spi_info_t(C.Structure):
@@ -53,10 +56,11 @@ class spi_info_t(C.Structure):
                 ("t_lauum_ms", C.c_double), ("t_selinv_ms", C.c_double),
                 ("t_sweep_bulk_ms", C.c_double), ("flops_sweep_bulk", C.c_double),
                 ("flops_exec_assembly", C.c_double), ("flops_exec_selinv", C.c_double),
-                ("flops_root_assembly", C.c_double)]
+                ("flops_root_assembly", C.c_double),
+                ("root_assembly_mode", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class spi_pcg_info(C.Structure):
@@ -92,11 +96,19 @@ def load_library(path: str = LIB_PATH):
     lib.spi_analyze.argtypes = [C.POINTER(C.c_void_p), I64, I64, P, P,
                                 C.POINTER(spi_opts), P]
     lib.spi_set_values.argtypes = [P, P, P]
+    lib.spi_set_leaf_values.argtypes = [P, P]
+    lib.spi_empty_field_update.argtypes = [P, P, P, P, P, P, P, P, I32, I32, P,
+                                           C.POINTER(D)]
+    lib.spi_empty_field_loop.argtypes = [P, P, P, P, P, P, P, I32, I32, I32, D, P,
+                                         P, P, P, C.POINTER(I32)]
+    lib.spi_mle_terms.argtypes = [P, P, P, P, P, P, C.POINTER(D)]
+    lib.spi_mle_newton.argtypes = [P, P, P, P, I32, D, P, P, C.POINTER(I32)]
     lib.spi_factor.argtypes = [P]
     lib.spi_rhs.argtypes = [P, P, P]
     lib.spi_solve.argtypes = [P, P, P, I32, I64]
     lib.spi_diag_inv.argtypes = [P, P]
     lib.spi_diag_inv_noalloc.argtypes = [P, P]
+    lib.spi_inv_entries.argtypes = [P, I64, P, P, P]
     lib.spi_symbolic.argtypes = [I64, I64, P, P, C.POINTER(spi_opts),
                                  C.POINTER(spi_info_t), P, P, P]
     lib.spi_info.argtypes = [P, C.POINTER(spi_info_t)]
@@ -240,6 +252,12 @@ class SpiSolver:
             self.h, _ptr(val, self.nnz, torch.float64),
             _ptr(w, self.m, torch.float64)))
 
+    def set_leaf_values(self, val):
+        """New values in the leaf-front (background) columns only."""
+        import torch
+        self._check(self.lib.spi_set_leaf_values(
+            self.h, _ptr(val, self.nnz, torch.float64)))
+
     def factor(self):
         self._check(self.lib.spi_factor(self.h))
 
@@ -268,6 +286,21 @@ class SpiSolver:
         self._check(self.lib.spi_diag_inv(self.h, _ptr(d, self.n, torch.float64)))
         return d
 
+    def inv_entries(self, rows, cols):
+        """(A^-1)_{rows[q], cols[q]} (device int32 tensors) as a device tensor."""
+        import torch
+        k = int(rows.numel())
+        if cols.numel() != k:
+            raise ValueError("rows and cols differ in length")
+        out = torch.empty(k, dtype=torch.float64, device=rows.device)
+        if k:
+            self._check(self.lib.spi_inv_entries(
+                self.h, k, _ptr(rows, k, torch.int32), _ptr(cols, k, torch.int32),
+                _ptr(out, k, torch.float64)))
+        else:
+            self._check(self.lib.spi_inv_entries(self.h, 0, None, None, None))
+        return out
+
     def diag_inv_noalloc(self, out):
         """diag(A^-1) into ``out`` with the library's fixed scratch array
         (no device allocation; see spi_diag_inv_noalloc)."""
@@ -291,6 +324,88 @@ class SpiSolver:
             self.close()
         except Exception:
             pass
+
+
+class EmptyField:
+    """Device arrays of the empty-field loop (App. A.4-A.5) for one handle:
+    background positions, effective times and the rows of each pattern
+    unit (see spi_empty_field_update in spi.h)."""
+
+    def __init__(self, solver: "SpiSolver", bg_pos, t, grp_ptr, grp_rows, stat=0):
+        import torch
+        dev = torch.device("cuda")
+        self.s = solver
+        self.bg_pos = torch.as_tensor(np.asarray(bg_pos, np.int64), device=dev)
+        self.t = torch.as_tensor(np.asarray(t, np.float64), device=dev)
+        self.grp_ptr = torch.as_tensor(np.asarray(grp_ptr, np.int64), device=dev)
+        self.grp_rows = torch.as_tensor(np.asarray(grp_rows, np.int32), device=dev)
+        self.n_u = int(len(grp_ptr) - 1)
+        self.stat = int(stat)
+
+    def _args(self):
+        import torch
+        s = self.s
+        return (_ptr(self.bg_pos, s.m, torch.int64), _ptr(self.t, s.m, torch.float64),
+                _ptr(self.grp_ptr, self.n_u + 1, torch.int64),
+                _ptr(self.grp_rows, None, torch.int32), self.n_u, self.stat)
+
+    def update(self, val, y, x, U):
+        """One closed-form pattern update (U and val's background entries
+        in place); returns chi^2 of x with the values before the update."""
+        import torch
+        s = self.s
+        c = C.c_double()
+        bg, t, gp, gr, nu, st = self._args()
+        s._check(s.lib.spi_empty_field_update(
+            s.h, _ptr(val, s.nnz, torch.float64), _ptr(y, s.m, torch.float64),
+            _ptr(x, s.n, torch.float64), bg, t, gp, gr, nu, st,
+            _ptr(U, nu, torch.float64), C.byref(c)))
+        return c.value
+
+    def loop(self, val, y, U, itermax=20, rtol=1e-6, want_diag=True):
+        """Algorithm 1; returns (x, d or None, chi^2 per pass)."""
+        import torch
+        s = self.s
+        x = torch.empty(s.n, dtype=torch.float64, device=y.device)
+        d = torch.empty_like(x) if want_diag else None
+        hist = np.zeros(itermax)
+        npass = C.c_int32()
+        bg, t, gp, gr, nu, st = self._args()
+        s._check(s.lib.spi_empty_field_loop(
+            s.h, _ptr(val, s.nnz, torch.float64), _ptr(y, s.m, torch.float64),
+            bg, t, gp, gr, nu, st, int(itermax), float(rtol),
+            _ptr(U, nu, torch.float64), _ptr(x, s.n, torch.float64),
+            None if d is None else _ptr(d, s.n, torch.float64),
+            hist.ctypes.data, C.byref(npass)))
+        return x, d, hist[:npass.value]
+
+
+def mle_terms(s: "SpiSolver", val, y, x):
+    """Likelihood terms at x: (C, weights y/e^2, H^T (y/e - 1))."""
+    import torch
+    w = torch.empty(s.m, dtype=torch.float64, device=x.device)
+    g = torch.empty(s.n, dtype=torch.float64, device=x.device)
+    c = C.c_double()
+    s._check(s.lib.spi_mle_terms(s.h, _ptr(val, s.nnz, torch.float64),
+                                 _ptr(y, s.m, torch.float64),
+                                 _ptr(x, s.n, torch.float64),
+                                 _ptr(w, s.m, torch.float64),
+                                 _ptr(g, s.n, torch.float64), C.byref(c)))
+    return c.value, w, g
+
+
+def mle_newton(s: "SpiSolver", val, y, x, itermax=20, tol=1e-10, want_diag=True):
+    """Newton's method from x (in place); returns (x, d or None, C per step)."""
+    import torch
+    d = torch.empty(s.n, dtype=torch.float64, device=x.device) if want_diag else None
+    hist = np.zeros(itermax + 1)
+    steps = C.c_int32()
+    s._check(s.lib.spi_mle_newton(
+        s.h, _ptr(val, s.nnz, torch.float64), _ptr(y, s.m, torch.float64),
+        _ptr(x, s.n, torch.float64), int(itermax), float(tol),
+        None if d is None else _ptr(d, s.n, torch.float64), hist.ctypes.data,
+        C.byref(steps)))
+    return x, d, hist[:steps.value + 1]
 
 
 class SpiLearnedPrecond:
