@@ -207,10 +207,7 @@ hipError_t launch_fill_rowpanels(Handle& h, bool compare) {
 // columns of both row blocks and both column blocks) are issued together
 // before its MFMAs, and each loaded panel row serves two products.  Results
 // are added into the LDS tile (LDS atomics, since waves work on different
-// incidences); the tile is then written once.  A panel row is read once per
-// tile pair it meets, so the larger the tile the fewer the reads: a 128-wide
-// tile (128 KB of LDS, one workgroup of 16 waves per CU) reads each row half
-// as often as a 64-wide one.
+// incidences); the tile is then written once.
 //
 // Within a tile the leaf fronts' incidences come first ([beg, split)), the
 // row panels' after ([split, end)).  Modes:

@@ -23,11 +23,14 @@ constexpr int kNB = 64;
 constexpr int kET = 64;
 // Rows of the dense root triangular-solve chunks.
 constexpr int kTrsvChunk = 512;
-// Edge of the root tiles the output-stationary assembly sums in LDS (a
-// 128 x 128 FP64 tile is 128 KB of the CU's 160 KB).  Every panel row is
-// read once per tile pair it meets, so larger tiles read less.
+// Edge of the root tiles the output-stationary assembly sums in LDS.  Every
+// panel row is read once per tile pair it meets, so larger tiles read less;
+// but 128 x 128 (128 KB of the CU's 160 KB: one workgroup of 16 waves per
+// CU) measured slower than 64 x 64 (two workgroups of 8 waves per CU) on
+// the medium workload (6.4 against 5.5 ms) and equal on the large one
+// (562 ms): the kernel waits on load latency, not on the bytes.
 #ifndef SPI_ASM_TILE
-#define SPI_ASM_TILE 128
+#define SPI_ASM_TILE 64
 #endif
 constexpr int kAsmTile = SPI_ASM_TILE;
 // Widest leaf front (root positions) accumulated in LDS by the leaf
