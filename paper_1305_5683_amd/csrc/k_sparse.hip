@@ -301,15 +301,18 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
             // Addresses are clamped into the incidence (and the panel) and
             // the out-of-range values replaced afterwards, so every load is
             // issued unconditionally and the whole batch is in flight at once.
+            // Rows and columns past the incidence read a clamped (valid)
+            // position and their products land only in output rows or
+            // columns that are dropped below, so only the steps past k
+            // need zero operands (one side suffices).
             int ac[2], bc[2], ra[2], rb[2][4];
-            bool va[2], vb[2];
+            bool va[2];
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
               const int a = sa + 16 * x + lx, b = sb + 16 * x + lx;
               va[x] = a < nI;
-              vb[x] = b < nJ;
-              ac[x] = va[x] ? a : nI - 1;
-              bc[x] = vb[x] ? b : nJ - 1;
+              ac[x] = min(a, nI - 1);
+              bc[x] = min(b, nJ - 1);
             }
             {
               // the 32 root rows and 32 root columns of the super-block: one
@@ -350,10 +353,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
               for (int s = 0; s < kAsmKC / 4; ++s) {
                 const bool vq = kc + 4 * s + lk < k;
 #pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                  av[x][s] = (vq && va[x]) ? (woff < 0 ? -av[x][s] : av[x][s]) : 0.0;
-                  bv[x][s] = (vq && vb[x]) ? bv[x][s] : 0.0;
-                }
+                for (int x = 0; x < 2; ++x) bv[x][s] = vq ? bv[x][s] : 0.0;
               }
               // lane (lx, lk) item v of block (x, y): row sa + 16 x + lx,
               // column sb + 16 y + 4 v + lk (operand order as in the root
@@ -370,6 +370,8 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
                 }
               }
             }
+            // leaf fronts' panels enter with sign -1
+            const double sgn = woff < 0 ? -1.0 : 1.0;
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -378,7 +380,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                   if (rb[y][v] >= 0 && (I != J || ra[x] >= rb[y][v]))
-                    atomicAdd(&C[ra[x]][rb[y][v]], acc[x][y][v]);
+                    atomicAdd(&C[ra[x]][rb[y][v]], sgn * acc[x][y][v]);
               }
           }
       }
