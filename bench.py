@@ -79,6 +79,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, choices=(1, 2))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--slots", type=int, default=4,
+                    help="batch workload: band systems run concurrently")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="batch workload: hardware queues of the process "
+                         "(GPU_MAX_HW_QUEUES, 1..32; 0 = leave as set)")
     ap.add_argument("--workload", choices=("medium", "batch", "learned", "copy"),
                     default="medium")
     ap.add_argument("--bands", type=int, default=64,
@@ -183,6 +188,9 @@ def cpu_baseline(p):
 
 def main():
     args = parse()
+    if not 0 <= args.hw_queues <= 32:
+        print("--hw-queues takes 0..32", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "this build has no multi-GPU path", file=sys.stderr)
@@ -284,7 +292,8 @@ def measure(p, prec, args, src=None):
         blk = args.potrf_block
     else:
         blk = s.autotune()
-    print(f"# {prec}: analysis {t_an:.2f}s; outer block {blk}; warmup {args.warmup}",
+    print(f"# {prec}: analysis {t_an:.2f}s; outer block {blk}, bulk tile "
+          f"{s.bulk_tile}; warmup {args.warmup}",
           file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -313,15 +322,16 @@ def measure(p, prec, args, src=None):
     bulk_ms = (i1["t_sweep_bulk_ms"] - i0["t_sweep_bulk_ms"]) / K
     bulk_flops = (i1["flops_sweep_bulk"] - i0["flops_sweep_bulk"]) / K
     launches = sweep_bulk_launches(i1["n_root_padded"], blk)
+    tile = s.bulk_tile
     asm_ms = ph["t_extend_ms"]
     kernels = {
         "assembly": {"kernel": "k_assemble_root (root front assembly)",
                      "ms_per_step": asm_ms, "launches_per_step": 1,
                      "flops_per_launch": i1["flops_root_assembly"],
                      "peak": PEAK_FP64_TFLOPS, "key": "assembly"},
-        "bulk": {"kernel": ("k_gemm<128,128,XC,XC,float> (root sweep bulk update)"
+        "bulk": {"kernel": (f"k_gemm<{tile},{tile},XC,XC,float> (root sweep bulk update)"
                             if mixed else
-                            "k_gemm<128,128,XC,XC> (root sweep bulk update)"),
+                            f"k_gemm<{tile},{tile},XC,XC> (root sweep bulk update)"),
                  "ms_per_step": bulk_ms, "launches_per_step": launches,
                  "flops_per_launch": bulk_flops / max(1, launches),
                  "peak": peak, "key": "bulk"},
@@ -369,6 +379,7 @@ def measure(p, prec, args, src=None):
         "kernels_ms_per_step": kernel_ms,
         "refine_steps": refine,
         "potrf_block": blk,
+        "bulk_tile": tile,
         "roofline": roof,
     }
 
@@ -393,6 +404,12 @@ def _mixed_opts():
 
 
 def run_batch(args):
+    # Hardware queues of this process: HIP maps streams onto 4 by default,
+    # which serialises the concurrent systems of a batch; 16 lets the band
+    # slots and sub-problems run side by side.  HIP reads it at start-up, so
+    # it is set before torch first touches the GPU.
+    if args.hw_queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     import torch
     import spi_synth
     from paper_1305_5683_amd import SpiSolver, SpiBatch
@@ -407,7 +424,7 @@ def run_batch(args):
     subs = [spi_synth.make_problem(c, seed=3500 + i) for i, c in
             enumerate(spi_synth.subproblem_configs(ns, seed=3500))]
     opts = _mixed_opts()
-    slots = 4
+    slots = args.slots
     streams = [torch.cuda.Stream() for _ in range(slots + ns)]
     _say("analysis")
     first = SpiSolver(base.m, base.n, base.rowptr, base.col, stream=streams[0], **opts)
@@ -424,6 +441,16 @@ def run_batch(args):
         return [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
     bout = [outs(base.n) for _ in range(slots)]
     sout = [outs(q.n) for q in subs]
+    # launch shapes: the library's autotuner on the first band (shared by
+    # every band slot) and on each sub-problem
+    _say("autotuning")
+    first.set_values(bvals[0][0], bvals[0][1])
+    first.autotune()
+    for s in bslots[1:]:
+        s.potrf_block, s.bulk_tile = first.potrf_block, first.bulk_tile
+    for s, v in zip(sub_s, svals):
+        s.set_values(v[0], v[1])
+        s.autotune()
 
     def alone(s, v, o):
         s.set_values(v[0], v[1])
@@ -471,6 +498,9 @@ def run_batch(args):
     s64 = SpiSolver(base.m, base.n, base.rowptr, base.col, stream=streams[0])
     sub64 = [SpiSolver(q.m, q.n, q.rowptr, q.col, stream=streams[slots + i])
              for i, q in enumerate(subs)]
+    for s, v in [(s64, bvals[0])] + list(zip(sub64, svals)):
+        s.set_values(v[0], v[1])
+        s.autotune()
 
     def sequential64():
         for b in range(nb):
@@ -496,7 +526,10 @@ def run_batch(args):
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"batch: {nb} bands on the medium pattern + {ns} "
                                "sub-problems (sky 30..120), mixed precision",
-                   "systems": k, "sub_problem_n": [q.n for q in subs]},
+                   "systems": k, "sub_problem_n": [q.n for q in subs],
+                   "band_potrf_block": first.potrf_block,
+                   "band_bulk_tile": first.bulk_tile,
+                   "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
         "sequential_s_per_system": t_seq / k,
         "batched_s_per_system": t_bat / k,
         "speedup": t_seq / t_bat,

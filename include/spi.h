@@ -75,7 +75,10 @@ enum spi_precision {
 
 typedef struct spi_opts {
     int32_t precision;      /* enum spi_precision; default SPI_FP64 */
-    int32_t max_group;      /* max leaf columns amalgamated in one front; default 32 */
+    int32_t max_group;      /* max leaf columns amalgamated in one front (and
+                               rows in one row panel); default 32.  A panel of
+                               (k + 24) (|U| + 32) 8 bytes or more is rejected
+                               by the analysis (32-bit offsets) */
     double leaf_max_work;   /* a column is a leaf candidate only if the total
                                length of the rows it appears in is <= this;
                                default 65536 */
@@ -599,16 +602,22 @@ int spi_batch_run(spi_batch* b, const double* const* y, double* const* rhs,
 void spi_batch_destroy(spi_batch* b);
 
 /*
- * Autotuner of the root front's outer block: the band width of the block
- * sweeps, or of the Cholesky's trailing updates (128, 256 or 512 columns,
- * one band or panel of lookahead).  It times spi_factor on the handle's
- * current values with each candidate, keeps the fastest, and leaves a
- * factor computed with it.
- *  chosen  host, may be NULL
+ * Autotuner of the root front's launch shapes: the outer block (the band
+ * width of the block sweeps, or of the Cholesky's trailing updates: 128,
+ * 256 or 512 columns, one band or panel of lookahead) and, for the sweeps
+ * on roots up to order 8192, the tile of their bulk update (128 x 128 or
+ * 64 x 64: a small root gets four times the workgroups from the smaller
+ * tile).  It times spi_factor on the handle's current values with each
+ * candidate pair, keeps the fastest, and leaves a factor computed with it.
+ *  chosen  host, may be NULL: the outer block chosen
  */
 int spi_autotune(spi_handle* h, int32_t* chosen);
 /* Current outer block of the root front, or -1 for a NULL handle. */
 int spi_get_potrf_block(const spi_handle* h);
+/* Tile edge of the sweeps' bulk update (64 or 128; default 128), or -1. */
+int spi_get_bulk_tile(const spi_handle* h);
+/* Set it by hand: 64 or 128. */
+int spi_set_bulk_tile(spi_handle* h, int32_t tile);
 /* Set the outer block by hand: 128, 256 or 512 (SPI_MIXED with
  * root_inverse = 0 uses at most 256, the longest binary32 accumulation it
  * allows; the sweeps split longer products into launches of 256). */

@@ -577,6 +577,12 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
     a.up_w_off.push_back((int32_t)a.rp_row_ptr[p]);
   }
   a.n_up = a.n_groups + a.n_rp;
+  // the root assembly addresses an update panel with 32-bit byte offsets,
+  // up to 24 columns (a batch of loads and one MFMA step) and 32 rows past
+  // its end
+  for (int64_t u = 0; u < a.n_up; ++u)
+    if ((int64_t)(a.up_k[u] + 24) * (a.up_nU[u] + 32) * 8 >= ((int64_t)1 << 31))
+      return "an update panel exceeds 2^31 bytes (reduce max_group)";
 
   // ---- incidences on the 64 x 64 lower tiles of the root
   if (a.n_pad) {

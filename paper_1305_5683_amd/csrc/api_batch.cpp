@@ -186,15 +186,21 @@ int spi_autotune(spi_handle* H, int32_t* chosen) {
   if (!h.have_values)
     return fail(h, SPI_E_STATE, hipSuccess, "spi_autotune before spi_set_values");
   const int cand[3] = {128, 256, 512};
+  // the bulk update's tile: 64 x 64 gives small roots four times the
+  // workgroups of 128 x 128 (tried only below order 8192, where that matters)
+  const int tiles[2] = {128, 64};
+  const int n_tiles_tried = (h.opts.root_inverse && h.an.n_pad <= 8192) ? 2 : 1;
   double best = 1e300;
-  int best_b = h.potrf_block;
+  int best_b = h.potrf_block, best_t = h.bulk_tile;
   const int timing = h.opts.timing;
   h.opts.timing = 0;
-  for (int c : cand) {
+  for (int c : cand)
+  for (int ti = 0; ti < n_tiles_tried; ++ti) {
     if (h.an.n_pad > 0 && c > h.an.n_pad) continue;
     // the Cholesky route caps binary32 sums by its outer block
     if (h.opts.precision == SPI_MIXED && !h.opts.root_inverse && c > 256) continue;
     h.potrf_block = c;
+    h.bulk_tile = tiles[ti];
     double t_min = 1e300;
     for (int rep = 0; rep < 2; ++rep) {
       SPI_CK(hipStreamSynchronize(h.stream), "autotune");
@@ -211,15 +217,25 @@ int spi_autotune(spi_handle* H, int32_t* chosen) {
     if (t_min < best) {
       best = t_min;
       best_b = c;
+      best_t = tiles[ti];
     }
   }
   h.potrf_block = best_b;
+  h.bulk_tile = best_t;
   h.opts.timing = timing;
   if (chosen) *chosen = best_b;
   return spi_factor(H);  // leave a factor made with the chosen block
 }
 
 int spi_get_potrf_block(const spi_handle* H) { return H ? H->h.potrf_block : -1; }
+
+int spi_get_bulk_tile(const spi_handle* H) { return H ? H->h.bulk_tile : -1; }
+
+int spi_set_bulk_tile(spi_handle* H, int32_t tile) {
+  if (!H || (tile != 64 && tile != 128)) return SPI_E_ARG;
+  H->h.bulk_tile = tile;
+  return SPI_OK;
+}
 
 int spi_set_potrf_block(spi_handle* H, int32_t block) {
   if (!H || (block != 128 && block != 256 && block != 512)) return SPI_E_ARG;

@@ -946,7 +946,7 @@ hipError_t root_sweep(Handle& h) {
       band.s0 = k1;
       band.s1 = k2;
       phase_begin(h, kPhBulk);
-      e = sweep_update(h, h.stream, 128, Bk, np, Vk, np, h.S, ld, np, np, kb,
+      e = sweep_update(h, h.stream, h.bulk_tile, Bk, np, Vk, np, h.S, ld, np, np, kb,
                        next ? -1.0 : 1.0, next ? 1.0 : -1.0, true, false, band);
       if (e != hipSuccess) return e;
       phase_end(h, kPhBulk);

@@ -354,6 +354,8 @@ hipError_t gemm(hipStream_t s, int bm, int bn, int opA, int opB,
   if (ksplit) {  // the shapes of the sweep updates
     if (bm == 128 && bn == 128 && opA == kXC && opB == kXC)
       return gemm_t<128, 128, kXC, kXC, float, true>(s, a);
+    if (bm == 64 && bn == 64 && opA == kXC && opB == kXC)
+      return gemm_t<64, 64, kXC, kXC, float, true>(s, a);
     if (bm == 32 && bn == 32 && opA == kXC && opB == kXC)
       return gemm_t<32, 32, kXC, kXC, float, true>(s, a);
     return hipErrorInvalidValue;

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "spi_internal.h"
 
@@ -209,6 +210,20 @@ hipError_t launch_fill_rowpanels(Handle& h, bool compare) {
 // are added into the LDS tile (LDS atomics, since waves work on different
 // incidences); the tile is then written once.
 //
+// The work per super-block is mostly instruction issue, so it is kept to a
+// few vector instructions per load and per result:
+//  - panel and index loads are buffer loads on a per-update resource whose
+//    range is the update's panel (or index list): a lane's offset is one
+//    32-bit add per load, and every load past the range returns zero, so the
+//    panel columns past k (the last MFMA step's padding) read as zeros on
+//    both sides and rows past the incidence read finite values of the same
+//    panel (their products land in output rows or columns that are dropped);
+//  - a dropped output row or column is sent to spare LDS cells (rows
+//    TS .. TS + 7, column TS) instead of being masked, so the LDS adds are
+//    unconditional; entries above the diagonal of a diagonal tile are added
+//    too and never written out;
+//  - the sign of the leaf fronts' products is the MFMA's operand negation.
+//
 // Within a tile the leaf fronts' incidences come first ([beg, split)), the
 // row panels' after ([split, end)).  Modes:
 //   0  S = row panels + leaf fronts;
@@ -218,6 +233,9 @@ hipError_t launch_fill_rowpanels(Handle& h, bool compare) {
 constexpr int kAsmChunk = 128;  // incidences staged per pass
 constexpr int kAsmKC = 20;      // panel columns per batch of loads
 constexpr int kAsmThreads = kAsmTile >= 128 ? 1024 : 512;
+constexpr int kAsmSpare = 8;    // spare LDS rows for dropped output rows
+// word 3 of a raw buffer resource on gfx9 (32-bit data, no swizzle)
+constexpr int kBufWord3 = 0x00020000;
 
 // A wave-uniform 64-bit value moved to scalar registers.
 __device__ inline int64_t uniform64(int64_t x) {
@@ -227,20 +245,149 @@ __device__ inline int64_t uniform64(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+__device__ inline double buf_load_f64(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+__device__ inline int buf_load_i32(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0);
+}
+
+// MFMA 16x16x4 FP64 step, the A operand negated when NEG (the leaf fronts).
+template <bool NEG>
+__device__ inline v4d mfma_step(double b, double a, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c, 0, 0, NEG ? 1 : 0);
+}
+
+// One incidence, wave-uniform: the update's panel and index list (element
+// offsets), the run starts in U and the run lengths.  The values are passed
+// through readfirstlane where they are used, so the buffer resources and
+// branch conditions built from them stay in scalar registers.
+struct AsmInc {
+  int64_t qo, uo;
+  int pa, pb, nI, nJ, k, nU;
+};
+
+// One side of a super-block for kAsmKC panel columns: lane (lx, lk) holds
+// rows s0 + 16 x + lx (x = 0, 1) of column kc + 4 s + lk; and the lane's
+// root index of row s0 + (lane & 31).
+struct AsmSide {
+  double v[2][kAsmKC / 4];
+  int u;
+};
+
+__device__ inline int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// The update's panel (nU x k, column-major) and index list as buffer
+// resources whose range is the panel (the analysis keeps nU k 8 and the
+// offsets computed here below 2^31).
+__device__ inline __amdgpu_buffer_rsrc_t asm_panel_rsrc(const AsmInc& d,
+                                                        const double* panel) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(panel + uniform64(d.qo)), (short)0,
+                                           uni(d.nU) * uni(d.k) * 8, kBufWord3);
+}
+__device__ inline __amdgpu_buffer_rsrc_t asm_index_rsrc(const AsmInc& d,
+                                                        const int32_t* U) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(U + uniform64(d.uo)), (short)0,
+                                           uni(d.nU) * 4, kBufWord3);
+}
+
+// Panel columns kc .. kc + kAsmKC - 1 of the run rows p0 + s0 + 16 x + lx,
+// the second block only when `two` (the run reaches it).  Columns past k
+// lie past the panel's range and read as zeros.
+__device__ inline void asm_load_vals(const AsmInc& d, const double* panel, int p0, int s0,
+                                     bool two, int kc, int lane, AsmSide& o) {
+  const __amdgpu_buffer_rsrc_t rq = asm_panel_rsrc(d, panel);
+  const int lx = lane & 15, lk = lane >> 4;
+  const int cbytes = uni(d.nU) * 8;
+  const int c0 = (p0 + s0 + lx) * 8 + (kc + lk) * cbytes;
+#pragma unroll
+  for (int s = 0; s < kAsmKC / 4; ++s) {
+    o.v[0][s] = buf_load_f64(rq, c0 + 4 * s * cbytes);
+    if (two) o.v[1][s] = buf_load_f64(rq, c0 + 128 + 4 * s * cbytes);
+  }
+}
+
+__device__ inline void asm_load_side(const AsmInc& d, const double* panel, const int32_t* U,
+                                     int p0, int s0, bool two, int lane, AsmSide& o) {
+  o.u = buf_load_i32(asm_index_rsrc(d, U), (p0 + s0 + (lane & 31)) * 4);
+  asm_load_vals(d, panel, p0, s0, two, 0, lane, o);
+}
+
+// The products of one super-block (run rows sa .. of A, sb .. of B) from
+// the loaded sides; for k > kAsmKC the further column batches are loaded
+// here into the same registers (the sides are then spent).  The results are
+// added into the LDS tile Cf (row stride TS + 1).
+template <bool NEG, int TS>
+__device__ inline void asm_compute(const AsmInc& d, const double* panel, int sa, int sb,
+                                   AsmSide& A, AsmSide& B, double* Cf, int i0, int j0,
+                                   int lane) {
+  const int lx = lane & 15, lk = lane >> 4;
+  const int nI = uni(d.nI), nJ = uni(d.nJ), k = uni(d.k);
+  const bool a2 = sa + 16 < nI, b2 = sb + 16 < nJ;  // wave-uniform
+  v4d acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+  auto products = [&]() {
+    // lane (lx, lk) item v of block (x, y): row sa + 16 x + lx, column
+    // sb + 16 y + 4 v + lk (operand order as in the root GEMM)
+#pragma unroll
+    for (int s = 0; s < kAsmKC / 4; ++s) {
+      acc[0][0] = mfma_step<NEG>(B.v[0][s], A.v[0][s], acc[0][0]);
+      if (b2) acc[0][1] = mfma_step<NEG>(B.v[1][s], A.v[0][s], acc[0][1]);
+      if (a2) {
+        acc[1][0] = mfma_step<NEG>(B.v[0][s], A.v[1][s], acc[1][0]);
+        if (b2) acc[1][1] = mfma_step<NEG>(B.v[1][s], A.v[1][s], acc[1][1]);
+      }
+    }
+  };
+  products();
+  for (int kc = kAsmKC; kc < k; kc += kAsmKC) {
+    asm_load_vals(d, panel, uni(d.pa), sa, a2, kc, lane, A);
+    asm_load_vals(d, panel, uni(d.pb), sb, b2, kc, lane, B);
+    products();
+  }
+  // output rows and columns in the tile; dropped ones go to the spare cells
+  int ra[2], rb[2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    const int r = __shfl(A.u, 16 * x + lx, 64);
+    ra[x] = (sa + 16 * x + lx < nI ? r - i0 : TS + (lx & (kAsmSpare - 1))) * (TS + 1);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = __shfl(B.u, 16 * x + 4 * v + lk, 64);
+      rb[x][v] = sb + 16 * x + 4 * v + lk < nJ ? c - j0 : TS;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) atomicAdd(Cf + ra[0] + rb[0][v], acc[0][0][v]);
+  if (b2) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) atomicAdd(Cf + ra[0] + rb[1][v], acc[0][1][v]);
+  }
+  if (a2) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) atomicAdd(Cf + ra[1] + rb[0][v], acc[1][0][v]);
+    if (b2) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) atomicAdd(Cf + ra[1] + rb[1][v], acc[1][1][v]);
+    }
+  }
+}
+
 template <int TS>
 __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
     const int32_t* __restrict__ tile_order, const int64_t* __restrict__ inc_ptr,
     const int64_t* __restrict__ inc_split,
     const int32_t* __restrict__ inc, const int64_t* __restrict__ up_U_off,
     const int64_t* __restrict__ up_Q_off, const int32_t* __restrict__ up_nU,
-    const int32_t* __restrict__ up_k, const int32_t* __restrict__ up_w_off,
-    const int32_t* __restrict__ U, const double* __restrict__ panel,
-    double* __restrict__ S, double* __restrict__ Akeep, int64_t ld, int64_t n_root,
-    int mode) {
-  __shared__ double C[TS][TS + 1];
-  __shared__ int64_t s_qa[kAsmChunk], s_qb[kAsmChunk];
-  __shared__ int64_t s_ua[kAsmChunk], s_ub[kAsmChunk];
-  __shared__ int32_t s_nU[kAsmChunk], s_k[kAsmChunk], s_w[kAsmChunk],
+    const int32_t* __restrict__ up_k, const int32_t* __restrict__ U,
+    const double* __restrict__ panel, double* __restrict__ S,
+    double* __restrict__ Akeep, int64_t ld, int64_t n_root, int mode) {
+  __shared__ double C[TS + kAsmSpare][TS + 1];
+  __shared__ int64_t s_q[kAsmChunk], s_u[kAsmChunk];
+  __shared__ int32_t s_ab[kAsmChunk][2], s_nU[kAsmChunk], s_k[kAsmChunk],
       s_n[kAsmChunk];
   const int t = tile_order[xcd_remap<64>(blockIdx.x, gridDim.x)];
   int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -248,7 +395,8 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
   while (I * (I + 1) / 2 > t) --I;
   const int J = t - I * (I + 1) / 2;
   const int64_t i0 = (int64_t)I * TS, j0 = (int64_t)J * TS;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // (uniform)
   constexpr int NW = kAsmThreads / 64;
   if (mode == 2) {  // start from the kept A_RR tile
     for (int e = tid; e < TS * TS; e += kAsmThreads) {
@@ -261,128 +409,55 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
       C[a][b] = (I == J && a == b && i0 + a >= n_root) ? 1.0 : 0.0;
     }
   }
-  const int lx = lane & 15, lk = lane >> 4;
-  // Sum the incidences [q_beg, q_end) into C.
-  auto accumulate = [&](int64_t q_beg, int64_t q_end) {
+  double* Cf = &C[0][0];
+  // Sum the incidences [q_beg, q_end) into C, negated when NEG.
+  auto accumulate = [&](auto neg_tag, int64_t q_beg, int64_t q_end) {
+    constexpr bool NEG = decltype(neg_tag)::value;
     for (int64_t c0 = q_beg; c0 < q_end; c0 += kAsmChunk) {
       const int nc = (int)min((int64_t)kAsmChunk, q_end - c0);
       __syncthreads();  // previous chunk consumed (and C initialised)
       if (tid < nc) {
         const int32_t* p = inc + 4 * (c0 + tid);
         const int u = p[0];
-        const int64_t qo = up_Q_off[u], uo = up_U_off[u];
-        s_qa[tid] = qo + p[1];
-        s_qb[tid] = qo + p[2];
-        s_ua[tid] = uo + p[1];
-        s_ub[tid] = uo + p[2];
+        s_q[tid] = up_Q_off[u];
+        s_u[tid] = up_U_off[u];
+        s_ab[tid][0] = p[1];
+        s_ab[tid][1] = p[2];
         s_nU[tid] = up_nU[u];
         s_k[tid] = up_k[u];
-        s_w[tid] = up_w_off[u];
         s_n[tid] = p[3];
       }
       __syncthreads();
+      // A wave's incidences (wave, wave + NW, ...), each by row strips of
+      // 32: with k <= kAsmKC the strip's A side is loaded once for all its
+      // column super-blocks.  In a diagonal tile an incidence pairs a run
+      // with itself: super-blocks above the diagonal are skipped and those
+      // on it take their B side from the A side.
+      const bool diag = I == J;
       for (int q = wave; q < nc; q += NW) {
-        // per-incidence values are wave-uniform: keep them in scalar registers
-        const double* Qa = panel + uniform64(s_qa[q]);
-        const double* Qb = panel + uniform64(s_qb[q]);
-        const int32_t* Ua = U + uniform64(s_ua[q]);
-        const int32_t* Ub = U + uniform64(s_ub[q]);
-        const int nU = __builtin_amdgcn_readfirstlane(s_nU[q]);
-        const int k = __builtin_amdgcn_readfirstlane(s_k[q]);
-        const int woff = __builtin_amdgcn_readfirstlane(s_w[q]);
-        const int nn = __builtin_amdgcn_readfirstlane(s_n[q]);
-        const int nI = nn & 0xffff, nJ = nn >> 16;
-        // 32 x 32 super-blocks of up to 2 x 2 blocks of 16 x 16: the panel
-        // rows of both row blocks and both column blocks are loaded once and
-        // shared by the (up to) four products.
-        for (int sa = 0; sa < nI; sa += 32)
-          for (int sb = 0; sb < nJ; sb += 32) {
-            const bool a2 = sa + 16 < nI, b2 = sb + 16 < nJ;  // wave-uniform
-            // Addresses are clamped into the incidence (and the panel) and
-            // the out-of-range values replaced afterwards, so every load is
-            // issued unconditionally and the whole batch is in flight at once.
-            // Rows and columns past the incidence read a clamped (valid)
-            // position and their products land only in output rows or
-            // columns that are dropped below, so only the steps past k
-            // need zero operands (one side suffices).
-            int ac[2], bc[2], ra[2], rb[2][4];
-            bool va[2];
-#pragma unroll
-            for (int x = 0; x < 2; ++x) {
-              const int a = sa + 16 * x + lx, b = sb + 16 * x + lx;
-              va[x] = a < nI;
-              ac[x] = min(a, nI - 1);
-              bc[x] = min(b, nJ - 1);
-            }
-            {
-              // the 32 root rows and 32 root columns of the super-block: one
-              // load per lane, handed to the lanes that need them by shuffles
-              const int la = min(sa + (lane & 31), nI - 1),
-                        lb = min(sb + (lane & 31), nJ - 1);
-              const int ua_l = Ua[la], ub_l = Ub[lb];
-#pragma unroll
-              for (int x = 0; x < 2; ++x) {
-                ra[x] = __shfl(ua_l, 16 * x + lx, 64);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) rb[x][v] = __shfl(ub_l, 16 * x + 4 * v + lk, 64);
-              }
-            }
-#pragma unroll
-            for (int x = 0; x < 2; ++x) {
-              ra[x] = va[x] ? ra[x] - (int)i0 : -1;
-#pragma unroll
-              for (int v = 0; v < 4; ++v)
-                rb[x][v] = (sb + 16 * x + 4 * v + lk < nJ) ? rb[x][v] - (int)j0 : -1;
-            }
-            v4d acc[2][2];
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-              for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-            for (int kc = 0; kc < k; kc += kAsmKC) {
-              double av[2][kAsmKC / 4], bv[2][kAsmKC / 4];
-#pragma unroll
-              for (int s = 0; s < kAsmKC / 4; ++s) {
-                const int qc = min(kc + 4 * s + lk, k - 1);
-                av[0][s] = Qa[ac[0] + qc * nU];
-                bv[0][s] = Qb[bc[0] + qc * nU];
-                av[1][s] = a2 ? Qa[ac[1] + qc * nU] : 0.0;
-                bv[1][s] = b2 ? Qb[bc[1] + qc * nU] : 0.0;
-              }
-#pragma unroll
-              for (int s = 0; s < kAsmKC / 4; ++s) {
-                const bool vq = kc + 4 * s + lk < k;
-#pragma unroll
-                for (int x = 0; x < 2; ++x) bv[x][s] = vq ? bv[x][s] : 0.0;
-              }
-              // lane (lx, lk) item v of block (x, y): row sa + 16 x + lx,
-              // column sb + 16 y + 4 v + lk (operand order as in the root
-              // GEMM); steps past k have zero operands
-#pragma unroll
-              for (int s = 0; s < kAsmKC / 4; ++s) {
-                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[0][s], av[0][s], acc[0][0], 0, 0, 0);
-                if (b2)
-                  acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[1][s], av[0][s], acc[0][1], 0, 0, 0);
-                if (a2) {
-                  acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[0][s], av[1][s], acc[1][0], 0, 0, 0);
-                  if (b2)
-                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[1][s], av[1][s], acc[1][1], 0, 0, 0);
-                }
-              }
-            }
-            // leaf fronts' panels enter with sign -1
-            const double sgn = woff < 0 ? -1.0 : 1.0;
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-              for (int y = 0; y < 2; ++y) {
-                if ((x == 1 && !a2) || (y == 1 && !b2) || ra[x] < 0) continue;
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                  if (rb[y][v] >= 0 && (I != J || ra[x] >= rb[y][v]))
-                    atomicAdd(&C[ra[x]][rb[y][v]], sgn * acc[x][y][v]);
-              }
+        AsmInc d;
+        d.qo = uniform64(s_q[q]);
+        d.uo = uniform64(s_u[q]);
+        d.pa = uni(s_ab[q][0]);
+        d.pb = uni(s_ab[q][1]);
+        d.nU = uni(s_nU[q]);
+        d.k = uni(s_k[q]);
+        const int nn = uni(s_n[q]);
+        d.nI = nn & 0xffff;
+        d.nJ = nn >> 16;
+        const bool multi = d.k > kAsmKC;  // further column batches
+        for (int sa = 0; sa < d.nI; sa += 32) {
+          const bool a2 = sa + 16 < d.nI;
+          AsmSide A, B;
+          asm_load_side(d, panel, U, d.pa, sa, a2, lane, A);
+          const int sb_end = diag ? sa + 1 : d.nJ;
+          for (int sb = 0; sb < sb_end; sb += 32) {
+            if (multi && sb > 0) asm_load_side(d, panel, U, d.pa, sa, a2, lane, A);
+            if (diag && sb == sa && !multi) B = A;
+            else asm_load_side(d, panel, U, d.pb, sb, sb + 16 < d.nJ, lane, B);
+            asm_compute<NEG, TS>(d, panel, sa, sb, A, B, Cf, (int)i0, (int)j0, lane);
           }
+        }
       }
     }
   };
@@ -394,15 +469,18 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
       out[(i0 + a) + (j0 + b) * ld] = C[a][b];
     }
   };
+  using neg_t = std::integral_constant<bool, true>;
+  using pos_t = std::integral_constant<bool, false>;
   const int64_t q_beg = inc_ptr[t], q_split = inc_split[t], q_end = inc_ptr[t + 1];
   if (mode == 1) {
-    accumulate(q_split, q_end);  // row panels: A_RR
+    accumulate(pos_t(), q_split, q_end);  // row panels: A_RR
     write_tile(Akeep);
-    accumulate(q_beg, q_split);  // leaf fronts
+    accumulate(neg_t(), q_beg, q_split);  // leaf fronts
   } else if (mode == 2) {
-    accumulate(q_beg, q_split);
+    accumulate(neg_t(), q_beg, q_split);
   } else {
-    accumulate(q_beg, q_end);
+    accumulate(neg_t(), q_beg, q_split);
+    accumulate(pos_t(), q_split, q_end);
   }
   write_tile(S);
 }
@@ -413,8 +491,7 @@ hipError_t launch_assemble_root(Handle& h, int mode) {
   hipLaunchKernelGGL(k_assemble_root<kAsmTile>, dim3((unsigned)a.n_tiles),
                      dim3(kAsmThreads), 0, h.stream, h.d.tile_order, h.d.inc_ptr,
                      h.d.inc_split, h.d.inc, h.d.up_U_off, h.d.up_Q_off, h.d.up_nU,
-                     h.d.up_k, h.d.up_w_off, h.d.U, h.panel, h.S, h.Akeep, a.n_pad,
-                     a.n_root, mode);
+                     h.d.up_k, h.d.U, h.panel, h.S, h.Akeep, a.n_pad, a.n_root, mode);
   return hipGetLastError();
 }
 

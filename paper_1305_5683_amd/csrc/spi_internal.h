@@ -259,6 +259,7 @@ struct Handle {
   } lp;
   bool val32_ok = false;
   int potrf_block = 256;     // outer block of the root POTRF (autotuned)
+  int bulk_tile = 128;       // tile edge of the sweeps' bulk update (autotuned)
   double bulk_flops = 0;     // algorithmic flops of the timed sweep bulk updates
   bool have_inv = false;     // W = L_RR^-1 is valid
   // phase timing (opts.timing): HIP event pairs recorded on the stream,

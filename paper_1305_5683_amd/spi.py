@@ -28,7 +28,8 @@ EXPORTED = ["spi_default_opts", "spi_analyze", "spi_set_values", "spi_factor",
             "spi_batch_destroy", "spi_autotune", "spi_get_potrf_block",
             "spi_set_potrf_block", "spi_diag_inv_noalloc", "spi_set_leaf_values",
             "spi_empty_field_update", "spi_empty_field_loop", "spi_mle_terms",
-            "spi_mle_newton", "spi_inv_entries"]
+            "spi_mle_newton", "spi_inv_entries", "spi_get_bulk_tile",
+            "spi_set_bulk_tile"]
 
 
 class spi_opts(C.Structure):
@@ -133,6 +134,8 @@ def load_library(path: str = LIB_PATH):
     lib.spi_autotune.argtypes = [P, C.POINTER(I32)]
     lib.spi_get_potrf_block.argtypes = [P]
     lib.spi_set_potrf_block.argtypes = [P, I32]
+    lib.spi_get_bulk_tile.argtypes = [P]
+    lib.spi_set_bulk_tile.argtypes = [P, I32]
     for name in EXPORTED:
         if name not in ("spi_default_opts", "spi_last_error", "spi_destroy",
                         "spi_lp_destroy", "spi_lp_param_count",
@@ -245,6 +248,14 @@ class SpiSolver:
     @potrf_block.setter
     def potrf_block(self, v):
         self._check(self.lib.spi_set_potrf_block(self.h, int(v)))
+
+    @property
+    def bulk_tile(self) -> int:
+        return int(self.lib.spi_get_bulk_tile(self.h))
+
+    @bulk_tile.setter
+    def bulk_tile(self, v):
+        self._check(self.lib.spi_set_bulk_tile(self.h, int(v)))
 
     def set_values(self, val, w):
         import torch

@@ -141,19 +141,23 @@ def test_autotune_picks_a_block_and_factor_stays_exact():
     s = SpiSolver(p.m, p.n, p.rowptr, p.col)
     _set(s, p)
     blk = s.autotune()
-    _say(f"  chosen block {blk}")
+    _say(f"  chosen block {blk}, bulk tile {s.bulk_tile}")
     assert blk in (128, 256, 512) and s.potrf_block == blk
+    assert s.bulk_tile in (64, 128)
     rhs = s.rhs(torch.from_numpy(p.y).cuda())
     x = s.solve(rhs).cpu().numpy()
     d = s.diag_inv().cpu().numpy()
     o = oracle_solve(p)
     assert _rel(x, o["x"]) <= TOL
     assert np.max(np.abs(d - o["diag"]) / o["diag"]) <= TOL
-    for blk in (128, 512):
-        s.potrf_block = blk
+    for blk, tile in ((128, 64), (512, 128)):
+        s.potrf_block, s.bulk_tile = blk, tile
         s.factor()
         x2 = s.solve(rhs).cpu().numpy()
         assert _rel(x2, o["x"]) <= TOL
+    from paper_1305_5683_amd import SpiError
+    with pytest.raises(SpiError):
+        s.bulk_tile = 96
     s.close()
 
 

@@ -455,12 +455,14 @@ def test_ragged_root_sizes_across_tile_edges():
         _check(p, g, o)
 
 
-def _run_blocks(p, block, **opts):
+def _run_blocks(p, block, tile=128, **opts):
     torch = _torch()
     from paper_1305_5683_amd import SpiSolver
     dev = torch.device("cuda")
     s = SpiSolver(p.m, p.n, p.rowptr, p.col, **opts)
     s.potrf_block = block
+    s.bulk_tile = tile
+    assert s.bulk_tile == tile
     s.set_values(torch.from_numpy(p.val).to(dev), torch.from_numpy(p.w).to(dev))
     s.factor()
     b = s.rhs(torch.from_numpy(p.y).to(dev))
@@ -503,31 +505,34 @@ def test_sweep_bulk_timers_count_the_bulk_flops():
     s.close()
 
 
+@pytest.mark.parametrize("tile", [128, 64])
 @pytest.mark.parametrize("block", [128, 256, 512])
-def test_mixed_sweeps_over_several_bands(block):
+def test_mixed_sweeps_over_several_bands(block, tile):
     """Mixed precision on a dense root of order 700 (padded 768) with 6, 3 or
     2 bands: bands of 128 and 256 take one binary32 sum per launch, bands of
     512 two sums of 256 terms added in binary64 (the split kernel), for the
-    bulk and for the next pivot block's update alike."""
+    bulk and for the next pivot block's update alike; bulk tiles of 128 and
+    64."""
     p = synth.make_random(2100, 700, 14, seed=77)
     o = oracle_solve(p)
-    _say(f"case mixed sweeps block={block}")
-    g = _run_blocks(p, block, leaf_max_work=0.0, precision=1)
+    _say(f"case mixed sweeps block={block} tile={tile}")
+    g = _run_blocks(p, block, tile, leaf_max_work=0.0, precision=1)
     assert g["info"]["n_root"] == 700 and g["info"]["precision"] == 1
     _check(p, g, o, tol_x=TOL_X_MIXED, tol_d=TOL_D_MIXED)
 
 
+@pytest.mark.parametrize("tile", [128, 64])
 @pytest.mark.parametrize("block", [128, 256, 512])
-def test_root_sweeps_over_several_bands(block):
+def test_root_sweeps_over_several_bands(block, tile):
     """Dense root of order 700 (padded 768): 6, 3 or 2 bands, so the
     lookahead band update, the bulk outside both bands and the negated last
-    band all run; also the Cholesky route (root_inverse=0) on the same
-    system with the same outer block."""
+    band all run, with bulk tiles of 128 and 64; also the Cholesky route
+    (root_inverse=0) on the same system with the same outer block."""
     p = synth.make_random(2100, 700, 14, seed=77)
     o = oracle_solve(p)
     for ri in (1, 0):
-        _say(f"case sweeps block={block} root_inverse={ri}")
-        g = _run_blocks(p, block, leaf_max_work=0.0, root_inverse=ri)
+        _say(f"case sweeps block={block} tile={tile} root_inverse={ri}")
+        g = _run_blocks(p, block, tile, leaf_max_work=0.0, root_inverse=ri)
         assert g["info"]["n_root"] == 700
         _check(p, g, o)
 
