@@ -49,27 +49,37 @@ CSRC = os.path.join(ROOT, "paper_1305_5683_amd", "csrc")
 
 # HBM bytes per launch of the reported kernels, from rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE; each scaled by what the same counter reads
-# for the copy workload of known size: fetch x2.0, write x1.0).  Keyed by
-# (config, kernel, outer block, precision); "src" is the SHA-256 prefix of
-# the kernel's source file when the counters were taken: once the source
-# changes the figure no longer applies and `traffic` is reported as null.
-HBM_COUNTERS = {
-    (1, "bulk", 512, "fp64"): {"bytes": 1.2546e9 + 0.3683e9,
-                               "src": ("k_gemm.hip", None)},
+# for the copy workload of known size).  Keyed by (config, kernel, outer
+# block or None, precision); "src" names the source file and the section of
+# it that holds the kernel (between two marker lines) with the SHA-256 prefix
+# of that section's text when the counters were taken: once it changes the
+# figure no longer applies and `traffic` is reported as null.
+HBM_COUNTERS = {}
+
+
+def src_hash(name, begin=None, end=None):
+    with open(os.path.join(CSRC, name), encoding="utf-8") as fh:
+        text = fh.read()
+    if begin is not None:
+        i = text.index(begin)
+        j = text.index(end, i) if end is not None else len(text)
+        text = text[i:j]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+# the sections the counters depend on
+SRC_SECTIONS = {
+    "bulk": ("k_gemm.hip", None, None),
+    "assembly": ("k_sparse.hip", "// --------------------------------------------------------- root assembly",
+                 "// ------------------------------------------------------------ equilibration"),
 }
 
 
-def src_hash(name):
-    with open(os.path.join(CSRC, name), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
-
-
 def counter_traffic(config, kernel, blk, prec):
-    c = HBM_COUNTERS.get((config, kernel, blk, prec))
+    c = HBM_COUNTERS.get((config, kernel, blk if kernel == "bulk" else None, prec))
     if c is None:
         return None
-    name, h = c["src"]
-    return c["bytes"] if h is not None and src_hash(name) == h else None
+    return c["bytes"] if src_hash(*SRC_SECTIONS[kernel]) == c["src"] else None
 
 
 def parse():

@@ -139,6 +139,22 @@ typedef struct spi_opts {
                                re-assembles only the leaf fronts' updates
                                (Sect. 4.1, modified columns of H; App. A.5,
                                the empty-field loop).  Default 0 */
+    int32_t indefinite;     /* 1: A may be symmetric indefinite (weights of
+                               either sign; Sect. 5: the SPI matrices are,
+                               numerically, and need 2 x 2 pivots; Sect.
+                               3.2.2 and 4.3: the factorisation must pivot).
+                               The root front's pivot blocks (64 columns)
+                               are swept with Bunch-Kaufman 1 x 1 and 2 x 2
+                               pivots of either sign chosen inside the
+                               block; a block with no usable pivot is
+                               reported as SPI_E_NOT_SPD at its first
+                               column.  Row panels carry the weights'
+                               signs.  Leaf pivots (A_cc of a leaf column)
+                               must still be positive: a column whose pivot
+                               is not is reported as before (it would have
+                               to move into the root).  Needs
+                               root_inverse = 1.  Default 0: positive
+                               definite, every pivot checked */
 } spi_opts;
 
 typedef struct spi_info_t {

@@ -114,7 +114,7 @@ void free_all(Handle& h) {
                   h.colscale, h.vbh, h.vxh, h.diagA, d.root_of_col, d.leaf_of_col,
                   h.vfront,
                   h.band, h.valc, h.Akeep, h.vrow, h.vsum, h.vb2, h.vm1, h.vm2,
-                  h.vw, h.vr};
+                  h.vw, h.vr, h.panelS};
   free_lp_work(h);
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -129,8 +129,13 @@ bool check_opts(spi_opts& o) {
   if (o.max_group < 1 || o.refine_steps < 0 || !(o.amalg_density >= 0.0) ||
       !(o.refine_tol >= 0.0) || (o.keep_root_order != 0 && o.keep_root_order != 1) ||
       o.leaf_lds_cap < 0 || o.leaf_lds_cap > kLeafLdsCapMax || o.selinv_chunk < 0 ||
-      (o.keep_root_sum != 0 && o.keep_root_sum != 1)) {
+      (o.keep_root_sum != 0 && o.keep_root_sum != 1) ||
+      (o.indefinite != 0 && o.indefinite != 1)) {
     g_analyze_err = "invalid options";
+    return false;
+  }
+  if (o.indefinite && !o.root_inverse) {
+    g_analyze_err = "indefinite = 1 needs root_inverse = 1";
     return false;
   }
   if (o.precision == SPI_MIXED && o.refine_tol == 0.0) {
@@ -168,6 +173,7 @@ int setup_device(spi_handle* H) {
   AL(h.sleaf, a.n_slots);
   AL(h.rrval, (int64_t)a.rr_src.size());
   AL(h.panel, a.grp_panel_off.back() + a.rp_val_off.back());
+  if (h.opts.indefinite) AL(h.panelS, a.rp_val_off.back());
   AL(h.ldiag, nl);
   AL(h.S, np * np);
   if (h.opts.keep_root_sum) AL(h.Akeep, np * np);

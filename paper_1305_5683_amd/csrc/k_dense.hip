@@ -646,6 +646,21 @@ __device__ inline double rcp_nr(double d) {
 // finite (index base + s * kNB + k) with atomicMin in `fail` and continues
 // with pivot 1.  Two 64 x 64 LDS buffers, so the workgroup fits beside a
 // GEMM workgroup on one CU.
+//
+// INDEF (symmetric indefinite matrices): the pivot block is swept with
+// Bunch-Kaufman pivots chosen inside it instead of in index order with
+// positive pivots.  The sweep operator's result does not depend on the
+// order in which indices are swept, nor on sweeping two at once, so M is
+// -Ds^-1 either way; the order only decides the rounding.  Each step looks
+// at the lowest unswept index k: with lambda the largest |M_ik| over the
+// other unswept i (at r), it sweeps k alone if |M_kk| >= alpha lambda; else,
+// with sigma the largest |M_jr| over the unswept j != r, k alone if
+// |M_kk| sigma >= alpha lambda^2, r alone if |M_rr| >= alpha sigma, and the
+// pair {k, r} as one 2 x 2 pivot otherwise (alpha = (1 + sqrt 17) / 8).
+// Pivots of either sign are taken; a block with no usable pivot (k's
+// column all zero, a zero or non-finite pivot or 2 x 2 determinant) is
+// reported at k and swept with pivot 1.
+template <bool INDEF>
 __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict__ Din,
                                                         int64_t ldin, int sym_lower,
                                                         double* __restrict__ Dout,
@@ -654,6 +669,7 @@ __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict
   __shared__ double Mv[kNB][kNB + 1];
   __shared__ double Xa[kNB][kNB + 1];
   __shared__ double colk[2][kNB];
+  __shared__ double colb[2][kNB];
   // these steps are the critical path while bulk updates share the CUs:
   // issue ahead of their waves
   __builtin_amdgcn_s_setprio(3);
@@ -685,6 +701,7 @@ __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict
   // row k M_kl / d and the pivot -1 / d.  Column k is written as
   // fma(M_ik, r, 0 * m) and the others as fma(-M_ik, M_kl r, 1 * m), so all
   // lanes run the same instructions.
+  if constexpr (!INDEF) {
   for (int kw = 0; kw < 4; ++kw) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -706,6 +723,117 @@ __global__ __launch_bounds__(256, 2) void k_dsweep_step(const double* __restrict
       for (int q2 = 0; q2 < 16; ++q2)
         m[q2] = fma(colk[par][16 * wave + q2], a, keep * m[q2]);
       if (wave == kw) m[q] = piv ? -r : tl;
+    }
+  }
+  } else {
+    const double alpha = 0.6403882032022076;  // (1 + sqrt(17)) / 8
+    // the largest |v| over the lanes not in `skip`, and the lowest such lane
+    auto lane_max = [&](double v, uint64_t skip, int& at) {
+      double x = ((skip >> lane) & 1) ? -1.0 : fabs(v);
+      int i = lane;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double xo = __shfl_xor(x, off, 64);
+        const int io = __shfl_xor(i, off, 64);
+        if (xo > x || (xo == x && io < i)) {
+          x = xo;
+          i = io;
+        }
+      }
+      at = i;
+      return x;
+    };
+    // column c of the block (= row c) into buf: lane c of every wave holds
+    // its 16 rows of it
+    auto publish = [&](double* buf, int c) {
+      if (lane == c) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) buf[16 * wave + q] = m[q];
+      }
+    };
+    uint64_t done = 0;  // swept indices (wave-uniform)
+    int par = 0;
+    while (done != ~0ull) {
+      const int k = __builtin_ctzll(~done);
+      double* ca = colk[par];
+      double* cb = colb[par];
+      publish(ca, k);
+      __syncthreads();
+      int r;
+      const double lam = lane_max(ca[lane], done | (1ull << k), r);
+      const double akk = fabs(ca[k]);
+      int p = k, s2 = -1;      // 1 x 1 at p, or 2 x 2 at {k, s2}
+      const double* cp = ca;   // column of p
+      bool bad = false;
+      if (!(lam > 0.0)) {
+        bad = !(akk > 0.0) || !isfinite(akk);
+      } else if (!(akk >= alpha * lam)) {
+        publish(cb, r);
+        __syncthreads();
+        int rr;
+        const double sig = lane_max(cb[lane], done | (1ull << r), rr);
+        if (akk * sig >= alpha * lam * lam) {
+          // k alone
+        } else if (fabs(cb[r]) >= alpha * sig) {
+          p = r;
+          cp = cb;
+        } else {
+          s2 = r;
+        }
+      }
+      if (s2 < 0) {
+        double d = cp[p];
+        if (bad || d == 0.0 || !isfinite(d)) {
+          if (reporter)
+            atomicMin((unsigned long long*)fail, (unsigned long long)(base + s0 + k));
+          d = 1.0;
+        }
+        const double rc = 1.0 / d;
+        const bool piv = lane == p;
+        const double tl = cp[lane] * rc;  // M_pl / d
+        const double a = piv ? rc : -tl;
+        const double keep = piv ? 0.0 : 1.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          m[q] = fma(cp[16 * wave + q], a, keep * m[q]);
+          if (16 * wave + q == p) m[q] = piv ? -rc : tl;
+        }
+        done |= 1ull << p;
+      } else {
+        // 2 x 2 pivot P = [[a, b], [b, c]] on {k, s2}: E = P^-1
+        const int sI = s2;
+        const double pa = ca[k], pb = ca[sI], pc = cb[sI];
+        double det = pa * pc - pb * pb;
+        double e00, e01, e11;
+        if (!(det != 0.0) || !isfinite(det)) {
+          if (reporter)
+            atomicMin((unsigned long long*)fail, (unsigned long long)(base + s0 + k));
+          e00 = 1.0, e01 = 0.0, e11 = 1.0;
+        } else {
+          const double ri = 1.0 / det;
+          e00 = pc * ri;
+          e01 = -pb * ri;
+          e11 = pa * ri;
+        }
+        const bool lk_ = lane == k, ls_ = lane == sI;
+        // t = E [M_kl; M_sl] for the other columns
+        const double t0 = e00 * ca[lane] + e01 * cb[lane];
+        const double t1 = e01 * ca[lane] + e11 * cb[lane];
+        const double a0 = lk_ ? e00 : (ls_ ? e01 : -t0);
+        const double a1 = lk_ ? e01 : (ls_ ? e11 : -t1);
+        const double keep = (lk_ || ls_) ? 0.0 : 1.0;
+        const double rowk = lk_ ? -e00 : (ls_ ? -e01 : t0);
+        const double rows = lk_ ? -e01 : (ls_ ? -e11 : t1);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int i = 16 * wave + q;
+          m[q] = fma(ca[i], a0, fma(cb[i], a1, keep * m[q]));
+          if (i == k) m[q] = rowk;
+          if (i == sI) m[q] = rows;
+        }
+        done |= (1ull << k) | (1ull << sI);
+      }
+      par ^= 1;
     }
   }
   auto load = [&](double (*X)[kNB + 1], int bi, int bc) {
@@ -840,10 +968,16 @@ static hipError_t band_pivot_sweep(Handle& h, hipStream_t st, int k0, int kb) {
   const int nsb = kb / kNB, nt = nsb * (nsb + 1) / 2;
   for (int sb = 0; sb < nsb; ++sb) {
     const bool first = sb == 0;
-    hipLaunchKernelGGL(k_dsweep_step, dim3(nt), dim3(256), 0, st,
-                       first ? h.S + (int64_t)k0 * (np + 1) : Dw[sb & 1],
-                       first ? np : (int64_t)kb, first ? 1 : 0,
-                       Dw[(sb + 1) & 1], kb, sb, h.flag, base);
+    if (h.opts.indefinite)
+      hipLaunchKernelGGL(k_dsweep_step<true>, dim3(nt), dim3(256), 0, st,
+                         first ? h.S + (int64_t)k0 * (np + 1) : Dw[sb & 1],
+                         first ? np : (int64_t)kb, first ? 1 : 0,
+                         Dw[(sb + 1) & 1], kb, sb, h.flag, base);
+    else
+      hipLaunchKernelGGL(k_dsweep_step<false>, dim3(nt), dim3(256), 0, st,
+                         first ? h.S + (int64_t)k0 * (np + 1) : Dw[sb & 1],
+                         first ? np : (int64_t)kb, first ? 1 : 0,
+                         Dw[(sb + 1) & 1], kb, sb, h.flag, base);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -153,25 +153,31 @@ __global__ void k_zero(double* __restrict__ p, int64_t n) {
 }
 
 // With `changed`, the panel already holds the values in use: any new value
-// that differs sets *changed (one atomic per wave that saw one).
+// that differs sets *changed (one atomic per wave that saw one).  With
+// `sbuf` (symmetric indefinite matrices, weights of either sign) rows are
+// stored scaled by sqrt|w_r| in rpbuf and by sign(w_r) sqrt|w_r| in sbuf
+// (same layout), so that Q S^T = sum_r w_r h_r h_r^T.
 __global__ __launch_bounds__(256) void k_fill_rowpanels(
     const double* __restrict__ val, const double* __restrict__ w,
     const int32_t* __restrict__ rp_rows, const int64_t* __restrict__ rp_rowbase,
     const int64_t* __restrict__ rpe_ptr, const int32_t* __restrict__ rpe_pos,
     const int64_t* __restrict__ rpe_src, double* __restrict__ rpbuf,
-    int64_t nrows, int64_t* changed) {
+    double* __restrict__ sbuf, int64_t nrows, int64_t* changed) {
   const int lane = threadIdx.x & 63;
   const int64_t pr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (pr >= nrows) return;
   double* col = rpbuf + rp_rowbase[pr];
   // rows are stored scaled by sqrt(w_r): the panel product is then
   // Q Q^T = sum_r w_r h_r h_r^T with no weights to load in the assembly
-  const double sw = sqrt(w[rp_rows[pr]]);
+  const double wr = w[rp_rows[pr]];
+  const double sw = sqrt(sbuf ? fabs(wr) : wr);
+  const double sg = wr < 0.0 ? -1.0 : 1.0;
   bool diff = false;
   for (int64_t e = rpe_ptr[pr] + lane; e < rpe_ptr[pr + 1]; e += 64) {
     const double v = sw * val[rpe_src[e]];
     if (changed) diff |= col[rpe_pos[e]] != v;
     col[rpe_pos[e]] = v;
+    if (sbuf) sbuf[rp_rowbase[pr] + rpe_pos[e]] = sg * v;
   }
   if (changed && __any(diff) && lane == 0) atomicOr((unsigned long long*)changed, 1ull);
 }
@@ -186,9 +192,13 @@ hipError_t launch_fill_rowpanels(Handle& h, bool compare) {
   if (!compare)
     hipLaunchKernelGGL(k_zero, dim3(grid_for(total, 256 * 8)), dim3(256), 0,
                        h.stream, rpbuf, total);
+  // (the signed copy's positions that no row entry fills stay zero too)
+  if (!compare && h.panelS)
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(total, 256 * 8)), dim3(256), 0, h.stream,
+                       h.panelS, total);
   hipLaunchKernelGGL(k_fill_rowpanels, dim3(wave_grid(nrows)), dim3(256), 0,
                      h.stream, h.val, h.w, h.d.rp_rows, h.d.rp_rowbase,
-                     h.d.rpe_ptr, h.d.rpe_pos, h.d.rpe_src, rpbuf, nrows,
+                     h.d.rpe_ptr, h.d.rpe_pos, h.d.rpe_src, rpbuf, h.panelS, nrows,
                      compare ? h.flag + 2 : nullptr);
   return hipGetLastError();
 }
@@ -318,9 +328,9 @@ __device__ inline void asm_load_side(const AsmInc& d, const double* panel, const
 // here into the same registers (the sides are then spent).  The results are
 // added into the LDS tile Cf (row stride TS + 1).
 template <bool NEG, int TS>
-__device__ inline void asm_compute(const AsmInc& d, const double* panel, int sa, int sb,
-                                   AsmSide& A, AsmSide& B, double* Cf, int i0, int j0,
-                                   int lane) {
+__device__ inline void asm_compute(const AsmInc& d, const double* panel,
+                                   const double* panelB, int sa, int sb, AsmSide& A,
+                                   AsmSide& B, double* Cf, int i0, int j0, int lane) {
   const int lx = lane & 15, lk = lane >> 4;
   const int nI = uni(d.nI), nJ = uni(d.nJ), k = uni(d.k);
   const bool a2 = sa + 16 < nI, b2 = sb + 16 < nJ;  // wave-uniform
@@ -345,7 +355,7 @@ __device__ inline void asm_compute(const AsmInc& d, const double* panel, int sa,
   products();
   for (int kc = kAsmKC; kc < k; kc += kAsmKC) {
     asm_load_vals(d, panel, uni(d.pa), sa, a2, kc, lane, A);
-    asm_load_vals(d, panel, uni(d.pb), sb, b2, kc, lane, B);
+    asm_load_vals(d, panelB, uni(d.pb), sb, b2, kc, lane, B);
     products();
   }
   // output rows and columns in the tile; dropped ones go to the spare cells
@@ -383,8 +393,9 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
     const int32_t* __restrict__ inc, const int64_t* __restrict__ up_U_off,
     const int64_t* __restrict__ up_Q_off, const int32_t* __restrict__ up_nU,
     const int32_t* __restrict__ up_k, const int32_t* __restrict__ U,
-    const double* __restrict__ panel, double* __restrict__ S,
-    double* __restrict__ Akeep, int64_t ld, int64_t n_root, int mode) {
+    const double* __restrict__ panel, const double* __restrict__ panelB,
+    double* __restrict__ S, double* __restrict__ Akeep, int64_t ld, int64_t n_root,
+    int mode) {
   __shared__ double C[TS + kAsmSpare][TS + 1];
   __shared__ int64_t s_q[kAsmChunk], s_u[kAsmChunk];
   __shared__ int32_t s_ab[kAsmChunk][2], s_nU[kAsmChunk], s_k[kAsmChunk],
@@ -432,8 +443,11 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
       // 32: with k <= kAsmKC the strip's A side is loaded once for all its
       // column super-blocks.  In a diagonal tile an incidence pairs a run
       // with itself: super-blocks above the diagonal are skipped and those
-      // on it take their B side from the A side.
+      // on it take their B side from the A side (unless it is the signed
+      // copy).
       const bool diag = I == J;
+      // B side: the leaf fronts' panels, or the row panels' (signed) copy
+      const double* pB = NEG ? panel : panelB;
       for (int q = wave; q < nc; q += NW) {
         AsmInc d;
         d.qo = uniform64(s_q[q]);
@@ -453,9 +467,9 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
           const int sb_end = diag ? sa + 1 : d.nJ;
           for (int sb = 0; sb < sb_end; sb += 32) {
             if (multi && sb > 0) asm_load_side(d, panel, U, d.pa, sa, a2, lane, A);
-            if (diag && sb == sa && !multi) B = A;
-            else asm_load_side(d, panel, U, d.pb, sb, sb + 16 < d.nJ, lane, B);
-            asm_compute<NEG, TS>(d, panel, sa, sb, A, B, Cf, (int)i0, (int)j0, lane);
+            if (diag && sb == sa && !multi && pB == panel) B = A;
+            else asm_load_side(d, pB, U, d.pb, sb, sb + 16 < d.nJ, lane, B);
+            asm_compute<NEG, TS>(d, panel, pB, sa, sb, A, B, Cf, (int)i0, (int)j0, lane);
           }
         }
       }
@@ -488,17 +502,23 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
 hipError_t launch_assemble_root(Handle& h, int mode) {
   const Analysis& a = h.an;
   if (!a.n_tiles) return hipSuccess;
+  // the row panels' B side: the signed copy for indefinite matrices (its
+  // offsets are the row panels' offsets in the panel buffer less the leaf
+  // panels' total)
+  const double* panelB =
+      h.panelS ? h.panelS - a.grp_panel_off[a.n_groups] : h.panel;
   hipLaunchKernelGGL(k_assemble_root<kAsmTile>, dim3((unsigned)a.n_tiles),
                      dim3(kAsmThreads), 0, h.stream, h.d.tile_order, h.d.inc_ptr,
                      h.d.inc_split, h.d.inc, h.d.up_U_off, h.d.up_Q_off, h.d.up_nU,
-                     h.d.up_k, h.d.U, h.panel, h.S, h.Akeep, a.n_pad, a.n_root, mode);
+                     h.d.up_k, h.d.U, h.panel, panelB, h.S, h.Akeep, a.n_pad, a.n_root,
+                     mode);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------ equilibration
 // Symmetric diagonal scaling A -> S A S with S = diag(s), applied as a column
-// scaling of H (H -> H S).  s_c is the power of two 2^-floor(log2(A_cc) / 2),
-// A_cc = sum_r w_r h_rc^2, so the scaled diagonal lies in [1, 4).  Powers of
+// scaling of H (H -> H S).  s_c is the power of two 2^-floor(log2|A_cc| / 2),
+// A_cc = sum_r w_r h_rc^2, so the scaled |diagonal| lies in [1, 4).  Powers of
 // two make the scaling exact: every product, sum, square root and quotient
 // of the factorisation of S A S is the scaled image of the same operation
 // on A, so it changes no rounding; what it buys is range (the FP32
@@ -556,8 +576,9 @@ __global__ __launch_bounds__(256) void k_col_scale(
   for (int off = 32; off > 0; off >>= 1) d += __shfl_down(d, off, 64);
   d = __shfl(d, 0, 64);
   double s = 1.0;
-  if (d > 0.0 && d <= 1.7976931348623157e308) {
-    const int e = ilogb(d);     // d = m 2^e, 1 <= m < 2
+  const double ad = fabs(d);  // (a negative diagonal: indefinite matrices)
+  if (ad > 0.0 && ad <= 1.7976931348623157e308) {
+    const int e = ilogb(ad);    // |d| = m 2^e, 1 <= m < 2
     s = ldexp(1.0, -(e >> 1));  // arithmetic shift: floor(e / 2)
   }
   if (lane == 0) {

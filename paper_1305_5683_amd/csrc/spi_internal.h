@@ -202,6 +202,8 @@ struct Handle {
   // factor
   double* panel = nullptr;   // leaf panels L_UG, dense column-major per front,
                              // followed by the dense row panels
+  double* panelS = nullptr;  // opts.indefinite: the row panels with their rows'
+                             // weight signs (sign(w_r) sqrt|w_r| h_r)
   double* ldiag = nullptr;   // leaf pivots L_ll
   double* S = nullptr;       // root front n_pad x n_pad, column-major; L after factor
   double* Akeep = nullptr;   // opts.keep_root_sum: A_RR (row panels only), lower tiles

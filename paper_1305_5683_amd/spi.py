@@ -39,7 +39,7 @@ class spi_opts(C.Structure):
                 ("root_inverse", C.c_int32), ("equilibrate", C.c_int32),
                 ("refine_tol", C.c_double), ("keep_root_order", C.c_int32),
                 ("leaf_lds_cap", C.c_int32), ("selinv_chunk", C.c_int32),
-                ("keep_root_sum", C.c_int32)]
+                ("keep_root_sum", C.c_int32), ("indefinite", C.c_int32)]
 
 
 class spi_info_t(C.Structure):

@@ -330,6 +330,77 @@ def make_random_leafy(n_groups: int, leaf_per_group: int, n_root: int,
                    name=f"leafy{n_groups}x{leaf_per_group}+{n_root}")
 
 
+def make_indefinite(n_groups: int, leaf_per_group: int, n_root: int,
+                    rows_per_leaf: int, root_per_row: int, neg_rows: int,
+                    zero_diag: int, seed: int, neg_scale: float = 1.0,
+                    partners: int = 8) -> Problem:
+    """Random problem whose ``H^T W H`` is symmetric indefinite while the
+    leaf unknowns keep positive pivots.
+
+    * Leaf unknowns as in :func:`make_random_leafy` (each owns
+      ``rows_per_leaf`` rows that also touch ``root_per_row`` root unknowns
+      from a window), with weights U(0.5, 1.5); every root unknown also has
+      one row of its own, weight U(0.5, 1.5).
+    * ``neg_rows`` rows touch 2..4 random root unknowns (outside the ones
+      below) with weights ``-neg_scale`` U(0.5, 1.5).
+    * ``zero_diag`` root unknowns z have a zero diagonal: each is seen only by
+      row pairs ``e_z + e_k`` (weight +1) and ``e_z - e_k`` (weight -1) with
+      ``partners`` other root unknowns k, all values 1, so their entries in
+      ``H^T W H`` are exact: ``A_zz = 0`` and ``A_zk = 2``.
+    * One row of weight 0 touches every root unknown (structure only: it
+      adds exact zeros to ``H^T W H``), so that an analysis with
+      ``leaf_max_work = rows_per_leaf (1 + root_per_row)`` takes exactly the
+      leaf unknowns as leaves and keeps every root unknown in the root.
+    Only random draws and structure here; ``y`` is U(0, 10).
+    """
+    rng = np.random.default_rng(seed)
+    n_leaf = n_groups * leaf_per_group
+    n = n_leaf + n_root
+    rows_c, rows_v, rows_w = [], [], []
+    zcols = n_leaf + np.sort(rng.choice(n_root, size=zero_diag, replace=False)) \
+        if zero_diag else np.zeros(0, dtype=np.int64)
+    normal = np.setdiff1d(np.arange(n_leaf, n), zcols)
+    zset = set(int(z) for z in zcols)
+
+    def add(c, v, w):
+        rows_c.append(np.asarray(c))
+        rows_v.append(np.asarray(v, dtype=np.float64))
+        rows_w.append(float(w))
+
+    for g in range(n_groups):
+        span = int(min(len(normal), max(root_per_row + 1,
+                                         rng.integers(root_per_row, 4 * root_per_row + 2))))
+        lo = int(rng.integers(0, max(1, len(normal) - span + 1)))
+        for q in range(leaf_per_group):
+            j = g * leaf_per_group + q
+            for _ in range(rows_per_leaf):
+                k = int(min(span, root_per_row))
+                rc = np.sort(normal[lo + rng.choice(span, size=k, replace=False)])
+                add(np.concatenate([[j], rc]), 0.05 + 0.95 * rng.random(k + 1),
+                    0.5 + rng.random())
+    for j in normal:
+        add([j], [0.05 + 0.95 * rng.random()], 0.5 + rng.random())
+    for _ in range(neg_rows):
+        k = int(rng.integers(2, 5))
+        c = np.sort(rng.choice(normal, size=min(k, len(normal)), replace=False))
+        add(c, 0.05 + 0.95 * rng.random(len(c)), -neg_scale * (0.5 + rng.random()))
+    for z in zcols:
+        ks = rng.choice(normal, size=min(partners, len(normal)), replace=False)
+        for kk in ks:
+            c = np.sort(np.array([z, kk]))
+            add(c, [1.0, 1.0], 1.0)
+            add(c, [1.0, -1.0] if c[0] == z else [-1.0, 1.0], -1.0)
+    add(np.arange(n_leaf, n), 0.05 + 0.95 * rng.random(n_root), 0.0)
+    rowptr, col, val = _csr_from_lists(rows_c, rows_v, n)
+    mm = len(rows_c)
+    w = np.array(rows_w)
+    y = 10.0 * rng.random(mm)
+    assert not (zset & set(range(n_leaf)))
+    return Problem(m=mm, n=n, n_bg=n_leaf, rowptr=rowptr, col=col, val=val,
+                   w=w, y=y, x_true=np.zeros(n), seed=seed,
+                   name=f"indef{n_groups}x{leaf_per_group}+{n_root}")
+
+
 def lp_init_params(hidden: int, seed: int = 0) -> np.ndarray:
     """Seeded initial weights of the learned-preconditioner network (float32,
     flat layout [W1 (H x 3), b1, W2 (H x H), b2, w3, b3, wl (3)]):

@@ -179,3 +179,14 @@ def test_root_order_option_is_validated():
     p = synth.make_config(0)
     with pytest.raises(SpiError, match="invalid options"):
         _symbolic(p, keep_root_order=2)
+
+
+def test_indefinite_needs_the_root_sweeps():
+    """opts.indefinite = 1 with the Cholesky route is refused by the
+    analysis (host-only check)."""
+    import spi_synth as synth
+    from paper_1305_5683_amd import symbolic, SpiError
+    p = synth.make_indefinite(4, 3, 40, 3, 6, 10, 2, seed=1)
+    symbolic(p.m, p.n, p.rowptr, p.col, indefinite=1)
+    with pytest.raises(SpiError):
+        symbolic(p.m, p.n, p.rowptr, p.col, indefinite=1, root_inverse=0)
