@@ -155,6 +155,11 @@ typedef struct spi_opts {
                                to move into the root).  Needs
                                root_inverse = 1.  Default 0: positive
                                definite, every pivot checked */
+    int32_t asm_tile;       /* edge of the root tiles summed on chip by the
+                               root assembly: 64 or 128; 0 (default): 128
+                               for roots of padded order 8192 and more, 64
+                               below (four times the workgroups for small
+                               fronts) */
 } spi_opts;
 
 typedef struct spi_info_t {
@@ -209,7 +214,7 @@ typedef struct spi_info_t {
                                    (opts.keep_root_sum), 2 the kept A_RR
                                    plus the leaf fronts (after
                                    spi_set_leaf_values) */
-    int32_t reserved;
+    int32_t asm_tile;           /* root assembly tile edge (64 or 128) */
 } spi_info_t;
 
 /* Fill `o` with the defaults listed above. */
@@ -375,7 +380,8 @@ int spi_symbolic(int64_t m, int64_t n, const int64_t* rowptr,
  * 2.2.3): the host analysis of `src` is copied instead of recomputed, then
  * uploaded and the device buffers sized as in spi_analyze.
  *  opts    may be NULL (src's options); the analysis options (max_group,
- *          leaf_max_work, amalg_density) must equal src's
+ *          leaf_max_work, amalg_density, keep_root_order, asm_tile) must
+ *          equal src's
  *  stream  hipStream_t of the new handle
  */
 int spi_analyze_like(spi_handle** h, const spi_handle* src, const spi_opts* opts,

@@ -38,7 +38,6 @@
 namespace spi {
 
 namespace {
-constexpr int kTile = kAsmTile;  // root assembly tile
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -88,15 +87,16 @@ std::vector<int64_t> balanced_ranges(const int64_t* w, int64_t n, unsigned T) {
   return b;
 }
 
-// Runs of a sorted index list by tile: (tile, first position, end position).
-void tile_runs(const int32_t* U, int64_t nU,
+// Runs of a sorted index list by tile of edge `tile`: (tile, first position,
+// end position).
+void tile_runs(const int32_t* U, int64_t nU, int tile,
                std::vector<std::array<int32_t, 3>>& runs) {
   runs.clear();
   int64_t a = 0;
   while (a < nU) {
-    const int32_t t = U[a] / kTile;
+    const int32_t t = U[a] / tile;
     int64_t b = a + 1;
-    while (b < nU && U[b] / kTile == t) ++b;
+    while (b < nU && U[b] / tile == t) ++b;
     runs.push_back({t, (int32_t)a, (int32_t)b});
     a = b;
   }
@@ -586,7 +586,9 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
 
   // ---- incidences on the 64 x 64 lower tiles of the root
   if (a.n_pad) {
-    const int64_t T = a.n_pad / kTile;
+    a.asm_tile = o.asm_tile ? o.asm_tile
+                            : (a.n_pad >= kAsmTile128From ? kAsmTileLarge : kAsmTileSmall);
+    const int64_t T = a.n_pad / a.asm_tile;
     a.n_tiles = T * (T + 1) / 2;
     std::vector<int64_t> cnt(a.n_tiles + 1, 0);
     std::vector<std::array<int32_t, 3>> runs;
@@ -600,7 +602,7 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
       }
       for (int64_t u = 0; u < a.n_up; ++u) {
         if (a.up_k[u] == 0) continue;
-        tile_runs(a.U.data() + a.up_U_off[u], a.up_nU[u], runs);
+        tile_runs(a.U.data() + a.up_U_off[u], a.up_nU[u], a.asm_tile, runs);
         for (size_t x = 0; x < runs.size(); ++x)
           for (size_t y = 0; y <= x; ++y) {
             const int64_t I = runs[x][0], J = runs[y][0];

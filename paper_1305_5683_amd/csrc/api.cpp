@@ -130,7 +130,8 @@ bool check_opts(spi_opts& o) {
       !(o.refine_tol >= 0.0) || (o.keep_root_order != 0 && o.keep_root_order != 1) ||
       o.leaf_lds_cap < 0 || o.leaf_lds_cap > kLeafLdsCapMax || o.selinv_chunk < 0 ||
       (o.keep_root_sum != 0 && o.keep_root_sum != 1) ||
-      (o.indefinite != 0 && o.indefinite != 1)) {
+      (o.indefinite != 0 && o.indefinite != 1) ||
+      (o.asm_tile != 0 && o.asm_tile != kAsmTileSmall && o.asm_tile != kAsmTileLarge)) {
     g_analyze_err = "invalid options";
     return false;
   }
@@ -402,7 +403,8 @@ int spi_analyze_like(spi_handle** out, const spi_handle* src, const spi_opts* op
   if (o.max_group != src->h.opts.max_group ||
       o.leaf_max_work != src->h.opts.leaf_max_work ||
       o.amalg_density != src->h.opts.amalg_density ||
-      o.keep_root_order != src->h.opts.keep_root_order) {
+      o.keep_root_order != src->h.opts.keep_root_order ||
+      o.asm_tile != src->h.opts.asm_tile) {
     g_analyze_err = "analysis options must match the source handle";
     return SPI_E_ARG;
   }
@@ -607,6 +609,7 @@ static void fill_analysis_info(const Analysis& a, spi_info_t* info) {
   info->n_groups = a.n_groups;
   info->n_root = a.n_root;
   info->n_root_padded = a.n_pad;
+  info->asm_tile = a.asm_tile;
   info->flops_factor = a.flops_factor;
   info->flops_selinv = a.flops_selinv;
   info->flops_solve = a.flops_solve;

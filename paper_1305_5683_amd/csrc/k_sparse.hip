@@ -204,7 +204,8 @@ hipError_t launch_fill_rowpanels(Handle& h, bool compare) {
 }
 
 // --------------------------------------------------------- root assembly
-// One workgroup per kAsmTile x kAsmTile lower tile (I, J) of the root front.
+// One workgroup per TS x TS lower tile (I, J) of the root front (TS = 64 or
+// 128, chosen by the analysis: 8 or 16 waves).
 // The tile is the sum of its incidences: update panel u (a leaf front's
 // panel L_Ug with sign -1, or a row panel, stored as sqrt(w_r) h_r with sign
 // +1) restricted to the positions of U that fall in the tile's rows
@@ -242,7 +243,8 @@ hipError_t launch_fill_rowpanels(Handle& h, bool compare) {
 //   2  S = Akeep + leaf fronts (only the leaf fronts' values changed).
 constexpr int kAsmChunk = 128;  // incidences staged per pass
 constexpr int kAsmKC = 20;      // panel columns per batch of loads
-constexpr int kAsmThreads = kAsmTile >= 128 ? 1024 : 512;
+template <int TS>
+constexpr int asm_threads() { return TS >= 128 ? 1024 : 512; }
 constexpr int kAsmSpare = 8;    // spare LDS rows for dropped output rows
 // word 3 of a raw buffer resource on gfx9 (32-bit data, no swizzle)
 constexpr int kBufWord3 = 0x00020000;
@@ -387,7 +389,7 @@ __device__ inline void asm_compute(const AsmInc& d, const double* panel,
 }
 
 template <int TS>
-__global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
+__global__ __launch_bounds__(asm_threads<TS>()) void k_assemble_root(
     const int32_t* __restrict__ tile_order, const int64_t* __restrict__ inc_ptr,
     const int64_t* __restrict__ inc_split,
     const int32_t* __restrict__ inc, const int64_t* __restrict__ up_U_off,
@@ -408,14 +410,14 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
   const int64_t i0 = (int64_t)I * TS, j0 = (int64_t)J * TS;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // (uniform)
-  constexpr int NW = kAsmThreads / 64;
+  constexpr int kThreads = asm_threads<TS>(), NW = kThreads / 64;
   if (mode == 2) {  // start from the kept A_RR tile
-    for (int e = tid; e < TS * TS; e += kAsmThreads) {
+    for (int e = tid; e < TS * TS; e += kThreads) {
       const int a = e % TS, b = e / TS;
       C[a][b] = (I == J && a < b) ? 0.0 : Akeep[(i0 + a) + (j0 + b) * ld];
     }
   } else {
-    for (int e = tid; e < TS * TS; e += kAsmThreads) {
+    for (int e = tid; e < TS * TS; e += kThreads) {
       const int a = e % TS, b = e / TS;
       C[a][b] = (I == J && a == b && i0 + a >= n_root) ? 1.0 : 0.0;
     }
@@ -477,7 +479,7 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_root(
   };
   auto write_tile = [&](double* out) {
     __syncthreads();
-    for (int e = tid; e < TS * TS; e += kAsmThreads) {
+    for (int e = tid; e < TS * TS; e += kThreads) {
       const int a = e % TS, b = e / TS;
       if (I == J && a < b) continue;
       out[(i0 + a) + (j0 + b) * ld] = C[a][b];
@@ -507,11 +509,18 @@ hipError_t launch_assemble_root(Handle& h, int mode) {
   // panels' total)
   const double* panelB =
       h.panelS ? h.panelS - a.grp_panel_off[a.n_groups] : h.panel;
-  hipLaunchKernelGGL(k_assemble_root<kAsmTile>, dim3((unsigned)a.n_tiles),
-                     dim3(kAsmThreads), 0, h.stream, h.d.tile_order, h.d.inc_ptr,
-                     h.d.inc_split, h.d.inc, h.d.up_U_off, h.d.up_Q_off, h.d.up_nU,
-                     h.d.up_k, h.d.U, h.panel, panelB, h.S, h.Akeep, a.n_pad, a.n_root,
-                     mode);
+  if (a.asm_tile == kAsmTileLarge)
+    hipLaunchKernelGGL(k_assemble_root<kAsmTileLarge>, dim3((unsigned)a.n_tiles),
+                       dim3(asm_threads<kAsmTileLarge>()), 0, h.stream, h.d.tile_order,
+                       h.d.inc_ptr, h.d.inc_split, h.d.inc, h.d.up_U_off, h.d.up_Q_off,
+                       h.d.up_nU, h.d.up_k, h.d.U, h.panel, panelB, h.S, h.Akeep, a.n_pad,
+                       a.n_root, mode);
+  else
+    hipLaunchKernelGGL(k_assemble_root<kAsmTileSmall>, dim3((unsigned)a.n_tiles),
+                       dim3(asm_threads<kAsmTileSmall>()), 0, h.stream, h.d.tile_order,
+                       h.d.inc_ptr, h.d.inc_split, h.d.inc, h.d.up_U_off, h.d.up_Q_off,
+                       h.d.up_nU, h.d.up_k, h.d.U, h.panel, panelB, h.S, h.Akeep, a.n_pad,
+                       a.n_root, mode);
   return hipGetLastError();
 }
 

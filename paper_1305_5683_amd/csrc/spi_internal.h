@@ -23,16 +23,14 @@ constexpr int kNB = 64;
 constexpr int kET = 64;
 // Rows of the dense root triangular-solve chunks.
 constexpr int kTrsvChunk = 512;
-// Edge of the root tiles the output-stationary assembly sums in LDS.  Every
-// panel row is read once per tile pair it meets, so larger tiles read less;
-// but 128 x 128 (128 KB of the CU's 160 KB: one workgroup of 16 waves per
-// CU) measured slower than 64 x 64 (two workgroups of 8 waves per CU) on
-// the medium workload (6.4 against 5.5 ms) and equal on the large one
-// (562 ms): the kernel waits on load latency, not on the bytes.
-#ifndef SPI_ASM_TILE
-#define SPI_ASM_TILE 64
-#endif
-constexpr int kAsmTile = SPI_ASM_TILE;
+// Edges of the root tiles the output-stationary assembly sums in LDS.
+// Every panel row is read once per tile pair it meets, so larger tiles read
+// less: 128 x 128 (one workgroup of 16 waves per CU, 140 KB of LDS) against
+// 64 x 64 (two of 8 waves): medium root assembly 4.50 against 4.61 ms,
+// large 481 against 551 ms.  Roots below order kAsmTile128From keep 64 x 64
+// tiles, four times as many workgroups for a small front.
+constexpr int kAsmTileSmall = 64, kAsmTileLarge = 128;
+constexpr int64_t kAsmTile128From = 8192;
 // Widest leaf front (root positions) accumulated in LDS by the leaf
 // assembly: 4 waves x 2048 x 8 B = 64 KB per workgroup.
 constexpr int kLeafLdsCapMax = 2048;
@@ -91,9 +89,10 @@ struct Analysis {
   std::vector<int32_t> up_nU;
   std::vector<int32_t> up_k;
   std::vector<int32_t> up_w_off;       // -1: leaf panel (sign -1); else row panel
-  // incidences of the update panels on the kAsmTile x kAsmTile lower tiles
+  // incidences of the update panels on the asm_tile x asm_tile lower tiles
   // of the root; within a tile the leaf fronts' incidences come first
-  int64_t n_tiles = 0;                 // T (T + 1) / 2, T = n_pad / kAsmTile
+  int asm_tile = kAsmTileSmall;        // root assembly tile edge (64 or 128)
+  int64_t n_tiles = 0;                 // T (T + 1) / 2, T = n_pad / asm_tile
   std::vector<int32_t> tile_order;     // launch order of the tiles
   std::vector<int64_t> inc_ptr;        // n_tiles + 1
   std::vector<int64_t> inc_split;      // n_tiles: first row-panel incidence

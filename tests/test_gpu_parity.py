@@ -255,12 +255,36 @@ def test_medium_config_parity():
         assert abs(g["d"][j] - float(zc[j])) <= TOL_D * float(zc[j])
 
 
+def test_medium_config_parity_tile64():
+    """The medium workload with 64 x 64 root assembly tiles (the analysis
+    takes 128 x 128 at this order): same parity bar."""
+    p, _, o = _medium()
+    _say(f"case medium config, assembly tile 64, m={p.m} n={p.n}")
+    g = run_gpu(p, asm_tile=64)
+    assert g["info"]["asm_tile"] == 64
+    _check(p, g, o)
+
+
+@pytest.mark.parametrize("case", LEAFY, ids=[f"leafy{i}" for i in range(len(LEAFY))])
+def test_leafy_structure_parity_tile128(case):
+    """The planted-structure cases with 128 x 128 root assembly tiles (the
+    analysis takes 64 x 64 at these orders): runs spanning tiles, ragged
+    tails and padded roots in the 16-wave kernel."""
+    ng, lpg, nr, rpl, rpr, ex, seed, opts = case
+    p = synth.make_random_leafy(ng, lpg, nr, rpl, rpr, ex, seed)
+    _say(f"case leafy tile128 seed={seed} m={p.m} n={p.n} opts={opts}")
+    g = run_gpu(p, asm_tile=128, **opts)
+    assert g["info"]["asm_tile"] == 128 or g["info"]["n_root"] == 0
+    _check(p, g, oracle_solve(p))
+
+
 @pytest.mark.timeout(900)
 def test_large_shape_parity_fp64():
     """The large workload's field of view (31x31) and random bin lengths:
     all of x and every variance at 1e-12.  Its fronts are wider than the
-    on-chip accumulation cap (in-place leaf assembly), and a chunk of 50,000
-    tasks splits the leaf selected inversion into several launches."""
+    on-chip accumulation cap (in-place leaf assembly), a chunk of 50,000
+    tasks splits the leaf selected inversion into several launches, and the
+    root is assembled in 128 x 128 tiles as the large workload's is."""
     p, o = _large_shape()
     widths, info = _front_widths(p)
     nt = -(-widths // 64)
@@ -268,7 +292,8 @@ def test_large_shape_parity_fp64():
     _say(f"case large-shape fp64 m={p.m} n={p.n} root={info['n_root']} "
          f"widest front {widths.max()}, {n_tasks} selected-inversion tasks")
     assert widths.max() > 2048 and n_tasks > 3 * 50000
-    g = run_gpu(p, selinv_chunk=50000)
+    g = run_gpu(p, selinv_chunk=50000, asm_tile=128)
+    assert g["info"]["asm_tile"] == 128
     _check(p, g, o)
 
 
