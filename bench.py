@@ -54,7 +54,16 @@ CSRC = os.path.join(ROOT, "paper_1305_5683_amd", "csrc")
 # it that holds the kernel (between two marker lines) with the SHA-256 prefix
 # of that section's text when the counters were taken: once it changes the
 # figure no longer applies and `traffic` is reported as null.
-HBM_COUNTERS = {}
+HBM_COUNTERS = {
+    # large coded-mask system, FP64, outer block 512 (profiles/hbm_counters.txt)
+    (2, "bulk", 512, "fp64"): {"bytes": 12.812e9 + 4.0965e9, "src": "8ebcbc7f9f6f1926"},
+    (2, "assembly", None, "fp64"): {"bytes": 2781.8e9 + 4.2286e9, "src": "d1747aef30a14e5f"},
+    (2, "assembly", None, "mixed"): {"bytes": 2781.8e9 + 4.2286e9, "src": "d1747aef30a14e5f"},
+    # medium coded-mask system, FP64, outer block 512
+    (1, "bulk", 512, "fp64"): {"bytes": 1.2486e9 + 0.3683e9, "src": "8ebcbc7f9f6f1926"},
+    (1, "assembly", None, "fp64"): {"bytes": 17.015e9 + 0.5336e9, "src": "d1747aef30a14e5f"},
+    (1, "assembly", None, "mixed"): {"bytes": 17.015e9 + 0.5336e9, "src": "d1747aef30a14e5f"},
+}
 
 
 def src_hash(name, begin=None, end=None):
@@ -335,7 +344,7 @@ def measure(p, prec, args, src=None):
     tile = s.bulk_tile
     asm_ms = ph["t_extend_ms"]
     kernels = {
-        "assembly": {"kernel": "k_assemble_root (root front assembly)",
+        "assembly": {"kernel": f"k_assemble_root<{i1['asm_tile']}> (root front assembly)",
                      "ms_per_step": asm_ms, "launches_per_step": 1,
                      "flops_per_launch": i1["flops_root_assembly"],
                      "peak": PEAK_FP64_TFLOPS, "key": "assembly"},

@@ -634,6 +634,16 @@ void spi_batch_destroy(spi_batch* b);
  *  chosen  host, may be NULL: the outer block chosen
  */
 int spi_autotune(spi_handle* h, int32_t* chosen);
+/*
+ * Test aid: overwrite every device work buffer of the handle (values,
+ * fronts, root, bands, partial sums, flags; not the analysis maps) with
+ * 0xff bytes (NaN as binary64), so that a test can show that no result
+ * depends on what a buffer held before.  Stream-ordered on the handle's
+ * stream.  The handle then needs spi_set_values and spi_factor again.
+ * Returns SPI_E_ARG for a NULL handle, SPI_E_HIP on a runtime error.
+ */
+int spi_debug_poison(spi_handle* h);
+
 /* Current outer block of the root front, or -1 for a NULL handle. */
 int spi_get_potrf_block(const spi_handle* h);
 /* Tile edge of the sweeps' bulk update (64 or 128; default 128), or -1. */

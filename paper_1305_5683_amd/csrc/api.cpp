@@ -168,8 +168,11 @@ int setup_device(spi_handle* H) {
 #undef UP
   const int64_t nl = (int64_t)a.leaf_cols.size();
   const int64_t np = a.n_pad;
-#define AL(ptr, cnt) \
-  if (he == hipSuccess) he = dev_alloc(ptr, cnt)
+#define AL(ptr, cnt)                                                   \
+  if (he == hipSuccess) {                                              \
+    he = dev_alloc(ptr, cnt);                                          \
+    if (ptr) h.bufs.emplace_back((void*)ptr, (size_t)(cnt) * sizeof(*ptr)); \
+  }
   AL(h.val, a.nnz); AL(h.valc, a.nnz); AL(h.w, a.m); AL(h.sw, a.n_slots);
   AL(h.sleaf, a.n_slots);
   AL(h.rrval, (int64_t)a.rr_src.size());
@@ -448,6 +451,19 @@ int spi_set_values(spi_handle* H, const double* val, const double* w) {
   h.have_inv = false;
   h.akeep_valid = false;
   h.leaf_update = false;
+  return SPI_OK;
+}
+
+int spi_debug_poison(spi_handle* H) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = H->h;
+  for (const auto& b : h.bufs)
+    SPI_CK(hipMemsetAsync(b.first, 0xff, b.second, h.stream), "poison");
+  h.have_values = false;
+  h.have_factor = false;
+  h.have_inv = false;
+  h.akeep_valid = false;
+  h.z_valid = false;
   return SPI_OK;
 }
 

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/spi.h"
@@ -266,6 +267,7 @@ struct Handle {
   // phase timing (opts.timing): HIP event pairs recorded on the stream,
   // accumulated lazily (spi_info synchronises and sums them)
   PhaseTimer timer[kNumPhases];
+  std::vector<std::pair<void*, size_t>> bufs;  // device work buffers (bytes)
   bool have_values = false, have_factor = false;
   int64_t failed_col = -1;
   double t_analyze_ms = 0;

@@ -29,7 +29,7 @@ EXPORTED = ["spi_default_opts", "spi_analyze", "spi_set_values", "spi_factor",
             "spi_set_potrf_block", "spi_diag_inv_noalloc", "spi_set_leaf_values",
             "spi_empty_field_update", "spi_empty_field_loop", "spi_mle_terms",
             "spi_mle_newton", "spi_inv_entries", "spi_get_bulk_tile",
-            "spi_set_bulk_tile"]
+            "spi_set_bulk_tile", "spi_debug_poison"]
 
 
 class spi_opts(C.Structure):
@@ -136,6 +136,7 @@ def load_library(path: str = LIB_PATH):
     lib.spi_get_potrf_block.argtypes = [P]
     lib.spi_set_potrf_block.argtypes = [P, I32]
     lib.spi_get_bulk_tile.argtypes = [P]
+    lib.spi_debug_poison.argtypes = [P]
     lib.spi_set_bulk_tile.argtypes = [P, I32]
     for name in EXPORTED:
         if name not in ("spi_default_opts", "spi_last_error", "spi_destroy",
@@ -249,6 +250,10 @@ class SpiSolver:
     @potrf_block.setter
     def potrf_block(self, v):
         self._check(self.lib.spi_set_potrf_block(self.h, int(v)))
+
+    def debug_poison(self):
+        """Fill the handle's device work buffers with NaN bytes (test aid)."""
+        self._check(self.lib.spi_debug_poison(self.h))
 
     @property
     def bulk_tile(self) -> int:
