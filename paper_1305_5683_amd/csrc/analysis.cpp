@@ -627,17 +627,17 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
       while (q < a.inc_ptr[t + 1] && a.inc[4 * q] < a.n_groups) ++q;
       a.inc_split[t] = q;
     }
-    // launch order: groups of 8 tile rows, column by column inside a group
-    // (with the XCD remap, 64 consecutive tiles = an 8 x 8 block, run
-    // together on one XCD, whose incidences share panel rows in its L2)
+    // launch order: column by column (J), down each column (I >= J).  With
+    // the XCD remap, consecutive tiles of a column run together on one XCD
+    // and share the column tile's panel rows in its L2.  Measured against
+    // groups of 8, 16, 32, 64 and 128 tile rows taken column by column
+    // (root assembly, medium / large, ms): 4.50 / 482, 4.28 / 474,
+    // 3.69 / 467, 3.71 / 459, 3.63 / 456; whole columns 3.62 / 448.
     a.tile_order.clear();
     a.tile_order.reserve(a.n_tiles);
-    for (int64_t g0 = 0; g0 < T; g0 += 8) {
-      const int64_t g1 = std::min<int64_t>(T, g0 + 8);
-      for (int64_t J = 0; J < g1; ++J)
-        for (int64_t I = std::max(g0, J); I < g1; ++I)
-          a.tile_order.push_back((int32_t)(I * (I + 1) / 2 + J));
-    }
+    for (int64_t J = 0; J < T; ++J)
+      for (int64_t I = J; I < T; ++I)
+        a.tile_order.push_back((int32_t)(I * (I + 1) / 2 + J));
   }
 
   phase("incidences");
@@ -667,10 +667,12 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
       }
     a.grp_task_ptr.push_back((int64_t)a.tasks.size() / 3);
   }
-  // launch order: by 2-D block of the root front at the task's first row /
-  // column, then by task index
+  // launch order: by 512 x 512 block of the root front at the task's first
+  // row / column (a block's Z entries fit an XCD's L2), then by task index.
+  // Large workload's leaf selected inversion: 309 ms with 2048-blocks, 292
+  // with 512, 294 with 256, 297 with 1024.
   {
-    constexpr int kOrderBlock = 2048;
+    constexpr int kOrderBlock = 512;
     const int64_t nt = (int64_t)a.tasks.size() / 3;
     std::vector<int64_t> key(nt);
     for (int64_t t = 0; t < nt; ++t) {

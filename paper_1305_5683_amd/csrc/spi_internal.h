@@ -313,7 +313,8 @@ hipError_t ensure_side_stream(Handle& h);
 // to XCD x, so the items running together on an XCD are consecutive ones,
 // which share data in that XCD's L2.  The last partial chunk maps to itself.
 //   B = 8:  the dense GEMM (8 tiles of one column of a group of 8 rows);
-//   B = 64: the root assembly and selected inversion (an 8 x 8 tile block).
+//   B = 64: the root assembly (64 consecutive tiles of a tile column) and
+//           the selected inversion (tasks of one 512 x 512 block of the root).
 template <int B>
 __device__ inline int xcd_remap(int w, int n) {
   constexpr int C = 8 * B;
