@@ -56,31 +56,40 @@ CSRC = os.path.join(ROOT, "paper_1305_5683_amd", "csrc")
 # figure no longer applies and `traffic` is reported as null.
 HBM_COUNTERS = {
     # large coded-mask system, FP64, outer block 512 (profiles/hbm_counters.txt)
-    (2, "bulk", 512, "fp64"): {"bytes": 12.812e9 + 4.0965e9, "src": "8ebcbc7f9f6f1926"},
+    (2, "bulk", 512, "fp64"): {"bytes": 12.812e9 + 4.0965e9, "src": "6291710c77d9dd5a"},
     (2, "assembly", None, "fp64"): {"bytes": 2781.8e9 + 4.2286e9, "src": "d1747aef30a14e5f"},
     (2, "assembly", None, "mixed"): {"bytes": 2781.8e9 + 4.2286e9, "src": "d1747aef30a14e5f"},
     # medium coded-mask system, FP64, outer block 512
-    (1, "bulk", 512, "fp64"): {"bytes": 1.2486e9 + 0.3683e9, "src": "8ebcbc7f9f6f1926"},
+    (1, "bulk", 512, "fp64"): {"bytes": 1.2486e9 + 0.3683e9, "src": "6291710c77d9dd5a"},
     (1, "assembly", None, "fp64"): {"bytes": 17.015e9 + 0.5336e9, "src": "d1747aef30a14e5f"},
     (1, "assembly", None, "mixed"): {"bytes": 17.015e9 + 0.5336e9, "src": "d1747aef30a14e5f"},
 }
 
 
-def src_hash(name, begin=None, end=None):
-    with open(os.path.join(CSRC, name), encoding="utf-8") as fh:
-        text = fh.read()
-    if begin is not None:
-        i = text.index(begin)
-        j = text.index(end, i) if end is not None else len(text)
-        text = text[i:j]
-    return hashlib.sha256(text.encode()).hexdigest()[:16]
+def src_hash(parts):
+    """SHA-256 prefix of the concatenated source sections: (file, first
+    marker line or None for the whole file, end marker or None)."""
+    h = hashlib.sha256()
+    for name, begin, end in parts:
+        with open(os.path.join(CSRC, name), encoding="utf-8") as fh:
+            text = fh.read()
+        if begin is not None:
+            i = text.index(begin)
+            j = text.index(end, i) if end is not None else len(text)
+            text = text[i:j]
+        h.update(text.encode())
+    return h.hexdigest()[:16]
 
 
-# the sections the counters depend on
+# the sources the counters depend on: the kernel and the code that decides
+# its launch order or its shapes
 SRC_SECTIONS = {
-    "bulk": ("k_gemm.hip", None, None),
-    "assembly": ("k_sparse.hip", "// --------------------------------------------------------- root assembly",
-                 "// ------------------------------------------------------------ equilibration"),
+    "bulk": [("k_gemm.hip", None, None),
+             ("k_dense.hip", "hipError_t root_sweep(Handle& h) {", "\n}\n")],
+    "assembly": [("k_sparse.hip",
+                  "// --------------------------------------------------------- root assembly",
+                  "// ------------------------------------------------------------ equilibration"),
+                 ("analysis.cpp", "  // ---- incidences on the", '  phase("incidences");')],
 }
 
 
@@ -88,7 +97,7 @@ def counter_traffic(config, kernel, blk, prec):
     c = HBM_COUNTERS.get((config, kernel, blk if kernel == "bulk" else None, prec))
     if c is None:
         return None
-    return c["bytes"] if src_hash(*SRC_SECTIONS[kernel]) == c["src"] else None
+    return c["bytes"] if src_hash(SRC_SECTIONS[kernel]) == c["src"] else None
 
 
 def parse():
