@@ -241,7 +241,11 @@ hipError_t launch_fill_rowpanels(Handle& h, bool compare) {
 //   1  the same, and the row panels' sum alone (A_RR, the root block of
 //      H^T W H) is also written to Akeep;
 //   2  S = Akeep + leaf fronts (only the leaf fronts' values changed).
-constexpr int kAsmChunk = 128;  // incidences staged per pass
+// incidences staged per pass (fewer passes, fewer barriers and less waiting
+// on a tile's slowest wave: root assembly medium / large 3.96 / 488 ms with
+// 64, 3.62 / 448 with 128, 3.43 / 425 with 256, 3.32 / 417 with 512; the
+// 128 x 128 kernel's LDS then holds 159 KB of its 160)
+constexpr int kAsmChunk = 512;
 constexpr int kAsmKC = 20;      // panel columns per batch of loads
 template <int TS>
 constexpr int asm_threads() { return TS >= 128 ? 1024 : 512; }
@@ -400,6 +404,7 @@ __global__ __launch_bounds__(asm_threads<TS>()) void k_assemble_root(
     int mode) {
   __shared__ double C[TS + kAsmSpare][TS + 1];
   __shared__ int64_t s_q[kAsmChunk], s_u[kAsmChunk];
+  __shared__ int32_t s_next;  // next incidence of the chunk to hand out
   __shared__ int32_t s_ab[kAsmChunk][2], s_nU[kAsmChunk], s_k[kAsmChunk],
       s_n[kAsmChunk];
   const int t = tile_order[xcd_remap<64>(blockIdx.x, gridDim.x)];
@@ -429,19 +434,22 @@ __global__ __launch_bounds__(asm_threads<TS>()) void k_assemble_root(
     for (int64_t c0 = q_beg; c0 < q_end; c0 += kAsmChunk) {
       const int nc = (int)min((int64_t)kAsmChunk, q_end - c0);
       __syncthreads();  // previous chunk consumed (and C initialised)
-      if (tid < nc) {
-        const int32_t* p = inc + 4 * (c0 + tid);
+      for (int e = tid; e < nc; e += kThreads) {
+        const int32_t* p = inc + 4 * (c0 + e);
         const int u = p[0];
-        s_q[tid] = up_Q_off[u];
-        s_u[tid] = up_U_off[u];
-        s_ab[tid][0] = p[1];
-        s_ab[tid][1] = p[2];
-        s_nU[tid] = up_nU[u];
-        s_k[tid] = up_k[u];
-        s_n[tid] = p[3];
+        s_q[e] = up_Q_off[u];
+        s_u[e] = up_U_off[u];
+        s_ab[e][0] = p[1];
+        s_ab[e][1] = p[2];
+        s_nU[e] = up_nU[u];
+        s_k[e] = up_k[u];
+        s_n[e] = p[3];
       }
+      if (tid == 0) s_next = NW;  // waves start on incidences 0 .. NW - 1
       __syncthreads();
-      // A wave's incidences (wave, wave + NW, ...), each by row strips of
+      // A wave takes incidence `wave` first, then whichever is next when it
+      // is done (an LDS counter), so the waves of a tile finish together;
+      // each incidence by row strips of
       // 32: with k <= kAsmKC the strip's A side is loaded once for all its
       // column super-blocks.  In a diagonal tile an incidence pairs a run
       // with itself: super-blocks above the diagonal are skipped and those
@@ -450,7 +458,7 @@ __global__ __launch_bounds__(asm_threads<TS>()) void k_assemble_root(
       const bool diag = I == J;
       // B side: the leaf fronts' panels, or the row panels' (signed) copy
       const double* pB = NEG ? panel : panelB;
-      for (int q = wave; q < nc; q += NW) {
+      for (int q = wave; q < nc;) {
         AsmInc d;
         d.qo = uniform64(s_q[q]);
         d.uo = uniform64(s_u[q]);
@@ -474,6 +482,9 @@ __global__ __launch_bounds__(asm_threads<TS>()) void k_assemble_root(
             asm_compute<NEG, TS>(d, panel, pB, sa, sb, A, B, Cf, (int)i0, (int)j0, lane);
           }
         }
+        int nq = 0;
+        if (lane == 0) nq = atomicAdd(&s_next, 1);
+        q = __builtin_amdgcn_readfirstlane(nq);
       }
     }
   };
