@@ -89,7 +89,7 @@ SRC_SECTIONS = {
     "assembly": [("k_sparse.hip",
                   "// --------------------------------------------------------- root assembly",
                   "// ------------------------------------------------------------ equilibration"),
-                 ("analysis.cpp", "  // ---- incidences on the", '  phase("incidences");')],
+                 ("analysis.cpp", "  // ---- amalgamate consecutive leaves", '  phase("incidences");')],
 }
 
 

@@ -56,7 +56,13 @@ struct PhaseLog {
   }
 };
 
+// Host threads of the analysis: up to 16, or SPI_ANALYSIS_THREADS (1..64;
+// the results do not depend on it, which a test checks).
 unsigned n_threads() {
+  if (const char* e = std::getenv("SPI_ANALYSIS_THREADS")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 64) return (unsigned)v;
+  }
   return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
 }
 
@@ -246,18 +252,41 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
     }
   }
   const int64_t nnz = rowptr[m];
-  for (int64_t r = 0; r < m; ++r) {
-    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-      int32_t c = col[e];
-      if (c < 0 || c >= n) {
-        err << "column index " << c << " out of range in row " << r;
-        return err.str();
-      }
-      if (e > rowptr[r] && col[e - 1] >= c) {
+  {
+    // every thread checks a range of rows; the first bad row is reported
+    const unsigned NT = n_threads();
+    const std::vector<int64_t> rb = balanced_ranges(rowptr, m, NT);
+    std::vector<int64_t> bad(NT, m);
+    std::vector<int> kind(NT, 0);
+    parallel(NT, [&](unsigned t) {
+      for (int64_t r = rb[t]; r < rb[t + 1] && bad[t] == m; ++r)
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+          const int32_t c = col[e];
+          if (c < 0 || c >= n) {
+            bad[t] = r;
+            kind[t] = 1;
+            break;
+          }
+          if (e > rowptr[r] && col[e - 1] >= c) {
+            bad[t] = r;
+            kind[t] = 2;
+            break;
+          }
+        }
+    });
+    for (unsigned t = 0; t < NT; ++t)
+      if (bad[t] < m) {
+        const int64_t r = bad[t];
+        if (kind[t] == 1) {
+          for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
+            if (col[e] < 0 || col[e] >= n) {
+              err << "column index " << col[e] << " out of range in row " << r;
+              return err.str();
+            }
+        }
         err << "columns not strictly increasing in row " << r;
         return err.str();
       }
-    }
   }
   a = Analysis();
   a.m = m;
@@ -351,77 +380,114 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   a.n_pad = a.n_root ? round_up(a.n_root, kRootPad) : 0;
 
   phase("root numbering");
-  // ---- amalgamate consecutive leaves into fronts
+  // ---- amalgamate consecutive leaves into fronts.  The leaves are taken in
+  // fixed chunks of kAmalgChunk (a front never spans two chunks), the chunks
+  // in parallel and concatenated in order: the fronts do not depend on the
+  // number of threads.
+  constexpr int64_t kAmalgChunk = 4096;
   std::vector<int32_t> leaves;
   for (int64_t j = 0; j < n; ++j)
     if (is_leaf[j]) leaves.push_back((int32_t)j);
   const int64_t nr = std::max<int64_t>(a.n_root, 1);
-  std::vector<int64_t> mark(nr, -1), seen(nr, -1);
+  struct FrontPart {
+    std::vector<int32_t> cols, U;
+    std::vector<int64_t> col_end, U_end, panel;  // per front
+    double work = 0.0, update = 0.0;
+  };
+  const int64_t n_lv = (int64_t)leaves.size();
+  const int64_t n_ch = (n_lv + kAmalgChunk - 1) / kAmalgChunk;
+  std::vector<FrontPart> fparts(n_ch);
+  parallel(NT, [&](unsigned t) {
+    std::vector<int64_t> mark(nr, -1), seen(nr, -1);
+    std::vector<int32_t> curU, curCols, rj;
+    for (int64_t ch = t; ch < n_ch; ch += NT) {
+      FrontPart& P = fparts[ch];
+      int64_t front = ch * kAmalgChunk;  // unique mark ids across chunks
+      int64_t cur_sum = 0;
+      curU.clear();
+      curCols.clear();
+      auto close_front = [&]() {
+        std::sort(curU.begin(), curU.end());
+        P.cols.insert(P.cols.end(), curCols.begin(), curCols.end());
+        P.U.insert(P.U.end(), curU.begin(), curU.end());
+        P.col_end.push_back((int64_t)P.cols.size());
+        P.U_end.push_back((int64_t)P.U.size());
+        P.panel.push_back((int64_t)curU.size() * (int64_t)curCols.size());
+        ++front;
+        curU.clear();
+        curCols.clear();
+        cur_sum = 0;
+      };
+      const int64_t l1 = std::min(n_lv, (ch + 1) * kAmalgChunk);
+      for (int64_t li = ch * kAmalgChunk; li < l1; ++li) {
+        const int32_t j = leaves[li];
+        rj.clear();
+        for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
+          int32_t r = a.csc_row[k];
+          for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+            int32_t ri = a.root_of_col[col[e]];
+            if (ri >= 0 && seen[ri] != j) {
+              seen[ri] = j;
+              rj.push_back(ri);
+            }
+          }
+        }
+        if (!curCols.empty()) {
+          int64_t add = 0;
+          for (int32_t u : rj)
+            if (mark[u] != front) ++add;
+          int64_t newU = (int64_t)curU.size() + add;
+          int64_t newp = (int64_t)curCols.size() + 1;
+          bool ok = newp <= o.max_group;
+          if (ok && newU > 0) {
+            double dens = (double)(cur_sum + (int64_t)rj.size()) /
+                          ((double)newU * (double)newp);
+            ok = dens >= o.amalg_density;
+          }
+          if (!ok) close_front();
+        }
+        for (int32_t u : rj)
+          if (mark[u] != front) {
+            mark[u] = front;
+            curU.push_back(u);
+          }
+        curCols.push_back(j);
+        cur_sum += (int64_t)rj.size();
+        // algorithmic work of leaf j as its own front (p = 1, c = the root
+        // unknowns of its rows, its exact column count in L)
+        const double c = (double)rj.size();
+        P.work += 1.0 / 3.0 + c + c * c;
+        P.update += c * (c + 1.0);
+      }
+      if (!curCols.empty()) close_front();
+    }
+  });
   a.grp_col_ptr.push_back(0);
   a.grp_U_ptr.push_back(0);
   a.grp_panel_off.push_back(0);
-  int64_t front = 0;
-  std::vector<int32_t> curU, curCols;
-  int64_t cur_sum = 0;
   double leaf_work = 0.0, leaf_update = 0.0;
-  auto close_front = [&]() {
-    std::sort(curU.begin(), curU.end());
-    for (int32_t j : curCols) {
-      a.leaf_cols.push_back(j);
-      a.leaf_grp.push_back((int32_t)front);
-    }
-    a.U.insert(a.U.end(), curU.begin(), curU.end());
-    a.grp_col_ptr.push_back((int64_t)a.leaf_cols.size());
-    a.grp_U_ptr.push_back((int64_t)a.U.size());
-    a.grp_panel_off.push_back(a.grp_panel_off.back() +
-                              (int64_t)curU.size() * (int64_t)curCols.size());
-    ++front;
-    curU.clear();
-    curCols.clear();
-    cur_sum = 0;
-  };
-  std::vector<int32_t> rj;
-  for (int32_t j : leaves) {
-    rj.clear();
-    for (int64_t k = a.colptr[j]; k < a.colptr[j + 1]; ++k) {
-      int32_t r = a.csc_row[k];
-      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        int32_t ri = a.root_of_col[col[e]];
-        if (ri >= 0 && seen[ri] != j) {
-          seen[ri] = j;
-          rj.push_back(ri);
-        }
+  int64_t front = 0;
+  for (const FrontPart& P : fparts) {
+    const int64_t c0 = (int64_t)a.leaf_cols.size(), u0 = (int64_t)a.U.size();
+    int64_t cb = 0;
+    for (size_t f = 0; f < P.col_end.size(); ++f) {
+      for (int64_t q = cb; q < P.col_end[f]; ++q) {
+        a.leaf_cols.push_back(P.cols[q]);
+        a.leaf_grp.push_back((int32_t)front);
       }
+      cb = P.col_end[f];
+      a.grp_col_ptr.push_back(c0 + P.col_end[f]);
+      a.grp_U_ptr.push_back(u0 + P.U_end[f]);
+      a.grp_panel_off.push_back(a.grp_panel_off.back() + P.panel[f]);
+      ++front;
     }
-    if (!curCols.empty()) {
-      int64_t add = 0;
-      for (int32_t u : rj)
-        if (mark[u] != front) ++add;
-      int64_t newU = (int64_t)curU.size() + add;
-      int64_t newp = (int64_t)curCols.size() + 1;
-      bool ok = newp <= o.max_group;
-      if (ok && newU > 0) {
-        double dens = (double)(cur_sum + (int64_t)rj.size()) /
-                      ((double)newU * (double)newp);
-        ok = dens >= o.amalg_density;
-      }
-      if (!ok) close_front();
-    }
-    for (int32_t u : rj)
-      if (mark[u] != front) {
-        mark[u] = front;
-        curU.push_back(u);
-      }
-    curCols.push_back(j);
-    cur_sum += (int64_t)rj.size();
-    // algorithmic work of leaf j as its own front (p = 1, c = the root
-    // unknowns of its rows, its exact column count in L)
-    const double c = (double)rj.size();
-    leaf_work += 1.0 / 3.0 + c + c * c;
-    leaf_update += c * (c + 1.0);
+    a.U.insert(a.U.end(), P.U.begin(), P.U.end());
+    leaf_work += P.work;
+    leaf_update += P.update;
   }
-  if (!curCols.empty()) close_front();
   a.n_groups = front;
+  fparts.clear();
+  fparts.shrink_to_fit();
 
   a.leaf_of_col.assign(n, -1);
   for (size_t l = 0; l < a.leaf_cols.size(); ++l) a.leaf_of_col[a.leaf_cols[l]] = (int32_t)l;
@@ -483,51 +549,81 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   phase("slots");
   // ---- row panels: consecutive rows (original order) with overlapping
   // root structure; rows without root entries contribute nothing to A_RR.
-  // The grouping is sequential (each decision depends on the open panel);
-  // the per-entry maps are then filled panel by panel in parallel.
+  // Each decision depends on the open panel, so the rows are grouped in
+  // fixed chunks of kRowChunk (a panel never spans two chunks), the chunks
+  // in parallel and concatenated in order (independent of the number of
+  // threads); the per-entry maps are then filled panel by panel in parallel.
+  constexpr int64_t kRowChunk = 65536;
   a.rp_U_base = (int64_t)a.U.size();
   a.rp_row_ptr.assign(1, 0);
   a.rp_U_ptr.assign(1, 0);
   a.rp_val_off.assign(1, 0);
-  std::fill(mark.begin(), mark.end(), -1);
   {
-    int64_t panel = 0, rows_in = 0, sum = 0, pU0 = (int64_t)a.U.size();
-    auto close_panel = [&]() {
-      std::sort(a.U.begin() + pU0, a.U.end());
-      const int64_t nU = (int64_t)a.U.size() - pU0;
-      a.rp_row_ptr.push_back((int64_t)a.rp_rows.size());
-      a.rp_U_ptr.push_back((int64_t)a.U.size() - a.rp_U_base);
-      a.rp_val_off.push_back(a.rp_val_off.back() + nU * rows_in);
-      ++panel;
-      pU0 = (int64_t)a.U.size();
-      rows_in = 0;
-      sum = 0;
+    struct PanelPart {
+      std::vector<int32_t> rows, U;
+      std::vector<int64_t> row_end, U_end, val;  // per panel
     };
-    for (int64_t r = 0; r < m; ++r) {
-      const int64_t len = root_cnt[r];
-      if (len == 0) continue;
-      if (rows_in > 0) {
-        int64_t add = 0;
-        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-          const int32_t ri = a.root_of_col[col[e]];
-          if (ri >= 0 && mark[ri] != panel) ++add;
+    const int64_t n_rc = (m + kRowChunk - 1) / kRowChunk;
+    std::vector<PanelPart> rparts(n_rc);
+    parallel(NT, [&](unsigned t) {
+      std::vector<int64_t> mark(nr, -1);
+      for (int64_t ch = t; ch < n_rc; ch += NT) {
+        PanelPart& P = rparts[ch];
+        int64_t panel = ch * kRowChunk;  // unique mark ids across chunks
+        int64_t rows_in = 0, sum = 0, pU0 = 0;
+        auto close_panel = [&]() {
+          std::sort(P.U.begin() + pU0, P.U.end());
+          const int64_t nU = (int64_t)P.U.size() - pU0;
+          P.row_end.push_back((int64_t)P.rows.size());
+          P.U_end.push_back((int64_t)P.U.size());
+          P.val.push_back(nU * rows_in);
+          ++panel;
+          pU0 = (int64_t)P.U.size();
+          rows_in = 0;
+          sum = 0;
+        };
+        const int64_t r1 = std::min(m, (ch + 1) * kRowChunk);
+        for (int64_t r = ch * kRowChunk; r < r1; ++r) {
+          const int64_t len = root_cnt[r];
+          if (len == 0) continue;
+          if (rows_in > 0) {
+            int64_t add = 0;
+            for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+              const int32_t ri = a.root_of_col[col[e]];
+              if (ri >= 0 && mark[ri] != panel) ++add;
+            }
+            const int64_t newU = (int64_t)P.U.size() - pU0 + add;
+            const double dens =
+                (double)(sum + len) / ((double)newU * (double)(rows_in + 1));
+            if (rows_in + 1 > o.max_group || dens < o.amalg_density) close_panel();
+          }
+          for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+            const int32_t ri = a.root_of_col[col[e]];
+            if (ri >= 0 && mark[ri] != panel) {
+              mark[ri] = panel;
+              P.U.push_back(ri);
+            }
+          }
+          P.rows.push_back((int32_t)r);
+          ++rows_in;
+          sum += len;
         }
-        const int64_t newU = (int64_t)a.U.size() - pU0 + add;
-        const double dens = (double)(sum + len) / ((double)newU * (double)(rows_in + 1));
-        if (rows_in + 1 > o.max_group || dens < o.amalg_density) close_panel();
+        if (rows_in > 0) close_panel();
       }
-      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        const int32_t ri = a.root_of_col[col[e]];
-        if (ri >= 0 && mark[ri] != panel) {
-          mark[ri] = panel;
-          a.U.push_back(ri);
-        }
+    });
+    int64_t panel = 0;
+    for (const PanelPart& P : rparts) {
+      const int64_t r0 = (int64_t)a.rp_rows.size();
+      const int64_t u0 = (int64_t)a.U.size() - a.rp_U_base;
+      for (size_t q = 0; q < P.row_end.size(); ++q) {
+        a.rp_row_ptr.push_back(r0 + P.row_end[q]);
+        a.rp_U_ptr.push_back(u0 + P.U_end[q]);
+        a.rp_val_off.push_back(a.rp_val_off.back() + P.val[q]);
+        ++panel;
       }
-      a.rp_rows.push_back((int32_t)r);
-      ++rows_in;
-      sum += len;
+      a.rp_rows.insert(a.rp_rows.end(), P.rows.begin(), P.rows.end());
+      a.U.insert(a.U.end(), P.U.begin(), P.U.end());
     }
-    if (rows_in > 0) close_panel();
     a.n_rp = panel;
   }
   {
@@ -674,18 +770,21 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   {
     constexpr int kOrderBlock = 512;
     const int64_t nt = (int64_t)a.tasks.size() / 3;
-    std::vector<int64_t> key(nt);
+    // keys bj * nb + bi take nb^2 values: a stable counting sort
+    const int64_t nb = std::max<int64_t>(1, (a.n_pad + kOrderBlock - 1) / kOrderBlock);
+    std::vector<int32_t> key(nt);
+    std::vector<int64_t> start(nb * nb + 1, 0);
     for (int64_t t = 0; t < nt; ++t) {
       const int64_t f = a.tasks[3 * t], I = a.tasks[3 * t + 1],
                     J = a.tasks[3 * t + 2];
       const int32_t* Uf = a.U.data() + a.grp_U_ptr[f];
       const int64_t bi = Uf[I * kET] / kOrderBlock, bj = Uf[J * kET] / kOrderBlock;
-      key[t] = (bj << 20) | bi;
+      key[t] = (int32_t)(bj * nb + bi);
+      start[key[t] + 1]++;
     }
+    for (int64_t k = 0; k < nb * nb; ++k) start[k + 1] += start[k];
     a.sel_order.resize(nt);
-    std::iota(a.sel_order.begin(), a.sel_order.end(), 0);
-    std::stable_sort(a.sel_order.begin(), a.sel_order.end(),
-                     [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+    for (int64_t t = 0; t < nt; ++t) a.sel_order[start[key[t]]++] = (int32_t)t;
   }
 
   phase("selected-inversion tasks");

@@ -190,3 +190,31 @@ def test_indefinite_needs_the_root_sweeps():
     symbolic(p.m, p.n, p.rowptr, p.col, indefinite=1)
     with pytest.raises(SpiError):
         symbolic(p.m, p.n, p.rowptr, p.col, indefinite=1, root_inverse=0)
+
+
+def test_analysis_does_not_depend_on_the_thread_count():
+    """The analysis runs its phases on host threads (fixed chunks of leaves
+    and rows where decisions are sequential): 1, 3 and 7 threads give the
+    same fronts, elimination order and counts."""
+    import os
+    from paper_1305_5683_amd import symbolic
+    p = synth.make_config(0)
+    q = synth.make_random_leafy(30, 6, 300, 3, 20, 200, seed=4)
+    outs = []
+    old = os.environ.get("SPI_ANALYSIS_THREADS")
+    try:
+        for nt in ("1", "3", "7"):
+            os.environ["SPI_ANALYSIS_THREADS"] = nt
+            outs.append([symbolic(r.m, r.n, r.rowptr, r.col) for r in (p, q)])
+    finally:
+        if old is None:
+            os.environ.pop("SPI_ANALYSIS_THREADS", None)
+        else:
+            os.environ["SPI_ANALYSIS_THREADS"] = old
+    for other in outs[1:]:
+        for (i0, o0, p0, f0), (i1, o1, p1, f1) in zip(outs[0], other):
+            assert np.array_equal(o0, o1) and np.array_equal(p0, p1)
+            assert np.array_equal(f0, f1)
+            for k in ("n_leaf", "n_groups", "n_root", "nnz_l", "asm_tile"):
+                assert i0[k] == i1[k]
+            assert i0["flops_exec_assembly"] == i1["flops_exec_assembly"]
