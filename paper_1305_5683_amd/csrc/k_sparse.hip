@@ -1074,9 +1074,26 @@ __global__ __launch_bounds__(256, 6) void k_selinv_leaf(
   const int32_t* Ug = U + grp_U_ptr[g];
   const int I0 = I * kET, J0 = J * kET;
   const int na = (int)min<int64_t>(kET, nU - I0), nb = (int)min<int64_t>(kET, nU - J0);
-  // Root indices of the two U ranges first (one round trip), then every
-  // gather of the Z_UU block is issued at once with clamped, always valid
-  // addresses (out-of-range entries are zeroed afterwards).
+  const double* Pg = panel + grp_panel_off[g];
+  // Three round trips to memory per task at most: (1) the panel values of
+  // the first pivot chunk and the root indices of the two U ranges, (2)
+  // every gather of the Z_UU block at once (clamped, always valid
+  // addresses), (3) the panel values of a second chunk (fronts of more than
+  // kQC pivots).  No value waits for a load until it is used: the Z entries
+  // of rows or columns past the ranges are not zeroed, the zero padding of
+  // the panel blocks in LDS cancels them (a finite Z entry times zero).
+  constexpr int kPP = kQC * kET / 256;
+  double pi[kPP], pj[kPP];
+  auto load_panel = [&](int q0, int pc) {
+#pragma unroll
+    for (int i = 0; i < kPP; ++i) {  // all panel loads in flight together
+      const int e = t + 256 * i, r = e % kET, q = e / kET;
+      const int64_t col = (int64_t)(q0 + min(q, pc - 1)) * nU;
+      pi[i] = Pg[col + I0 + min(r, na - 1)];
+      pj[i] = Pg[col + J0 + min(r, nb - 1)];
+    }
+  };
+  load_panel(0, min(kQC, p));
   __shared__ int32_t sU[2][kET];
   if (t < 2 * kET) {
     const int side = t / kET, a = t % kET;
@@ -1087,33 +1104,23 @@ __global__ __launch_bounds__(256, 6) void k_selinv_leaf(
   // The block Z_IJ stays in registers as the first operand of the FP64
   // matrix-core products: wave w holds rows a = 16 w + lx, lane (lx, lk)
   // the columns b = 4 s + lk for the 16 steps s over b.
-  const int lx = lane & 15, lk = lane >> 4, a = 16 * wave + lx;
-  const int64_t ua = sU[0][a];
+  const int lx = lane & 15, lk = lane >> 4;
+  const int64_t ua = sU[0][16 * wave + lx];
   double zf[kET / 4];
 #pragma unroll
   for (int st = 0; st < kET / 4; ++st) {
     const int64_t ub = sU[1][4 * st + lk];
     zf[st] = ua >= ub ? Z[ua + ub * ld] : Z[ub + ua * ld];  // lower storage
   }
-#pragma unroll
-  for (int st = 0; st < kET / 4; ++st)
-    if (!(a < na && 4 * st + lk < nb)) zf[st] = 0.0;
-  const double* Pg = panel + grp_panel_off[g];
   const double fac = (I == J) ? 1.0 : 2.0;
   // the front's partial sums, pivot-major: [q][task of the front]
   const int64_t t0g = grp_task_ptr[g], ntg = grp_task_ptr[g + 1] - t0g;
   double* pg = part + task_part_off[t0g] + (tk - t0g);
   for (int q0 = 0; q0 < p; q0 += kQC) {
     const int pc = min(kQC, p - q0);
-    __syncthreads();
-    constexpr int kPP = kQC * kET / 256;
-    double pi[kPP], pj[kPP];
-#pragma unroll
-    for (int i = 0; i < kPP; ++i) {  // all panel loads in flight together
-      const int e = t + 256 * i, r = e % kET, q = e / kET;
-      const int64_t col = (int64_t)(q0 + min(q, pc - 1)) * nU;
-      pi[i] = Pg[col + I0 + min(r, na - 1)];
-      pj[i] = Pg[col + J0 + min(r, nb - 1)];
+    if (q0 > 0) {
+      __syncthreads();  // the previous chunk's PI, PJ and red are consumed
+      load_panel(q0, pc);
     }
 #pragma unroll
     for (int i = 0; i < kPP; ++i) {
