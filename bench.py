@@ -117,7 +117,7 @@ def parse():
     ap.add_argument("--bands", type=int, default=64,
                     help="batch: number of bands; learned: PCG sample size")
     ap.add_argument("--subproblems", type=int, default=32)
-    ap.add_argument("--potrf-block", type=int, default=0, choices=(0, 128, 256, 512),
+    ap.add_argument("--potrf-block", type=int, default=0, choices=(0, 128, 256, 512, 1024),
                     help="root POTRF outer block; 0 = the library's autotuner")
     ap.add_argument("--precision", choices=("fp64", "mixed", "both"), default="both",
                     help="fp64: every stage in binary64; mixed: binary32 "
@@ -269,7 +269,7 @@ def sweep_bulk_launches(np_pad, blk):
     """Bulk updates of one root inversion by sweeps: one per band that
     leaves lower-triangle entries outside its rows and columns and outside
     the next band's pivot block."""
-    nb = min(blk, np_pad, 512)
+    nb = min(blk, np_pad)
     widths = [min(nb, np_pad - k) for k in range(0, np_pad, nb)]
     cnt = 0
     for k, w in enumerate(widths):

@@ -626,7 +626,8 @@ void spi_batch_destroy(spi_batch* b);
 /*
  * Autotuner of the root front's launch shapes: the outer block (the band
  * width of the block sweeps, or of the Cholesky's trailing updates: 128,
- * 256 or 512 columns, one band or panel of lookahead) and, for the sweeps
+ * 256 or 512 columns, and 1024 for the sweeps in SPI_FP64 on roots of
+ * padded order 1024 or more; one band or panel of lookahead) and, for the sweeps
  * on roots up to order 8192, the tile of their bulk update (128 x 128 or
  * 64 x 64: a small root gets four times the workgroups from the smaller
  * tile).  It times spi_factor on the handle's current values with each
@@ -650,9 +651,12 @@ int spi_get_potrf_block(const spi_handle* h);
 int spi_get_bulk_tile(const spi_handle* h);
 /* Set it by hand: 64 or 128. */
 int spi_set_bulk_tile(spi_handle* h, int32_t tile);
-/* Set the outer block by hand: 128, 256 or 512 (SPI_MIXED with
- * root_inverse = 0 uses at most 256, the longest binary32 accumulation it
- * allows; the sweeps split longer products into launches of 256). */
+/* Set the outer block by hand: 128, 256 or 512, or 1024 for the sweeps
+ * (root_inverse = 1) in SPI_FP64 on a root of padded order 1024 or more
+ * (fewer, wider bands: the bulk updates read and write the root half as
+ * often); SPI_E_ARG otherwise.  SPI_MIXED with root_inverse = 0 uses at
+ * most 256, the longest binary32 accumulation it allows; the sweeps split
+ * longer products into launches of 256. */
 int spi_set_potrf_block(spi_handle* h, int32_t block);
 
 #ifdef __cplusplus

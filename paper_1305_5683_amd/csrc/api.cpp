@@ -187,7 +187,11 @@ int setup_device(spi_handle* H) {
     AL(h.W, np * np); AL(h.Z, np * np);
     AL(h.invd, np * kNB); AL(h.invd2, ((np + 255) / 256) * 256 * 256);
   }
-  h.band_nb = (int)std::min<int64_t>(512, np);
+  // widest band of the root sweeps: 1024 columns in binary64 (a band's
+  // bulk update reads and writes the root once per band), 512 with binary32
+  // products (two binary32 sums of at most 256 terms per launch)
+  h.band_nb = (int)std::min<int64_t>(
+      h.opts.root_inverse && h.opts.precision == SPI_FP64 ? 1024 : 512, np);
   AL(h.band, 4 * (int64_t)h.band_nb * np + 2 * (int64_t)h.band_nb * h.band_nb);
   AL(h.part, a.task_part_off.back());
   AL(h.flag, 4); AL(h.vleaf, nl); AL(h.vfront, a.grp_U_ptr.back()); AL(h.vroot, np); AL(h.vres, a.n);

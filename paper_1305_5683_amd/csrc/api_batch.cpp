@@ -185,7 +185,7 @@ int spi_autotune(spi_handle* H, int32_t* chosen) {
   Handle& h = H->h;
   if (!h.have_values)
     return fail(h, SPI_E_STATE, hipSuccess, "spi_autotune before spi_set_values");
-  const int cand[3] = {128, 256, 512};
+  const int cand[4] = {128, 256, 512, 1024};
   // the bulk update's tile: 64 x 64 gives small roots four times the
   // workgroups of 128 x 128 (tried only below order 8192, where that matters)
   const int tiles[2] = {128, 64};
@@ -196,7 +196,7 @@ int spi_autotune(spi_handle* H, int32_t* chosen) {
   h.opts.timing = 0;
   for (int c : cand)
   for (int ti = 0; ti < n_tiles_tried; ++ti) {
-    if (h.an.n_pad > 0 && c > h.an.n_pad) continue;
+    if ((h.an.n_pad > 0 && c > h.an.n_pad) || c > std::max(512, h.band_nb)) continue;
     // the Cholesky route caps binary32 sums by its outer block
     if (h.opts.precision == SPI_MIXED && !h.opts.root_inverse && c > 256) continue;
     h.potrf_block = c;
@@ -238,7 +238,9 @@ int spi_set_bulk_tile(spi_handle* H, int32_t tile) {
 }
 
 int spi_set_potrf_block(spi_handle* H, int32_t block) {
-  if (!H || (block != 128 && block != 256 && block != 512)) return SPI_E_ARG;
+  if (!H || (block != 128 && block != 256 && block != 512 &&
+             !(block == 1024 && H->h.band_nb >= 1024)))
+    return SPI_E_ARG;
   H->h.potrf_block = block;
   return SPI_OK;
 }

@@ -73,6 +73,7 @@ CASES = [
     (8, 4, 150, 3, 8, 0, 6, 2, None),     # zero diagonal: 2 x 2 pivots
     (10, 5, 700, 3, 10, 300, 12, 3, 128),  # several bands of 128 (padded 768)
     (10, 5, 700, 3, 10, 300, 12, 4, 512),  # two bands of 512
+    (10, 5, 1300, 3, 10, 500, 12, 5, 1024),  # bands of 1024 and 384
 ]
 
 

@@ -562,6 +562,26 @@ def test_root_sweeps_over_several_bands(block, tile):
         _check(p, g, o)
 
 
+def test_root_sweeps_with_1024_column_bands():
+    """FP64 sweeps take bands of up to 1024 columns (the large root's
+    autotuned choice): a dense root of order 2300 (padded 2304) in bands of
+    1024, 1024 and 256, so a 16-step pivot chain, the lookahead update of a
+    1024 pivot block and the negated last band all run.  Mixed precision
+    and the Cholesky route refuse the block (their bands stay at 512)."""
+    from paper_1305_5683_amd import SpiSolver, SpiError
+    p = synth.make_random(6900, 2300, 14, seed=78)
+    o = oracle_solve(p)
+    _say("case sweeps block=1024 n_root=2300")
+    g = _run_blocks(p, 1024, 128, leaf_max_work=0.0)
+    assert g["info"]["n_root"] == 2300
+    _check(p, g, o)
+    for opts in ({"precision": 1}, {"root_inverse": 0}):
+        s = SpiSolver(p.m, p.n, p.rowptr, p.col, leaf_max_work=0.0, **opts)
+        with pytest.raises(SpiError):
+            s.potrf_block = 1024
+        s.close()
+
+
 def test_root_pivot_failure_same_column_both_routes():
     """A dense root made indefinite by strongly negative weights on a few
     rows: the sweeps and the Cholesky factorisation pivot on the same Schur
