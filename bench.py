@@ -57,6 +57,7 @@ CSRC = os.path.join(ROOT, "paper_1305_5683_amd", "csrc")
 HBM_COUNTERS = {
     # large coded-mask system, FP64, outer block 512 (profiles/hbm_counters.txt)
     (2, "bulk", 512, "fp64"): {"bytes": 12.812e9 + 4.0965e9, "src": "6291710c77d9dd5a"},
+    (2, "bulk", 1024, "fp64"): {"bytes": 28.628e9 + 3.9645e9, "src": "6291710c77d9dd5a"},
     (2, "assembly", None, "fp64"): {"bytes": 2969.4e9 + 4.2286e9, "src": "5bf19dc26a598eab"},
     (2, "assembly", None, "mixed"): {"bytes": 2969.4e9 + 4.2286e9, "src": "5bf19dc26a598eab"},
     # medium coded-mask system, FP64, outer block 512
