@@ -160,6 +160,27 @@ typedef struct spi_opts {
                                for roots of padded order 8192 and more, 64
                                below (four times the workgroups for small
                                fronts) */
+    int64_t device_mem_cap; /* > 0: most device memory (bytes) spi_analyze /
+                               spi_analyze_like may allocate for the handle
+                               (the analysis maps and every work buffer they
+                               size; spi_info.device_bytes reports what a
+                               handle holds): a handle that needs more is
+                               refused with SPI_E_OOM before any allocation
+                               beyond the cap, and nothing is left
+                               allocated.  0 (default): no cap */
+    int32_t fp64_fallback;  /* 1: with SPI_MIXED, a spi_factor that meets a
+                               non-positive pivot, or a spi_solve whose
+                               refinement does not reach refine_tol (the
+                               binary32 products too coarse for the
+                               system's conditioning), is redone with every
+                               stage in binary64: the root refactored, the
+                               solve repeated (b must not overlap x); the
+                               handle stays in binary64 until the next
+                               spi_set_values or spi_set_leaf_values, and
+                               spi_info.fp64_fallbacks counts the switches.
+                               Batches (spi_batch_run) report such systems
+                               as before.  0 (default): the call returns
+                               SPI_E_NOT_SPD / SPI_E_NOCONV */
 } spi_opts;
 
 typedef struct spi_info_t {
@@ -215,6 +236,13 @@ typedef struct spi_info_t {
                                    plus the leaf fronts (after
                                    spi_set_leaf_values) */
     int32_t asm_tile;           /* root assembly tile edge (64 or 128) */
+    int64_t device_bytes;       /* device memory the handle holds: analysis
+                                   maps and work buffers sized by
+                                   spi_analyze (not the learned
+                                   preconditioner's, nor the library's fixed
+                                   scratch array); 0 from spi_symbolic */
+    int32_t fp64_fallbacks;     /* opts.fp64_fallback: switches from
+                                   SPI_MIXED to binary64 so far */
 } spi_info_t;
 
 /* Fill `o` with the defaults listed above. */

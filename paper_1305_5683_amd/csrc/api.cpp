@@ -135,6 +135,10 @@ bool check_opts(spi_opts& o) {
     g_analyze_err = "invalid options";
     return false;
   }
+  if (o.device_mem_cap < 0 || (o.fp64_fallback != 0 && o.fp64_fallback != 1)) {
+    g_analyze_err = "invalid options";
+    return false;
+  }
   if (o.indefinite && !o.root_inverse) {
     g_analyze_err = "indefinite = 1 needs root_inverse = 1";
     return false;
@@ -154,8 +158,23 @@ int setup_device(spi_handle* H) {
   const Analysis& a = h.an;
   DevAnalysis& d = h.d;
   hipError_t he = hipSuccess;
-#define UP(field) \
-  if (he == hipSuccess) he = dev_copy(d.field, a.field, h.stream)
+  // opts.device_mem_cap: every allocation is counted first and refused
+  // (hipErrorOutOfMemory, reported as SPI_E_OOM) once the total would pass it
+  bool capped = false;
+  h.dev_bytes = 0;
+  auto admit = [&](int64_t bytes) {
+    if (he != hipSuccess) return false;
+    if (h.opts.device_mem_cap > 0 && h.dev_bytes + bytes > h.opts.device_mem_cap) {
+      he = hipErrorOutOfMemory;
+      capped = true;
+      return false;
+    }
+    h.dev_bytes += bytes;
+    return true;
+  };
+#define UP(field)                                                           \
+  if (admit((int64_t)(a.field.size() * sizeof(a.field[0]))))                \
+  he = dev_copy(d.field, a.field, h.stream)
   UP(rowptr); UP(col); UP(colptr); UP(csc_pos); UP(csc_row); UP(leaf_cols);
   UP(leaf_grp); UP(leaf_slot_ptr); UP(grp_col_ptr); UP(grp_U_ptr); UP(U);
   UP(grp_panel_off); UP(grp_slot_ptr); UP(slot_row); UP(slot_rr_ptr);
@@ -169,7 +188,7 @@ int setup_device(spi_handle* H) {
   const int64_t nl = (int64_t)a.leaf_cols.size();
   const int64_t np = a.n_pad;
 #define AL(ptr, cnt)                                                   \
-  if (he == hipSuccess) {                                              \
+  if (admit(std::max<int64_t>(0, (int64_t)(cnt)) * (int64_t)sizeof(*ptr))) { \
     he = dev_alloc(ptr, cnt);                                          \
     if (ptr) h.bufs.emplace_back((void*)ptr, (size_t)(cnt) * sizeof(*ptr)); \
   }
@@ -203,7 +222,9 @@ int setup_device(spi_handle* H) {
 #undef AL
   if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
   if (he != hipSuccess) {
-    g_analyze_err = std::string("device setup failed: ") + hipGetErrorString(he);
+    g_analyze_err = capped ? std::string("device memory cap exceeded: the handle needs "
+                                         "more than opts.device_mem_cap bytes")
+                           : std::string("device setup failed: ") + hipGetErrorString(he);
     free_all(h);
     delete H;
     return he == hipErrorOutOfMemory ? SPI_E_OOM : SPI_E_HIP;
@@ -379,6 +400,7 @@ int spi_analyze(spi_handle** out, int64_t m, int64_t n, const int64_t* rowptr,
   }
   Handle& h = H->h;
   h.opts = o;
+  h.req_precision = o.precision;
   h.stream = (hipStream_t)stream;
   (void)hipGetDevice(&h.device);
   auto t0 = std::chrono::steady_clock::now();
@@ -422,6 +444,7 @@ int spi_analyze_like(spi_handle** out, const spi_handle* src, const spi_opts* op
   }
   Handle& h = H->h;
   h.opts = o;
+  h.req_precision = o.precision;
   h.stream = (hipStream_t)stream;
   (void)hipGetDevice(&h.device);
   auto t0 = std::chrono::steady_clock::now();
@@ -450,6 +473,7 @@ int spi_set_values(spi_handle* H, const double* val, const double* w) {
   h.val32_ok = false;
   SPI_CK(launch_gather_values(h), "gather values");
   SPI_CK(launch_fill_rowpanels(h), "row panels");
+  h.opts.precision = h.req_precision;  // new values: the precision asked for
   h.have_values = true;
   h.have_factor = false;
   h.have_inv = false;
@@ -486,17 +510,17 @@ int spi_set_leaf_values(spi_handle* H, const double* val) {
   SPI_CK(launch_gather_values(h), "gather values");
   // rewrite the row panels comparing with the root entries in use
   SPI_CK(launch_fill_rowpanels(h, true), "row panels");
+  h.opts.precision = h.req_precision;
   h.have_factor = false;
   h.have_inv = false;
   h.leaf_update = true;
   return SPI_OK;
 }
 
-int spi_factor(spi_handle* H) {
-  if (!H) return SPI_E_ARG;
-  Handle& h = H->h;
-  if (!h.have_values)
-    return fail(h, SPI_E_STATE, hipSuccess, "spi_factor before spi_set_values");
+namespace {
+
+// The factorisation, its pivot flag read back and interpreted.
+int factor_sync(Handle& h) {
   int st = factor_enqueue(h, true);
   if (st != SPI_OK) return st;
   uint64_t f[2] = {0, 0};
@@ -504,6 +528,30 @@ int spi_factor(spi_handle* H) {
          "flag readback");
   SPI_CK(hipStreamSynchronize(h.stream), "factor");
   return factor_finish(h, f);
+}
+
+// opts.fp64_fallback: a SPI_MIXED handle whose binary32 stages failed is
+// switched to binary64 (until new values arrive) and refactored.
+bool can_fall_back(const Handle& h) {
+  return h.opts.fp64_fallback && h.opts.precision == SPI_MIXED;
+}
+
+int refactor_fp64(Handle& h) {
+  h.opts.precision = SPI_FP64;
+  ++h.fp64_fallbacks;
+  return factor_sync(h);
+}
+
+}  // namespace
+
+int spi_factor(spi_handle* H) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = H->h;
+  if (!h.have_values)
+    return fail(h, SPI_E_STATE, hipSuccess, "spi_factor before spi_set_values");
+  const int st = factor_sync(h);
+  if (st == SPI_E_NOT_SPD && can_fall_back(h)) return refactor_fp64(h);
+  return st;
 }
 
 int spi_rhs(spi_handle* H, const double* y, double* b) {
@@ -571,6 +619,12 @@ int spi_solve(spi_handle* H, const double* b, double* x, int32_t nrhs,
   phase_end(h, kPhSolve);
   h.refine_done = done_max;
   h.last_norm_pair = 0;
+  if (status == SPI_E_NOCONV && can_fall_back(h)) {
+    // the binary32 factor does not refine to refine_tol: binary64 throughout
+    const int fs = refactor_fp64(h);
+    if (fs != SPI_OK) return fs;
+    return spi_solve(H, b, x, nrhs, ldb);
+  }
   if (status != SPI_OK)
     return fail(h, status, hipSuccess,
                 "iterative refinement did not reach refine_tol");
@@ -703,6 +757,8 @@ int spi_info(const spi_handle* Hc, spi_info_t* info) {
   std::memset(info, 0, sizeof(*info));
   fill_analysis_info(a, info);
   info->failed_col = h.failed_col;
+  info->device_bytes = h.dev_bytes;
+  info->fp64_fallbacks = h.fp64_fallbacks;
   info->t_analyze_ms = h.t_analyze_ms;
   info->precision = h.opts.precision;
   info->refine_steps_done = h.refine_done;

@@ -188,6 +188,10 @@ struct PhaseTimer {
 
 struct Handle {
   spi_opts opts{};
+  int64_t dev_bytes = 0;     // device memory sized by the analysis (held)
+  int req_precision = 0;     // the precision asked for (opts.precision is the
+                             // one in use: binary64 after a fallback)
+  int fp64_fallbacks = 0;    // opts.fp64_fallback: switches so far
   hipStream_t stream = nullptr;
   int device = 0;
   Analysis an;

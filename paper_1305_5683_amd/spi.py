@@ -40,7 +40,8 @@ class spi_opts(C.Structure):
                 ("refine_tol", C.c_double), ("keep_root_order", C.c_int32),
                 ("leaf_lds_cap", C.c_int32), ("selinv_chunk", C.c_int32),
                 ("keep_root_sum", C.c_int32), ("indefinite", C.c_int32),
-                ("asm_tile", C.c_int32)]
+                ("asm_tile", C.c_int32), ("device_mem_cap", C.c_int64),
+                ("fp64_fallback", C.c_int32)]
 
 
 class spi_info_t(C.Structure):
@@ -59,7 +60,8 @@ class spi_info_t(C.Structure):
                 ("t_sweep_bulk_ms", C.c_double), ("flops_sweep_bulk", C.c_double),
                 ("flops_exec_assembly", C.c_double), ("flops_exec_selinv", C.c_double),
                 ("flops_root_assembly", C.c_double),
-                ("root_assembly_mode", C.c_int32), ("asm_tile", C.c_int32)]
+                ("root_assembly_mode", C.c_int32), ("asm_tile", C.c_int32),
+                ("device_bytes", C.c_int64), ("fp64_fallbacks", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -617,3 +617,91 @@ def test_root_order_original_and_locality_agree():
         _say(f"case root order keep_root_order={keep}")
         g = run_gpu(p, keep_root_order=keep)
         _check(p, g, o)
+
+
+def _near_collinear(seed=3, delta=1e-3, far=279):
+    """A leafy system whose sky columns 10 and 10 + far are nearly collinear
+    (the second = the first times 1 + delta N(0, 1) per row): cond(A) about
+    5.6e8 for delta = 1e-3 (measured with numpy)."""
+    import scipy.sparse as sp
+    p = synth.make_random_leafy(8, 4, 300, 3, 20, 60, seed=seed)
+    H = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.m, p.n)).toarray()
+    rng = np.random.default_rng(seed)
+    j1, j2 = p.n_bg + 10, p.n_bg + 10 + far
+    nz = H[:, j1] != 0
+    H[:, j2] = 0.0
+    H[nz, j2] = H[nz, j1] * (1.0 + delta * rng.standard_normal(int(nz.sum())))
+    Hs = sp.csr_matrix(H)
+    Hs.sort_indices()
+    return synth.Problem(m=p.m, n=p.n, n_bg=p.n_bg,
+                         rowptr=Hs.indptr.astype(np.int64),
+                         col=Hs.indices.astype(np.int32), val=Hs.data.copy(),
+                         w=p.w, y=p.y, x_true=p.x_true, name="near-collinear")
+
+
+def test_mixed_precision_falls_back_to_fp64():
+    """cond(A) about 5.6e8 (two nearly collinear sky columns), the root in
+    its original order and bands of 128, so the binary32 bulk products
+    carry the near-null direction: the mixed refinement stalls far above
+    refine_tol = 1e-10 (its corrections stay near 1e-3), while binary64
+    reaches it in two steps (measured).  Without opts.fp64_fallback the
+    mixed handle reports SPI_E_NOCONV; with it the work is redone in
+    binary64: x within 1e-9 of the oracle (the refinement's floor on this
+    system is about 1e-11), the variances within 1e-6 of a plain FP64
+    handle's (unrefined: about cond(A) times the unit roundoff), spi_info
+    reporting the switch; new values bring the handle back to mixed
+    precision."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiError
+    dev = torch.device("cuda")
+    q = _near_collinear(far=1)
+    o = oracle_solve(q)
+    val = torch.from_numpy(q.val).to(dev)
+    w = torch.from_numpy(q.w).to(dev)
+    y = torch.from_numpy(q.y).to(dev)
+    opts = dict(keep_root_order=1, refine_tol=1e-10, refine_steps=10)
+
+    def handle(**more):
+        s = SpiSolver(q.m, q.n, q.rowptr, q.col, **opts, **more)
+        s.potrf_block = 128
+        s.set_values(val, w)
+        return s
+
+    _say(f"case mixed precision fallback n={q.n}")
+    s = handle(precision=1)
+    s.factor()
+    with pytest.raises(SpiError) as ei:
+        s.solve(s.rhs(y))
+    _say(f"  without the fallback: status {ei.value.status}, last correction "
+         f"{s.info()['last_refine_norm']:.1e}")
+    assert ei.value.status == 6
+    s.close()
+    s = handle(precision=0)
+    s.factor()
+    s.solve(s.rhs(y))
+    d_ref = s.diag_inv().cpu().numpy()
+    s.close()
+    s = handle(precision=1, fp64_fallback=1)
+    s.factor()
+    x = s.solve(s.rhs(y))
+    d = s.diag_inv()
+    torch.cuda.synchronize()
+    info = s.info()
+    x, d = x.cpu().numpy(), d.cpu().numpy()
+    ex = np.linalg.norm(x - o["x"]) / np.linalg.norm(o["x"])
+    ed = np.max(np.abs(d - d_ref) / d_ref)
+    _say(f"  with it: switches {info['fp64_fallbacks']}, err_x {ex:.2e}, d vs FP64 {ed:.2e}")
+    assert info["fp64_fallbacks"] == 1 and info["precision"] == 0
+    assert ex <= 1e-9
+    assert ed <= 1e-6
+    # values of a well-conditioned system on the same pattern: mixed again
+    val2 = q.val.copy()
+    sel = q.col == q.n_bg + 11
+    val2[sel] = np.random.default_rng(5).uniform(0.5, 1.0, int(sel.sum()))
+    s.set_values(torch.from_numpy(val2).to(dev), w)
+    assert s.info()["precision"] == 1
+    s.factor()
+    s.solve(s.rhs(y))
+    info = s.info()
+    s.close()
+    assert info["precision"] == 1 and info["fp64_fallbacks"] == 1

@@ -135,3 +135,30 @@ def test_repeatability():
     assert np.array_equal(b1, b2)
     assert _rel(x2, x1) <= 1e-13
     assert np.max(np.abs(d2 - d1) / d1) <= 1e-13
+
+
+def test_device_memory_cap():
+    """opts.device_mem_cap: a handle that needs more device memory than the
+    cap is refused with SPI_E_OOM (nothing allocated beyond it, nothing
+    left); at exactly what spi_info.device_bytes reports it is built and
+    matches the oracle."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiError
+    p = synth.make_random_leafy(12, 7, 600, 3, 25, 50, seed=5)
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col)
+    need = s.info()["device_bytes"]
+    s.close()
+    # the root front alone (n_pad^2 doubles) is part of it
+    assert need >= 8 * 640 * 640
+    _say(f"case device memory cap: the handle holds {need} bytes")
+    for cap in (need - 1, need // 2, 1):
+        with pytest.raises(SpiError) as ei:
+            SpiSolver(p.m, p.n, p.rowptr, p.col, device_mem_cap=cap)
+        assert ei.value.status == 4 and "cap" in str(ei.value)
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col, device_mem_cap=need)
+    assert s.info()["device_bytes"] == need
+    _, x, d = _pipeline(s, p, torch)
+    s.close()
+    o = oracle_solve(p)
+    assert _rel(x, o["x"]) <= 1e-12
+    assert np.max(np.abs(d - o["diag"]) / o["diag"]) <= 1e-12

@@ -181,6 +181,17 @@ def test_root_order_option_is_validated():
         _symbolic(p, keep_root_order=2)
 
 
+def test_device_memory_cap_option_is_validated():
+    from paper_1305_5683_amd import SpiError
+    p = synth.make_config(0)
+    info, _, _, _ = _symbolic(p, device_mem_cap=1 << 30)
+    assert info["device_bytes"] == 0  # host-only analysis holds no device memory
+    with pytest.raises(SpiError, match="invalid options"):
+        _symbolic(p, device_mem_cap=-1)
+    with pytest.raises(SpiError, match="invalid options"):
+        _symbolic(p, fp64_fallback=2)
+
+
 def test_indefinite_needs_the_root_sweeps():
     """opts.indefinite = 1 with the Cholesky route is refused by the
     analysis (host-only check)."""
