@@ -404,6 +404,35 @@ int spi_symbolic(int64_t m, int64_t n, const int64_t* rowptr,
                  int32_t* elim_order, int32_t* col_parent, int32_t* front_of);
 
 /*
+ * Checkpoint of the analysis (Sect. 3.2.1: the ordering and symbolic
+ * factorisation are done once per pattern; later runs on the same pattern
+ * skip them).  The files are binary, of this library's own format (a
+ * version tag, every array of the analysis with its length, a 64-bit hash);
+ * reading refuses a missing, truncated, corrupted or foreign file with
+ * SPI_E_ARG (spi_last_error(NULL) says why, or spi_last_error(h) for
+ * spi_save_analysis) before anything reaches the device.
+ *
+ * spi_save_analysis     write the analysis of handle h (and the analysis
+ *                       options that shaped it: max_group, leaf_max_work,
+ *                       amalg_density, keep_root_order, asm_tile) to path.
+ * spi_symbolic_save     host only: analyse the pattern as spi_symbolic
+ *                       does and write the file (no device needed).
+ * spi_analysis_file_info host only: read and check a file; fill `info` with
+ *                       its counters as spi_symbolic does.
+ * spi_analyze_load      a new handle from a file, as spi_analyze from the
+ *                       same pattern: opts may be NULL (defaults); their
+ *                       analysis options are replaced by the file's.  The
+ *                       handle holds the file's pattern (H's rowptr and col)
+ *                       and is then used exactly as one from spi_analyze.
+ */
+int spi_save_analysis(const spi_handle* h, const char* path);
+int spi_symbolic_save(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
+                      const spi_opts* opts, const char* path);
+int spi_analysis_file_info(const char* path, spi_info_t* info);
+int spi_analyze_load(spi_handle** h, const char* path, const spi_opts* opts,
+                     void* stream);
+
+/*
  * A new handle on the same pattern as `src` (another energy band, Sect.
  * 2.2.3): the host analysis of `src` is copied instead of recomputed, then
  * uploaded and the device buffers sized as in spi_analyze.

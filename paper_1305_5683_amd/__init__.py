@@ -6,4 +6,5 @@ triangular solves and selected inversion for ``diag(A^-1)`` in HIP kernels.
 """
 from .spi import (SpiSolver, SpiError, load_library, symbolic,  # noqa: F401
                   default_opts, SPI_FP64, SPI_MIXED, SpiLearnedPrecond,
-                  pcg_solve, SpiBatch, EmptyField, mle_terms, mle_newton)
+                  pcg_solve, SpiBatch, EmptyField, mle_terms, mle_newton,
+                  symbolic_save, analysis_file_info)

@@ -19,8 +19,8 @@ ARCH = "gfx950"
 
 HIP_SOURCES = ["k_gemm.hip", "k_dense.hip", "k_sparse.hip", "k_learned.hip",
                "k_model.hip", "api_noalloc.hip"]
-CPP_SOURCES = ["analysis.cpp", "api.cpp", "api_learned.cpp", "api_batch.cpp",
-               "api_model.cpp"]
+CPP_SOURCES = ["analysis.cpp", "analysis_io.cpp", "api.cpp", "api_learned.cpp",
+               "api_batch.cpp", "api_model.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           f"-I{os.path.join(PKG, '..', 'include')}"]

@@ -748,6 +748,89 @@ int spi_symbolic(int64_t m, int64_t n, const int64_t* rowptr,
   return SPI_OK;
 }
 
+int spi_save_analysis(const spi_handle* H, const char* path) {
+  if (!H) return SPI_E_ARG;
+  Handle& h = const_cast<spi_handle*>(H)->h;  // only its error text changes
+  const std::string e = save_analysis(h.an, h.opts, path);
+  if (!e.empty()) return fail(h, SPI_E_ARG, hipSuccess, e.c_str());
+  return SPI_OK;
+}
+
+int spi_symbolic_save(int64_t m, int64_t n, const int64_t* rowptr, const int32_t* col,
+                      const spi_opts* opts, const char* path) {
+  g_analyze_err.clear();
+  spi_opts o;
+  spi_default_opts(&o);
+  if (opts) o = *opts;
+  if (!check_opts(o)) return SPI_E_ARG;
+  Analysis a;
+  std::string e = analyze(m, n, rowptr, col, o, a);
+  if (e.empty()) e = save_analysis(a, o, path);
+  if (!e.empty()) {
+    g_analyze_err = e;
+    return SPI_E_ARG;
+  }
+  return SPI_OK;
+}
+
+int spi_analysis_file_info(const char* path, spi_info_t* info) {
+  g_analyze_err.clear();
+  if (!info) {
+    g_analyze_err = "null info pointer";
+    return SPI_E_ARG;
+  }
+  spi_opts o;
+  spi_default_opts(&o);
+  Analysis a;
+  const std::string e = load_analysis(path, a, o);
+  if (!e.empty()) {
+    g_analyze_err = e;
+    return SPI_E_ARG;
+  }
+  std::memset(info, 0, sizeof(*info));
+  fill_analysis_info(a, info);
+  info->failed_col = -1;
+  return SPI_OK;
+}
+
+int spi_analyze_load(spi_handle** out, const char* path, const spi_opts* opts,
+                     void* stream) {
+  g_analyze_err.clear();
+  if (!out) {
+    g_analyze_err = "null handle pointer";
+    return SPI_E_ARG;
+  }
+  *out = nullptr;
+  spi_opts o;
+  spi_default_opts(&o);
+  if (opts) o = *opts;
+  auto t0 = std::chrono::steady_clock::now();
+  Analysis a;
+  const std::string e = load_analysis(path, a, o);  // the file's analysis options
+  if (!e.empty()) {
+    g_analyze_err = e;
+    return SPI_E_ARG;
+  }
+  if (!check_opts(o)) return SPI_E_ARG;
+  spi_handle* H = new (std::nothrow) spi_handle();
+  if (!H) {
+    g_analyze_err = "host allocation failed";
+    return SPI_E_OOM;
+  }
+  Handle& h = H->h;
+  h.opts = o;
+  h.req_precision = o.precision;
+  h.stream = (hipStream_t)stream;
+  (void)hipGetDevice(&h.device);
+  h.an = std::move(a);
+  const int st = setup_device(H);
+  if (st != SPI_OK) return st;
+  h.t_analyze_ms = std::chrono::duration<double, std::milli>(
+                       std::chrono::steady_clock::now() - t0).count();
+  *out = H;
+  return SPI_OK;
+}
+
 int spi_info(const spi_handle* Hc, spi_info_t* info) {
   if (!Hc || !info) return SPI_E_ARG;
   // collecting timers mutates the handle's event pools, not its results

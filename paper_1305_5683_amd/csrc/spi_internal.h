@@ -125,6 +125,11 @@ struct Analysis {
 // Returns an empty string on success, else the error text.
 std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
                     const int32_t* col, const spi_opts& opts, Analysis& out);
+// Analysis files (analysis_io.cpp): write `a` and the analysis options of
+// `o`; read them back into `a` and the analysis options of `o`, refusing a
+// truncated, corrupted or foreign file.  Empty string on success.
+std::string save_analysis(const Analysis& a, const spi_opts& o, const char* path);
+std::string load_analysis(const char* path, Analysis& a, spi_opts& o);
 
 // ------------------------------------------------------------ device side
 struct DevAnalysis {

@@ -29,7 +29,8 @@ EXPORTED = ["spi_default_opts", "spi_analyze", "spi_set_values", "spi_factor",
             "spi_set_potrf_block", "spi_diag_inv_noalloc", "spi_set_leaf_values",
             "spi_empty_field_update", "spi_empty_field_loop", "spi_mle_terms",
             "spi_mle_newton", "spi_inv_entries", "spi_get_bulk_tile",
-            "spi_set_bulk_tile", "spi_debug_poison"]
+            "spi_set_bulk_tile", "spi_debug_poison", "spi_save_analysis",
+            "spi_symbolic_save", "spi_analysis_file_info", "spi_analyze_load"]
 
 
 class spi_opts(C.Structure):
@@ -140,6 +141,11 @@ def load_library(path: str = LIB_PATH):
     lib.spi_get_bulk_tile.argtypes = [P]
     lib.spi_debug_poison.argtypes = [P]
     lib.spi_set_bulk_tile.argtypes = [P, I32]
+    lib.spi_save_analysis.argtypes = [P, C.c_char_p]
+    lib.spi_symbolic_save.argtypes = [I64, I64, P, P, C.POINTER(spi_opts), C.c_char_p]
+    lib.spi_analysis_file_info.argtypes = [C.c_char_p, C.POINTER(spi_info_t)]
+    lib.spi_analyze_load.argtypes = [C.POINTER(C.c_void_p), C.c_char_p,
+                                     C.POINTER(spi_opts), P]
     for name in EXPORTED:
         if name not in ("spi_default_opts", "spi_last_error", "spi_destroy",
                         "spi_lp_destroy", "spi_lp_param_count",
@@ -181,6 +187,27 @@ def symbolic(m, n, rowptr, col, **opts):
     if st != SPI_OK:
         raise SpiError(st, lib.spi_last_error(None).decode())
     return info.as_dict(), order, parent, front
+
+
+def symbolic_save(m, n, rowptr, col, path, **opts):
+    """Host-only analysis written to ``path`` (see ``SpiSolver.from_analysis``)."""
+    lib = load_library()
+    rp, cl = _pattern(rowptr, col)
+    o = default_opts(**opts)
+    st = lib.spi_symbolic_save(m, n, rp.ctypes.data, cl.ctypes.data, C.byref(o),
+                               os.fsencode(path))
+    if st != SPI_OK:
+        raise SpiError(st, lib.spi_last_error(None).decode())
+
+
+def analysis_file_info(path) -> dict:
+    """Read and check an analysis file; its counters as ``symbolic`` gives them."""
+    lib = load_library()
+    info = spi_info_t()
+    st = lib.spi_analysis_file_info(os.fsencode(path), C.byref(info))
+    if st != SPI_OK:
+        raise SpiError(st, lib.spi_last_error(None).decode())
+    return info.as_dict()
 
 
 def _ptr(t, n=None, dtype=None):
@@ -234,6 +261,30 @@ class SpiSolver:
             raise SpiError(st, self.lib.spi_last_error(None).decode())
         self.h = h
         return self
+
+    @classmethod
+    def from_analysis(cls, path, stream=None, **opts):
+        """A handle from an analysis file (``save_analysis`` or
+        ``symbolic_save``); ``opts`` as for the constructor, whose analysis
+        options the file's replace."""
+        import torch
+        self = cls.__new__(cls)
+        self.lib = load_library()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        o = default_opts(**opts)
+        st = self.lib.spi_analyze_load(C.byref(h), os.fsencode(path), C.byref(o),
+                                       C.c_void_p(self.stream.cuda_stream))
+        if st != SPI_OK:
+            raise SpiError(st, self.lib.spi_last_error(None).decode())
+        self.h = h
+        i = self.info()
+        self.m, self.n, self.nnz = int(i["m"]), int(i["n"]), int(i["nnz_h"])
+        return self
+
+    def save_analysis(self, path):
+        """Write this handle's analysis to ``path``."""
+        self._check(self.lib.spi_save_analysis(self.h, os.fsencode(path)))
 
     def _check(self, st):
         if st != SPI_OK:

@@ -108,14 +108,16 @@ void expect(bool ok, const char* what, const char* name) {
   }
 }
 
-// Invariants of a successful analysis.
-void check(const spi::Analysis& a, const Csr& h, const char* name) {
+// Invariants of a successful analysis (of the pattern h when with_pattern).
+void check(const spi::Analysis& a, const Csr& h, const char* name,
+           bool with_pattern = true) {
   const int64_t nl = (int64_t)a.leaf_cols.size();
-  expect(nl + a.n_root == h.n, "leaves + root != n", name);
-  std::vector<int> hit(h.n, 0);
+  const int64_t n = with_pattern ? h.n : a.n;
+  expect(nl + a.n_root == n, "leaves + root != n", name);
+  std::vector<int> hit(n, 0);
   for (int32_t j : a.leaf_cols) ++hit[j];
   for (int32_t j : a.root_cols) ++hit[j];
-  for (int64_t j = 0; j < h.n; ++j) expect(hit[j] == 1, "column not placed once", name);
+  for (int64_t j = 0; j < n; ++j) expect(hit[j] == 1, "column not placed once", name);
   expect(a.n_pad % 128 == 0 && a.n_pad >= a.n_root, "root padding", name);
   expect((int64_t)a.grp_col_ptr.size() == a.n_groups + 1 &&
              a.grp_col_ptr.back() == nl, "front column pointers", name);
@@ -139,6 +141,35 @@ void check(const spi::Analysis& a, const Csr& h, const char* name) {
   for (int v : perm) expect(v == 1, "task order not a permutation", name);
 }
 
+// Analysis files: write, read back, write again: the same bytes.
+void round_trip(const spi::Analysis& a, const spi_opts& o, const char* name) {
+  const char* p1 = "analysis_driver_1.spia";
+  const char* p2 = "analysis_driver_2.spia";
+  std::string e = spi::save_analysis(a, o, p1);
+  expect(e.empty(), e.c_str(), name);
+  spi::Analysis b;
+  spi_opts q = default_opts();
+  e = spi::load_analysis(p1, b, q);
+  expect(e.empty(), e.c_str(), name);
+  if (!e.empty()) return;
+  check(b, Csr(), name, false);
+  e = spi::save_analysis(b, q, p2);
+  expect(e.empty(), e.c_str(), name);
+  std::FILE* f1 = std::fopen(p1, "rb");
+  std::FILE* f2 = std::fopen(p2, "rb");
+  bool same = f1 && f2;
+  while (same) {
+    const int c1 = std::fgetc(f1), c2 = std::fgetc(f2);
+    same = c1 == c2;
+    if (c1 == EOF || c2 == EOF) break;
+  }
+  if (f1) std::fclose(f1);
+  if (f2) std::fclose(f2);
+  expect(same, "analysis file differs after a round trip", name);
+  std::remove(p1);
+  std::remove(p2);
+}
+
 void run_valid(const Csr& h, const spi_opts& o, const char* name) {
   std::string first;
   for (const char* nt : {"1", "3", "7"}) {
@@ -148,6 +179,7 @@ void run_valid(const Csr& h, const spi_opts& o, const char* name) {
     expect(e.empty(), e.c_str(), name);
     if (!e.empty()) return;
     check(a, h, name);
+    if (nt[0] == '3') round_trip(a, o, name);
     std::string sig = std::to_string(a.n_groups) + "/" + std::to_string(a.n_root) + "/" +
                       std::to_string(a.inc.size()) + "/" + std::to_string(a.tasks.size());
     if (first.empty()) first = sig;

@@ -162,3 +162,40 @@ def test_device_memory_cap():
     o = oracle_solve(p)
     assert _rel(x, o["x"]) <= 1e-12
     assert np.max(np.abs(d - o["diag"]) / o["diag"]) <= 1e-12
+
+
+def test_handle_from_an_analysis_file(tmp_path):
+    """A handle read from an analysis file (spi_save_analysis, or the
+    host-only spi_symbolic_save, then spi_analyze_load) gives the fresh
+    handle's results: b bit for bit, x and the variances to rounding (1e-13:
+    the root assembly's additions come in no fixed order).  The file's
+    analysis options replace the caller's; the caller's others (mixed
+    precision here) apply."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, symbolic_save
+    p = synth.make_random_leafy(12, 7, 600, 3, 25, 50, seed=5)
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col, max_group=8)
+    i0 = s.info()
+    b1, x1, d1 = _pipeline(s, p, torch)
+    f1 = tmp_path / "saved.spia"
+    s.save_analysis(f1)
+    s.close()
+    _say(f"case analysis file: {f1.stat().st_size} bytes, {i0['n_groups']} fronts")
+    t = SpiSolver.from_analysis(f1)  # default options: max_group from the file
+    i1 = t.info()
+    for k in ("n_groups", "n_root", "n_root_padded", "nnz_l", "asm_tile"):
+        assert i1[k] == i0[k], k
+    b2, x2, d2 = _pipeline(t, p, torch)
+    t.close()
+    assert np.array_equal(b1, b2)
+    assert _rel(x2, x1) <= 1e-13
+    assert np.max(np.abs(d2 - d1) / d1) <= 1e-13
+    f2 = tmp_path / "symbolic.spia"
+    symbolic_save(p.m, p.n, p.rowptr, p.col, f2, max_group=8)
+    u = SpiSolver.from_analysis(f2, precision=1)
+    assert u.info()["precision"] == 1 and u.info()["n_groups"] == i0["n_groups"]
+    _, x3, d3 = _pipeline(u, p, torch)
+    u.close()
+    o = oracle_solve(p)
+    assert _rel(x3, o["x"]) <= 1e-10
+    assert np.max(np.abs(d3 - o["diag"]) / o["diag"]) <= 1e-6

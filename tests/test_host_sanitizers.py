@@ -1,12 +1,13 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU).
 
 The host analysis (``csrc/analysis.cpp``: validation, ordering, fronts,
-maps, incidences, task order; multithreaded) is compiled with g++ and both
-sanitizers, linked with the driver ``tests/host_sanitize/analysis_driver.cpp``
+maps, incidences, task order; multithreaded) and its files
+(``csrc/analysis_io.cpp``) are compiled with g++ and both sanitizers, linked with the driver ``tests/host_sanitize/analysis_driver.cpp``
 and run with leak checking on.  The driver analyses coded-mask shaped and
 random patterns, a dense root, empty rows and a single unknown with 1, 3 and
-7 threads, checks each result's invariants, and feeds invalid patterns that
-must be refused.  An out-of-bounds access, use after free, leak, data
+7 threads, checks each result's invariants and that it survives a write and
+read of its analysis file unchanged, and feeds invalid patterns that must be
+refused.  An out-of-bounds access, use after free, leak, data
 overflow or other undefined operation stops it with the sanitizer's report.
 """
 import os
@@ -27,17 +28,21 @@ def test_host_analysis_under_sanitizers(tmp_path):
     gxx = shutil.which("g++")
     if gxx is None or not os.path.isdir("/opt/rocm/include"):
         pytest.skip("g++ or the ROCm headers are missing")
-    obj = str(tmp_path / "analysis.o")
     exe = str(tmp_path / "analysis_driver")
-    src = os.path.join(ROOT, "paper_1305_5683_amd", "csrc", "analysis.cpp")
+    csrc = os.path.join(ROOT, "paper_1305_5683_amd", "csrc")
+    objs = []
+    for name in ("analysis.cpp", "analysis_io.cpp"):
+        o = str(tmp_path / (name + ".o"))
+        subprocess.run([gxx] + FLAGS + ["-c", os.path.join(csrc, name), "-o", o],
+                       check=True, capture_output=True, text=True)
+        objs.append(o)
     drv = os.path.join(ROOT, "tests", "host_sanitize", "analysis_driver.cpp")
-    subprocess.run([gxx] + FLAGS + ["-c", src, "-o", obj], check=True,
-                   capture_output=True, text=True)
-    subprocess.run([gxx] + FLAGS + [drv, obj, "-o", exe, "-lpthread"], check=True,
+    subprocess.run([gxx] + FLAGS + [drv] + objs + ["-o", exe, "-lpthread"], check=True,
                    capture_output=True, text=True)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
                UBSAN_OPTIONS="print_stacktrace=1")
-    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600,
+                       cwd=str(tmp_path))
     print(r.stdout[-3000:])
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "ALL OK" in r.stdout

@@ -229,3 +229,39 @@ def test_analysis_does_not_depend_on_the_thread_count():
             for k in ("n_leaf", "n_groups", "n_root", "nnz_l", "asm_tile"):
                 assert i0[k] == i1[k]
             assert i0["flops_exec_assembly"] == i1["flops_exec_assembly"]
+
+
+def test_analysis_file_round_trip(tmp_path):
+    """spi_symbolic_save / spi_analysis_file_info: a file gives back the
+    counters of the analysis it holds, the same pattern and options write
+    the same bytes, and a missing, foreign, truncated or corrupted file is
+    refused (host only)."""
+    from paper_1305_5683_amd import (symbolic, symbolic_save, analysis_file_info,
+                                     SpiError)
+    for p, opts in ((synth.make_config(0), {}),
+                    (synth.make_random_leafy(12, 7, 600, 3, 25, 50, seed=5),
+                     {"max_group": 8, "asm_tile": 128})):
+        f1, f2 = tmp_path / "a1.spia", tmp_path / "a2.spia"
+        symbolic_save(p.m, p.n, p.rowptr, p.col, f1, **opts)
+        symbolic_save(p.m, p.n, p.rowptr, p.col, f2, **opts)
+        assert f1.read_bytes() == f2.read_bytes()
+        info, _, _, _ = symbolic(p.m, p.n, p.rowptr, p.col, **opts)
+        got = analysis_file_info(f1)
+        for k in ("m", "n", "nnz_h", "nnz_a", "nnz_l", "n_leaf", "n_groups", "n_root",
+                  "n_root_padded", "flops_factor", "flops_selinv", "flops_solve",
+                  "flops_assembly", "flops_exec_assembly", "flops_exec_selinv",
+                  "flops_root_assembly", "asm_tile"):
+            assert got[k] == info[k], k
+    data = f1.read_bytes()
+    bad = tmp_path / "bad.spia"
+    k = len(data) // 3  # inside one of the arrays
+    cases = [(data[: len(data) // 2], "truncated"),
+             (data[:k] + bytes([data[k] ^ 1]) + data[k + 1:], "corrupted"),
+             (b"not an analysis" * 10, "not an analysis file"),
+             (data + b"\0", "too long")]
+    for blob, why in cases:
+        bad.write_bytes(blob)
+        with pytest.raises(SpiError, match=why):
+            analysis_file_info(bad)
+    with pytest.raises(SpiError, match="cannot open"):
+        analysis_file_info(tmp_path / "missing.spia")
