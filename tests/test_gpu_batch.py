@@ -288,3 +288,55 @@ def test_batch_reports_nonfinite_input():
     batch.close()
     s0.close()
     s1.close()
+
+
+def test_mixed_batch_at_config_scale():
+    """The batch workload's shapes: two energy bands on the medium pattern
+    (33,750 unknowns, a 10,000-pixel root; drifted response and background
+    scales, fresh counts) sharing one analysis, and two sub-problems of sky
+    side 30 and 60, in one graph-replayed mixed-precision batch.  Against
+    the FP64 oracle: x in full at 1e-10, the variances at 1e-6 on 96 sampled
+    unknowns of each band (every one on the sub-problems)."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiBatch
+    base = synth.make_config(1)
+    bands = [synth.make_band(base, *synth.band_scales_drift(b, 64), seed=3000 + b)
+             for b in (0, 40)]
+    subs = [synth.make_problem(synth.SkyConfig(f"sub-s{s}", s, 4 * -(-s * s // 10), 17, 4),
+                               seed=40 + s) for s in (30, 60)]
+    _say(f"case mixed batch at config scale: bands n={base.n}, sub-problems "
+         f"n={[q.n for q in subs]}")
+    opts = dict(precision=1, refine_tol=1e-14, refine_steps=3)
+    first = SpiSolver(base.m, base.n, base.rowptr, base.col,
+                      stream=torch.cuda.Stream(), **opts)
+    solvers = [first, SpiSolver.like(first, stream=torch.cuda.Stream())]
+    solvers += [SpiSolver(q.m, q.n, q.rowptr, q.col, stream=torch.cuda.Stream(), **opts)
+                for q in subs]
+    probs = bands + subs
+    for s, q in zip(solvers, probs):
+        _set(s, q)
+    batch = SpiBatch(solvers, use_graphs=True)
+    y = [torch.from_numpy(q.y).cuda() for q in probs]
+    rhs = [torch.empty(q.n, dtype=torch.float64, device="cuda") for q in probs]
+    x = [torch.empty_like(r) for r in rhs]
+    d = [torch.empty_like(r) for r in rhs]
+    torch.cuda.synchronize()
+    assert batch.run(y, rhs, x, d) == [0] * len(probs)
+    rng = np.random.default_rng(7)
+    for i, q in enumerate(probs):
+        idx = None
+        if q.n == base.n:
+            idx = np.sort(np.concatenate([rng.choice(q.n_bg, 48, replace=False),
+                                          q.n_bg + rng.choice(q.n - q.n_bg, 48,
+                                                              replace=False)]))
+        o = oracle_solve(q, diag_idx=idx)
+        di = d[i].cpu().numpy()
+        if idx is not None:
+            di = di[idx]
+        ex = _rel(x[i].cpu().numpy(), o["x"])
+        ed = np.max(np.abs(di - o["diag"]) / o["diag"])
+        _say(f"  system {i} n={q.n}: err_x={ex:.2e} err_d={ed:.2e}")
+        assert ex <= 1e-10 and ed <= 1e-6
+    batch.close()
+    for s in solvers:
+        s.close()

@@ -198,3 +198,54 @@ def test_trained_network_reduces_iterations():
     lp.close()
     ref.close()
     work.close()
+
+
+def test_trained_network_reduces_iterations_on_the_medium_pattern():
+    """The learned workload's recipe on its pattern: bands on the medium
+    configuration (33,750 unknowns), trained on bands 0..30 for 20 epochs
+    against the factor of band 31; the correction reduces the PCG
+    iterations on later, drifted bands (64, 128, 192) by at least a fifth,
+    with no fallback."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiLearnedPrecond, pcg_solve
+    base = synth.make_config(1)
+    _say(f"case lp-gain, medium pattern m={base.m} n={base.n}")
+    ref_p = _band(base, 31)
+    ref = _solver(ref_p)
+    ref.factor()
+    work = _solver(ref_p)
+    lp = SpiLearnedPrecond(HID, synth.lp_init_params(HID, 0))
+    data = []
+    for b in range(31):
+        bp = _band(base, b)
+        work.set_values(torch.from_numpy(bp.val).cuda(), torch.from_numpy(bp.w).cuda())
+        work.factor()
+        rhs = work.rhs(torch.from_numpy(bp.y).cuda())
+        data.append((bp, rhs, work.solve(rhs).clone()))
+    vals = [(torch.from_numpy(bp.val).cuda(), torch.from_numpy(bp.w).cuda())
+            for bp, _, _ in data]
+    losses = []
+    for epoch in range(20):
+        tot = 0.0
+        for (val, w), (_, rhs, x) in zip(vals, data):
+            work.set_values(val, w)
+            tot += lp.train_step(work, ref, rhs, x, lr=0.02)
+        losses.append(tot / len(data))
+    _say(f"  train loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert losses[-1] < 0.5 * losses[0]
+    it0 = it1 = 0
+    for b in (64, 128, 192):
+        bp = _band(base, b)
+        work.set_values(torch.from_numpy(bp.val).cuda(), torch.from_numpy(bp.w).cuda())
+        rhs = work.rhs(torch.from_numpy(bp.y).cuda())
+        _, i0 = pcg_solve(work, ref, rhs, lp=None, tol=1e-10, maxit=400)
+        _, i1 = pcg_solve(work, ref, rhs, lp=lp, tol=1e-10, maxit=400)
+        _say(f"  band {b}: iterations without {i0['iterations']} with {i1['iterations']}")
+        assert i0["fell_back"] == 0 and i1["fell_back"] == 0
+        it0 += i0["iterations"]
+        it1 += i1["iterations"]
+    _say(f"  total iterations without {it0} with {it1}")
+    assert it1 <= 0.8 * it0
+    lp.close()
+    ref.close()
+    work.close()
