@@ -7,7 +7,7 @@
 //     amalg_density, keep_root_order, asm_tile)
 //   every scalar and vector of the Analysis, each as (tag, element size,
 //     element count, bytes)
-//   FNV-1a 64-bit hash of everything before it
+//   a 64-bit FNV-1a hash (over words) of everything before it
 //
 // Reading checks the magic, the version, every tag, element size and the
 // counts the structure implies (vector lengths against m, n, the number of
@@ -16,7 +16,6 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
-#include <sstream>
 
 #include "spi_internal.h"
 
@@ -30,11 +29,20 @@ constexpr uint32_t kVersion = 1;
 // and must be added to it (and the version raised)
 static_assert(sizeof(Analysis) == 1248, "Analysis changed: update its file format");
 
+// FNV-1a over 64-bit words (the bytes of a final partial word one by one):
+// a checksum against truncation and corruption, not a cryptographic hash.
 struct Hash {
   uint64_t h = 1469598103934665603ull;
   void add(const void* p, size_t n) {
     const unsigned char* c = static_cast<const unsigned char*>(p);
-    for (size_t i = 0; i < n; ++i) {
+    size_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+      uint64_t w;
+      std::memcpy(&w, c + i, 8);
+      h ^= w;
+      h *= 1099511628211ull;
+    }
+    for (; i < n; ++i) {
       h ^= c[i];
       h *= 1099511628211ull;
     }
@@ -75,9 +83,11 @@ void visit(A& a, F&& f) {
   f("flra", a.flops_root_asm);
 }
 
+// Streams to the file (no copy of the whole analysis in memory).
 struct Writer {
-  std::ostringstream out;
+  std::ofstream& out;
   Hash hash;
+  explicit Writer(std::ofstream& o) : out(o) {}
   void raw(const void* p, size_t n) {
     out.write(static_cast<const char*>(p), (std::streamsize)n);
     hash.add(p, n);
@@ -96,21 +106,27 @@ struct Writer {
   }
 };
 
+// Streams from the file; `left` (the bytes not yet read) bounds every
+// length before anything is allocated for it.
 struct Reader {
-  const std::string& buf;
-  size_t pos = 0;
+  std::ifstream& in;
+  uint64_t left;
   Hash hash;
   std::string err;
-  explicit Reader(const std::string& b) : buf(b) {}
+  Reader(std::ifstream& i, uint64_t size) : in(i), left(size) {}
   bool raw(void* p, size_t n) {
     if (!err.empty()) return false;
-    if (n > buf.size() - pos) {
+    if (n > left) {
       err = "the analysis file is truncated";
       return false;
     }
-    std::memcpy(p, buf.data() + pos, n);
-    hash.add(buf.data() + pos, n);
-    pos += n;
+    in.read(static_cast<char*>(p), (std::streamsize)n);
+    if (!in) {
+      err = "cannot read the analysis file";
+      return false;
+    }
+    hash.add(p, n);
+    left -= n;
     return true;
   }
   bool head(const char* tag, uint32_t esize, uint64_t& count) {
@@ -122,7 +138,7 @@ struct Reader {
             std::string(tag, 4) + "'";
       return false;
     }
-    if (count > (buf.size() - pos) / esize) {
+    if (count > left / esize) {
       err = "the analysis file is truncated";
       return false;
     }
@@ -183,7 +199,9 @@ std::string check_shape(const Analysis& a) {
 
 std::string save_analysis(const Analysis& a, const spi_opts& o, const char* path) {
   if (!path) return "null path";
-  Writer w;
+  std::ofstream f(path, std::ios::binary | std::ios::trunc);
+  if (!f) return std::string("cannot write the analysis file ") + path;
+  Writer w(f);
   w.raw(kMagic, sizeof(kMagic));
   const uint32_t ver = kVersion, asz = (uint32_t)sizeof(Analysis);
   w.raw(&ver, sizeof(ver));
@@ -195,10 +213,7 @@ std::string save_analysis(const Analysis& a, const spi_opts& o, const char* path
   w("oast", o.asm_tile);
   visit(a, w);
   const uint64_t h = w.hash.h;
-  w.out.write(reinterpret_cast<const char*>(&h), sizeof(h));
-  std::ofstream f(path, std::ios::binary | std::ios::trunc);
-  const std::string s = w.out.str();
-  f.write(s.data(), (std::streamsize)s.size());
+  f.write(reinterpret_cast<const char*>(&h), sizeof(h));
   f.close();
   if (!f) return std::string("cannot write the analysis file ") + path;
   return std::string();
@@ -206,10 +221,12 @@ std::string save_analysis(const Analysis& a, const spi_opts& o, const char* path
 
 std::string load_analysis(const char* path, Analysis& a, spi_opts& o) {
   if (!path) return "null path";
-  std::ifstream f(path, std::ios::binary);
+  std::ifstream f(path, std::ios::binary | std::ios::ate);
   if (!f) return std::string("cannot open the analysis file ") + path;
-  std::string buf((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
-  Reader r(buf);
+  const std::streamoff size = f.tellg();
+  f.seekg(0);
+  if (size < 0 || !f) return std::string("cannot read the analysis file ") + path;
+  Reader r(f, (uint64_t)size);
   char magic[8];
   uint32_t ver = 0, asz = 0;
   if (!r.raw(magic, 8) || std::memcmp(magic, kMagic, 8) != 0)
@@ -228,8 +245,9 @@ std::string load_analysis(const char* path, Analysis& a, spi_opts& o) {
   if (!r.err.empty()) return r.err;
   uint64_t h = 0;
   const uint64_t want = r.hash.h;
-  if (buf.size() - r.pos != sizeof(h)) return "the analysis file is truncated or too long";
-  std::memcpy(&h, buf.data() + r.pos, sizeof(h));
+  if (r.left != sizeof(h)) return "the analysis file is truncated or too long";
+  f.read(reinterpret_cast<char*>(&h), sizeof(h));
+  if (!f) return "the analysis file is truncated";
   if (h != want) return "the analysis file is corrupted (hash mismatch)";
   const std::string e = check_shape(b);
   if (!e.empty()) return e;
