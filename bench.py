@@ -58,12 +58,12 @@ HBM_COUNTERS = {
     # large coded-mask system, FP64, outer block 512 (profiles/hbm_counters.txt)
     (2, "bulk", 512, "fp64"): {"bytes": 12.812e9 + 4.0965e9, "src": "6291710c77d9dd5a"},
     (2, "bulk", 1024, "fp64"): {"bytes": 28.628e9 + 3.9645e9, "src": "6291710c77d9dd5a"},
-    (2, "assembly", None, "fp64"): {"bytes": 2969.4e9 + 4.2286e9, "src": "5bf19dc26a598eab"},
-    (2, "assembly", None, "mixed"): {"bytes": 2969.4e9 + 4.2286e9, "src": "5bf19dc26a598eab"},
+    (2, "assembly", None, "fp64"): {"bytes": 2969.4e9 + 4.2286e9, "src": "db0047727ae4bf4a"},
+    (2, "assembly", None, "mixed"): {"bytes": 2969.4e9 + 4.2286e9, "src": "db0047727ae4bf4a"},
     # medium coded-mask system, FP64, outer block 512
     (1, "bulk", 512, "fp64"): {"bytes": 1.2486e9 + 0.3683e9, "src": "6291710c77d9dd5a"},
-    (1, "assembly", None, "fp64"): {"bytes": 16.516e9 + 0.4092e9, "src": "5bf19dc26a598eab"},
-    (1, "assembly", None, "mixed"): {"bytes": 16.516e9 + 0.4092e9, "src": "5bf19dc26a598eab"},
+    (1, "assembly", None, "fp64"): {"bytes": 16.516e9 + 0.4092e9, "src": "db0047727ae4bf4a"},
+    (1, "assembly", None, "mixed"): {"bytes": 16.516e9 + 0.4092e9, "src": "db0047727ae4bf4a"},
 }
 
 

@@ -686,35 +686,54 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
                             : (a.n_pad >= kAsmTile128From ? kAsmTileLarge : kAsmTileSmall);
     const int64_t T = a.n_pad / a.asm_tile;
     a.n_tiles = T * (T + 1) / 2;
-    std::vector<int64_t> cnt(a.n_tiles + 1, 0);
-    std::vector<std::array<int32_t, 3>> runs;
-    for (int pass = 0; pass < 2; ++pass) {
-      std::vector<int64_t> fillp;
-      if (pass == 1) {
-        a.inc_ptr.assign(a.n_tiles + 1, 0);
-        for (int64_t t = 0; t < a.n_tiles; ++t) a.inc_ptr[t + 1] = a.inc_ptr[t] + cnt[t];
-        a.inc.resize(4 * a.inc_ptr[a.n_tiles]);
-        fillp.assign(a.inc_ptr.begin(), a.inc_ptr.end() - 1);
-      }
-      for (int64_t u = 0; u < a.n_up; ++u) {
+    // Two passes over the updates, split into NT contiguous ranges (balanced
+    // by |U|^2): counts per range and tile, then every range fills its own
+    // stretch of each tile's list, so the lists hold their incidences in
+    // increasing u whatever the number of threads.
+    std::vector<int64_t> wpre(a.n_up + 1, 0);
+    for (int64_t u = 0; u < a.n_up; ++u)
+      wpre[u + 1] = wpre[u] + (int64_t)a.up_nU[u] * a.up_nU[u];
+    const std::vector<int64_t> ub = balanced_ranges(wpre.data(), a.n_up, NT);
+    std::vector<std::vector<int64_t>> cnt(NT, std::vector<int64_t>(a.n_tiles, 0));
+    auto each = [&](unsigned t, auto&& f) {
+      std::vector<std::array<int32_t, 3>> runs;
+      for (int64_t u = ub[t]; u < ub[t + 1]; ++u) {
         if (a.up_k[u] == 0) continue;
         tile_runs(a.U.data() + a.up_U_off[u], a.up_nU[u], a.asm_tile, runs);
         for (size_t x = 0; x < runs.size(); ++x)
           for (size_t y = 0; y <= x; ++y) {
             const int64_t I = runs[x][0], J = runs[y][0];
-            const int64_t t = I * (I + 1) / 2 + J;
-            if (pass == 0) {
-              cnt[t]++;
-            } else {
-              int32_t* p = a.inc.data() + 4 * fillp[t]++;
-              p[0] = (int32_t)u;
-              p[1] = runs[x][1];
-              p[2] = runs[y][1];
-              p[3] = (runs[x][2] - runs[x][1]) | ((runs[y][2] - runs[y][1]) << 16);
-            }
+            f(u, I * (I + 1) / 2 + J, runs[x], runs[y]);
           }
       }
+    };
+    parallel(NT, [&](unsigned t) {
+      int64_t* c = cnt[t].data();
+      each(t, [&](int64_t, int64_t tt, const std::array<int32_t, 3>&,
+                  const std::array<int32_t, 3>&) { c[tt]++; });
+    });
+    a.inc_ptr.assign(a.n_tiles + 1, 0);
+    for (int64_t tt = 0; tt < a.n_tiles; ++tt) {
+      int64_t sum = a.inc_ptr[tt];
+      for (unsigned t = 0; t < NT; ++t) {
+        const int64_t c = cnt[t][tt];
+        cnt[t][tt] = sum;  // this range's first slot in the tile's list
+        sum += c;
+      }
+      a.inc_ptr[tt + 1] = sum;
     }
+    a.inc.resize(4 * a.inc_ptr[a.n_tiles]);
+    parallel(NT, [&](unsigned t) {
+      int64_t* fillp = cnt[t].data();
+      each(t, [&](int64_t u, int64_t tt, const std::array<int32_t, 3>& rx,
+                  const std::array<int32_t, 3>& ry) {
+        int32_t* p = a.inc.data() + 4 * fillp[tt]++;
+        p[0] = (int32_t)u;
+        p[1] = rx[1];
+        p[2] = ry[1];
+        p[3] = (rx[2] - rx[1]) | ((ry[2] - ry[1]) << 16);
+      });
+    });
     // the first row-panel incidence of each tile (leaf fronts, u < n_groups,
     // come first: incidences are listed by increasing u)
     a.inc_split.assign(a.n_tiles, 0);
@@ -737,73 +756,109 @@ std::string analyze(int64_t m, int64_t n, const int64_t* rowptr,
   }
 
   phase("incidences");
-  // ---- selected-inversion tasks of the leaf fronts
-  {
-    int64_t nt_all = 0;
-    for (int64_t f = 0; f < a.n_groups; ++f) {
-      const int64_t nt = (a.grp_U_ptr[f + 1] - a.grp_U_ptr[f] + kET - 1) / kET;
-      nt_all += nt * (nt + 1) / 2;
-    }
-    a.tasks.reserve(3 * nt_all);
-    a.task_part_off.reserve(nt_all + 1);
-    a.grp_task_ptr.reserve(a.n_groups + 1);
-  }
-  a.grp_task_ptr.push_back(0);
-  a.task_part_off.push_back(0);
+  // ---- selected-inversion tasks of the leaf fronts: (front, I, J) for the
+  // kET-blocks I >= J of the front's U, front by front; the partial sums of
+  // a task take one entry per pivot of its front.  Filled by ranges of fronts
+  // in parallel.
+  a.grp_task_ptr.assign(a.n_groups + 1, 0);
+  std::vector<int64_t> part_base(a.n_groups + 1, 0);
   for (int64_t f = 0; f < a.n_groups; ++f) {
-    int64_t nU = a.grp_U_ptr[f + 1] - a.grp_U_ptr[f];
-    int64_t p = a.grp_col_ptr[f + 1] - a.grp_col_ptr[f];
-    int64_t nt = (nU + kET - 1) / kET;
-    for (int64_t I = 0; I < nt; ++I)
-      for (int64_t J = 0; J <= I; ++J) {
-        a.tasks.push_back((int32_t)f);
-        a.tasks.push_back((int32_t)I);
-        a.tasks.push_back((int32_t)J);
-        a.task_part_off.push_back(a.task_part_off.back() + p);
-      }
-    a.grp_task_ptr.push_back((int64_t)a.tasks.size() / 3);
+    const int64_t nb = (a.grp_U_ptr[f + 1] - a.grp_U_ptr[f] + kET - 1) / kET;
+    const int64_t p = a.grp_col_ptr[f + 1] - a.grp_col_ptr[f];
+    a.grp_task_ptr[f + 1] = a.grp_task_ptr[f] + nb * (nb + 1) / 2;
+    part_base[f + 1] = part_base[f] + nb * (nb + 1) / 2 * p;
   }
+  const int64_t nt_all = a.grp_task_ptr[a.n_groups];
+  a.tasks.resize(3 * nt_all);
+  a.task_part_off.resize(nt_all + 1);
+  a.task_part_off[nt_all] = part_base[a.n_groups];
+  const std::vector<int64_t> fb = balanced_ranges(a.grp_task_ptr.data(), a.n_groups, NT);
+  parallel(NT, [&](unsigned th) {
+    for (int64_t f = fb[th]; f < fb[th + 1]; ++f) {
+      const int64_t nb = (a.grp_U_ptr[f + 1] - a.grp_U_ptr[f] + kET - 1) / kET;
+      const int64_t p = a.grp_col_ptr[f + 1] - a.grp_col_ptr[f];
+      int64_t t = a.grp_task_ptr[f];
+      for (int64_t I = 0; I < nb; ++I)
+        for (int64_t J = 0; J <= I; ++J, ++t) {
+          a.tasks[3 * t] = (int32_t)f;
+          a.tasks[3 * t + 1] = (int32_t)I;
+          a.tasks[3 * t + 2] = (int32_t)J;
+          a.task_part_off[t] = part_base[f] + (t - a.grp_task_ptr[f]) * p;
+        }
+    }
+  });
   // launch order: by 512 x 512 block of the root front at the task's first
   // row / column (a block's Z entries fit an XCD's L2), then by task index.
   // Large workload's leaf selected inversion: 309 ms with 2048-blocks, 292
-  // with 512, 294 with 256, 297 with 1024.
+  // with 512, 294 with 256, 297 with 1024.  A stable counting sort over
+  // contiguous ranges of tasks (each range fills its own stretch of every
+  // key's list, so the order does not depend on the number of threads).
   {
     constexpr int kOrderBlock = 512;
-    const int64_t nt = (int64_t)a.tasks.size() / 3;
-    // keys bj * nb + bi take nb^2 values: a stable counting sort
+    const int64_t nt = nt_all;
     const int64_t nb = std::max<int64_t>(1, (a.n_pad + kOrderBlock - 1) / kOrderBlock);
-    std::vector<int32_t> key(nt);
-    std::vector<int64_t> start(nb * nb + 1, 0);
-    for (int64_t t = 0; t < nt; ++t) {
-      const int64_t f = a.tasks[3 * t], I = a.tasks[3 * t + 1],
-                    J = a.tasks[3 * t + 2];
-      const int32_t* Uf = a.U.data() + a.grp_U_ptr[f];
-      const int64_t bi = Uf[I * kET] / kOrderBlock, bj = Uf[J * kET] / kOrderBlock;
-      key[t] = (int32_t)(bj * nb + bi);
-      start[key[t] + 1]++;
-    }
-    for (int64_t k = 0; k < nb * nb; ++k) start[k + 1] += start[k];
+    const int64_t nk = nb * nb;
+    bigvec<int32_t> key(nt);
+    std::vector<int64_t> tb(NT + 1);
+    for (unsigned th = 0; th <= NT; ++th) tb[th] = nt * (int64_t)th / (int64_t)NT;
+    std::vector<std::vector<int64_t>> kc(NT, std::vector<int64_t>(nk, 0));
+    parallel(NT, [&](unsigned th) {
+      int64_t* c = kc[th].data();
+      for (int64_t t = tb[th]; t < tb[th + 1]; ++t) {
+        const int64_t f = a.tasks[3 * t], I = a.tasks[3 * t + 1], J = a.tasks[3 * t + 2];
+        const int32_t* Uf = a.U.data() + a.grp_U_ptr[f];
+        const int64_t bi = Uf[I * kET] / kOrderBlock, bj = Uf[J * kET] / kOrderBlock;
+        key[t] = (int32_t)(bj * nb + bi);
+        c[key[t]]++;
+      }
+    });
+    int64_t sum = 0;
+    for (int64_t k = 0; k < nk; ++k)
+      for (unsigned th = 0; th < NT; ++th) {
+        const int64_t c = kc[th][k];
+        kc[th][k] = sum;
+        sum += c;
+      }
     a.sel_order.resize(nt);
-    for (int64_t t = 0; t < nt; ++t) a.sel_order[start[key[t]]++] = (int32_t)t;
+    parallel(NT, [&](unsigned th) {
+      int64_t* fill = kc[th].data();
+      for (int64_t t = tb[th]; t < tb[th + 1]; ++t) a.sel_order[fill[key[t]]++] = (int32_t)t;
+    });
   }
 
   phase("selected-inversion tasks");
   // ---- root incidences of the leaf panels (forward solve)
+  // (a counting sort over contiguous ranges of fronts, each range filling
+  // its own stretch of every root index's list: in increasing front order
+  // whatever the number of threads)
   a.rinc_ptr.assign(a.n_root + 1, 0);
-  for (int64_t g = 0; g < a.n_groups; ++g)
-    for (int64_t u = a.grp_U_ptr[g]; u < a.grp_U_ptr[g + 1]; ++u)
-      a.rinc_ptr[a.U[u] + 1]++;
-  for (int64_t i = 0; i < a.n_root; ++i) a.rinc_ptr[i + 1] += a.rinc_ptr[i];
-  a.rinc_grp.resize(a.rinc_ptr[a.n_root]);
-  a.rinc_u.resize(a.rinc_ptr[a.n_root]);
   {
-    std::vector<int64_t> fill(a.rinc_ptr.begin(), a.rinc_ptr.end() - 1);
-    for (int64_t g = 0; g < a.n_groups; ++g)
-      for (int64_t u = a.grp_U_ptr[g]; u < a.grp_U_ptr[g + 1]; ++u) {
-        int64_t k = fill[a.U[u]]++;
-        a.rinc_grp[k] = (int32_t)g;
-        a.rinc_u[k] = (int32_t)(u - a.grp_U_ptr[g]);
+    const std::vector<int64_t> gb = balanced_ranges(a.grp_U_ptr.data(), a.n_groups, NT);
+    std::vector<std::vector<int64_t>> rc(NT, std::vector<int64_t>(a.n_root, 0));
+    parallel(NT, [&](unsigned t) {
+      int64_t* c = rc[t].data();
+      for (int64_t u = a.grp_U_ptr[gb[t]]; u < a.grp_U_ptr[gb[t + 1]]; ++u) c[a.U[u]]++;
+    });
+    for (int64_t i = 0; i < a.n_root; ++i) {
+      int64_t sum = a.rinc_ptr[i];
+      for (unsigned t = 0; t < NT; ++t) {
+        const int64_t c = rc[t][i];
+        rc[t][i] = sum;
+        sum += c;
       }
+      a.rinc_ptr[i + 1] = sum;
+    }
+    a.rinc_grp.resize(a.rinc_ptr[a.n_root]);
+    a.rinc_u.resize(a.rinc_ptr[a.n_root]);
+    parallel(NT, [&](unsigned t) {
+      int64_t* fill = rc[t].data();
+      for (int64_t g = gb[t]; g < gb[t + 1]; ++g)
+        for (int64_t u = a.grp_U_ptr[g]; u < a.grp_U_ptr[g + 1]; ++u) {
+          const int64_t k = fill[a.U[u]]++;
+          a.rinc_grp[k] = (int32_t)g;
+          a.rinc_u[k] = (int32_t)(u - a.grp_U_ptr[g]);
+        }
+    });
   }
 
   phase("root incidences");

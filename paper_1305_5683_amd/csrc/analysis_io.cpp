@@ -100,8 +100,8 @@ struct Writer {
   }
   template <class T>
   void operator()(const char* tag, const T& v) { item(tag, sizeof(T), 1, &v); }
-  template <class T>
-  void operator()(const char* tag, const std::vector<T>& v) {
+  template <class T, class Al>
+  void operator()(const char* tag, const std::vector<T, Al>& v) {
     item(tag, sizeof(T), v.size(), v.data());
   }
 };
@@ -154,8 +154,8 @@ struct Reader {
     }
     raw(&v, sizeof(T));
   }
-  template <class T>
-  void operator()(const char* tag, std::vector<T>& v) {
+  template <class T, class Al>
+  void operator()(const char* tag, std::vector<T, Al>& v) {
     uint64_t c = 0;
     if (!head(tag, sizeof(T), c)) return;
     v.resize(c);

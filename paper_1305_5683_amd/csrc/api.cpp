@@ -16,8 +16,8 @@ namespace {
 
 thread_local std::string g_analyze_err;
 
-template <class T>
-hipError_t dev_copy(T*& dst, const std::vector<T>& src, hipStream_t s) {
+template <class T, class Al>
+hipError_t dev_copy(T*& dst, const std::vector<T, Al>& src, hipStream_t s) {
   dst = nullptr;
   if (src.empty()) return hipSuccess;
   hipError_t e = hipMalloc((void**)&dst, src.size() * sizeof(T));

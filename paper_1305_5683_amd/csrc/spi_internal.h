@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -43,14 +44,37 @@ constexpr int64_t kSelinvChunk = int64_t(1) << 22;
 // Host result of the symbolic analysis.  "slot" = a measurement row in
 // front order: rows of front 0, rows of front 1, ...; within a leaf front
 // the rows of its first leaf column, then its second, and so on.
+// Allocator whose new elements are left uninitialised: the analysis sizes
+// its largest index arrays (one entry per non-zero of H) and fills every
+// element in parallel right away, and value-initialising them first would
+// be a serial pass over gigabytes.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U*) noexcept {}
+  template <class U, class... Args>
+  void construct(U* p, Args&&... args) {
+    ::new ((void*)p) U(std::forward<Args>(args)...);
+  }
+};
+template <class T>
+using bigvec = std::vector<T, NoInitAlloc<T>>;
+
 struct Analysis {
   int64_t m = 0, n = 0, nnz = 0;
   std::vector<int64_t> rowptr;
-  std::vector<int32_t> col;
+  bigvec<int32_t> col;
   // transpose of the pattern
   std::vector<int64_t> colptr;    // n + 1
-  std::vector<int64_t> csc_pos;   // CSR position of each CSC entry
-  std::vector<int32_t> csc_row;   // row of each CSC entry
+  bigvec<int64_t> csc_pos;        // CSR position of each CSC entry
+  bigvec<int32_t> csc_row;        // row of each CSC entry
   // leaves (eliminated first), in front order
   std::vector<int32_t> leaf_cols;       // original column of leaf l
   std::vector<int32_t> leaf_grp;        // front of leaf l
@@ -68,8 +92,8 @@ struct Analysis {
   std::vector<int32_t> slot_row;       // original row
   std::vector<int64_t> slot_rr_ptr;    // n_slots + 1 into the compact root entries
   std::vector<int64_t> slot_leaf_src;  // CSR position of the leaf entry
-  std::vector<int32_t> rr_lpos;        // U-local position of each root entry
-  std::vector<int64_t> rr_src;         // CSR position of each root entry
+  bigvec<int32_t> rr_lpos;             // U-local position of each root entry
+  bigvec<int64_t> rr_src;              // CSR position of each root entry
   // row panels: consecutive rows with overlapping root structure, stored
   // dense |U| x rows (values h, weights w kept per row) for the assembly of
   // A_RR = sum_r w_r h_rR h_rR^T
@@ -81,8 +105,8 @@ struct Analysis {
   std::vector<int64_t> rp_val_off;     // n_rp + 1, offsets of the dense panels
   std::vector<int64_t> rp_rowbase;     // per panel row: offset of its column
   std::vector<int64_t> rpe_ptr;        // per panel row + 1: its root entries
-  std::vector<int32_t> rpe_pos;        // U-local position
-  std::vector<int64_t> rpe_src;        // CSR position
+  bigvec<int32_t> rpe_pos;             // U-local position
+  bigvec<int64_t> rpe_src;             // CSR position
   // update panels (leaf fronts, then row panels): descriptors
   int64_t n_up = 0;
   std::vector<int64_t> up_U_off;       // into U
@@ -97,7 +121,7 @@ struct Analysis {
   std::vector<int32_t> tile_order;     // launch order of the tiles
   std::vector<int64_t> inc_ptr;        // n_tiles + 1
   std::vector<int64_t> inc_split;      // n_tiles: first row-panel incidence
-  std::vector<int32_t> inc;            // 4 per incidence: up, aI0, aJ0, nI|nJ<<16
+  bigvec<int32_t> inc;                 // 4 per incidence: up, aI0, aJ0, nI|nJ<<16
   // root
   int64_t n_root = 0, n_pad = 0;
   std::vector<int32_t> root_cols;      // original column of root index i
@@ -106,16 +130,16 @@ struct Analysis {
   // root incidences (transpose of the U lists): for root index i the
   // (front, U-local position) pairs, as global panel row offsets
   std::vector<int64_t> rinc_ptr;       // n_root + 1
-  std::vector<int32_t> rinc_grp;
-  std::vector<int32_t> rinc_u;
+  bigvec<int32_t> rinc_grp;
+  bigvec<int32_t> rinc_u;
   // selected-inversion tasks of the leaf fronts: (front, I, J), I >= J,
   // tiles of kET positions of the front's U
-  std::vector<int32_t> tasks;          // 3 per task
+  bigvec<int32_t> tasks;               // 3 per task
   std::vector<int64_t> grp_task_ptr;   // n_groups + 1
-  std::vector<int64_t> task_part_off;  // n_tasks + 1 (partial sums)
+  bigvec<int64_t> task_part_off;       // n_tasks + 1 (partial sums)
   // launch order of the tasks: grouped by the 2-D block of the root front
   // they read, so that tasks running together share a region of it
-  std::vector<int32_t> sel_order;
+  bigvec<int32_t> sel_order;
   // counters
   int64_t nnz_a = 0, nnz_l = 0;
   double flops_factor = 0, flops_selinv = 0, flops_solve = 0, flops_asm = 0;

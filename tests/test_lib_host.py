@@ -203,25 +203,35 @@ def test_indefinite_needs_the_root_sweeps():
         symbolic(p.m, p.n, p.rowptr, p.col, indefinite=1, root_inverse=0)
 
 
-def test_analysis_does_not_depend_on_the_thread_count():
+def test_analysis_does_not_depend_on_the_thread_count(tmp_path):
     """The analysis runs its phases on host threads (fixed chunks of leaves
-    and rows where decisions are sequential): 1, 3 and 7 threads give the
-    same fronts, elimination order and counts."""
+    and rows where decisions are sequential, counting sorts over contiguous
+    ranges where lists are filled): 1, 3 and 7 threads give the same fronts,
+    elimination order and counts, and the same analysis files byte for
+    byte (every array of the analysis)."""
+    from paper_1305_5683_amd import symbolic_save
     import os
     from paper_1305_5683_amd import symbolic
     p = synth.make_config(0)
     q = synth.make_random_leafy(30, 6, 300, 3, 20, 200, seed=4)
-    outs = []
+    outs, files = [], []
     old = os.environ.get("SPI_ANALYSIS_THREADS")
     try:
         for nt in ("1", "3", "7"):
             os.environ["SPI_ANALYSIS_THREADS"] = nt
             outs.append([symbolic(r.m, r.n, r.rowptr, r.col) for r in (p, q)])
+            blobs = []
+            for k, r in enumerate((p, q)):
+                f = tmp_path / f"t{nt}_{k}.spia"
+                symbolic_save(r.m, r.n, r.rowptr, r.col, f)
+                blobs.append(f.read_bytes())
+            files.append(blobs)
     finally:
         if old is None:
             os.environ.pop("SPI_ANALYSIS_THREADS", None)
         else:
             os.environ["SPI_ANALYSIS_THREADS"] = old
+    assert files[1] == files[0] and files[2] == files[0]
     for other in outs[1:]:
         for (i0, o0, p0, f0), (i1, o1, p1, f1) in zip(outs[0], other):
             assert np.array_equal(o0, o1) and np.array_equal(p0, p1)
