@@ -275,3 +275,40 @@ def test_analysis_file_round_trip(tmp_path):
             analysis_file_info(bad)
     with pytest.raises(SpiError, match="cannot open"):
         analysis_file_info(tmp_path / "missing.spia")
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    """The ctypes mirrors of spi_opts, spi_info_t and spi_pcg_info have the
+    C header's size and every field at the C header's offset (a C99 program
+    compiled against include/spi.h prints them)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    from paper_1305_5683_amd.spi import spi_opts, spi_info_t, spi_pcg_info
+    structs = (("spi_opts", spi_opts), ("spi_info_t", spi_info_t),
+               ("spi_pcg_info", spi_pcg_info))
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc is missing")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "spi.h"',
+             "int main(void) {"]
+    for cname, py in structs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-I", os.path.join(root, "include"), str(src),
+                    "-o", str(exe)], check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for cname, py in structs:
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
