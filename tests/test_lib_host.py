@@ -312,3 +312,25 @@ def test_binding_structs_match_the_c_header(tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without libspi.so the binding raises on first use: there is no CPU
+    fallback to route the solver through.  Run in a fresh interpreter so the
+    library this process already loaded does not answer."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_1305_5683_amd.spi as spi\n"
+        "spi.LIB_PATH = %r\n"
+        "try:\n"
+        "    spi.load_library(spi.LIB_PATH)\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(3)\n" % (ROOT, str(tmp_path / "libspi.so")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "not found" in r.stdout
