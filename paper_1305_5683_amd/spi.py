@@ -94,6 +94,11 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build it with "
                            "`python -m paper_1305_5683_amd.build`")
+    # torch first: libspi.so's HIP and HSA runtime dependencies then resolve
+    # to the copies torch has already loaded.  Loaded the other way round,
+    # the process holds two HIP runtimes, and the one libspi.so calls finds
+    # no device.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     lib.spi_default_opts.argtypes = [C.POINTER(spi_opts)]

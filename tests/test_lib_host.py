@@ -334,3 +334,24 @@ def test_missing_library_fails_loudly(tmp_path):
                        timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "not found" in r.stdout
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before torch must not bring a second HIP runtime
+    into the process (libspi.so's own dependency next to torch's bundled
+    copy): the binding imports torch first.  Checked from the process's
+    memory map in a fresh interpreter."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1305_5683_amd import load_library\n"
+        "load_library()\n"
+        "import torch\n"
+        "maps = open('/proc/self/maps').read().splitlines()\n"
+        "libs = sorted({l.split()[-1] for l in maps if 'libamdhip64' in l})\n"
+        "print(libs)\n"
+        "sys.exit(0 if len(libs) == 1 else 3)\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
