@@ -178,8 +178,11 @@ typedef struct spi_opts {
                                handle stays in binary64 until the next
                                spi_set_values or spi_set_leaf_values, and
                                spi_info.fp64_fallbacks counts the switches.
-                               Batches (spi_batch_run) report such systems
-                               as before.  0 (default): the call returns
+                               In spi_batch_run such a system is redone
+                               alone in binary64 after the batch's
+                               synchronisation (outside any graph; its
+                               graph is captured again at the next run).
+                               0 (default): the call returns
                                SPI_E_NOT_SPD / SPI_E_NOCONV */
 } spi_opts;
 

@@ -27,6 +27,7 @@ struct Captured {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
+  int precision = -1;  // the handle's precision when captured
 };
 
 void drop(Captured& c) {
@@ -103,7 +104,8 @@ int spi_batch_run(spi_batch* B, const double* const* y, double* const* rhs,
     } else {
       Captured& c = B->graphs[i];
       const void* key[4] = {y[i], rhs[i], x[i], d ? d[i] : nullptr};
-      if (c.exec && !std::equal(key, key + 4, c.key)) drop(c);
+      if (c.exec && (!std::equal(key, key + 4, c.key) || c.precision != h.opts.precision))
+        drop(c);
       if (!c.exec) {
         // everything that allocates or creates must exist before capture
         he = ensure_side_stream(h);
@@ -118,6 +120,7 @@ int spi_batch_run(spi_batch* B, const double* const* y, double* const* rhs,
             he = hipGraphInstantiate(&c.exec, g, nullptr, nullptr, 0);
             c.graph = g;
             std::copy(key, key + 4, c.key);
+            c.precision = h.opts.precision;
           } else if (g) {
             (void)hipGraphDestroy(g);
           }
@@ -139,9 +142,7 @@ int spi_batch_run(spi_batch* B, const double* const* y, double* const* rhs,
   }
   // one synchronisation per stream; the input and pivot flags, then the
   // sizes of the last two refinement corrections, decide each status
-  for (int i = 0; i < k; ++i) {
-    if (!launched[i]) continue;
-    Handle& h = B->hs[i]->h;
+  auto finish = [&](Handle& h) -> int {
     uint64_t f[2] = {0, 0};
     double nv[4] = {0, 0, 0, 0};
     hipError_t he = hipMemcpyAsync(f, h.flag, sizeof(f), hipMemcpyDeviceToHost,
@@ -149,10 +150,7 @@ int spi_batch_run(spi_batch* B, const double* const* y, double* const* rhs,
     if (he == hipSuccess)
       he = hipMemcpyAsync(nv, h.vnorm, sizeof(nv), hipMemcpyDeviceToHost, h.stream);
     if (he == hipSuccess) he = hipStreamSynchronize(h.stream);
-    if (he != hipSuccess) {
-      note(i, fail(h, SPI_E_HIP, he, "batch"));
-      continue;
-    }
+    if (he != hipSuccess) return fail(h, SPI_E_HIP, he, "batch");
     int st = factor_finish(h, f);
     const int steps = h.opts.refine_steps;
     h.refine_done = steps;
@@ -168,6 +166,26 @@ int spi_batch_run(spi_batch* B, const double* const* y, double* const* rhs,
       if (!refine_converged(cur, prev, h.opts.refine_tol))
         st = fail(h, SPI_E_NOCONV, hipSuccess,
                   "iterative refinement did not reach refine_tol in the batch");
+    }
+    return st;
+  };
+  for (int i = 0; i < k; ++i) {
+    if (!launched[i]) continue;
+    Handle& h = B->hs[i]->h;
+    int st = finish(h);
+    if ((st == SPI_E_NOT_SPD || st == SPI_E_NOCONV) && h.opts.fp64_fallback &&
+        h.opts.precision == SPI_MIXED) {
+      // opts.fp64_fallback: this system alone again, every stage in
+      // binary64, outside any graph (its graph is recaptured at the next
+      // run); the handle stays in binary64 until new values arrive
+      h.opts.precision = SPI_FP64;
+      ++h.fp64_fallbacks;
+      drop(B->graphs[i]);
+      const int timing = h.opts.timing;
+      h.opts.timing = 0;
+      st = enqueue_system(h, y[i], rhs[i], x[i], d ? d[i] : nullptr);
+      h.opts.timing = timing;
+      if (st == SPI_OK) st = finish(h);
     }
     note(i, st);
   }

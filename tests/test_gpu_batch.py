@@ -340,3 +340,70 @@ def test_mixed_batch_at_config_scale():
     batch.close()
     for s in solvers:
         s.close()
+
+
+@pytest.mark.parametrize("graphs", [1, 0])
+def test_mixed_batch_falls_back_to_fp64(graphs):
+    """opts.fp64_fallback in a batch.  Beside a well-conditioned band, the
+    near-collinear system of the parity tests (cond(A) about 5.6e8, root in
+    its original order, bands of 128), whose mixed refinement stalls far
+    above refine_tol = 1e-10, is redone alone in binary64 after the batch's
+    synchronisation: both report SPI_OK; its x within 1e-9 of the oracle and
+    its variances within 1e-6 of a plain FP64 handle's; spi_info counts one
+    switch for it and none for the band.  A second run replays the band's
+    graph and recaptures the other in binary64.  Without the option the same
+    batch reports SPI_E_NOCONV for that system only."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver, SpiBatch
+    from test_gpu_parity import _near_collinear
+    base, bands, _ = _systems()
+    q = _near_collinear(far=1)
+    o = oracle_solve(q)
+    ob = oracle_solve(bands[0])
+    qopts = dict(keep_root_order=1, refine_tol=1e-10, refine_steps=10)
+    dev = torch.device("cuda")
+
+    def near(stream=None, **more):
+        s = SpiSolver(q.m, q.n, q.rowptr, q.col, stream=stream, **qopts, **more)
+        s.potrf_block = 128
+        return s
+
+    ref = near(precision=0)       # plain FP64 on the current stream
+    _set(ref, q)
+    ref.factor()
+    ref.solve(ref.rhs(torch.from_numpy(q.y).to(dev)))
+    d_ref = ref.diag_inv().cpu().numpy()
+    ref.close()
+    probs = [bands[0], q]
+    y = [torch.from_numpy(p.y).to(dev) for p in probs]
+    rhs = [torch.empty(p.n, dtype=torch.float64, device=dev) for p in probs]
+    x = [torch.empty_like(r) for r in rhs]
+    d = [torch.empty_like(r) for r in rhs]
+    for fallback in (0, 1):
+        _say(f"case mixed batch fallback={fallback} graphs={graphs}")
+        band = SpiSolver(base.m, base.n, base.rowptr, base.col, stream=torch.cuda.Stream(),
+                         precision=1, refine_tol=1e-12, refine_steps=4,
+                         fp64_fallback=fallback)
+        s = near(stream=torch.cuda.Stream(), precision=1, fp64_fallback=fallback)
+        for h, p in zip((band, s), probs):
+            _set(h, p)
+        torch.cuda.synchronize()
+        batch = SpiBatch([band, s], use_graphs=bool(graphs))
+        for rnd in range(2 if fallback else 1):
+            st = batch.run(y, rhs, x, d)
+            ex = _rel(x[1].cpu().numpy(), o["x"])
+            ed = np.max(np.abs(d[1].cpu().numpy() - d_ref) / d_ref)
+            eb = _rel(x[0].cpu().numpy(), ob["x"])
+            _say(f"  run {rnd}: status {st}; near-collinear err_x={ex:.2e} "
+                 f"err_d={ed:.2e} switches {s.info()['fp64_fallbacks']}; band "
+                 f"err_x={eb:.2e} switches {band.info()['fp64_fallbacks']}")
+            assert eb <= 1e-10 and band.info()["fp64_fallbacks"] == 0
+            if not fallback:
+                assert st == [0, 6]
+                continue
+            assert st == [0, 0]
+            assert ex <= 1e-9 and ed <= 1e-6
+            assert s.info()["fp64_fallbacks"] == 1
+        batch.close()
+        band.close()
+        s.close()
