@@ -6,8 +6,8 @@
 // the whole pipeline of every system (factorisation, right-hand side, solve,
 // variances) on each handle's own stream before synchronising once, so
 // systems run concurrently and fill the gaps of each other's dependency
-// chains (the diagonal-block chain of a root POTRF leaves most of the GPU
-// idle).  With graphs, each handle's pipeline is captured into a HIP graph
+// chains (the pivot-block steps between the root sweeps' bulk updates, the
+// small fronts of uneven sub-problems).  With graphs, each handle's pipeline is captured into a HIP graph
 // on first use and replayed afterwards: one launch per system instead of
 // about a thousand.
 #include <hip/hip_runtime.h>
