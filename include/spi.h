@@ -675,8 +675,10 @@ int spi_batch_create(spi_batch** b, spi_handle* const* hs, int32_t k,
  * so in SPI_MIXED) the sizes of the last two corrections are read back at
  * the final synchronisation, and a system whose refinement did not reach
  * refine_tol by the rule of spi_solve gets SPI_E_NOCONV (x is still
- * written).  Returns SPI_OK, or the first failing status.  All systems are
- * finished on return.
+ * written); with opts.fp64_fallback such a system, or one that met a
+ * non-positive pivot in SPI_MIXED, is first redone alone in binary64 (see
+ * spi_opts).  Returns SPI_OK, or the first failing status.  All systems
+ * are finished on return.
  */
 int spi_batch_run(spi_batch* b, const double* const* y, double* const* rhs,
                   double* const* x, double* const* d, int32_t* status);
