@@ -656,9 +656,12 @@ typedef struct spi_batch spi_batch;
 
 /* Group k distinct handles.  use_graphs = 1: on its first run, each
  * handle's pipeline is captured into a HIP graph.  Later runs with the
- * same buffer pointers replay the graph; new pointers re-capture it.  This
- * needs non-NULL streams.  The handles stay owned by the caller and must
- * outlive the batch. */
+ * same buffer pointers and precision replay the graph; new pointers (or a
+ * switch to binary64, see opts.fp64_fallback) re-capture it.  The launch
+ * shapes are those of the capture: set the outer block and bulk tile
+ * (spi_autotune, spi_set_potrf_block, spi_set_bulk_tile) before the first
+ * run.  This needs non-NULL streams.  The handles stay owned by the caller
+ * and must outlive the batch. */
 int spi_batch_create(spi_batch** b, spi_handle* const* hs, int32_t k,
                      int32_t use_graphs);
 
