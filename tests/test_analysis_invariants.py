@@ -9,8 +9,12 @@ pattern of H in numpy:
 * leaves share no row (the leaf block of A is diagonal);
 * fronts partition the leaves; a front's U is exactly the set of root
   unknowns in the rows of its columns; its panel holds p x |U| values;
+  the slots (a leaf's rows) point at the leaf's entry of H and at each
+  root entry of the row with its position in U;
 * row panels hold every row with root entries exactly once, and a panel's
-  U is exactly the set of root unknowns of its rows;
+  U is exactly the set of root unknowns of its rows; each panel row's
+  entries point at H's root entries with their positions in U, and its
+  column of the dense panel starts where the panel layout says;
 * the selected-inversion tasks of a front are its 64 x 64 blocks (I, J),
   J <= I, each once, their launch order a permutation, their partial sums
   laid out pivot-major without overlap;
@@ -41,7 +45,10 @@ INT = {"rptr": np.int64, "col ": np.int32, "cptr": np.int64, "crow": np.int32,
        "sord": np.int32, "tord": np.int32, "iptr": np.int64, "ispl": np.int64,
        "inc ": np.int32, "rprp": np.int64, "rprw": np.int32, "rpUp": np.int64,
        "rpvo": np.int64, "upUo": np.int64, "upQo": np.int64, "upnU": np.int32,
-       "upk ": np.int32}
+       "upk ": np.int32, "cpos": np.int64, "lslp": np.int64, "gslp": np.int64,
+       "srow": np.int32, "srrp": np.int64, "slsr": np.int64, "rrlp": np.int32,
+       "rrsr": np.int64, "rprb": np.int64, "rpep": np.int64, "rpeq": np.int32,
+       "rpes": np.int64}
 SCALAR = {"m   ", "n   ", "nnz ", "ngrp", "nrp ", "rpUb", "nup ", "asmt", "ntil",
           "nrt ", "npad"}
 
@@ -118,6 +125,13 @@ def test_analysis_invariants(name, p, opts, tmp_path):
     order = np.lexsort((rows_of, col))
     assert np.array_equal(cptr, np.concatenate([[0], np.cumsum(np.bincount(col, minlength=n))]))
     assert np.array_equal(crow, rows_of[order])
+    assert np.array_equal(a["cpos"], order)
+
+    def root_entries(r, Ulist):
+        """H positions of row r's root entries and their positions in U."""
+        e = np.arange(rp[r], rp[r + 1])
+        e = e[rofc[col[e]] >= 0]
+        return e, np.searchsorted(Ulist, rofc[col[e]])
 
     # root unknowns of each row
     rroot = [np.unique(rofc[col[rp[r]:rp[r + 1]]]) for r in range(m)]
@@ -133,6 +147,19 @@ def test_analysis_invariants(name, p, opts, tmp_path):
         want = np.unique(np.concatenate([rroot[r] for r in rows] + [np.zeros(0, np.int32)]))
         assert np.array_equal(Ug, want), (name, g)
         assert gpan[g + 1] - gpan[g] == (gcol[g + 1] - gcol[g]) * len(Ug)
+        # slots of the front's leaves
+        for l in range(gcol[g], gcol[g + 1]):
+            c = lcol[l]
+            sl = np.arange(a["lslp"][l], a["lslp"][l + 1])
+            assert np.array_equal(a["srow"][sl], crow[cptr[c]:cptr[c + 1]])
+            assert np.array_equal(a["slsr"][sl], order[cptr[c]:cptr[c + 1]])
+            for s_ in sl:
+                e, pos = root_entries(a["srow"][s_], Ug)
+                q = np.arange(a["srrp"][s_], a["srrp"][s_ + 1])
+                assert np.array_equal(a["rrsr"][q], e)
+                assert np.array_equal(a["rrlp"][q], pos)
+                assert np.array_equal(Ug[pos], rofc[col[e]])
+    assert np.array_equal(a["gslp"], a["lslp"][gcol])
 
     # row panels
     nrp, rprp, rprw, rpUp, rpUb = a["nrp "], a["rprp"], a["rprw"], a["rpUp"], a["rpUb"]
@@ -143,6 +170,15 @@ def test_analysis_invariants(name, p, opts, tmp_path):
         Uq = U[rpUb + rpUp[q]:rpUb + rpUp[q + 1]]
         want = np.unique(np.concatenate([rroot[r] for r in rprw[rprp[q]:rprp[q + 1]]]))
         assert np.array_equal(Uq, want), (name, q)
+        rpvo = a["rpvo"]
+        assert rpvo[q + 1] - rpvo[q] == len(Uq) * (rprp[q + 1] - rprp[q])
+        for i in range(rprp[q], rprp[q + 1]):
+            assert a["rprb"][i] == rpvo[q] + (i - rprp[q]) * len(Uq)
+            e, pos = root_entries(rprw[i], Uq)
+            z = np.arange(a["rpep"][i], a["rpep"][i + 1])
+            assert np.array_equal(a["rpes"][z], e)
+            assert np.array_equal(a["rpeq"][z], pos)
+            assert np.array_equal(Uq[pos], rofc[col[e]])
 
     # selected-inversion tasks
     task, gtsk, tpof, sord = a["task"].reshape(-1, 3), a["gtsk"], a["tpof"], a["sord"]
