@@ -12,7 +12,7 @@ compared with the FP64 GPU result.  ``--config 1`` times the medium
 configuration (100x100 sky, 5000 pointings, 17x17 field of view, bins of 4
 pointings: 95,000 rows, 33,750 unknowns) instead.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on
+Prints one JSON line.  ``--gpus`` above 1 is refused: the solver runs on
 one GPU.
 
 Other workloads (``--workload``), each printing its own JSON line:
@@ -222,7 +222,7 @@ def main():
         sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "this build has no multi-GPU path", file=sys.stderr)
+              "the solver has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         return run_batch(args)
