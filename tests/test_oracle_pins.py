@@ -272,7 +272,7 @@ def test_block_diagonal_problem_splits():
         assert np.allclose(x[sl], Zi @ bi, rtol=1e-11)
 
 
-# ----------------------------------------------- block factorisation (cfg0)
+# ----------------------------------------------- block factorisation (tiny workload)
 @pytest.fixture(scope="module")
 def tiny():
     p = synth.make_config(0)
