@@ -295,6 +295,21 @@ class SpiSolver:
         if st != SPI_OK:
             raise SpiError(st, self.lib.spi_last_error(self.h).decode())
 
+    def _enter(self, *tensors):
+        """Stream order of a call on the handle's stream when that is not the
+        current stream: the handle's stream first waits for the current
+        stream's work (whatever produced the inputs there), and the tensors'
+        memory is kept from reuse until the handle's stream has used it.
+        Results are ready in the handle's stream order."""
+        import torch
+        cur = torch.cuda.current_stream()
+        if self.stream == cur:
+            return
+        self.stream.wait_stream(cur)
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.stream)
+
     def autotune(self) -> int:
         """Pick the root POTRF outer block by timing; returns it."""
         c = C.c_int32()
@@ -323,6 +338,7 @@ class SpiSolver:
 
     def set_values(self, val, w):
         import torch
+        self._enter(val, w)
         self._check(self.lib.spi_set_values(
             self.h, _ptr(val, self.nnz, torch.float64),
             _ptr(w, self.m, torch.float64)))
@@ -330,16 +346,19 @@ class SpiSolver:
     def set_leaf_values(self, val):
         """New values in the leaf-front (background) columns only."""
         import torch
+        self._enter(val)
         self._check(self.lib.spi_set_leaf_values(
             self.h, _ptr(val, self.nnz, torch.float64)))
 
     def factor(self):
+        self._enter()
         self._check(self.lib.spi_factor(self.h))
 
     def rhs(self, y, out=None):
         import torch
         b = out if out is not None else torch.empty(self.n, dtype=torch.float64,
                                                     device=y.device)
+        self._enter(y, b)
         self._check(self.lib.spi_rhs(self.h, _ptr(y, self.m, torch.float64),
                                      _ptr(b, self.n, torch.float64)))
         return b
@@ -349,6 +368,7 @@ class SpiSolver:
         import torch
         nrhs = 1 if b.dim() == 1 else b.shape[0]
         x = out if out is not None else torch.empty_like(b)
+        self._enter(b, x)
         self._check(self.lib.spi_solve(self.h, _ptr(b, nrhs * self.n, torch.float64),
                                        _ptr(x, nrhs * self.n, torch.float64),
                                        nrhs, self.n))
@@ -358,6 +378,7 @@ class SpiSolver:
         import torch
         d = out if out is not None else torch.empty(
             self.n, dtype=torch.float64, device=torch.device("cuda"))
+        self._enter(d)
         self._check(self.lib.spi_diag_inv(self.h, _ptr(d, self.n, torch.float64)))
         return d
 
@@ -368,6 +389,7 @@ class SpiSolver:
         if cols.numel() != k:
             raise ValueError("rows and cols differ in length")
         out = torch.empty(k, dtype=torch.float64, device=rows.device)
+        self._enter(rows, cols, out)
         if k:
             self._check(self.lib.spi_inv_entries(
                 self.h, k, _ptr(rows, k, torch.int32), _ptr(cols, k, torch.int32),
@@ -380,6 +402,7 @@ class SpiSolver:
         """diag(A^-1) into ``out`` with the library's fixed scratch array
         (no device allocation; see spi_diag_inv_noalloc)."""
         import torch
+        self._enter(out)
         self._check(self.lib.spi_diag_inv_noalloc(
             self.h, _ptr(out, self.n, torch.float64)))
         return out
@@ -431,6 +454,7 @@ class EmptyField:
         s = self.s
         c = C.c_double()
         bg, t, gp, gr, nu, st = self._args()
+        s._enter(val, y, x, U, self.bg_pos, self.t, self.grp_ptr, self.grp_rows)
         s._check(s.lib.spi_empty_field_update(
             s.h, _ptr(val, s.nnz, torch.float64), _ptr(y, s.m, torch.float64),
             _ptr(x, s.n, torch.float64), bg, t, gp, gr, nu, st,
@@ -446,6 +470,7 @@ class EmptyField:
         hist = np.zeros(itermax)
         npass = C.c_int32()
         bg, t, gp, gr, nu, st = self._args()
+        s._enter(val, y, U, x, d, self.bg_pos, self.t, self.grp_ptr, self.grp_rows)
         s._check(s.lib.spi_empty_field_loop(
             s.h, _ptr(val, s.nnz, torch.float64), _ptr(y, s.m, torch.float64),
             bg, t, gp, gr, nu, st, int(itermax), float(rtol),
@@ -461,6 +486,7 @@ def mle_terms(s: "SpiSolver", val, y, x):
     w = torch.empty(s.m, dtype=torch.float64, device=x.device)
     g = torch.empty(s.n, dtype=torch.float64, device=x.device)
     c = C.c_double()
+    s._enter(val, y, x, w, g)
     s._check(s.lib.spi_mle_terms(s.h, _ptr(val, s.nnz, torch.float64),
                                  _ptr(y, s.m, torch.float64),
                                  _ptr(x, s.n, torch.float64),
@@ -475,6 +501,7 @@ def mle_newton(s: "SpiSolver", val, y, x, itermax=20, tol=1e-10, want_diag=True)
     d = torch.empty(s.n, dtype=torch.float64, device=x.device) if want_diag else None
     hist = np.zeros(itermax + 1)
     steps = C.c_int32()
+    s._enter(val, y, x, d)
     s._check(s.lib.spi_mle_newton(
         s.h, _ptr(val, s.nnz, torch.float64), _ptr(y, s.m, torch.float64),
         _ptr(x, s.n, torch.float64), int(itermax), float(tol),
@@ -513,6 +540,8 @@ class SpiLearnedPrecond:
         import torch
         loss = C.c_double()
         g = np.empty(self.P, dtype=np.float64) if grad else None
+        band._enter(rhs, x)
+        ref._enter()
         band._check(self.lib.spi_lp_loss_grad(
             self.h, band.h, ref.h, _ptr(rhs, band.n, torch.float64),
             _ptr(x, band.n, torch.float64), C.byref(loss),
@@ -522,6 +551,8 @@ class SpiLearnedPrecond:
     def train_step(self, band: "SpiSolver", ref: "SpiSolver", rhs, x, lr):
         import torch
         loss = C.c_double()
+        band._enter(rhs, x)
+        ref._enter()
         band._check(self.lib.spi_lp_train_step(
             self.h, band.h, ref.h, _ptr(rhs, band.n, torch.float64),
             _ptr(x, band.n, torch.float64), float(lr), C.byref(loss)))
@@ -548,6 +579,8 @@ def pcg_solve(band: "SpiSolver", ref: "SpiSolver", b, lp=None, tol=1e-10,
     lib = load_library()
     x = out if out is not None else torch.empty_like(b)
     info = spi_pcg_info()
+    band._enter(b, x)
+    ref._enter()
     band._check(lib.spi_pcg_solve(
         band.h, ref.h, None if lp is None else lp.h,
         _ptr(b, band.n, torch.float64), _ptr(x, band.n, torch.float64),
@@ -583,6 +616,8 @@ class SpiBatch:
                     a[i] = _ptr(t, cnt(s), torch.float64).value
             return a
         st = (C.c_int32 * k)()
+        for i, s in enumerate(self.solvers):
+            s._enter(y[i], rhs[i], x[i], None if d is None else d[i])
         ya = arr(y, lambda s: s.m)
         ra = arr(rhs, lambda s: s.n)
         xa = arr(x, lambda s: s.n)

@@ -407,3 +407,40 @@ def test_mixed_batch_falls_back_to_fp64(graphs):
         batch.close()
         band.close()
         s.close()
+
+
+def test_handle_on_its_own_stream():
+    """A handle on a stream of its own, its inputs computed by torch on the
+    current stream right before each call, behind a long fill kernel: the
+    binding makes the handle's stream wait for them, keeps the tensors'
+    memory from reuse, and after the current stream waits for the handle's
+    stream x and diag(A^-1) match the FP64 oracle (three rounds)."""
+    torch = _torch()
+    from paper_1305_5683_amd import SpiSolver
+    _, bands, _ = _systems()
+    p = bands[1]
+    o = oracle_solve(p)
+    _say(f"case handle on its own stream n={p.n}")
+    st = torch.cuda.Stream()
+    s = SpiSolver(p.m, p.n, p.rowptr, p.col, stream=st)
+    val0 = torch.from_numpy(p.val).cuda()
+    w0 = torch.from_numpy(p.w).cuda()
+    y0 = torch.from_numpy(p.y).cuda()
+    torch.cuda.synchronize()
+    for rnd in range(3):
+        busy = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        busy.fill_(1.0)                    # keeps the current stream busy
+        val = val0 * 2.0 / 2.0             # exact, produced behind the fill
+        w = w0 * 4.0 / 4.0
+        y = y0 * 0.5 * 2.0
+        s.set_values(val, w)
+        s.factor()
+        x = s.solve(s.rhs(y))
+        d = s.diag_inv()
+        del val, w, y, busy
+        torch.cuda.current_stream().wait_stream(st)
+        ex = _rel(x.cpu().numpy(), o["x"])
+        ed = np.max(np.abs(d.cpu().numpy() - o["diag"]) / o["diag"])
+        _say(f"  round {rnd}: err_x={ex:.2e} err_d={ed:.2e}")
+        assert ex <= TOL and ed <= TOL
+    s.close()
