@@ -439,7 +439,8 @@ int spi_analyze_load(spi_handle** h, const char* path, const spi_opts* opts,
  * A new handle on the same pattern as `src` (another energy band, Sect.
  * 2.2.3): the host analysis of `src` is copied instead of recomputed, then
  * uploaded and the device buffers sized as in spi_analyze.
- *  opts    may be NULL (src's options); the analysis options (max_group,
+ *  opts    may be NULL (src's options as created: the precision asked
+ *          for, not a binary64 fallback src has made); the analysis options (max_group,
  *          leaf_max_work, amalg_density, keep_root_order, asm_tile) must
  *          equal src's
  *  stream  hipStream_t of the new handle

@@ -427,6 +427,7 @@ int spi_analyze_like(spi_handle** out, const spi_handle* src, const spi_opts* op
   }
   *out = nullptr;
   spi_opts o = src->h.opts;
+  o.precision = src->h.req_precision;  // not a binary64 fallback of src's
   if (opts) o = *opts;
   if (!check_opts(o)) return SPI_E_ARG;
   if (o.max_group != src->h.opts.max_group ||

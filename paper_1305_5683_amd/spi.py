@@ -166,7 +166,10 @@ def default_opts(**kw) -> spi_opts:
     lib = load_library()
     o = spi_opts()
     lib.spi_default_opts(C.byref(o))
+    names = {f[0] for f in spi_opts._fields_}
     for k, v in kw.items():
+        if k not in names:   # a ctypes structure would take it silently
+            raise TypeError(f"unknown solver option {k!r}")
         setattr(o, k, v)
     return o
 
@@ -240,6 +243,7 @@ class SpiSolver:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        self.opts = dict(opts)
         h = C.c_void_p()
         o = default_opts(**opts)
         st = self.lib.spi_analyze(C.byref(h), self.m, self.n, rp.ctypes.data,
@@ -251,14 +255,16 @@ class SpiSolver:
 
     @classmethod
     def like(cls, src: "SpiSolver", stream=None, **opts):
-        """A handle on ``src``'s pattern with a copy of its analysis."""
+        """A handle on ``src``'s pattern with a copy of its analysis; its
+        options are ``src``'s, with ``opts`` replacing some of them."""
         import torch
         self = cls.__new__(cls)
         self.lib = src.lib
         self.m, self.n, self.nnz = src.m, src.n, src.nnz
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.opts = {**src.opts, **opts}
         h = C.c_void_p()
-        o = default_opts(**opts) if opts else None
+        o = default_opts(**self.opts) if opts else None
         st = self.lib.spi_analyze_like(C.byref(h), src.h,
                                        None if o is None else C.byref(o),
                                        C.c_void_p(self.stream.cuda_stream))
@@ -276,6 +282,7 @@ class SpiSolver:
         self = cls.__new__(cls)
         self.lib = load_library()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.opts = dict(opts)
         h = C.c_void_p()
         o = default_opts(**opts)
         st = self.lib.spi_analyze_load(C.byref(h), os.fsencode(path), C.byref(o),

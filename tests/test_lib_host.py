@@ -355,3 +355,12 @@ def test_one_hip_runtime_whatever_the_import_order():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
                        timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_unknown_option_names_are_refused():
+    """A misspelt option must not be dropped silently (ctypes structures
+    accept any attribute name)."""
+    from paper_1305_5683_amd import default_opts
+    assert default_opts(precision=1).precision == 1
+    with pytest.raises(TypeError):
+        default_opts(presicion=1)
