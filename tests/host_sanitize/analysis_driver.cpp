@@ -170,7 +170,57 @@ void round_trip(const spi::Analysis& a, const spi_opts& o, const char* name) {
   std::remove(p2);
 }
 
-void run_valid(const Csr& h, const spi_opts& o, const char* name) {
+// Damaged analysis files: every byte of the header and of the first field
+// descriptors changed in turn, then random single-byte changes and
+// truncations over the whole file.  Each must be refused; under the
+// sanitizers the reader must also touch no memory it does not own while it
+// finds out.
+void damaged_files(const spi::Analysis& a, const spi_opts& o, const char* name) {
+  const char* p = "analysis_driver_d.spia";
+  std::string e = spi::save_analysis(a, o, p);
+  expect(e.empty(), e.c_str(), name);
+  std::string buf;
+  {
+    std::FILE* f = std::fopen(p, "rb");
+    int c;
+    while (f && (c = std::fgetc(f)) != EOF) buf.push_back((char)c);
+    if (f) std::fclose(f);
+  }
+  expect(buf.size() > 64, "analysis file too short", name);
+  std::mt19937_64 rng(12345);
+  int refused = 0, tried = 0;
+  auto attempt = [&](const std::string& b) {
+    std::FILE* f = std::fopen(p, "wb");
+    if (!f) return;
+    std::fwrite(b.data(), 1, b.size(), f);
+    std::fclose(f);
+    spi::Analysis c;
+    spi_opts q = default_opts();
+    const std::string err = spi::load_analysis(p, c, q);
+    ++tried;
+    refused += !err.empty();
+  };
+  for (size_t i = 0; i < std::min<size_t>(buf.size(), 320); ++i) {
+    std::string b = buf;
+    b[i] = (char)(b[i] ^ 0x5a);
+    attempt(b);
+  }
+  for (int k = 0; k < 200; ++k) {
+    std::string b = buf;
+    if (k % 4 == 3) {
+      b.resize(rng() % b.size());
+    } else {
+      const size_t i = rng() % b.size();
+      b[i] = (char)(b[i] ^ (char)(1 + rng() % 255));
+    }
+    attempt(b);
+  }
+  expect(refused == tried, "a damaged analysis file was accepted", name);
+  std::remove(p);
+  std::printf("refused %d of %d damaged files (%s)\n", refused, tried, name);
+}
+
+void run_valid(const Csr& h, const spi_opts& o, const char* name, bool damage = false) {
   std::string first;
   for (const char* nt : {"1", "3", "7"}) {
     setenv("SPI_ANALYSIS_THREADS", nt, 1);
@@ -180,6 +230,7 @@ void run_valid(const Csr& h, const spi_opts& o, const char* name) {
     if (!e.empty()) return;
     check(a, h, name);
     if (nt[0] == '3') round_trip(a, o, name);
+    if (nt[0] == '3' && damage) damaged_files(a, o, name);
     std::string sig = std::to_string(a.n_groups) + "/" + std::to_string(a.n_root) + "/" +
                       std::to_string(a.inc.size()) + "/" + std::to_string(a.tasks.size());
     if (first.empty()) first = sig;
@@ -200,7 +251,7 @@ void run_invalid(const Csr& h, const char* name) {
 
 int main() {
   const spi_opts o = default_opts();
-  run_valid(coded_mask(24, 300, 9, 19, 10, 1), o, "coded-mask 24x24");
+  run_valid(coded_mask(24, 300, 9, 19, 10, 1), o, "coded-mask 24x24", true);
   run_valid(coded_mask(40, 700, 15, 19, 6, 2), o, "coded-mask 40x40");
   spi_opts o64 = o;
   o64.asm_tile = 128;

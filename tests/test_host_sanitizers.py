@@ -6,8 +6,10 @@ maps, incidences, task order; multithreaded) and its files
 and run with leak checking on.  The driver analyses coded-mask shaped and
 random patterns, a dense root, empty rows and a single unknown with 1, 3 and
 7 threads, checks each result's invariants and that it survives a write and
-read of its analysis file unchanged, and feeds invalid patterns that must be
-refused.  An out-of-bounds access, use after free, leak, data
+read of its analysis file unchanged, feeds invalid patterns that must be
+refused, and reads 520 damaged copies of one analysis file (each header and
+descriptor byte changed in turn, random byte changes, truncations), each of
+which must be refused.  An out-of-bounds access, use after free, leak, data
 overflow or other undefined operation stops it with the sanitizer's report.
 """
 import os
